@@ -1,0 +1,280 @@
+"""CPU oracle for SM-compressed integer matrices (arXiv 1303.0270, Method 1).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It wraps the plain C
+implementation in ``ccmref.c`` (bit-at-a-time reader and writer, exact
+``__int128`` arithmetic) through ctypes and shares no code with the GPU
+library.
+
+Every matrix-valued operation follows the definition "decode -> exact integer
+arithmetic -> encode at the minimal width of the result" (see ``ccmref.h`` for
+the readings taken where the paper is silent and for the parity pins).
+
+The module-level functions use the library built from ``ccmref.c``;
+``Oracle(path)`` binds the same API to another build of that source (the
+mutation tests use it to show that the pins catch planted mistakes).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from ._build import build_oracle, library_path
+
+OK, E_INVAL, E_SHAPE, E_RANGE, E_OVERFLOW = 0, -1, -2, -3, -4
+_NAMES = {E_INVAL: "invalid argument", E_SHAPE: "shape mismatch", E_RANGE: "out of range",
+          E_OVERFLOW: "overflow"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle: {_NAMES.get(code, code)}")
+        self.code = code
+
+
+class _Matrix(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("vmin", ctypes.c_int64), ("vmax", ctypes.c_int64),
+                ("bits", ctypes.c_int32), ("is_signed", ctypes.c_int32),
+                ("words", ctypes.c_uint64), ("payload", ctypes.c_void_p)]
+
+
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_U64P = ctypes.POINTER(ctypes.c_uint64)
+_MP = ctypes.POINTER(_Matrix)
+_SIGNATURES = {
+    "ccmref_bitlen": (ctypes.c_int, [ctypes.c_uint64]),
+    "ccmref_sm_width": (ctypes.c_int, [ctypes.c_uint64]),
+    "ccmref_width": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)]),
+    "ccmref_words": (ctypes.c_uint64, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]),
+    "ccmref_plan": (ctypes.c_int, [_I64P, ctypes.c_int64, ctypes.c_int64, _MP]),
+    "ccmref_compress": (ctypes.c_int, [_I64P, _MP]),
+    "ccmref_decompress": (ctypes.c_int, [_MP, _I64P]),
+    "ccmref_get": (ctypes.c_int, [_MP, ctypes.c_int64, ctypes.c_int64, _I64P]),
+    "ccmref_encode_run": (None, [_I64P, ctypes.c_int64, ctypes.c_int32, _U64P]),
+    "ccmref_decode_run": (None, [_U64P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _I64P]),
+    "ccmref_header": (None, [_MP, ctypes.POINTER(ctypes.c_uint8)]),
+    "ccmref_add_dense": (ctypes.c_int, [_MP, _MP, _I64P]),
+    "ccmref_scale_dense": (ctypes.c_int, [_MP, ctypes.c_int64, _I64P]),
+    "ccmref_matvec_rows": (ctypes.c_int, [_MP, _I64P, ctypes.c_int64, ctypes.c_int64, _I64P]),
+    "ccmref_matmul_check": (ctypes.c_int, [_MP, _MP]),
+    "ccmref_matmul_dense": (ctypes.c_int, [_MP, _MP, _I64P]),
+    "ccmref_matmul_entries": (ctypes.c_int, [_MP, _MP, _I64P, _I64P, ctypes.c_int64, _I64P]),
+}
+
+
+def _i64(a: np.ndarray):
+    return a.ctypes.data_as(_I64P)
+
+
+def _u64(a: np.ndarray):
+    return a.ctypes.data_as(_U64P)
+
+
+def _check(rc: int) -> None:
+    if rc != OK:
+        raise OracleError(rc)
+
+
+@dataclass
+class Packed:
+    """The oracle's compressed matrix: header fields plus host payload words."""
+    rows: int
+    cols: int
+    vmin: int
+    vmax: int
+    bits: int
+    is_signed: bool
+    payload: np.ndarray  # uint64 bitstrings, floor(rows*cols*bits/64)+1 of them
+
+    @property
+    def words(self) -> int:
+        return int(self.payload.size)
+
+    def _struct(self) -> _Matrix:
+        return _Matrix(self.rows, self.cols, self.vmin, self.vmax, self.bits,
+                       1 if self.is_signed else 0, self.words,
+                       self.payload.ctypes.data_as(ctypes.c_void_p))
+
+    def payload_bytes(self) -> bytes:
+        return self.payload.astype("<u8").tobytes()
+
+
+class Oracle:
+    """The oracle's API bound to one build of ``ccmref.c``."""
+
+    def __init__(self, path: str):
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        self._lib = lib
+        self.path = path
+
+    # -- bit-length and width ------------------------------------------------
+    def bitlen(self, u: int) -> int:
+        return int(self._lib.ccmref_bitlen(u))
+
+    def sm_width(self, sup: int) -> int:
+        return int(self._lib.ccmref_sm_width(sup))
+
+    def width(self, vmin: int, vmax: int) -> tuple[int, bool]:
+        b, s = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.ccmref_width(vmin, vmax, ctypes.byref(b), ctypes.byref(s)))
+        return int(b.value), bool(s.value)
+
+    def words(self, rows: int, cols: int, bits: int) -> int:
+        return int(self._lib.ccmref_words(rows, cols, bits))
+
+    def packed_bytes(self, rows: int, cols: int, bits: int) -> int:
+        """Closed-form compressed size: 64-byte header plus the bitstrings."""
+        return 64 + 8 * self.words(rows, cols, bits)
+
+    # -- compress / decompress / get ----------------------------------------
+    def compress(self, dense) -> Packed:
+        d = np.ascontiguousarray(np.asarray(dense, dtype=np.int64))
+        if d.ndim != 2:
+            raise OracleError(E_INVAL)
+        m = _Matrix()
+        _check(self._lib.ccmref_plan(_i64(d), d.shape[0], d.shape[1], ctypes.byref(m)))
+        payload = np.zeros(int(m.words), dtype=np.uint64)
+        m.payload = payload.ctypes.data_as(ctypes.c_void_p)
+        _check(self._lib.ccmref_compress(_i64(d), ctypes.byref(m)))
+        return Packed(int(m.rows), int(m.cols), int(m.vmin), int(m.vmax), int(m.bits),
+                      bool(m.is_signed), payload)
+
+    def decompress(self, p: Packed) -> np.ndarray:
+        out = np.empty((p.rows, p.cols), dtype=np.int64)
+        m = p._struct()
+        _check(self._lib.ccmref_decompress(ctypes.byref(m), _i64(out)))
+        return out
+
+    def get(self, p: Packed, i: int, j: int) -> int:
+        v = ctypes.c_int64()
+        m = p._struct()
+        _check(self._lib.ccmref_get(ctypes.byref(m), i, j, ctypes.byref(v)))
+        return int(v.value)
+
+    def header(self, p: Packed) -> bytes:
+        buf = (ctypes.c_uint8 * 64)()
+        m = p._struct()
+        self._lib.ccmref_header(ctypes.byref(m), buf)
+        return bytes(buf)
+
+    def encode_run(self, vals, bits: int, nwords: int | None = None) -> np.ndarray:
+        v = np.ascontiguousarray(np.asarray(vals, dtype=np.int64).ravel())
+        n = v.size
+        if nwords is None:
+            nwords = (n * bits) // 64 + 1
+        if nwords * 64 < n * bits:
+            raise OracleError(E_INVAL)
+        w = np.zeros(nwords, dtype=np.uint64)
+        self._lib.ccmref_encode_run(_i64(v), n, bits, _u64(w))
+        return w
+
+    def decode_run(self, wds, n: int, bits: int, is_signed: bool) -> np.ndarray:
+        w = np.ascontiguousarray(np.asarray(wds, dtype=np.uint64))
+        if w.size * 64 < n * bits:
+            raise OracleError(E_INVAL)
+        out = np.empty(n, dtype=np.int64)
+        self._lib.ccmref_decode_run(_u64(w), n, bits, 1 if is_signed else 0, _i64(out))
+        return out
+
+    # -- arithmetic -----------------------------------------------------------
+    def add_dense(self, a: Packed, b: Packed) -> np.ndarray:
+        out = np.empty((a.rows, a.cols), dtype=np.int64)
+        ma, mb = a._struct(), b._struct()
+        _check(self._lib.ccmref_add_dense(ctypes.byref(ma), ctypes.byref(mb), _i64(out)))
+        return out
+
+    def add(self, a: Packed, b: Packed) -> Packed:
+        return self.compress(self.add_dense(a, b))
+
+    def scale_dense(self, a: Packed, s: int) -> np.ndarray:
+        out = np.empty((a.rows, a.cols), dtype=np.int64)
+        ma = a._struct()
+        _check(self._lib.ccmref_scale_dense(ctypes.byref(ma), s, _i64(out)))
+        return out
+
+    def scale(self, a: Packed, s: int) -> Packed:
+        return self.compress(self.scale_dense(a, s))
+
+    def matvec(self, a: Packed, x, row_begin: int = 0, row_end: int | None = None) -> np.ndarray:
+        """y = A x modulo 2^64 for rows [row_begin, row_end)."""
+        xv = np.ascontiguousarray(np.asarray(x, dtype=np.int64).ravel())
+        if xv.size != a.cols:
+            raise OracleError(E_SHAPE)
+        if row_end is None:
+            row_end = a.rows
+        y = np.empty(max(row_end - row_begin, 0), dtype=np.int64)
+        ma = a._struct()
+        _check(self._lib.ccmref_matvec_rows(ctypes.byref(ma), _i64(xv), row_begin, row_end,
+                                            _i64(y)))
+        return y
+
+    def matmul_check(self, a: Packed, b: Packed) -> None:
+        ma, mb = a._struct(), b._struct()
+        _check(self._lib.ccmref_matmul_check(ctypes.byref(ma), ctypes.byref(mb)))
+
+    def matmul_dense(self, a: Packed, b: Packed) -> np.ndarray:
+        out = np.empty((a.rows, b.cols), dtype=np.int64)
+        ma, mb = a._struct(), b._struct()
+        _check(self._lib.ccmref_matmul_dense(ctypes.byref(ma), ctypes.byref(mb), _i64(out)))
+        return out
+
+    def matmul(self, a: Packed, b: Packed) -> Packed:
+        return self.compress(self.matmul_dense(a, b))
+
+    def matmul_entries(self, a: Packed, b: Packed, ii, jj) -> np.ndarray:
+        i = np.ascontiguousarray(np.asarray(ii, dtype=np.int64).ravel())
+        j = np.ascontiguousarray(np.asarray(jj, dtype=np.int64).ravel())
+        out = np.empty(i.size, dtype=np.int64)
+        ma, mb = a._struct(), b._struct()
+        _check(self._lib.ccmref_matmul_entries(ctypes.byref(ma), ctypes.byref(mb), _i64(i),
+                                               _i64(j), i.size, _i64(out)))
+        return out
+
+
+def _default() -> Oracle:
+    path = library_path()
+    if not os.path.exists(path):
+        build_oracle()
+    return Oracle(path)
+
+
+_ORACLE = _default()
+
+bitlen = _ORACLE.bitlen
+sm_width = _ORACLE.sm_width
+width = _ORACLE.width
+words = _ORACLE.words
+packed_bytes = _ORACLE.packed_bytes
+compress = _ORACLE.compress
+decompress = _ORACLE.decompress
+get = _ORACLE.get
+header = _ORACLE.header
+encode_run = _ORACLE.encode_run
+decode_run = _ORACLE.decode_run
+add_dense = _ORACLE.add_dense
+add = _ORACLE.add
+scale_dense = _ORACLE.scale_dense
+scale = _ORACLE.scale
+matvec = _ORACLE.matvec
+matmul_check = _ORACLE.matmul_check
+matmul_dense = _ORACLE.matmul_dense
+matmul = _ORACLE.matmul
+matmul_entries = _ORACLE.matmul_entries
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's row loops use (OMP_NUM_THREADS or all cores)."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        return int(env)
+    return len(os.sched_getaffinity(0))

@@ -1,0 +1,131 @@
+/*
+ * ccmref.h -- CPU oracle for Supreme-Minimum (SM) compressed integer matrices.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, obviously-correct
+ * definition that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or helper with the GPU library.
+ *
+ * Paper: Paixao & Codeco Coelho, "Computable Compressed Matrices"
+ * (arXiv 1303.0270).  Section references below are to that paper.
+ *
+ * Encoding (Methods, "Matrix compression" and "Method 1: The Supreme Minimum"):
+ *   - one fixed field width b per matrix, b = b(sup M) from Eq. 1;
+ *   - elements unravelled row-major and written as adjacent b-bit chunks,
+ *     least significant bit first ("read from right to left"), with a chunk
+ *     that does not fit in the current 64-bit bitstring straddling into the
+ *     next one (Eq. 3 and the step-by-step example that follows it);
+ *   - floor(dim(M) * b / 64) + 1 bitstrings (text after Table 1).
+ *
+ * Readings where the paper is silent (each is also listed in the design notes):
+ *   - negative values: two's complement in b bits with a per-matrix signed flag,
+ *     set iff min < 0; non-negative matrices encode exactly as in the paper;
+ *   - all bits of the payload past rows*cols*b are zero;
+ *   - operations (add, scale, matvec, matmul) are exact integer arithmetic on
+ *     the decoded values, and every matrix result is re-encoded at the minimal
+ *     width of its own values (signedness also from the result values);
+ *   - overflow: add/scale fail iff an exact result leaves int64; matmul fails
+ *     iff K*max|A|*max|B| >= 2^63 (an O(1) bound from the headers); matvec
+ *     wraps modulo 2^64.
+ *
+ * Parity pins (all in tests/, run without a GPU):
+ *   bitlen / width: Table 1's eight bit-lengths, Eq. 1's {0,1} case, brute force
+ *     against Python's int.bit_length;
+ *   encode / decode / size: the worked example's two bitstrings (Eq. 3 and the
+ *     straddle step), round trips, closed-form size, zero padding, width
+ *     minimality;
+ *   signed encoding: parity unpinned by the paper (it treats positive integers
+ *     only); pinned by round trips, minimality and brute force;
+ *   add / scale / matvec / matmul: parity unpinned by the paper (it gives no
+ *     arithmetic example); pinned by brute force against uncompressed Python
+ *     integer arithmetic and by algebraic identities.
+ */
+#ifndef CCMREF_H
+#define CCMREF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CCMREF_OK = 0,
+  CCMREF_E_INVAL = -1,
+  CCMREF_E_SHAPE = -2,
+  CCMREF_E_RANGE = -3,
+  CCMREF_E_OVERFLOW = -4
+};
+
+/* A compressed matrix "m" (lower-case name for the compressed form of M,
+ * Method 1).  The payload is host memory owned by the caller, `words`
+ * 64-bit bitstrings long. */
+typedef struct {
+  int64_t rows, cols;
+  int64_t vmin, vmax;   /* exact extremes of the values */
+  int32_t bits;         /* field width b */
+  int32_t is_signed;    /* 1 iff vmin < 0 */
+  uint64_t words;       /* floor(rows*cols*bits/64) + 1 */
+  uint64_t *payload;
+} ccmref_matrix;
+
+/* Smallest L with u < 2^L (so bitlen(0) == 0). */
+int ccmref_bitlen(uint64_t u);
+
+/* Eq. 1: b(sup M) = 1 if sup M is 0 or 1, else floor(log2(sup M)) + 1. */
+int ccmref_sm_width(uint64_t sup);
+
+/* Width rule for a value range: Eq. 1 applied to sup M when min >= 0,
+ * otherwise the smallest two's-complement width that holds [min, max]. */
+int ccmref_width(int64_t vmin, int64_t vmax, int32_t *bits, int32_t *is_signed);
+
+/* Number of 64-bit bitstrings, floor(n*b/64) + 1 (text after Table 1). */
+uint64_t ccmref_words(int64_t rows, int64_t cols, int32_t bits);
+
+/* Fill rows, cols, vmin, vmax, bits, is_signed and words from dense values
+ * (row-major, rows*cols int64).  Does not touch payload. */
+int ccmref_plan(const int64_t *dense, int64_t rows, int64_t cols, ccmref_matrix *m);
+
+/* Write the SM bitstrings of dense into m->payload (m from ccmref_plan). */
+int ccmref_compress(const int64_t *dense, ccmref_matrix *m);
+
+/* Decode every element of m into dense (row-major). */
+int ccmref_decompress(const ccmref_matrix *m, int64_t *dense);
+
+/* Element access by row i and column j (both 0-based). */
+int ccmref_get(const ccmref_matrix *m, int64_t i, int64_t j, int64_t *out);
+
+/* Write / read n fields of width b starting at stream bit 0 of words
+ * (a run of adjacent chunks; the building block of compress/decompress). */
+void ccmref_encode_run(const int64_t *vals, int64_t n, int32_t bits, uint64_t *words);
+void ccmref_decode_run(const uint64_t *words, int64_t n, int32_t bits, int32_t is_signed,
+                       int64_t *vals);
+
+/* The 64-byte little-endian header: "CCM1", u16 version 1, u8 bits,
+ * u8 flags (bit 0 signed), i64 rows, cols, min, max, u64 words, 16 zero bytes. */
+void ccmref_header(const ccmref_matrix *m, uint8_t out[64]);
+
+/* Exact elementwise results as dense int64 (to be re-encoded with
+ * ccmref_plan + ccmref_compress). */
+int ccmref_add_dense(const ccmref_matrix *a, const ccmref_matrix *b, int64_t *out);
+int ccmref_scale_dense(const ccmref_matrix *a, int64_t s, int64_t *out);
+
+/* y[i] = sum_j a[i][j] * x[j] modulo 2^64, for rows [row_begin, row_end). */
+int ccmref_matvec_rows(const ccmref_matrix *a, const int64_t *x, int64_t row_begin,
+                       int64_t row_end, int64_t *y);
+
+/* Overflow rule for C = A*B (see the header comment). */
+int ccmref_matmul_check(const ccmref_matrix *a, const ccmref_matrix *b);
+
+/* Dense C = A*B, exact (after ccmref_matmul_check). */
+int ccmref_matmul_dense(const ccmref_matrix *a, const ccmref_matrix *b, int64_t *out);
+
+/* Selected entries C[ii[t]][jj[t]] of A*B, exact. */
+int ccmref_matmul_entries(const ccmref_matrix *a, const ccmref_matrix *b, const int64_t *ii,
+                          const int64_t *jj, int64_t n, int64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

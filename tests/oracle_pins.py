@@ -1,0 +1,414 @@
+"""Pins of the CPU oracle to facts other than the oracle itself.
+
+Each ``pin_*`` function takes an ``oracle.Oracle`` and raises AssertionError if
+the oracle disagrees with what the paper or the mathematics fixes:
+
+* values the paper prints (Table 1, Eq. 1, the worked example of Method 1 and
+  the bitstring count), read from ``tests/golden/``;
+* closed forms (the word count, Eq. 15's bits-used relation);
+* invariants (round trips, minimality of the width, zero padding, locality of
+  the encoding);
+* brute force against uncompressed Python integer arithmetic on tiny inputs,
+  exhaustive for 2x2 matrices of 2-bit values;
+* algebraic identities of the operations.
+
+``tests/test_oracle_pins.py`` runs them on the oracle; the mutation test runs
+them on deliberately broken builds of the oracle source and requires each
+build to fail at least one of them.
+"""
+from __future__ import annotations
+
+import itertools
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+M64 = (1 << 64) - 1
+
+
+def _golden_kv(name: str) -> dict:
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split("=", 1)
+            out[k.strip()] = v.strip()
+    return out
+
+
+def _table1():
+    rows = []
+    with open(os.path.join(GOLDEN, "table1_bitlengths.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                v, binary, bl = line.split()
+                rows.append((int(v), binary, int(bl)))
+    return rows
+
+
+def _to_signed64(u: int) -> int:
+    u &= M64
+    return u - (1 << 64) if u >> 63 else u
+
+
+def _min_width(lo: int, hi: int) -> tuple[int, bool]:
+    """Smallest width holding [lo, hi], searched by brute force over b."""
+    signed = lo < 0
+    for b in range(1, 65):
+        if signed:
+            if -(1 << (b - 1)) <= lo and hi < (1 << (b - 1)):
+                return b, True
+        else:
+            if hi < (1 << b):
+                return b, False
+    raise AssertionError("no width")
+
+
+# ---------------------------------------------------------------------------
+# bit-length and width
+# ---------------------------------------------------------------------------
+
+def pin_table1(o):
+    """Table 1: bit-lengths of the eight printed elements (Eq. 1)."""
+    for v, binary, bl in _table1():
+        assert int(binary, 2) == v and len(binary) == bl
+        assert o.sm_width(v) == bl, (v, o.sm_width(v), bl)
+        assert o.width(0, v) == (bl, False)
+
+
+def pin_eq1_special_case(o):
+    """Eq. 1: sup M in {0, 1} needs one bit; all-zero and all-one matrices get b = 1."""
+    assert o.sm_width(0) == 1 and o.sm_width(1) == 1
+    assert o.width(0, 0) == (1, False) and o.width(1, 1) == (1, False)
+    for fill in (0, 1):
+        p = o.compress(np.full((3, 5), fill, dtype=np.int64))
+        assert p.bits == 1 and not p.is_signed
+        assert o.decompress(p).tolist() == np.full((3, 5), fill).tolist()
+
+
+def pin_bitlen_bruteforce(o):
+    """bitlen against Python's int.bit_length on all u < 2^14 and at every 2^t +- 1."""
+    for u in range(1 << 14):
+        assert o.bitlen(u) == u.bit_length(), u
+    for t in range(64):
+        for u in ((1 << t) - 1, 1 << t, (1 << t) + 1):
+            if u <= M64:
+                assert o.bitlen(u) == u.bit_length(), u
+    assert o.bitlen(M64) == 64
+
+
+def pin_width_bruteforce(o):
+    """The width rule equals a brute-force search for the smallest holding width."""
+    rng = np.random.default_rng(7)
+    cases = [(0, 0), (0, 1), (-1, 0), (-1, -1), (-2, 1), (-3, 0), (0, 2**63 - 1),
+             (-2**63, 2**63 - 1), (-2**63, -2**63), (-2**63, 0), (5, 5), (-129, 127),
+             (-128, 127), (-128, 128)]
+    for t in range(1, 63):
+        cases += [(0, (1 << t) - 1), (0, 1 << t), (-(1 << t), (1 << t) - 1),
+                  (-(1 << t) - 1, 0), (-(1 << t), 1 << t)]
+    for _ in range(300):
+        a, b = sorted(int(v) for v in rng.integers(-2**63, 2**63 - 1, size=2, endpoint=True))
+        sh = int(rng.integers(0, 63))
+        cases.append((a >> sh, b >> sh))
+    for lo, hi in cases:
+        assert o.width(lo, hi) == _min_width(lo, hi), (lo, hi)
+
+
+# ---------------------------------------------------------------------------
+# encoding
+# ---------------------------------------------------------------------------
+
+def pin_worked_example(o):
+    """Method 1's worked example: the two bitstrings of Eq. 3 and the straddle step."""
+    g = _golden_kv("sm_worked_example.txt")
+    vals = [int(v) for v in g["values"].split()]
+    w0 = int(g["bitstring_1"].replace(" ", ""), 2)
+    w1 = int(g["bitstring_2"].replace(" ", ""), 2)
+    p = o.compress(np.array([vals], dtype=np.int64))
+    assert p.bits == int(g["bits"]) and not p.is_signed
+    assert p.words == int(g["words"]) == o.words(1, 8, 10)
+    assert [int(w) for w in p.payload] == [w0, w1]
+    # the same bytes read as 32-bit words, little-endian
+    w32 = np.frombuffer(p.payload_bytes(), dtype="<u4").tolist()
+    assert w32 == [w0 & 0xFFFFFFFF, w0 >> 32, w1 & 0xFFFFFFFF, w1 >> 32]
+    assert o.decompress(p).tolist() == [vals]
+    assert [o.get(p, 0, j) for j in range(8)] == vals
+    h = o.header(p)
+    assert h[:4] == b"CCM1" and h[4:6] == b"\x01\x00" and h[6] == 10 and h[7] == 0
+    le = lambda a, b: int.from_bytes(h[a:b], "little", signed=True)
+    assert (le(8, 16), le(16, 24), le(24, 32), le(32, 40), le(40, 48)) == (1, 8, 1, 1023, 2)
+    assert h[48:] == bytes(16)
+
+
+def pin_word_count(o):
+    """floor(n*b/64) + 1 bitstrings; the payload uses exactly n*b bits (Eq. 15)."""
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        r, c, b = int(rng.integers(1, 1000)), int(rng.integers(1, 1000)), int(rng.integers(1, 65))
+        assert o.words(r, c, b) == (r * c * b) // 64 + 1
+        assert o.packed_bytes(r, c, b) == 64 + 8 * ((r * c * b) // 64 + 1)
+    # n*b a multiple of 64: the paper's formula still adds one (zero) bitstring
+    assert o.words(8, 8, 1) == 2 and o.words(1, 64, 1) == 2
+    for b in range(1, 65):
+        # Eq. 15: eta_1 = (64 - b) / 64 from the bits used, n*b
+        n = 64
+        assert (64 * n - n * b) / (64 * n) == (64 - b) / 64
+
+
+def _random_matrix(rng, rows, cols, b, signed):
+    if signed:
+        lo, hi = -(1 << (b - 1)), (1 << (b - 1)) - 1
+    else:
+        lo, hi = 0, (1 << b) - 1
+    vals = rng.integers(lo, hi, size=(rows, cols), endpoint=True, dtype=np.int64)
+    # force the extremes in so the width is exactly b
+    flat = vals.reshape(-1)
+    flat[int(rng.integers(0, flat.size))] = hi
+    if signed:
+        flat[int(rng.integers(0, flat.size))] = lo
+    return vals
+
+
+def _field_bits(p, e):
+    """Field e of p read from the payload bytes with Python big integers."""
+    big = int.from_bytes(p.payload_bytes(), "little")
+    return (big >> (e * p.bits)) & ((1 << p.bits) - 1)
+
+
+def pin_round_trip(o):
+    """compress -> decompress is the identity; size, padding and minimality hold."""
+    rng = np.random.default_rng(5)
+    shapes = [(1, 1), (1, 7), (7, 1), (3, 21), (64, 1), (2, 32), (5, 13), (17, 19), (1, 200)]
+    for b in range(1, 65):
+        for signed in ((False, True) if b < 64 else (True,)):
+            for rows, cols in shapes[int(rng.integers(0, 3)):][:4]:
+                if b == 1 and signed and rows * cols < 2:
+                    continue
+                m = _random_matrix(rng, rows, cols, b, signed)
+                p = o.compress(m)
+                lo, hi = int(m.min()), int(m.max())
+                assert (p.vmin, p.vmax) == (lo, hi)
+                assert (p.bits, p.is_signed) == _min_width(lo, hi), (b, signed)
+                assert p.words == (rows * cols * p.bits) // 64 + 1
+                assert np.array_equal(o.decompress(p), m)
+                # every field holds the low b bits of the value's two's complement
+                for e in (0, rows * cols // 2, rows * cols - 1):
+                    v = int(m.reshape(-1)[e])
+                    assert _field_bits(p, e) == v & ((1 << p.bits) - 1)
+                # bits past n*b are zero
+                big = int.from_bytes(p.payload_bytes(), "little")
+                assert big >> (rows * cols * p.bits) == 0
+
+
+def pin_signed_small_bruteforce(o):
+    """Every value of every width up to 5 bits, alone and in pairs, round-trips."""
+    for b in range(1, 6):
+        vals = list(range(-(1 << (b - 1)), 1 << (b - 1))) if b > 0 else []
+        for v in vals:
+            p = o.compress(np.array([[v]], dtype=np.int64))
+            assert o.decompress(p)[0, 0] == v
+            assert p.bits == _min_width(v, v)[0]
+        for v, w in itertools.product(vals, repeat=2):
+            m = np.array([[v, w]], dtype=np.int64)
+            p = o.compress(m)
+            assert o.decompress(p).tolist() == m.tolist()
+
+
+def pin_locality(o):
+    """Fields are independent: a run of elements starting at a multiple of 64
+    elements encodes to the corresponding bitstrings of the whole matrix."""
+    rng = np.random.default_rng(3)
+    for b in (1, 5, 10, 31, 33, 64):
+        m = _random_matrix(rng, 9, 100, b, signed=(b > 32))
+        p = o.compress(m)
+        flat = m.reshape(-1)
+        for start in (0, 64, 192, 576):
+            n = min(128, flat.size - start)
+            w = o.encode_run(flat[start:start + n], p.bits, nwords=(n * p.bits + 63) // 64)
+            w0 = start * p.bits // 64
+            full = p.payload[w0:w0 + w.size].copy()
+            if (n * p.bits) % 64:
+                full[-1] &= np.uint64((1 << ((n * p.bits) % 64)) - 1)
+            assert np.array_equal(full, w), (b, start)
+            back = o.decode_run(p.payload[w0:], n, p.bits, p.is_signed)
+            assert np.array_equal(back, flat[start:start + n])
+
+
+def pin_get(o):
+    """get(i, j) equals the (i, j) element; out-of-range indices are rejected."""
+    import oracle as _mod
+    rng = np.random.default_rng(9)
+    m = _random_matrix(rng, 6, 11, 13, True)
+    p = o.compress(m)
+    for i in range(6):
+        for j in range(11):
+            assert o.get(p, i, j) == m[i, j]
+    for i, j in ((-1, 0), (6, 0), (0, 11), (0, -1)):
+        try:
+            o.get(p, i, j)
+        except _mod.OracleError as e:
+            assert e.code == _mod.E_RANGE
+        else:
+            raise AssertionError("out-of-range get accepted")
+
+
+# ---------------------------------------------------------------------------
+# operations: brute force on uncompressed values
+# ---------------------------------------------------------------------------
+
+def _py(m):
+    return [[int(v) for v in row] for row in np.asarray(m)]
+
+
+def _check_ops(o, A, B, x, s, C=None):
+    pa, pb = o.compress(A), o.compress(B)
+    a, b = _py(A), _py(B)
+    rows, cols = len(a), len(a[0])
+    add = [[a[i][j] + b[i][j] for j in range(cols)] for i in range(rows)]
+    got = o.add(pa, pb)
+    assert _py(o.decompress(got)) == add
+    lo, hi = min(map(min, add)), max(map(max, add))
+    assert (got.vmin, got.vmax) == (lo, hi) and (got.bits, got.is_signed) == _min_width(lo, hi)
+    sc = [[s * a[i][j] for j in range(cols)] for i in range(rows)]
+    got = o.scale(pa, s)
+    assert _py(o.decompress(got)) == sc
+    lo, hi = min(map(min, sc)), max(map(max, sc))
+    assert (got.bits, got.is_signed) == _min_width(lo, hi)
+    y = [_to_signed64(sum(a[i][j] * int(x[j]) for j in range(cols))) for i in range(rows)]
+    assert o.matvec(pa, x).tolist() == y
+    if C is not None:
+        pc = o.compress(C)
+        c = _py(C)
+        mm = [[sum(a[i][k] * c[k][j] for k in range(cols)) for j in range(len(c[0]))]
+              for i in range(rows)]
+        got = o.matmul(pa, pc)
+        assert _py(o.decompress(got)) == mm
+        lo, hi = min(map(min, mm)), max(map(max, mm))
+        assert (got.bits, got.is_signed) == _min_width(lo, hi)
+        ii = [i for i in range(rows) for _ in range(len(c[0]))]
+        jj = [j for _ in range(rows) for j in range(len(c[0]))]
+        assert o.matmul_entries(pa, pc, ii, jj).tolist() == [mm[i][j] for i, j in zip(ii, jj)]
+
+
+def pin_ops_bruteforce(o):
+    """add, scale, matvec and matmul equal Python integer arithmetic on the values."""
+    rng = np.random.default_rng(13)
+    for trial in range(40):
+        rows, cols, k2 = (int(v) for v in rng.integers(1, 9, size=3))
+        ba, bb = (int(v) for v in rng.integers(1, 40, size=2))
+        A = _random_matrix(rng, rows, cols, ba, bool(trial % 2))
+        B = _random_matrix(rng, rows, cols, bb, bool(trial % 3 == 0))
+        C = _random_matrix(rng, cols, k2, int(rng.integers(1, 20)), bool(trial % 5 == 0))
+        x = rng.integers(-2**31, 2**31, size=cols, dtype=np.int64)
+        s = int(rng.integers(-1000, 1000))
+        _check_ops(o, A, B, x, s, C)
+    # matvec wraps modulo 2^64
+    A = np.full((2, 3), 2**62, dtype=np.int64)
+    x = np.array([3, 5, 1], dtype=np.int64)  # exact row sum 9 * 2^62 = 2^65 + 2^62
+    assert o.matvec(o.compress(A), x).tolist() == [2**62] * 2
+
+
+def pin_ops_exhaustive_2x2(o):
+    """Every 2x2 matrix of 2-bit unsigned values against every signed 2-bit partner."""
+    una = list(itertools.product(range(4), repeat=4))
+    sgn = list(itertools.product(range(-2, 2), repeat=4))
+    x = np.array([3, -5], dtype=np.int64)
+    partners = sgn[::17]
+    for va in una:
+        A = np.array(va, dtype=np.int64).reshape(2, 2)
+        pa = o.compress(A)
+        a = _py(A)
+        assert o.matvec(pa, x).tolist() == [a[i][0] * 3 - a[i][1] * 5 for i in range(2)]
+        for vb in partners:
+            B = np.array(vb, dtype=np.int64).reshape(2, 2)
+            pb = o.compress(B)
+            b = _py(B)
+            assert _py(o.decompress(o.add(pa, pb))) == [[a[i][j] + b[i][j] for j in range(2)]
+                                                       for i in range(2)]
+            assert _py(o.decompress(o.matmul(pa, pb))) == [
+                [a[i][0] * b[0][j] + a[i][1] * b[1][j] for j in range(2)] for i in range(2)]
+    for vb in sgn:
+        B = np.array(vb, dtype=np.int64).reshape(2, 2)
+        pb = o.compress(B)
+        b = _py(B)
+        assert _py(o.decompress(o.scale(pb, -3))) == [[-3 * v for v in row] for row in b]
+        assert o.matvec(pb, x).tolist() == [b[i][0] * 3 - b[i][1] * 5 for i in range(2)]
+
+
+def pin_identities(o):
+    """A e_j = column j, A 1 = row sums, A + 0 = A, 1 A = A, 0 A = 0 (b = 1),
+    A I = A, (A + B) x = A x + B x (mod 2^64)."""
+    rng = np.random.default_rng(17)
+    for b, signed in ((1, False), (10, False), (12, True), (31, True), (40, False)):
+        A = _random_matrix(rng, 7, 9, b, signed)
+        B = _random_matrix(rng, 7, 9, max(1, b - 3), not signed)
+        pa, pb = o.compress(A), o.compress(B)
+        for j in range(9):
+            e = np.zeros(9, dtype=np.int64)
+            e[j] = 1
+            assert o.matvec(pa, e).tolist() == A[:, j].tolist()
+        assert o.matvec(pa, np.ones(9, dtype=np.int64)).tolist() == [
+            _to_signed64(sum(int(v) for v in row)) for row in A]
+        zero = o.compress(np.zeros((7, 9), dtype=np.int64))
+        same = o.add(pa, zero)
+        assert (o.header(same), same.payload_bytes()) == (o.header(pa), pa.payload_bytes())
+        one = o.scale(pa, 1)
+        assert (o.header(one), one.payload_bytes()) == (o.header(pa), pa.payload_bytes())
+        z = o.scale(pa, 0)
+        assert z.bits == 1 and not z.is_signed and not z.payload.any()
+        neg = o.scale(pa, -1)
+        assert np.array_equal(o.decompress(neg), -A)
+        assert neg.is_signed == (int(A.max()) > 0)
+        eye = o.compress(np.eye(9, dtype=np.int64))
+        ai = o.matmul(pa, eye)
+        assert (o.header(ai), ai.payload_bytes()) == (o.header(pa), pa.payload_bytes())
+        x = rng.integers(-2**31, 2**31, size=9, dtype=np.int64)
+        lhs = o.matvec(o.add(pa, pb), x)
+        rhs = [_to_signed64(int(u) + int(v)) for u, v in zip(o.matvec(pa, x), o.matvec(pb, x))]
+        assert lhs.tolist() == rhs
+
+
+def pin_overflow_rules(o):
+    """add and scale fail exactly when a result leaves int64; matmul fails iff
+    K * max|A| * max|B| >= 2^63; matvec never fails (it wraps)."""
+    import oracle as _mod
+
+    def raises(fn):
+        try:
+            fn()
+        except _mod.OracleError as e:
+            return e.code
+        return None
+
+    big = o.compress(np.array([[2**63 - 1, 0]], dtype=np.int64))
+    one = o.compress(np.array([[1, 0]], dtype=np.int64))
+    m1 = o.compress(np.array([[-1, 0]], dtype=np.int64))
+    assert raises(lambda: o.add(big, one)) == _mod.E_OVERFLOW
+    assert raises(lambda: o.add(big, m1)) is None
+    low = o.compress(np.array([[-2**63, 1]], dtype=np.int64))
+    assert raises(lambda: o.scale(low, -1)) == _mod.E_OVERFLOW
+    assert raises(lambda: o.scale(low, 1)) is None
+    assert raises(lambda: o.scale(o.compress(np.array([[2**32]], dtype=np.int64)), 2**31)) \
+        == _mod.E_OVERFLOW
+    assert raises(lambda: o.scale(o.compress(np.array([[2**31]], dtype=np.int64)), 2**31)) is None
+    a1 = o.compress(np.array([[2**31]], dtype=np.int64))
+    a2 = o.compress(np.array([[2**31, 2**31]], dtype=np.int64))
+    bcol = o.compress(np.array([[2**31], [-2**31]], dtype=np.int64))
+    b1 = o.compress(np.array([[-2**31]], dtype=np.int64))
+    # K=2: bound 2 * 2^31 * 2^31 = 2^63 -> rejected even though the exact entry is 0
+    assert raises(lambda: o.matmul(a2, bcol)) == _mod.E_OVERFLOW
+    # K=1: bound 2^62 -> accepted
+    assert o.decompress(o.matmul(a1, b1)).tolist() == [[-2**62]]
+    assert raises(lambda: o.matmul(a1, a2)) is None  # 1x1 * 1x2
+    assert raises(lambda: o.matmul(a2, a2)) == _mod.E_SHAPE
+    assert raises(lambda: o.add(a1, a2)) == _mod.E_SHAPE
+
+
+ALL_PINS = [pin_table1, pin_eq1_special_case, pin_bitlen_bruteforce, pin_width_bruteforce,
+            pin_worked_example, pin_word_count, pin_round_trip, pin_signed_small_bruteforce,
+            pin_locality, pin_get, pin_ops_bruteforce, pin_ops_exhaustive_2x2, pin_identities,
+            pin_overflow_rules]

@@ -1,0 +1,89 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each mutant is the oracle source with one plausible mistake (bit order, a
+dropped term, a wrong sign or index, a transposed operand), built into a
+temporary library on the CPU.  The pin suite must reject every mutant; the
+unmodified source must pass it (checked by test_oracle_pins.py).
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+from oracle_pins import ALL_PINS
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "ccmref.c")
+TESTS = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(TESTS)
+
+MUTANTS = {
+    # bitstrings written from left to right instead of right to left
+    "msb_first_words": [("(uint64_t)1 << (p % 64u)", "(uint64_t)1 << (63u - p % 64u)"),
+                        ("(words[p / 64u] >> (p % 64u))", "(words[p / 64u] >> (63u - p % 64u))")],
+    # fields written most significant bit first (consistently on both sides)
+    "msb_first_fields": [("put_bit(words, p0 + (uint64_t)t,", "put_bit(words, p0 + (uint64_t)(bits - 1 - t),"),
+                         ("get_bit(words, p0 + (uint64_t)t) << t", "get_bit(words, p0 + (uint64_t)(bits - 1 - t)) << t")],
+    # the "+1" of the bitstring count dropped
+    "word_count": [("/ 64u + 1u", "/ 64u")],
+    # bit-length off by one
+    "bitlen": [("(u >> L) != 0", "(u >> L) > 1")],
+    # Eq. 1's first case returns 0 bits
+    "eq1_zero": [("if (sup == 0 || sup == 1) return 1;", "if (sup == 0 || sup == 1) return (int)sup;")],
+    # the sign bit left out of the signed width
+    "signed_width": [("*bits = 1 + (lo > hi ? lo : hi);", "*bits = (lo > hi ? lo : hi) + (lo == hi);")],
+    # sign extension by 2^(b-1) instead of 2^b
+    "sign_extend": [("u = u - ((uint64_t)1 << bits);", "u = u - ((uint64_t)1 << (bits - 1));")],
+    # matmul reads B transposed
+    "matmul_transposed": [("(uint64_t)(k * b->cols + j)", "(uint64_t)(j * b->cols + k)")],
+    # matvec drops the first column
+    "matvec_first_term": [("for (int64_t j = 0; j < a->cols; j++) {\n      int64_t v",
+                           "for (int64_t j = 1; j < a->cols; j++) {\n      int64_t v")],
+    # add subtracts
+    "add_sign": [("(__int128)get_field(a->payload, (uint64_t)e, a->bits, a->is_signed) +",
+                  "(__int128)get_field(a->payload, (uint64_t)e, a->bits, a->is_signed) -")],
+    # overflow bound compares with > instead of >=
+    "matmul_bound": [("if (p * (unsigned __int128)(uint64_t)a->cols >= lim)",
+                      "if (p * (unsigned __int128)(uint64_t)a->cols > lim)")],
+    # signed flag ignored when decoding
+    "decode_unsigned": [("if (is_signed && ((u >> (bits - 1)) & 1u)) {", "if (0) {")],
+}
+
+
+@pytest.fixture(scope="module")
+def src():
+    with open(SRC) as f:
+        return f.read()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, src, tmp_path):
+    text = src
+    for old, new in MUTANTS[name]:
+        assert old in text, f"mutation pattern not found: {old!r}"
+        text = text.replace(old, new)
+    c = tmp_path / "ccmref.c"
+    c.write_text(text)
+    (tmp_path / "ccmref.h").write_text(open(SRC[:-1] + "h").read())
+    so = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-std=gnu11", "-O1", "-fPIC", "-shared", "-fopenmp", str(c), "-o",
+                    str(so)], check=True)
+    # The pins run in a child process: a mutant may also crash (e.g. by writing
+    # past a payload it sized wrongly), which counts as caught.
+    script = (
+        "import sys; sys.path[:0] = [%r, %r]\n"
+        "import oracle, oracle_pins\n"
+        "mut = oracle.Oracle(%r)\n"
+        "failed = []\n"
+        "for pin in oracle_pins.ALL_PINS:\n"
+        "    try:\n"
+        "        pin(mut)\n"
+        "    except Exception as e:\n"
+        "        failed.append(pin.__name__)\n"
+        "print('FAILED', failed)\n"
+        "sys.exit(1 if failed else 0)\n"
+    ) % (ROOT, TESTS, str(so))
+    r = subprocess.run([sys.executable, "-c", script], capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode != 0, f"mutant {name} passed every pin: {r.stdout}{r.stderr}"
