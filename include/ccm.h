@@ -1,0 +1,233 @@
+/*
+ * ccm.h -- C ABI of libccm, linear algebra on SM-compressed integer matrices
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Paper: Paixao & Codeco Coelho, "Computable Compressed Matrices"
+ * (arXiv 1303.0270).  "Methods" below means its section "Methods" and the
+ * subsections "Matrix compression" and "Method 1: The Supreme Minimum (SM)".
+ *
+ * Encoding (Method 1, Eq. 1, Eq. 3):
+ *   A matrix of rows x cols int64 values is stored at ONE field width b:
+ *     - min >= 0: b = b(sup M) from Eq. 1 (1 if max is 0 or 1, else
+ *       floor(log2 max) + 1), unsigned fields;
+ *     - min < 0 (the paper treats positive integers only; this library's
+ *       reading): the smallest b with -2^(b-1) <= min and max < 2^(b-1),
+ *       fields hold the low b bits of the two's complement.
+ *   Elements are unravelled row-major; element e = i*cols + j occupies stream
+ *   bits [e*b, e*b + b), least significant bit first ("read from right to
+ *   left").  Stream bit p is bit p%64 of 64-bit bitstring p/64; a field that
+ *   does not fit in one bitstring straddles into the next (Eq. 3 and the
+ *   straddle step after it).  The canonical payload is W = floor(rows*cols*b
+ *   /64) + 1 little-endian 64-bit bitstrings (the count stated after Table 1)
+ *   with every bit past rows*cols*b zero; the serialized form is a 64-byte
+ *   header (ccm_header_encode) followed by the payload: 64 + 8*W bytes.
+ *   The GPU reads the same bytes as 32-bit words: word q holds stream bits
+ *   [32q, 32q+32).
+ *
+ * Operations (the paper asks that compressed matrices undergo the same
+ * mathematical operations as the uncompressed ones, Introduction; it gives no
+ * algorithm): exact integer arithmetic on the decoded values.  Every
+ * matrix-valued result is re-encoded at the minimal width of its own values
+ * (its signedness too), found by a max/min-reduction pass ("plan") before the
+ * packing pass.  matvec results are int64 modulo 2^64.
+ *
+ * Memory and ownership:
+ *   - Every data pointer marked "device" is GPU memory owned by the caller;
+ *     the library never frees it.  A compressed matrix's payload buffer must
+ *     hold ccm_payload_capacity(rows, cols, bits) bytes (the canonical 8*W
+ *     bytes plus guard words that kernels may read past the last field) and
+ *     be 256-byte aligned (hipMalloc allocations are).  Kernels
+ *     that write a payload write every byte of that capacity.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls marked "async" only enqueue work on it; calls marked "blocking"
+ *     synchronize it before returning.  Inputs must stay valid until the
+ *     enqueued work completes.
+ *   - The library keeps a few bytes of device memory per device for blocking
+ *     reductions (taken under a lock) and the batch objects' metadata.
+ *
+ * Errors: every call returns a ccm_status and never throws.  Arguments are
+ * validated before any work is enqueued; CCM_E_DEVICE reports a HIP error
+ * (the HIP error string is logged to stderr when CCM_LOG is set).
+ */
+#ifndef CCM_H
+#define CCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CCM_OK = 0,
+  CCM_E_INVAL = -1,       /* null pointer, rows or cols < 1, invalid descriptor */
+  CCM_E_SHAPE = -2,       /* operand shapes do not match */
+  CCM_E_RANGE = -3,       /* element index out of range */
+  CCM_E_OVERFLOW = -4,    /* an exact result does not fit in int64 (rules below) */
+  CCM_E_NOMEM = -5,       /* a caller buffer is too small, or an allocation failed */
+  CCM_E_DEVICE = -6,      /* HIP runtime error */
+  CCM_E_UNSUPPORTED = -7  /* valid request this build does not implement */
+} ccm_status;
+
+typedef enum { CCM_I32 = 0, CCM_I64 = 1 } ccm_dtype;
+
+/* Descriptor of a compressed matrix "m" (the paper's lower-case name for the
+ * compressed form of M).  Host struct; `payload` is a device pointer. */
+typedef struct ccm_desc {
+  int64_t rows, cols;
+  int64_t vmin, vmax;  /* exact extremes of the values (not bounds) */
+  int32_t bits;        /* field width b, 1..64 */
+  int32_t is_signed;   /* 1 iff vmin < 0 (fields are two's complement) */
+  uint64_t words;      /* W = floor(rows*cols*bits/64) + 1 */
+  void *payload;       /* device, caller-owned, >= ccm_payload_capacity bytes */
+} ccm_desc;
+
+/* ---- sizes, widths, headers (host only, no GPU work) -------------------- */
+
+/* Library version (major*10000 + minor*100 + patch). */
+int ccm_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char *ccm_status_str(int status);
+
+/* W = floor(rows*cols*bits/64) + 1, the bitstring count after Table 1.
+ * Returns 0 for invalid arguments. */
+uint64_t ccm_words(int64_t rows, int64_t cols, int32_t bits);
+
+/* Serialized size 64 + 8*W bytes (header + payload). 0 if invalid. */
+uint64_t ccm_packed_bytes(int64_t rows, int64_t cols, int32_t bits);
+
+/* Device bytes a payload buffer must hold: 8*W rounded up, plus guard words.
+ * 0 if invalid. */
+uint64_t ccm_payload_capacity(int64_t rows, int64_t cols, int32_t bits);
+
+/* Width rule (Eq. 1 for min >= 0, two's complement otherwise).
+ * CCM_E_INVAL if vmin > vmax or an output pointer is NULL. */
+int ccm_width(int64_t vmin, int64_t vmax, int32_t *bits, int32_t *is_signed);
+
+/* 64-byte little-endian header: "CCM1", u16 version 1, u8 bits, u8 flags
+ * (bit 0 = signed), i64 rows, cols, min, max, u64 W, 16 zero bytes.
+ * decode validates magic, version, flags, bits, W and that the width equals
+ * the width rule applied to [min, max]; it leaves `payload` NULL. */
+int ccm_header_encode(const ccm_desc *d, uint8_t out[64]);
+int ccm_header_decode(const uint8_t in[64], ccm_desc *d);
+
+/* ---- compress / decompress / get (Methods; element access by (i, j)) --- */
+
+/* Exact (min, max) of n dense values (device, dtype CCM_I32 or CCM_I64).
+ * Blocking. */
+int ccm_range(const void *dense, int32_t dtype, int64_t n, int64_t *vmin, int64_t *vmax,
+              void *stream);
+
+/* Plan a compression: runs the range pass over dense (device, rows*cols
+ * row-major values of `dtype`) and fills every field of `out` except
+ * `payload`, which is set to NULL.  Blocking. */
+int ccm_compress_plan(const void *dense, int32_t dtype, int64_t rows, int64_t cols,
+                      ccm_desc *out, void *stream);
+
+/* Pack dense into out->payload at out->bits (Method 1's SM packing).  `out`
+ * must come from ccm_compress_plan over the same values with `payload`
+ * set by the caller.  Async. */
+int ccm_compress(const void *dense, int32_t dtype, const ccm_desc *out, void *stream);
+
+/* Decode every element into dense_out (device, rows*cols int64).  Async. */
+int ccm_decompress(const ccm_desc *a, int64_t *dense_out, void *stream);
+
+/* Element (i, j) into *value (host).  CCM_E_RANGE outside the matrix.
+ * Blocking. */
+int ccm_get(const ccm_desc *a, int64_t i, int64_t j, int64_t *value, void *stream);
+
+/* out[t] = element (ii[t], jj[t]) for t < n; ii, jj, out are device arrays.
+ * Out-of-range pairs yield 0 and set *bad (device int32, may be NULL) to 1.
+ * Async. */
+int ccm_gather(const ccm_desc *a, const int64_t *ii, const int64_t *jj, int64_t n,
+               int64_t *out, int32_t *bad, void *stream);
+
+/* ---- elementwise add and scalar multiply -------------------------------- */
+
+/* C = A + B.  Plan: range pass over the exact sums, fills out (payload
+ * NULL); CCM_E_OVERFLOW iff some sum leaves int64.  Blocking.
+ * Op: decode, add, pack at out->bits.  Async. */
+int ccm_add_plan(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *stream);
+int ccm_add(const ccm_desc *a, const ccm_desc *b, const ccm_desc *out, void *stream);
+
+/* C = s * A.  The result range [s*min, s*max] (ordered) comes from A's
+ * header, so the plan is host-only; CCM_E_OVERFLOW iff it leaves int64.
+ * s = 0 gives an all-zero matrix with b = 1.  Op: async. */
+int ccm_scale_plan(const ccm_desc *a, int64_t s, ccm_desc *out);
+int ccm_scale(const ccm_desc *a, int64_t s, const ccm_desc *out, void *stream);
+
+/* ---- matvec and matmul --------------------------------------------------- */
+
+/* y = A x (y[i] = sum_j a_ij x_j modulo 2^64).  x: device, cols values of
+ * xdtype (CCM_I32 or CCM_I64); y: device, rows int64.  Async; no error for
+ * wrap-around. */
+int ccm_matvec(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, void *stream);
+
+/* C = A B.  CCM_E_OVERFLOW iff K * max|A| * max|B| >= 2^63 (max|M| =
+ * max(|min|, |max|) from the headers; an O(1) conservative bound), so every
+ * entry fits in int64.  Fields of at most 8 bits whose values fit int8 go
+ * through int8 MFMA tiles with exact integer accumulation; others through an
+ * exact int64 path.
+ *   scratch_bytes: device scratch the two calls need (dense C at 4 or 8 bytes
+ *     per entry).
+ *   plan: computes C into scratch and its exact range, fills out (payload
+ *     NULL).  Blocking.
+ *   op: packs the scratch into out->payload.  Async.
+ * The scratch must not be modified between the two calls. */
+uint64_t ccm_matmul_scratch_bytes(const ccm_desc *a, const ccm_desc *b);
+int ccm_matmul_plan(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *scratch,
+                    uint64_t scratch_bytes, void *stream);
+int ccm_matmul(const ccm_desc *a, const ccm_desc *b, const ccm_desc *out,
+               const void *scratch, uint64_t scratch_bytes, void *stream);
+
+/* ---- batched matvec (many matrices, one persistent launch) ------------- */
+
+/* A batch binds n compressed matrices (their descriptors are copied; the
+ * payloads must stay valid) and an int32 or int64 x dtype.  Creating it
+ * builds a work list of (matrix, row block) items ordered by width and size,
+ * with per-width tile choices from a tuning table (JSON written by the
+ * project's autotuner; NULL or an unreadable path uses built-in defaults),
+ * and copies it to device memory the batch owns. */
+typedef struct ccm_batch ccm_batch;
+
+int ccm_batch_create(const ccm_desc *as, int32_t n, int32_t xdtype, const char *tune_json,
+                     ccm_batch **out);
+
+/* Bind the x and y device pointers of every matrix (host arrays of n device
+ * pointers).  Enqueues one host-to-device copy on `stream`.  Async. */
+int ccm_batch_set_io(ccm_batch *b, const void *const *xs, int64_t *const *ys, void *stream);
+
+/* y_t = A_t x_t for every matrix t, in one persistent kernel launch.  With
+ * use_graph != 0 the launch is captured once into a HIP graph and replayed.
+ * Async. */
+int ccm_batch_matvec(ccm_batch *b, int32_t use_graph, void *stream);
+
+/* Work-list statistics: number of items, total packed bytes, max width. */
+int ccm_batch_info(const ccm_batch *b, int64_t *items, uint64_t *packed_bytes,
+                   int32_t *max_bits);
+
+int ccm_batch_destroy(ccm_batch *b);
+
+/* ---- seeded synthetic data (SplitMix64, counter-based) ------------------ */
+
+/* dense[t] = draw number (stream_id << 40) + start + t of SplitMix64 from
+ * `seed`, mapped to [lo, hi) as lo + (((h >> 32) * (hi - lo)) >> 32);
+ * requires 1 <= hi - lo <= 2^32.  Async. */
+int ccm_fill_uniform(void *dense, int32_t dtype, int64_t n, int64_t lo, int64_t hi,
+                     uint64_t seed, uint64_t stream_id, uint64_t start, void *stream);
+
+/* Compress the rows x cols matrix whose row-major elements are the draws
+ * above (start = 0) without a dense copy: plan runs the range pass (blocking)
+ * and fills out (payload NULL); op packs (async). */
+int ccm_generate_plan(int64_t rows, int64_t cols, int64_t lo, int64_t hi, uint64_t seed,
+                      uint64_t stream_id, ccm_desc *out, void *stream);
+int ccm_generate(const ccm_desc *out, int64_t lo, int64_t hi, uint64_t seed,
+                 uint64_t stream_id, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

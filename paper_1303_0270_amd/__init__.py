@@ -1,0 +1,243 @@
+"""ccm: linear algebra on SM-compressed integer matrices on AMD MI355X.
+
+Paper: Paixao & Codeco Coelho, "Computable Compressed Matrices" (arXiv
+1303.0270), Method 1 (Supreme Minimum).  Python binding of libccm (C ABI in
+include/ccm.h): these functions only marshal arguments; every step runs in the
+library's HIP kernels.  PyTorch provides device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import (E_INVAL, E_NOMEM, E_OVERFLOW, E_RANGE, E_SHAPE, E_UNSUPPORTED, I32, I64,
+                   OK, CcmError, Desc, check, lib)
+
+__all__ = ["CMatrix", "CcmError", "compress", "decompress", "get", "gather", "add", "scale",
+           "matvec", "matmul", "fill_uniform", "generate", "from_serialized", "words",
+           "packed_bytes", "payload_capacity", "width", "Batch"]
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.int32:
+        return I32
+    if t.dtype == torch.int64:
+        return I64
+    raise TypeError(f"int32 or int64 tensor expected, got {t.dtype}")
+
+
+def _device_tensor(t: torch.Tensor, what: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    return t.contiguous()
+
+
+def words(rows: int, cols: int, bits: int) -> int:
+    return int(lib.ccm_words(rows, cols, bits))
+
+
+def packed_bytes(rows: int, cols: int, bits: int) -> int:
+    return int(lib.ccm_packed_bytes(rows, cols, bits))
+
+
+def payload_capacity(rows: int, cols: int, bits: int) -> int:
+    return int(lib.ccm_payload_capacity(rows, cols, bits))
+
+
+def width(vmin: int, vmax: int) -> tuple[int, bool]:
+    b, s = ctypes.c_int32(), ctypes.c_int32()
+    check(lib.ccm_width(vmin, vmax, ctypes.byref(b), ctypes.byref(s)), "ccm_width")
+    return int(b.value), bool(s.value)
+
+
+class CMatrix:
+    """A compressed matrix: its descriptor plus the device payload it owns."""
+
+    def __init__(self, desc: Desc, payload: torch.Tensor | None = None, device=None):
+        self.desc = desc
+        if payload is None:
+            cap = int(lib.ccm_payload_capacity(desc.rows, desc.cols, desc.bits))
+            payload = torch.empty(cap, dtype=torch.uint8, device=device or "cuda")
+        self.payload = payload
+        self.desc.payload = payload.data_ptr()
+
+    rows = property(lambda self: int(self.desc.rows))
+    cols = property(lambda self: int(self.desc.cols))
+    vmin = property(lambda self: int(self.desc.vmin))
+    vmax = property(lambda self: int(self.desc.vmax))
+    bits = property(lambda self: int(self.desc.bits))
+    is_signed = property(lambda self: bool(self.desc.is_signed))
+    words = property(lambda self: int(self.desc.words))
+
+    @property
+    def shape(self):
+        return (self.rows, self.cols)
+
+    @property
+    def nbytes(self) -> int:
+        """Serialized size: 64-byte header plus 8*W payload bytes."""
+        return 64 + 8 * self.words
+
+    def header(self) -> bytes:
+        buf = (ctypes.c_uint8 * 64)()
+        check(lib.ccm_header_encode(ctypes.byref(self.desc), buf), "ccm_header_encode")
+        return bytes(buf)
+
+    def payload_bytes(self) -> bytes:
+        """The canonical payload (W little-endian 64-bit bitstrings) as bytes."""
+        torch.cuda.current_stream().synchronize()
+        return bytes(self.payload[: 8 * self.words].cpu().numpy().tobytes())
+
+    def serialize(self) -> bytes:
+        return self.header() + self.payload_bytes()
+
+    def __repr__(self):
+        return (f"CMatrix({self.rows}x{self.cols}, bits={self.bits}, signed={self.is_signed}, "
+                f"range=[{self.vmin}, {self.vmax}])")
+
+
+def from_serialized(blob: bytes, device="cuda") -> CMatrix:
+    """Rebuild a compressed matrix from header + payload bytes."""
+    if len(blob) < 64:
+        raise CcmError(E_INVAL, "from_serialized")
+    d = Desc()
+    hdr = (ctypes.c_uint8 * 64).from_buffer_copy(blob[:64])
+    check(lib.ccm_header_decode(hdr, ctypes.byref(d)), "ccm_header_decode")
+    nbytes = 8 * int(d.words)
+    if len(blob) != 64 + nbytes:
+        raise CcmError(E_INVAL, "from_serialized: payload length")
+    m = CMatrix(d, device=device)
+    m.payload.zero_()
+    host = torch.frombuffer(bytearray(blob[64:]), dtype=torch.uint8)
+    m.payload[:nbytes].copy_(host)
+    return m
+
+
+def compress(dense: torch.Tensor, stream=None) -> CMatrix:
+    """SM-compress a 2-D int32/int64 device tensor (range pass, then packing)."""
+    t = _device_tensor(dense, "dense")
+    if t.dim() != 2:
+        raise ValueError("2-D tensor expected")
+    code = _dtype_code(t)
+    s = _stream(stream)
+    d = Desc()
+    check(lib.ccm_compress_plan(_ptr(t), code, t.shape[0], t.shape[1], ctypes.byref(d), s),
+          "ccm_compress_plan")
+    m = CMatrix(d, device=t.device)
+    check(lib.ccm_compress(_ptr(t), code, ctypes.byref(m.desc), s), "ccm_compress")
+    return m
+
+
+def decompress(m: CMatrix, stream=None) -> torch.Tensor:
+    out = torch.empty((m.rows, m.cols), dtype=torch.int64, device=m.payload.device)
+    check(lib.ccm_decompress(ctypes.byref(m.desc), _ptr(out), _stream(stream)), "ccm_decompress")
+    return out
+
+
+def get(m: CMatrix, i: int, j: int, stream=None) -> int:
+    v = ctypes.c_int64()
+    check(lib.ccm_get(ctypes.byref(m.desc), i, j, ctypes.byref(v), _stream(stream)), "ccm_get")
+    return int(v.value)
+
+
+def gather(m: CMatrix, ii: torch.Tensor, jj: torch.Tensor, stream=None):
+    """Elements (ii[t], jj[t]); returns (values, any_out_of_range)."""
+    ii = _device_tensor(ii.to(torch.int64), "ii")
+    jj = _device_tensor(jj.to(torch.int64), "jj")
+    out = torch.empty(ii.numel(), dtype=torch.int64, device=ii.device)
+    bad = torch.zeros(1, dtype=torch.int32, device=ii.device)
+    check(lib.ccm_gather(ctypes.byref(m.desc), _ptr(ii), _ptr(jj), ii.numel(), _ptr(out),
+                         _ptr(bad), _stream(stream)), "ccm_gather")
+    return out, bool(bad.item())
+
+
+def add(a: CMatrix, b: CMatrix, stream=None) -> CMatrix:
+    s = _stream(stream)
+    d = Desc()
+    check(lib.ccm_add_plan(ctypes.byref(a.desc), ctypes.byref(b.desc), ctypes.byref(d), s),
+          "ccm_add_plan")
+    c = CMatrix(d, device=a.payload.device)
+    check(lib.ccm_add(ctypes.byref(a.desc), ctypes.byref(b.desc), ctypes.byref(c.desc), s),
+          "ccm_add")
+    return c
+
+
+def scale(a: CMatrix, s_: int, stream=None) -> CMatrix:
+    d = Desc()
+    check(lib.ccm_scale_plan(ctypes.byref(a.desc), s_, ctypes.byref(d)), "ccm_scale_plan")
+    c = CMatrix(d, device=a.payload.device)
+    check(lib.ccm_scale(ctypes.byref(a.desc), s_, ctypes.byref(c.desc), _stream(stream)),
+          "ccm_scale")
+    return c
+
+
+def matvec(a: CMatrix, x: torch.Tensor, y: torch.Tensor | None = None, stream=None):
+    """y = A x (int64, modulo 2^64); x is an int32 or int64 device vector."""
+    x = _device_tensor(x, "x")
+    if x.numel() != a.cols:
+        raise CcmError(E_SHAPE, "matvec")
+    if y is None:
+        y = torch.empty(a.rows, dtype=torch.int64, device=x.device)
+    elif y.dtype != torch.int64 or y.numel() != a.rows or not y.is_contiguous():
+        raise CcmError(E_INVAL, "matvec: y")
+    check(lib.ccm_matvec(ctypes.byref(a.desc), _ptr(x), _dtype_code(x), _ptr(y),
+                         _stream(stream)), "ccm_matvec")
+    return y
+
+
+def matmul_scratch_bytes(a: CMatrix, b: CMatrix) -> int:
+    return int(lib.ccm_matmul_scratch_bytes(ctypes.byref(a.desc), ctypes.byref(b.desc)))
+
+
+def matmul(a: CMatrix, b: CMatrix, scratch: torch.Tensor | None = None, stream=None) -> CMatrix:
+    if a.cols != b.rows:
+        raise CcmError(E_SHAPE, "matmul")
+    need = matmul_scratch_bytes(a, b)
+    if need == 0:
+        # invalid descriptors or the overflow bound: let the plan report which
+        need = 8
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(need, dtype=torch.uint8, device=a.payload.device)
+    s = _stream(stream)
+    d = Desc()
+    check(lib.ccm_matmul_plan(ctypes.byref(a.desc), ctypes.byref(b.desc), ctypes.byref(d),
+                              _ptr(scratch), scratch.numel(), s), "ccm_matmul_plan")
+    c = CMatrix(d, device=a.payload.device)
+    check(lib.ccm_matmul(ctypes.byref(a.desc), ctypes.byref(b.desc), ctypes.byref(c.desc),
+                         _ptr(scratch), scratch.numel(), s), "ccm_matmul")
+    return c
+
+
+def fill_uniform(t: torch.Tensor, lo: int, hi: int, seed: int, stream_id: int = 0,
+                 start: int = 0, stream=None) -> torch.Tensor:
+    """Fill a device int32/int64 tensor with seeded SplitMix64 draws in [lo, hi)."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("contiguous device tensor expected")
+    check(lib.ccm_fill_uniform(_ptr(t), _dtype_code(t), t.numel(), lo, hi, seed, stream_id,
+                               start, _stream(stream)), "ccm_fill_uniform")
+    return t
+
+
+def generate(rows: int, cols: int, lo: int, hi: int, seed: int, stream_id: int = 0,
+             device="cuda", stream=None) -> CMatrix:
+    """Compressed matrix of seeded draws, packed on the device without a dense copy."""
+    s = _stream(stream)
+    d = Desc()
+    check(lib.ccm_generate_plan(rows, cols, lo, hi, seed, stream_id, ctypes.byref(d), s),
+          "ccm_generate_plan")
+    m = CMatrix(d, device=device)
+    check(lib.ccm_generate(ctypes.byref(m.desc), lo, hi, seed, stream_id, s), "ccm_generate")
+    return m
+
+
+from .batch import Batch  # noqa: E402

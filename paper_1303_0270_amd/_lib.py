@@ -1,0 +1,98 @@
+"""ctypes binding of libccm.so (the C ABI declared in include/ccm.h).
+
+Argument marshalling only: every step of every operation runs in the HIP
+kernels of libccm.  Loading fails loudly when the library is missing; there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libccm.so")
+
+OK, E_INVAL, E_SHAPE, E_RANGE, E_OVERFLOW, E_NOMEM, E_DEVICE, E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+I32, I64 = 0, 1
+
+
+class CcmError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        msg = lib.ccm_status_str(status).decode() if lib is not None else str(status)
+        super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    """Mirror of ccm_desc."""
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("vmin", ctypes.c_int64), ("vmax", ctypes.c_int64),
+                ("bits", ctypes.c_int32), ("is_signed", ctypes.c_int32),
+                ("words", ctypes.c_uint64), ("payload", ctypes.c_void_p)]
+
+
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_i32 = ctypes.c_int32
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(Desc)
+
+SIGNATURES = {
+    "ccm_version": (ctypes.c_int, []),
+    "ccm_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "ccm_words": (_u64, [_i64, _i64, _i32]),
+    "ccm_packed_bytes": (_u64, [_i64, _i64, _i32]),
+    "ccm_payload_capacity": (_u64, [_i64, _i64, _i32]),
+    "ccm_width": (ctypes.c_int, [_i64, _i64, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "ccm_header_encode": (ctypes.c_int, [_dp, ctypes.POINTER(ctypes.c_uint8)]),
+    "ccm_header_decode": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint8), _dp]),
+    "ccm_range": (ctypes.c_int, [_vp, _i32, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                 _vp]),
+    "ccm_compress_plan": (ctypes.c_int, [_vp, _i32, _i64, _i64, _dp, _vp]),
+    "ccm_compress": (ctypes.c_int, [_vp, _i32, _dp, _vp]),
+    "ccm_decompress": (ctypes.c_int, [_dp, _vp, _vp]),
+    "ccm_get": (ctypes.c_int, [_dp, _i64, _i64, ctypes.POINTER(_i64), _vp]),
+    "ccm_gather": (ctypes.c_int, [_dp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "ccm_add_plan": (ctypes.c_int, [_dp, _dp, _dp, _vp]),
+    "ccm_add": (ctypes.c_int, [_dp, _dp, _dp, _vp]),
+    "ccm_scale_plan": (ctypes.c_int, [_dp, _i64, _dp]),
+    "ccm_scale": (ctypes.c_int, [_dp, _i64, _dp, _vp]),
+    "ccm_matvec": (ctypes.c_int, [_dp, _vp, _i32, _vp, _vp]),
+    "ccm_matmul_scratch_bytes": (_u64, [_dp, _dp]),
+    "ccm_matmul_plan": (ctypes.c_int, [_dp, _dp, _dp, _vp, _u64, _vp]),
+    "ccm_matmul": (ctypes.c_int, [_dp, _dp, _dp, _vp, _u64, _vp]),
+    "ccm_batch_create": (ctypes.c_int, [_dp, _i32, _i32, ctypes.c_char_p,
+                                        ctypes.POINTER(_vp)]),
+    "ccm_batch_set_io": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+    "ccm_batch_matvec": (ctypes.c_int, [_vp, _i32, _vp]),
+    "ccm_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_u64),
+                                      ctypes.POINTER(_i32)]),
+    "ccm_batch_destroy": (ctypes.c_int, [_vp]),
+    "ccm_fill_uniform": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i64, _u64, _u64, _u64, _vp]),
+    "ccm_generate_plan": (ctypes.c_int, [_i64, _i64, _i64, _i64, _u64, _u64, _dp, _vp]),
+    "ccm_generate": (ctypes.c_int, [_dp, _i64, _i64, _u64, _u64, _vp]),
+}
+
+
+def load(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(
+            f"libccm.so not found at {path}: build it first (python -m "
+            f"paper_1303_0270_amd.build, or __graft_entry__.build()).  There is no CPU "
+            f"fallback.")
+    handle = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(handle, name)
+        fn.restype = res
+        fn.argtypes = args
+    return handle
+
+
+lib = None
+lib = load()
+
+
+def check(status: int, what: str = "") -> None:
+    if status != OK:
+        raise CcmError(status, what)

@@ -1,0 +1,59 @@
+"""Batched matvec over many compressed matrices in one persistent launch
+(binding of ccm_batch_* in include/ccm.h)."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import I32, I64, Desc, check, lib
+
+
+class Batch:
+    """A fixed set of compressed matrices whose matvecs run in one launch."""
+
+    def __init__(self, mats, xdtype=torch.int32, tune_json: str | None = None):
+        self.mats = list(mats)
+        n = len(self.mats)
+        arr = (Desc * n)()
+        for t, m in enumerate(self.mats):
+            arr[t] = m.desc
+        self._descs = arr
+        self.xcode = I32 if xdtype == torch.int32 else I64
+        h = ctypes.c_void_p()
+        check(lib.ccm_batch_create(arr, n, self.xcode,
+                                   tune_json.encode() if tune_json else None, ctypes.byref(h)),
+              "ccm_batch_create")
+        self._h = h
+
+    def set_io(self, xs, ys, stream=None):
+        n = len(self.mats)
+        xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        yp = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
+        s = stream if stream is not None else torch.cuda.current_stream()
+        check(lib.ccm_batch_set_io(self._h, xp, yp, ctypes.c_void_p(s.cuda_stream)),
+              "ccm_batch_set_io")
+        self._io = (xs, ys)  # keep the tensors alive while bound
+
+    def run(self, use_graph: bool = True, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream()
+        check(lib.ccm_batch_matvec(self._h, 1 if use_graph else 0, ctypes.c_void_p(s.cuda_stream)),
+              "ccm_batch_matvec")
+
+    def info(self):
+        items, nbytes, mb = ctypes.c_int64(), ctypes.c_uint64(), ctypes.c_int32()
+        check(lib.ccm_batch_info(self._h, ctypes.byref(items), ctypes.byref(nbytes),
+                                 ctypes.byref(mb)), "ccm_batch_info")
+        return {"items": int(items.value), "packed_bytes": int(nbytes.value),
+                "max_bits": int(mb.value)}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            check(lib.ccm_batch_destroy(self._h), "ccm_batch_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

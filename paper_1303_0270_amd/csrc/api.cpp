@@ -1,0 +1,494 @@
+// C ABI of libccm: argument and descriptor validation, width arithmetic, the
+// blocking range ("plan") passes and kernel dispatch.  See include/ccm.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "ccm.h"
+#include "ccm_internal.hpp"
+
+namespace {
+
+bool log_enabled() {
+  static const bool on = std::getenv("CCM_LOG") != nullptr;
+  return on;
+}
+
+int dev_err(hipError_t e, const char *where) {
+  if (e == hipSuccess) return CCM_OK;
+  if (log_enabled()) std::fprintf(stderr, "ccm: %s: %s\n", where, hipGetErrorString(e));
+  if (e == hipErrorOutOfMemory) return CCM_E_NOMEM;
+  return CCM_E_DEVICE;
+}
+
+#define CCM_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return dev_err(e_, #call);    \
+  } while (0)
+
+// Blocking reductions share one device slot and one pinned host mirror per
+// device, used under a lock (each use ends with a stream synchronize).
+struct DeviceCtx {
+  ccm::RangeSlot *slot = nullptr;
+  ccm::RangeSlot *host = nullptr;
+  int64_t *one = nullptr;  // single-element get
+};
+std::mutex g_mu;
+std::vector<DeviceCtx> g_ctx;
+
+int device_ctx(DeviceCtx **out) {
+  int dev = 0;
+  CCM_HIP(hipGetDevice(&dev));
+  if ((size_t)dev >= g_ctx.size()) g_ctx.resize((size_t)dev + 1);
+  DeviceCtx &c = g_ctx[(size_t)dev];
+  if (!c.slot) {
+    void *p = nullptr;
+    CCM_HIP(hipMalloc(&p, 256));
+    c.slot = (ccm::RangeSlot *)p;
+    c.one = (int64_t *)((char *)p + 64);
+    void *h = nullptr;
+    CCM_HIP(hipHostMalloc(&h, sizeof(ccm::RangeSlot) + 64, hipHostMallocDefault));
+    c.host = (ccm::RangeSlot *)h;
+  }
+  *out = &c;
+  return CCM_OK;
+}
+
+int read_slot(DeviceCtx *c, hipStream_t s, ccm::RangeSlot *res) {
+  CCM_HIP(hipMemcpyAsync(c->host, c->slot, sizeof(ccm::RangeSlot), hipMemcpyDeviceToHost, s));
+  CCM_HIP(hipStreamSynchronize(s));
+  *res = *c->host;
+  return CCM_OK;
+}
+
+int width_rule(int64_t vmin, int64_t vmax, int32_t *bits, int32_t *sgn) {
+  if (vmin > vmax) return CCM_E_INVAL;
+  auto bitlen = [](uint64_t u) {
+    int L = 0;
+    while (L < 64 && (u >> L) != 0) ++L;
+    return L;
+  };
+  if (vmin >= 0) {
+    *sgn = 0;
+    *bits = vmax <= 1 ? 1 : bitlen((uint64_t)vmax);
+  } else {
+    const int lo = bitlen(~(uint64_t)vmin);  // -(vmin+1)
+    const int hi = vmax > 0 ? bitlen((uint64_t)vmax) : 0;
+    *sgn = 1;
+    *bits = 1 + (lo > hi ? lo : hi);
+  }
+  return CCM_OK;
+}
+
+bool shape_ok(int64_t rows, int64_t cols) {
+  if (rows < 1 || cols < 1) return false;
+  // keep rows*cols*64 inside uint64
+  const unsigned __int128 n = (unsigned __int128)rows * (unsigned __int128)cols;
+  return n <= ((unsigned __int128)1 << 57);
+}
+
+uint64_t nelem(const ccm_desc *d) { return (uint64_t)d->rows * (uint64_t)d->cols; }
+
+// A descriptor is valid when its width is the width rule of its range and the
+// word count matches; with need_payload, payload must be set.
+int check_desc(const ccm_desc *d, bool need_payload) {
+  if (!d) return CCM_E_INVAL;
+  if (!shape_ok(d->rows, d->cols)) return CCM_E_INVAL;
+  int32_t b = 0, s = 0;
+  if (width_rule(d->vmin, d->vmax, &b, &s) != CCM_OK) return CCM_E_INVAL;
+  if (b != d->bits || s != d->is_signed) return CCM_E_INVAL;
+  if (d->words != ccm_words(d->rows, d->cols, d->bits)) return CCM_E_INVAL;
+  if (need_payload && !d->payload) return CCM_E_INVAL;
+  return CCM_OK;
+}
+
+int fill_desc(int64_t rows, int64_t cols, int64_t vmin, int64_t vmax, ccm_desc *out) {
+  int32_t b = 0, s = 0;
+  int rc = width_rule(vmin, vmax, &b, &s);
+  if (rc != CCM_OK) return rc;
+  out->rows = rows;
+  out->cols = cols;
+  out->vmin = vmin;
+  out->vmax = vmax;
+  out->bits = b;
+  out->is_signed = s;
+  out->words = ccm_words(rows, cols, b);
+  out->payload = nullptr;
+  return CCM_OK;
+}
+
+ccm::PackedOperand operand(const ccm_desc *d) {
+  return ccm::PackedOperand{(const uint32_t *)d->payload, d->bits, d->is_signed};
+}
+
+uint64_t max_abs(int64_t lo, int64_t hi) {
+  const uint64_t a = lo < 0 ? 0 - (uint64_t)lo : (uint64_t)lo;
+  const uint64_t b = hi < 0 ? 0 - (uint64_t)hi : (uint64_t)hi;
+  return a > b ? a : b;
+}
+
+// The matmul overflow rule: K * max|A| * max|B| >= 2^63 is rejected.
+bool matmul_bound(const ccm_desc *a, const ccm_desc *b, unsigned __int128 *bound) {
+  const unsigned __int128 lim = (unsigned __int128)1 << 63;
+  const unsigned __int128 p =
+      (unsigned __int128)max_abs(a->vmin, a->vmax) * (unsigned __int128)max_abs(b->vmin, b->vmax);
+  if (p >= lim) return false;
+  *bound = p * (unsigned __int128)(uint64_t)a->cols;
+  return *bound < lim;
+}
+
+bool fits_i8(const ccm_desc *d) { return d->vmin >= -128 && d->vmax <= 127; }
+
+}  // namespace
+
+extern "C" {
+
+int ccm_version(void) { return 10000; }
+
+const char *ccm_status_str(int status) {
+  switch (status) {
+    case CCM_OK: return "ok";
+    case CCM_E_INVAL: return "invalid argument";
+    case CCM_E_SHAPE: return "shape mismatch";
+    case CCM_E_RANGE: return "index out of range";
+    case CCM_E_OVERFLOW: return "result overflows int64";
+    case CCM_E_NOMEM: return "out of memory or buffer too small";
+    case CCM_E_DEVICE: return "HIP runtime error";
+    case CCM_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+uint64_t ccm_words(int64_t rows, int64_t cols, int32_t bits) {
+  if (!shape_ok(rows, cols) || bits < 1 || bits > 64) return 0;
+  return ((uint64_t)rows * (uint64_t)cols * (uint64_t)bits) / 64u + 1u;
+}
+
+uint64_t ccm_packed_bytes(int64_t rows, int64_t cols, int32_t bits) {
+  const uint64_t w = ccm_words(rows, cols, bits);
+  return w ? 64u + 8u * w : 0u;
+}
+
+uint64_t ccm_payload_capacity(int64_t rows, int64_t cols, int32_t bits) {
+  if (!ccm_words(rows, cols, bits)) return 0;
+  return 4u * ccm::cap_words32((uint64_t)rows * (uint64_t)cols, bits);
+}
+
+int ccm_width(int64_t vmin, int64_t vmax, int32_t *bits, int32_t *is_signed) {
+  if (!bits || !is_signed) return CCM_E_INVAL;
+  return width_rule(vmin, vmax, bits, is_signed);
+}
+
+int ccm_header_encode(const ccm_desc *d, uint8_t out[64]) {
+  if (!out) return CCM_E_INVAL;
+  int rc = check_desc(d, false);
+  if (rc != CCM_OK) return rc;
+  std::memset(out, 0, 64);
+  std::memcpy(out, "CCM1", 4);
+  out[4] = 1;
+  out[5] = 0;
+  out[6] = (uint8_t)d->bits;
+  out[7] = (uint8_t)(d->is_signed ? 1 : 0);
+  auto put = [&](int at, uint64_t v) {
+    for (int k = 0; k < 8; ++k) out[at + k] = (uint8_t)(v >> (8 * k));
+  };
+  put(8, (uint64_t)d->rows);
+  put(16, (uint64_t)d->cols);
+  put(24, (uint64_t)d->vmin);
+  put(32, (uint64_t)d->vmax);
+  put(40, d->words);
+  return CCM_OK;
+}
+
+int ccm_header_decode(const uint8_t in[64], ccm_desc *d) {
+  if (!in || !d) return CCM_E_INVAL;
+  if (std::memcmp(in, "CCM1", 4) != 0 || in[4] != 1 || in[5] != 0) return CCM_E_INVAL;
+  if (in[7] & ~1u) return CCM_E_INVAL;
+  for (int k = 48; k < 64; ++k)
+    if (in[k]) return CCM_E_INVAL;
+  auto get = [&](int at) {
+    uint64_t v = 0;
+    for (int k = 0; k < 8; ++k) v |= (uint64_t)in[at + k] << (8 * k);
+    return v;
+  };
+  ccm_desc t;
+  t.rows = (int64_t)get(8);
+  t.cols = (int64_t)get(16);
+  t.vmin = (int64_t)get(24);
+  t.vmax = (int64_t)get(32);
+  t.bits = in[6];
+  t.is_signed = in[7] & 1;
+  t.words = get(40);
+  t.payload = nullptr;
+  int rc = check_desc(&t, false);
+  if (rc != CCM_OK) return rc;
+  *d = t;
+  return CCM_OK;
+}
+
+int ccm_range(const void *dense, int32_t dtype, int64_t n, int64_t *vmin, int64_t *vmax,
+              void *stream) {
+  if (!dense || !vmin || !vmax || n < 1 || (dtype != CCM_I32 && dtype != CCM_I64))
+    return CCM_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx *c = nullptr;
+  int rc = device_ctx(&c);
+  if (rc != CCM_OK) return rc;
+  CCM_HIP(ccm::launch_range_init(c->slot, s));
+  CCM_HIP(ccm::launch_range_dense(dense, dtype, (uint64_t)n, c->slot, s));
+  ccm::RangeSlot r;
+  rc = read_slot(c, s, &r);
+  if (rc != CCM_OK) return rc;
+  *vmin = r.vmin;
+  *vmax = r.vmax;
+  return CCM_OK;
+}
+
+int ccm_compress_plan(const void *dense, int32_t dtype, int64_t rows, int64_t cols,
+                      ccm_desc *out, void *stream) {
+  if (!out || !shape_ok(rows, cols)) return CCM_E_INVAL;
+  int64_t lo = 0, hi = 0;
+  int rc = ccm_range(dense, dtype, rows * cols, &lo, &hi, stream);
+  if (rc != CCM_OK) return rc;
+  return fill_desc(rows, cols, lo, hi, out);
+}
+
+int ccm_compress(const void *dense, int32_t dtype, const ccm_desc *out, void *stream) {
+  if (!dense || (dtype != CCM_I32 && dtype != CCM_I64)) return CCM_E_INVAL;
+  int rc = check_desc(out, true);
+  if (rc != CCM_OK) return rc;
+  const uint64_t n = nelem(out);
+  CCM_HIP(ccm::launch_compress(dense, dtype, n, out->bits, (uint32_t *)out->payload,
+                               ccm::cap_words32(n, out->bits), (hipStream_t)stream));
+  return CCM_OK;
+}
+
+int ccm_decompress(const ccm_desc *a, int64_t *dense_out, void *stream) {
+  int rc = check_desc(a, true);
+  if (rc != CCM_OK) return rc;
+  if (!dense_out) return CCM_E_INVAL;
+  CCM_HIP(ccm::launch_decompress((const uint32_t *)a->payload, nelem(a), a->bits, a->is_signed,
+                                 dense_out, (hipStream_t)stream));
+  return CCM_OK;
+}
+
+int ccm_get(const ccm_desc *a, int64_t i, int64_t j, int64_t *value, void *stream) {
+  int rc = check_desc(a, true);
+  if (rc != CCM_OK) return rc;
+  if (!value) return CCM_E_INVAL;
+  if (i < 0 || i >= a->rows || j < 0 || j >= a->cols) return CCM_E_RANGE;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx *c = nullptr;
+  rc = device_ctx(&c);
+  if (rc != CCM_OK) return rc;
+  CCM_HIP(ccm::launch_get_one((const uint32_t *)a->payload, (uint64_t)(i * a->cols + j), a->bits,
+                              a->is_signed, c->one, s));
+  int64_t *h = (int64_t *)((char *)c->host + sizeof(ccm::RangeSlot));
+  CCM_HIP(hipMemcpyAsync(h, c->one, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  CCM_HIP(hipStreamSynchronize(s));
+  *value = *h;
+  return CCM_OK;
+}
+
+int ccm_gather(const ccm_desc *a, const int64_t *ii, const int64_t *jj, int64_t n,
+               int64_t *out, int32_t *bad, void *stream) {
+  int rc = check_desc(a, true);
+  if (rc != CCM_OK) return rc;
+  if (n < 0 || (n > 0 && (!ii || !jj || !out))) return CCM_E_INVAL;
+  CCM_HIP(ccm::launch_gather((const uint32_t *)a->payload, a->rows, a->cols, a->bits,
+                             a->is_signed, ii, jj, n, out, bad, (hipStream_t)stream));
+  return CCM_OK;
+}
+
+int ccm_add_plan(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *stream) {
+  int rc = check_desc(a, true);
+  if (rc == CCM_OK) rc = check_desc(b, true);
+  if (rc != CCM_OK) return rc;
+  if (!out) return CCM_E_INVAL;
+  if (a->rows != b->rows || a->cols != b->cols) return CCM_E_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx *c = nullptr;
+  rc = device_ctx(&c);
+  if (rc != CCM_OK) return rc;
+  CCM_HIP(ccm::launch_range_init(c->slot, s));
+  CCM_HIP(ccm::launch_ewise_range(ccm::EW_ADD, operand(a), operand(b), 0, nelem(a), c->slot, s));
+  ccm::RangeSlot r;
+  rc = read_slot(c, s, &r);
+  if (rc != CCM_OK) return rc;
+  if (r.flag) return CCM_E_OVERFLOW;
+  return fill_desc(a->rows, a->cols, r.vmin, r.vmax, out);
+}
+
+static int check_result(const ccm_desc *out, int64_t rows, int64_t cols) {
+  int rc = check_desc(out, true);
+  if (rc != CCM_OK) return rc;
+  if (out->rows != rows || out->cols != cols) return CCM_E_SHAPE;
+  return CCM_OK;
+}
+
+int ccm_add(const ccm_desc *a, const ccm_desc *b, const ccm_desc *out, void *stream) {
+  int rc = check_desc(a, true);
+  if (rc == CCM_OK) rc = check_desc(b, true);
+  if (rc != CCM_OK) return rc;
+  if (a->rows != b->rows || a->cols != b->cols) return CCM_E_SHAPE;
+  rc = check_result(out, a->rows, a->cols);
+  if (rc != CCM_OK) return rc;
+  const uint64_t n = nelem(a);
+  CCM_HIP(ccm::launch_ewise_pack(ccm::EW_ADD, operand(a), operand(b), 0, n, out->bits,
+                                 (uint32_t *)out->payload, ccm::cap_words32(n, out->bits),
+                                 (hipStream_t)stream));
+  return CCM_OK;
+}
+
+int ccm_scale_plan(const ccm_desc *a, int64_t s, ccm_desc *out) {
+  int rc = check_desc(a, false);
+  if (rc != CCM_OK) return rc;
+  if (!out) return CCM_E_INVAL;
+  const __int128 p = (__int128)a->vmin * s, q = (__int128)a->vmax * s;
+  const __int128 lo = p < q ? p : q, hi = p < q ? q : p;
+  if (lo < (__int128)INT64_MIN || hi > (__int128)INT64_MAX) return CCM_E_OVERFLOW;
+  return fill_desc(a->rows, a->cols, (int64_t)lo, (int64_t)hi, out);
+}
+
+int ccm_scale(const ccm_desc *a, int64_t s, const ccm_desc *out, void *stream) {
+  int rc = check_desc(a, true);
+  if (rc != CCM_OK) return rc;
+  ccm_desc expect;
+  rc = ccm_scale_plan(a, s, &expect);
+  if (rc != CCM_OK) return rc;
+  rc = check_result(out, a->rows, a->cols);
+  if (rc != CCM_OK) return rc;
+  if (out->bits != expect.bits || out->vmin != expect.vmin || out->vmax != expect.vmax)
+    return CCM_E_INVAL;
+  const uint64_t n = nelem(a);
+  ccm::PackedOperand none{nullptr, 0, 0};
+  CCM_HIP(ccm::launch_ewise_pack(ccm::EW_SCALE, operand(a), none, s, n, out->bits,
+                                 (uint32_t *)out->payload, ccm::cap_words32(n, out->bits),
+                                 (hipStream_t)stream));
+  return CCM_OK;
+}
+
+int ccm_matvec(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, void *stream) {
+  int rc = check_desc(a, true);
+  if (rc != CCM_OK) return rc;
+  if (!x || !y || (xdtype != CCM_I32 && xdtype != CCM_I64)) return CCM_E_INVAL;
+  CCM_HIP(ccm::launch_matvec((const uint32_t *)a->payload, a->rows, a->cols, a->bits,
+                             a->is_signed, x, xdtype, y, (hipStream_t)stream));
+  return CCM_OK;
+}
+
+uint64_t ccm_matmul_scratch_bytes(const ccm_desc *a, const ccm_desc *b) {
+  if (check_desc(a, false) != CCM_OK || check_desc(b, false) != CCM_OK) return 0;
+  if (a->cols != b->rows) return 0;
+  unsigned __int128 bound = 0;
+  if (!matmul_bound(a, b, &bound)) return 0;
+  const uint64_t per = bound < ((unsigned __int128)1 << 31) ? 4u : 8u;
+  return per * (uint64_t)a->rows * (uint64_t)b->cols;
+}
+
+static int matmul_common(const ccm_desc *a, const ccm_desc *b, uint64_t scratch_bytes,
+                         const void *scratch, int *out32) {
+  int rc = check_desc(a, true);
+  if (rc == CCM_OK) rc = check_desc(b, true);
+  if (rc != CCM_OK) return rc;
+  if (a->cols != b->rows) return CCM_E_SHAPE;
+  if (!shape_ok(a->rows, b->cols)) return CCM_E_INVAL;
+  unsigned __int128 bound = 0;
+  if (!matmul_bound(a, b, &bound)) return CCM_E_OVERFLOW;
+  if (!scratch) return CCM_E_INVAL;
+  *out32 = bound < ((unsigned __int128)1 << 31) ? 1 : 0;
+  const uint64_t need = (*out32 ? 4u : 8u) * (uint64_t)a->rows * (uint64_t)b->cols;
+  if (scratch_bytes < need) return CCM_E_NOMEM;
+  return CCM_OK;
+}
+
+int ccm_matmul_plan(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *scratch,
+                    uint64_t scratch_bytes, void *stream) {
+  int out32 = 0;
+  int rc = matmul_common(a, b, scratch_bytes, scratch, &out32);
+  if (rc != CCM_OK) return rc;
+  if (!out) return CCM_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx *c = nullptr;
+  rc = device_ctx(&c);
+  if (rc != CCM_OK) return rc;
+  CCM_HIP(ccm::launch_range_init(c->slot, s));
+  const int use_i8 = fits_i8(a) && fits_i8(b);
+  CCM_HIP(ccm::launch_matmul((const uint32_t *)a->payload, a->bits, a->is_signed,
+                             (const uint32_t *)b->payload, b->bits, b->is_signed, a->rows,
+                             a->cols, b->cols, use_i8, out32, scratch, c->slot, s));
+  ccm::RangeSlot r;
+  rc = read_slot(c, s, &r);
+  if (rc != CCM_OK) return rc;
+  return fill_desc(a->rows, b->cols, r.vmin, r.vmax, out);
+}
+
+int ccm_matmul(const ccm_desc *a, const ccm_desc *b, const ccm_desc *out, const void *scratch,
+               uint64_t scratch_bytes, void *stream) {
+  int out32 = 0;
+  int rc = matmul_common(a, b, scratch_bytes, scratch, &out32);
+  if (rc != CCM_OK) return rc;
+  rc = check_result(out, a->rows, b->cols);
+  if (rc != CCM_OK) return rc;
+  const uint64_t n = nelem(out);
+  CCM_HIP(ccm::launch_compress(scratch, out32 ? CCM_I32 : CCM_I64, n, out->bits,
+                               (uint32_t *)out->payload, ccm::cap_words32(n, out->bits),
+                               (hipStream_t)stream));
+  return CCM_OK;
+}
+
+int ccm_fill_uniform(void *dense, int32_t dtype, int64_t n, int64_t lo, int64_t hi,
+                     uint64_t seed, uint64_t stream_id, uint64_t start, void *stream) {
+  if (!dense || n < 0 || (dtype != CCM_I32 && dtype != CCM_I64)) return CCM_E_INVAL;
+  if (hi <= lo) return CCM_E_INVAL;
+  const uint64_t span = (uint64_t)hi - (uint64_t)lo;
+  if (span > (1ull << 32)) return CCM_E_INVAL;
+  if (dtype == CCM_I32 && (lo < INT32_MIN || hi - 1 > INT32_MAX)) return CCM_E_INVAL;
+  CCM_HIP(ccm::launch_fill_uniform(dense, dtype, (uint64_t)n, lo, span, seed, stream_id, start,
+                                   (hipStream_t)stream));
+  return CCM_OK;
+}
+
+int ccm_generate_plan(int64_t rows, int64_t cols, int64_t lo, int64_t hi, uint64_t seed,
+                      uint64_t stream_id, ccm_desc *out, void *stream) {
+  if (!out || !shape_ok(rows, cols) || hi <= lo) return CCM_E_INVAL;
+  const uint64_t span = (uint64_t)hi - (uint64_t)lo;
+  if (span > (1ull << 32)) return CCM_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx *c = nullptr;
+  int rc = device_ctx(&c);
+  if (rc != CCM_OK) return rc;
+  CCM_HIP(ccm::launch_range_init(c->slot, s));
+  CCM_HIP(ccm::launch_gen_range((uint64_t)rows * (uint64_t)cols, lo, span, seed, stream_id,
+                                c->slot, s));
+  ccm::RangeSlot r;
+  rc = read_slot(c, s, &r);
+  if (rc != CCM_OK) return rc;
+  return fill_desc(rows, cols, r.vmin, r.vmax, out);
+}
+
+int ccm_generate(const ccm_desc *out, int64_t lo, int64_t hi, uint64_t seed,
+                 uint64_t stream_id, void *stream) {
+  int rc = check_desc(out, true);
+  if (rc != CCM_OK) return rc;
+  if (hi <= lo) return CCM_E_INVAL;
+  const uint64_t span = (uint64_t)hi - (uint64_t)lo;
+  if (span > (1ull << 32)) return CCM_E_INVAL;
+  const uint64_t n = nelem(out);
+  CCM_HIP(ccm::launch_gen_pack(n, lo, span, seed, stream_id, out->bits,
+                               (uint32_t *)out->payload, ccm::cap_words32(n, out->bits),
+                               (hipStream_t)stream));
+  return CCM_OK;
+}
+
+}  // extern "C"

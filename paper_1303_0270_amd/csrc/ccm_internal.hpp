@@ -1,0 +1,259 @@
+// Internal declarations of libccm: device helpers shared by the kernels and
+// the launchers the C ABI layer (api.cpp) calls.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ccm.h"
+
+namespace ccm {
+
+// ---------------------------------------------------------------------------
+// Layout constants
+// ---------------------------------------------------------------------------
+
+// A "group" is 32 consecutive elements of the row-major stream.  Group g
+// occupies stream bits [32*g*b, 32*(g+1)*b), i.e. exactly 32-bit words
+// [g*b, (g+1)*b): every group starts on a word boundary whatever b is, so a
+// lane that owns a group decodes it with fixed (compile-time) bit offsets.
+constexpr int kGroup = 32;
+
+// Payload capacity in 32-bit words: every group that holds an element (so a
+// writer may write whole groups), plus b + 4 guard words (a reader may fetch
+// one group-length past a field that starts in the last group, and three
+// words around any field), rounded up to 256 bytes.
+__host__ __device__ inline uint64_t cap_words32(uint64_t n, int bits) {
+  uint64_t full = (n * (uint64_t)bits + 31u) / 32u;
+  uint64_t need = full + (uint64_t)bits + 4u;
+  return (need + 63u) / 64u * 64u;
+}
+
+__host__ __device__ inline uint64_t mask64(int bits) {
+  return bits >= 64 ? ~0ull : ((1ull << bits) - 1ull);
+}
+
+__host__ __device__ inline uint32_t mask32(int bits) {
+  return bits >= 32 ? ~0u : ((1u << bits) - 1u);
+}
+
+// Two's-complement sign extension of the low `bits` bits.
+__host__ __device__ inline int64_t sext64(uint64_t u, int bits) {
+  const int s = 64 - bits;
+  return (int64_t)(u << s) >> s;
+}
+
+// ---------------------------------------------------------------------------
+// Runtime-width bit reader / writer for one lane's group.  All lanes of a wave
+// process groups with the same bit phase, so `avail` / `used` and every branch
+// on them are wave-uniform: the refill and flush points cost no divergence.
+// ---------------------------------------------------------------------------
+
+struct BitReader {
+  const uint32_t *p;
+  uint64_t buf;
+  int avail;
+
+  __device__ explicit BitReader(const uint32_t *ptr) : p(ptr), buf(0), avail(0) {}
+
+  // next nb bits (1 <= nb <= 32)
+  __device__ __forceinline__ uint32_t take(int nb) {
+    if (avail < nb) {
+      buf |= (uint64_t)(*p) << avail;
+      ++p;
+      avail += 32;
+    }
+    const uint32_t v = (uint32_t)buf & mask32(nb);
+    buf >>= nb;
+    avail -= nb;
+    return v;
+  }
+
+  // next field of `bits` bits (1..64), zero-extended
+  __device__ __forceinline__ uint64_t field(int bits) {
+    if (bits <= 32) return take(bits);
+    const uint64_t lo = take(32);
+    return lo | ((uint64_t)take(bits - 32) << 32);
+  }
+};
+
+struct BitWriter {
+  uint32_t *p;
+  uint64_t idx, cap;  // next word index, capacity in words (stores past it are dropped)
+  uint64_t buf;
+  int used;
+
+  __device__ BitWriter(uint32_t *base, uint64_t first_word, uint64_t cap_words)
+      : p(base), idx(first_word), cap(cap_words), buf(0), used(0) {}
+
+  __device__ __forceinline__ void put(uint32_t v, int nb) {
+    buf |= (uint64_t)(v & mask32(nb)) << used;
+    used += nb;
+    if (used >= 32) {
+      if (idx < cap) p[idx] = (uint32_t)buf;
+      ++idx;
+      buf >>= 32;
+      used -= 32;
+    }
+  }
+
+  __device__ __forceinline__ void field(uint64_t u, int bits) {
+    if (bits <= 32) {
+      put((uint32_t)u, bits);
+    } else {
+      put((uint32_t)u, 32);
+      put((uint32_t)(u >> 32), bits - 32);
+    }
+  }
+};
+
+// Field e of a stream of `bits`-bit fields (random access; reads words
+// e*bits/32 .. +2, all inside the payload capacity).
+__device__ __forceinline__ uint64_t field_at(const uint32_t *w, uint64_t e, int bits) {
+  const uint64_t p = e * (uint64_t)bits;
+  const uint64_t k = p >> 5;
+  const int off = (int)(p & 31u);
+  uint64_t v = ((uint64_t)w[k] | ((uint64_t)w[k + 1] << 32)) >> off;
+  if (off + bits > 64) v |= (uint64_t)w[k + 2] << (64 - off);
+  return v & mask64(bits);
+}
+
+__device__ __forceinline__ int64_t value_at(const uint32_t *w, uint64_t e, int bits, int sgn) {
+  const uint64_t u = field_at(w, e, bits);
+  return sgn ? sext64(u, bits) : (int64_t)u;
+}
+
+// ---------------------------------------------------------------------------
+// Wave and block reductions (64-lane wavefronts)
+// ---------------------------------------------------------------------------
+
+// Sum over the wave modulo 2^64.
+__device__ __forceinline__ int64_t wave_sum(int64_t v) {
+  uint64_t u = (uint64_t)v;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) u += (uint64_t)__shfl_xor((int64_t)u, m, 64);
+  return (int64_t)u;
+}
+
+__device__ __forceinline__ int64_t wave_min(int64_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int64_t o = __shfl_xor(v, m, 64);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int64_t wave_max(int64_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int64_t o = __shfl_xor(v, m, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Reduction target of the range passes: exact min, max and an error flag.
+struct RangeSlot {
+  int64_t vmin;
+  int64_t vmax;
+  int32_t flag;
+  int32_t pad;
+};
+
+// Block-wide (min, max, flag) folded into *slot with one atomic each per
+// block.  Every thread of the block must call it.
+__device__ inline void block_range_commit(int64_t lo, int64_t hi, int flag, RangeSlot *slot) {
+  __shared__ int64_t s_lo[16], s_hi[16];
+  __shared__ int s_flag[16];
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  const int wf = __any(flag) ? 1 : 0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    s_lo[wave] = lo;
+    s_hi[wave] = hi;
+    s_flag[wave] = wf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 1; w < nw; ++w) {
+      lo = s_lo[w] < lo ? s_lo[w] : lo;
+      hi = s_hi[w] > hi ? s_hi[w] : hi;
+    }
+    int f = 0;
+    for (int w = 0; w < nw; ++w) f |= s_flag[w];
+    atomicMin((long long *)&slot->vmin, (long long)lo);
+    atomicMax((long long *)&slot->vmax, (long long)hi);
+    if (f) atomicOr(&slot->flag, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (each returns the launch's hipError_t)
+// ---------------------------------------------------------------------------
+
+hipError_t launch_range_init(RangeSlot *slot, hipStream_t s);
+hipError_t launch_range_dense(const void *dense, int dtype, uint64_t n, RangeSlot *slot,
+                              hipStream_t s);
+hipError_t launch_compress(const void *dense, int dtype, uint64_t n, int bits, uint32_t *out,
+                           uint64_t cap32, hipStream_t s);
+hipError_t launch_decompress(const uint32_t *w, uint64_t n, int bits, int sgn, int64_t *out,
+                             hipStream_t s);
+hipError_t launch_get_one(const uint32_t *w, uint64_t e, int bits, int sgn, int64_t *out,
+                          hipStream_t s);
+hipError_t launch_gather(const uint32_t *w, int64_t rows, int64_t cols, int bits, int sgn,
+                         const int64_t *ii, const int64_t *jj, int64_t n, int64_t *out,
+                         int32_t *bad, hipStream_t s);
+
+// Elementwise ops on two packed operands (b may be null for unary ops).
+enum EwiseOp { EW_ADD = 0, EW_SCALE = 1 };
+struct PackedOperand {
+  const uint32_t *w;
+  int bits;
+  int sgn;
+};
+hipError_t launch_ewise_range(int op, PackedOperand a, PackedOperand b, int64_t scalar,
+                              uint64_t n, RangeSlot *slot, hipStream_t s);
+hipError_t launch_ewise_pack(int op, PackedOperand a, PackedOperand b, int64_t scalar,
+                             uint64_t n, int out_bits, uint32_t *out, uint64_t cap32,
+                             hipStream_t s);
+
+hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t s);
+
+// matvec: y = A x.  x dtype CCM_I32 / CCM_I64.
+hipError_t launch_matvec(const uint32_t *w, int64_t rows, int64_t cols, int bits, int sgn,
+                         const void *x, int xdtype, int64_t *y, hipStream_t s);
+
+// matmul into dense scratch (int32 if out32 else int64) with its range.
+hipError_t launch_matmul(const uint32_t *aw, int abits, int asgn, const uint32_t *bw,
+                         int bbits, int bsgn, int64_t M, int64_t K, int64_t N, int use_i8,
+                         int out32, void *scratch, RangeSlot *slot, hipStream_t s);
+
+// synthetic data
+hipError_t launch_fill_uniform(void *dense, int dtype, uint64_t n, int64_t lo, uint64_t span,
+                               uint64_t seed, uint64_t stream_id, uint64_t start,
+                               hipStream_t s);
+hipError_t launch_gen_range(uint64_t n, int64_t lo, uint64_t span, uint64_t seed,
+                            uint64_t stream_id, RangeSlot *slot, hipStream_t s);
+hipError_t launch_gen_pack(uint64_t n, int64_t lo, uint64_t span, uint64_t seed,
+                           uint64_t stream_id, int bits, uint32_t *out, uint64_t cap32,
+                           hipStream_t s);
+
+// SplitMix64 draw `ctr` of the sequence starting at `seed`, mapped to
+// [lo, lo + span) with span <= 2^32.
+__host__ __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t ctr) {
+  uint64_t z = seed + (ctr + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__host__ __device__ inline int64_t uniform_at(uint64_t seed, uint64_t stream_id, uint64_t idx,
+                                              int64_t lo, uint64_t span) {
+  const uint64_t h = splitmix64_at(seed, (stream_id << 40) + idx);
+  return lo + (int64_t)(((h >> 32) * span) >> 32);
+}
+
+}  // namespace ccm

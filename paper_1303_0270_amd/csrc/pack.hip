@@ -1,0 +1,341 @@
+// Range reduction, SM packing / unpacking, element access and elementwise
+// operations on packed matrices (gfx950).
+//
+// Packing follows Method 1 (Eq. 3 and the straddle step): element e's b-bit
+// field goes to stream bits [e*b, e*b+b), least significant bit first.  Every
+// packing kernel works group-per-lane: a lane turns 32 consecutive elements
+// into exactly b 32-bit words, so no two lanes ever write the same word and no
+// atomics are needed; lanes of a wave share one bit phase, which keeps the
+// runtime-width reader/writer branch-uniform.  Dense operands are staged
+// through LDS so that HBM reads and writes stay coalesced.
+#include "ccm_internal.hpp"
+
+namespace ccm {
+namespace {
+
+constexpr int kTileThreads = 128;           // lanes per block in the tile kernels
+constexpr int kTileElems = kTileThreads * kGroup;
+constexpr int kPad = kGroup + 1;            // LDS row pitch (elements) of a lane's group
+
+__global__ void k_range_init(RangeSlot *slot) {
+  slot->vmin = INT64_MAX;
+  slot->vmax = INT64_MIN;
+  slot->flag = 0;
+  slot->pad = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_range_dense(const T *__restrict__ d, uint64_t n,
+                                                     RangeSlot *slot) {
+  int64_t lo = INT64_MAX, hi = INT64_MIN;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const int64_t v = (int64_t)d[e];
+    lo = v < lo ? v : lo;
+    hi = v > hi ? v : hi;
+  }
+  block_range_commit(lo, hi, 0, slot);
+}
+
+// dense (n values) -> packed words [0, cap32): lane g writes words [g*b, g*b+b).
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void k_compress(const T *__restrict__ d, uint64_t n,
+                                                           int bits, uint32_t *__restrict__ out,
+                                                           uint64_t cap32, uint64_t ngroups) {
+  __shared__ T tile[kTileThreads * kPad];
+  const uint64_t g0 = (uint64_t)blockIdx.x * kTileThreads;
+  const uint64_t e0 = g0 * kGroup;
+  if (e0 < n) {
+    for (int q = threadIdx.x; q < kTileElems; q += kTileThreads) {
+      const uint64_t e = e0 + q;
+      tile[q + (q >> 5)] = e < n ? d[e] : T(0);
+    }
+  } else {
+    for (int q = threadIdx.x; q < kTileElems; q += kTileThreads) tile[q + (q >> 5)] = T(0);
+  }
+  __syncthreads();
+  const uint64_t g = g0 + threadIdx.x;
+  if (g >= ngroups) return;
+  BitWriter w(out, g * (uint64_t)bits, cap32);
+  const T *src = tile + threadIdx.x * kPad;
+#pragma unroll 4
+  for (int i = 0; i < kGroup; ++i) w.field((uint64_t)(int64_t)src[i], bits);
+}
+
+// packed -> dense int64 (n values)
+__global__ __launch_bounds__(kTileThreads) void k_decompress(const uint32_t *__restrict__ wds,
+                                                             uint64_t n, int bits, int sgn,
+                                                             int64_t *__restrict__ out) {
+  __shared__ int64_t tile[kTileThreads * kPad];
+  const uint64_t g0 = (uint64_t)blockIdx.x * kTileThreads;
+  const uint64_t g = g0 + threadIdx.x;
+  const uint64_t ngroups = (n + kGroup - 1) / kGroup;
+  if (g < ngroups) {
+    BitReader r(wds + g * (uint64_t)bits);
+    int64_t *dst = tile + threadIdx.x * kPad;
+#pragma unroll 4
+    for (int i = 0; i < kGroup; ++i) {
+      const uint64_t u = r.field(bits);
+      dst[i] = sgn ? sext64(u, bits) : (int64_t)u;
+    }
+  }
+  __syncthreads();
+  const uint64_t e0 = g0 * kGroup;
+  for (int q = threadIdx.x; q < kTileElems; q += kTileThreads) {
+    const uint64_t e = e0 + q;
+    if (e < n) out[e] = tile[q + (q >> 5)];
+  }
+}
+
+__global__ void k_gather(const uint32_t *__restrict__ wds, int64_t rows, int64_t cols, int bits,
+                         int sgn, const int64_t *__restrict__ ii, const int64_t *__restrict__ jj,
+                         int64_t n, int64_t *__restrict__ out, int32_t *bad) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int64_t i = ii[t], j = jj[t];
+  if (i < 0 || i >= rows || j < 0 || j >= cols) {
+    out[t] = 0;
+    if (bad) atomicOr(bad, 1);
+    return;
+  }
+  out[t] = value_at(wds, (uint64_t)(i * cols + j), bits, sgn);
+}
+
+__global__ void k_get_one(const uint32_t *__restrict__ wds, uint64_t e, int bits, int sgn,
+                          int64_t *out) {
+  *out = value_at(wds, e, bits, sgn);
+}
+
+// One elementwise result value; returns overflow in *ovf.
+__device__ __forceinline__ int64_t ewise_value(int op, int64_t a, int64_t b, int64_t scalar,
+                                               int *ovf) {
+  if (op == EW_ADD) {
+    const int64_t s = (int64_t)((uint64_t)a + (uint64_t)b);
+    *ovf |= ((a ^ s) & (b ^ s)) < 0;
+    return s;
+  }
+  int64_t p;
+  *ovf |= __builtin_mul_overflow(a, scalar, &p);
+  return p;
+}
+
+// Range pass of an elementwise result: one group of 32 elements per lane.
+__global__ __launch_bounds__(256) void k_ewise_range(int op, PackedOperand a, PackedOperand b,
+                                                     int64_t scalar, uint64_t n,
+                                                     RangeSlot *slot) {
+  int64_t lo = INT64_MAX, hi = INT64_MIN;
+  int ovf = 0;
+  const uint64_t ngroups = (n + kGroup - 1) / kGroup;
+  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < ngroups) {
+    BitReader ra(a.w + g * (uint64_t)a.bits);
+    BitReader rb(op == EW_ADD ? b.w + g * (uint64_t)b.bits : a.w);
+    const uint64_t e0 = g * kGroup;
+#pragma unroll 2
+    for (int i = 0; i < kGroup; ++i) {
+      const uint64_t ua = ra.field(a.bits);
+      const int64_t va = a.sgn ? sext64(ua, a.bits) : (int64_t)ua;
+      int64_t vb = 0;
+      if (op == EW_ADD) {
+        const uint64_t ub = rb.field(b.bits);
+        vb = b.sgn ? sext64(ub, b.bits) : (int64_t)ub;
+      }
+      if (e0 + i < n) {
+        const int64_t c = ewise_value(op, va, vb, scalar, &ovf);
+        lo = c < lo ? c : lo;
+        hi = c > hi ? c : hi;
+      }
+    }
+  }
+  block_range_commit(lo, hi, ovf, slot);
+}
+
+// Packing pass of an elementwise result: lane g writes output words
+// [g*out_bits, (g+1)*out_bits) for the 32 results of group g (zeros past n).
+__global__ __launch_bounds__(256) void k_ewise_pack(int op, PackedOperand a, PackedOperand b,
+                                                    int64_t scalar, uint64_t n, int out_bits,
+                                                    uint32_t *__restrict__ out, uint64_t cap32,
+                                                    uint64_t ngroups_out) {
+  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroups_out) return;
+  BitWriter w(out, g * (uint64_t)out_bits, cap32);
+  const uint64_t ngroups_in = (n + kGroup - 1) / kGroup;
+  if (g >= ngroups_in) {
+    for (int i = 0; i < out_bits; ++i) w.put(0u, 32);
+    return;
+  }
+  BitReader ra(a.w + g * (uint64_t)a.bits);
+  BitReader rb(op == EW_ADD ? b.w + g * (uint64_t)b.bits : a.w);
+  const uint64_t e0 = g * kGroup;
+  int ovf = 0;
+#pragma unroll 2
+  for (int i = 0; i < kGroup; ++i) {
+    const uint64_t ua = ra.field(a.bits);
+    const int64_t va = a.sgn ? sext64(ua, a.bits) : (int64_t)ua;
+    int64_t vb = 0;
+    if (op == EW_ADD) {
+      const uint64_t ub = rb.field(b.bits);
+      vb = b.sgn ? sext64(ub, b.bits) : (int64_t)ub;
+    }
+    const int64_t c = e0 + i < n ? ewise_value(op, va, vb, scalar, &ovf) : 0;
+    w.field((uint64_t)c, out_bits);
+  }
+}
+
+__global__ void k_fill_i64(int64_t *p, uint64_t n, int64_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) p[e] = v;
+}
+
+// ---- synthetic data -------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_uniform(T *d, uint64_t n, int64_t lo, uint64_t span,
+                                                      uint64_t seed, uint64_t sid,
+                                                      uint64_t start) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+    d[e] = (T)uniform_at(seed, sid, start + e, lo, span);
+}
+
+__global__ __launch_bounds__(256) void k_gen_range(uint64_t n, int64_t lo, uint64_t span,
+                                                   uint64_t seed, uint64_t sid,
+                                                   RangeSlot *slot) {
+  int64_t mn = INT64_MAX, mx = INT64_MIN;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const int64_t v = uniform_at(seed, sid, e, lo, span);
+    mn = v < mn ? v : mn;
+    mx = v > mx ? v : mx;
+  }
+  block_range_commit(mn, mx, 0, slot);
+}
+
+__global__ __launch_bounds__(256) void k_gen_pack(uint64_t n, int64_t lo, uint64_t span,
+                                                  uint64_t seed, uint64_t sid, int bits,
+                                                  uint32_t *__restrict__ out, uint64_t cap32,
+                                                  uint64_t ngroups_out) {
+  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroups_out) return;
+  BitWriter w(out, g * (uint64_t)bits, cap32);
+  const uint64_t e0 = g * kGroup;
+#pragma unroll 4
+  for (int i = 0; i < kGroup; ++i) {
+    const uint64_t e = e0 + i;
+    const int64_t v = e < n ? uniform_at(seed, sid, e, lo, span) : 0;
+    w.field((uint64_t)v, bits);
+  }
+}
+
+inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap = 1u << 20) {
+  uint64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_range_init(RangeSlot *slot, hipStream_t s) {
+  k_range_init<<<1, 1, 0, s>>>(slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_range_dense(const void *dense, int dtype, uint64_t n, RangeSlot *slot,
+                              hipStream_t s) {
+  const unsigned grid = grid_for(n, 256 * 16, 4096);
+  if (dtype == CCM_I64)
+    k_range_dense<int64_t><<<grid, 256, 0, s>>>((const int64_t *)dense, n, slot);
+  else
+    k_range_dense<int32_t><<<grid, 256, 0, s>>>((const int32_t *)dense, n, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_compress(const void *dense, int dtype, uint64_t n, int bits, uint32_t *out,
+                           uint64_t cap32, hipStream_t s) {
+  const uint64_t ngroups = (cap32 + bits - 1) / bits;
+  const unsigned grid = grid_for(ngroups, kTileThreads, 0x7fffffffu);
+  if (dtype == CCM_I64)
+    k_compress<int64_t><<<grid, kTileThreads, 0, s>>>((const int64_t *)dense, n, bits, out,
+                                                       cap32, ngroups);
+  else
+    k_compress<int32_t><<<grid, kTileThreads, 0, s>>>((const int32_t *)dense, n, bits, out,
+                                                       cap32, ngroups);
+  return hipGetLastError();
+}
+
+hipError_t launch_decompress(const uint32_t *w, uint64_t n, int bits, int sgn, int64_t *out,
+                             hipStream_t s) {
+  const uint64_t ngroups = (n + kGroup - 1) / kGroup;
+  k_decompress<<<grid_for(ngroups, kTileThreads, 0x7fffffffu), kTileThreads, 0, s>>>(
+      w, n, bits, sgn, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const uint32_t *w, int64_t rows, int64_t cols, int bits, int sgn,
+                         const int64_t *ii, const int64_t *jj, int64_t n, int64_t *out,
+                         int32_t *bad, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_gather<<<grid_for((uint64_t)n, 256, 0x7fffffffu), 256, 0, s>>>(w, rows, cols, bits, sgn, ii,
+                                                                   jj, n, out, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_one(const uint32_t *w, uint64_t e, int bits, int sgn, int64_t *out,
+                          hipStream_t s) {
+  k_get_one<<<1, 1, 0, s>>>(w, e, bits, sgn, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ewise_range(int op, PackedOperand a, PackedOperand b, int64_t scalar,
+                              uint64_t n, RangeSlot *slot, hipStream_t s) {
+  const uint64_t ngroups = (n + kGroup - 1) / kGroup;
+  k_ewise_range<<<grid_for(ngroups, 256, 0x7fffffffu), 256, 0, s>>>(op, a, b, scalar, n, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_ewise_pack(int op, PackedOperand a, PackedOperand b, int64_t scalar,
+                             uint64_t n, int out_bits, uint32_t *out, uint64_t cap32,
+                             hipStream_t s) {
+  const uint64_t ngroups_out = (cap32 + out_bits - 1) / out_bits;
+  k_ewise_pack<<<grid_for(ngroups_out, 256, 0x7fffffffu), 256, 0, s>>>(
+      op, a, b, scalar, n, out_bits, out, cap32, ngroups_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_fill_i64<<<grid_for(n, 256, 4096), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_uniform(void *dense, int dtype, uint64_t n, int64_t lo, uint64_t span,
+                               uint64_t seed, uint64_t stream_id, uint64_t start,
+                               hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned grid = grid_for(n, 256 * 8, 16384);
+  if (dtype == CCM_I64)
+    k_fill_uniform<int64_t><<<grid, 256, 0, s>>>((int64_t *)dense, n, lo, span, seed, stream_id,
+                                                  start);
+  else
+    k_fill_uniform<int32_t><<<grid, 256, 0, s>>>((int32_t *)dense, n, lo, span, seed, stream_id,
+                                                  start);
+  return hipGetLastError();
+}
+
+hipError_t launch_gen_range(uint64_t n, int64_t lo, uint64_t span, uint64_t seed,
+                            uint64_t stream_id, RangeSlot *slot, hipStream_t s) {
+  k_gen_range<<<grid_for(n, 256 * 16, 8192), 256, 0, s>>>(n, lo, span, seed, stream_id, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_gen_pack(uint64_t n, int64_t lo, uint64_t span, uint64_t seed,
+                           uint64_t stream_id, int bits, uint32_t *out, uint64_t cap32,
+                           hipStream_t s) {
+  const uint64_t ngroups_out = (cap32 + bits - 1) / bits;
+  k_gen_pack<<<grid_for(ngroups_out, 256, 0x7fffffffu), 256, 0, s>>>(
+      n, lo, span, seed, stream_id, bits, out, cap32, ngroups_out);
+  return hipGetLastError();
+}
+
+}  // namespace ccm

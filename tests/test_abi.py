@@ -1,0 +1,169 @@
+"""The C-ABI library loads, exports every symbol include/ccm.h declares, and
+its host-only logic (sizes, width rule, headers, plans that need no GPU)
+agrees with the oracle.  No GPU work is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ccm.h")
+
+
+def _load():
+    from paper_1303_0270_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1303_0270_amd.build import build_library
+        build_library()
+    return _lib
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 25
+    handle = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in names if not hasattr(handle, n)]
+    assert not missing, missing
+    # the binding declares exactly the header's functions
+    assert sorted(L.SIGNATURES) == names
+
+
+def test_no_torch_types_in_header():
+    text = open(HEADER).read()
+    code = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    assert "torch" not in code.lower() and "at::" not in code
+    assert 'extern "C"' in code
+
+
+def test_status_strings(L):
+    for code in range(-7, 1):
+        assert L.lib.ccm_status_str(code)
+    assert L.lib.ccm_status_str(-99) == b"unknown status"
+
+
+def test_sizes_match_oracle(L):
+    rng = np.random.default_rng(1)
+    for _ in range(500):
+        r, c, b = int(rng.integers(1, 5000)), int(rng.integers(1, 5000)), int(rng.integers(1, 65))
+        assert L.lib.ccm_words(r, c, b) == oracle.words(r, c, b)
+        assert L.lib.ccm_packed_bytes(r, c, b) == oracle.packed_bytes(r, c, b)
+        cap = L.lib.ccm_payload_capacity(r, c, b)
+        assert cap >= 8 * oracle.words(r, c, b) and cap % 256 == 0
+    for bad in ((0, 5, 3), (5, 0, 3), (5, 5, 0), (5, 5, 65), (-1, 2, 2)):
+        assert L.lib.ccm_words(*bad) == 0 and L.lib.ccm_payload_capacity(*bad) == 0
+
+
+def test_width_rule_matches_oracle(L):
+    rng = np.random.default_rng(2)
+    cases = [(0, 0), (0, 1), (1, 1), (-1, 0), (-1, -1), (0, 2**63 - 1), (-2**63, 2**63 - 1),
+             (-2**63, -2**63), (-128, 127), (-129, 127), (-128, 128), (1023, 1023)]
+    for t in range(63):
+        cases += [(0, (1 << t)), (-(1 << t), 0), (-(1 << t) - 1, 1 << t)]
+    for _ in range(2000):
+        a, b = sorted(int(v) for v in rng.integers(-2**63, 2**63 - 1, size=2, endpoint=True))
+        sh = int(rng.integers(0, 63))
+        cases.append((a >> sh, b >> sh))
+    bits, sgn = ctypes.c_int32(), ctypes.c_int32()
+    for lo, hi in cases:
+        assert L.lib.ccm_width(lo, hi, ctypes.byref(bits), ctypes.byref(sgn)) == L.OK
+        assert (bits.value, bool(sgn.value)) == oracle.width(lo, hi), (lo, hi)
+    assert L.lib.ccm_width(3, 2, ctypes.byref(bits), ctypes.byref(sgn)) == L.E_INVAL
+
+
+def _desc_from(p):
+    from paper_1303_0270_amd._lib import Desc
+    return Desc(p.rows, p.cols, p.vmin, p.vmax, p.bits, 1 if p.is_signed else 0, p.words, None)
+
+
+def test_header_bytes_match_oracle(L):
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        r, c = (int(v) for v in rng.integers(1, 9, size=2))
+        lo = int(rng.integers(-2**40, 2**40))
+        hi = lo + int(rng.integers(0, 2**41))
+        m = np.array(rng.integers(lo, hi, size=(r, c), endpoint=True), dtype=np.int64)
+        p = oracle.compress(m)
+        d = _desc_from(p)
+        buf = (ctypes.c_uint8 * 64)()
+        assert L.lib.ccm_header_encode(ctypes.byref(d), buf) == L.OK
+        assert bytes(buf) == oracle.header(p)
+        back = L.Desc()
+        assert L.lib.ccm_header_decode(buf, ctypes.byref(back)) == L.OK
+        assert (back.rows, back.cols, back.vmin, back.vmax, back.bits, back.is_signed,
+                back.words) == (d.rows, d.cols, d.vmin, d.vmax, d.bits, d.is_signed, d.words)
+
+
+def test_header_decode_rejects_corruption(L):
+    p = oracle.compress(np.array([[900, 1023, 721, 256, 1, 10, 700, 20]]))
+    good = bytearray(oracle.header(p))
+    d = L.Desc()
+    for pos, val in ((0, ord("X")), (4, 2), (6, 9), (7, 2), (40, 3), (50, 1), (33, 0)):
+        bad = bytearray(good)
+        bad[pos] = val
+        buf = (ctypes.c_uint8 * 64).from_buffer_copy(bytes(bad))
+        assert L.lib.ccm_header_decode(buf, ctypes.byref(d)) == L.E_INVAL, pos
+
+
+def test_scale_plan_matches_oracle(L):
+    rng = np.random.default_rng(4)
+    for _ in range(200):
+        m = np.array(rng.integers(-5000, 5000, size=(3, 4)), dtype=np.int64)
+        if rng.integers(0, 2):
+            m = np.abs(m)
+        s = int(rng.integers(-2**20, 2**20))
+        p = oracle.compress(m)
+        want = oracle.scale(p, s)
+        out = L.Desc()
+        assert L.lib.ccm_scale_plan(ctypes.byref(_desc_from(p)), s, ctypes.byref(out)) == L.OK
+        assert (out.vmin, out.vmax, out.bits, bool(out.is_signed), out.words) == \
+            (want.vmin, want.vmax, want.bits, want.is_signed, want.words)
+    p = oracle.compress(np.array([[-2**63, 1]], dtype=np.int64))
+    out = L.Desc()
+    assert L.lib.ccm_scale_plan(ctypes.byref(_desc_from(p)), -1, ctypes.byref(out)) == \
+        L.E_OVERFLOW
+
+
+def test_matmul_overflow_rule_matches_oracle(L):
+    cases = [([[2**31, 2**31]], [[2**31], [-2**31]]), ([[2**31]], [[-2**31]]),
+             ([[3, 4]], [[5], [6]]), ([[2**62]], [[1]]), ([[2**62, 1]], [[2], [1]])]
+    for a, b in cases:
+        pa, pb = oracle.compress(np.array(a)), oracle.compress(np.array(b))
+        try:
+            oracle.matmul_check(pa, pb)
+            want_ok = True
+        except oracle.OracleError as e:
+            assert e.code == oracle.E_OVERFLOW
+            want_ok = False
+        got = L.lib.ccm_matmul_scratch_bytes(ctypes.byref(_desc_from(pa)),
+                                             ctypes.byref(_desc_from(pb)))
+        assert (got > 0) == want_ok, (a, b)
+
+
+def test_invalid_descriptors_rejected_before_gpu_work(L):
+    p = oracle.compress(np.array([[1, 2], [3, 4]]))
+    d = _desc_from(p)
+    d.bits = 5  # not the width of [1, 4]
+    out = L.Desc()
+    assert L.lib.ccm_scale_plan(ctypes.byref(d), 2, ctypes.byref(out)) == L.E_INVAL
+    d = _desc_from(p)
+    d.words += 1
+    assert L.lib.ccm_scale_plan(ctypes.byref(d), 2, ctypes.byref(out)) == L.E_INVAL
+    d = _desc_from(p)  # payload NULL: ops that touch the device refuse it
+    y = ctypes.c_int64()
+    assert L.lib.ccm_get(ctypes.byref(d), 0, 0, ctypes.byref(y), None) == L.E_INVAL
+    assert L.lib.ccm_matvec(ctypes.byref(d), None, L.I32, None, None) == L.E_INVAL

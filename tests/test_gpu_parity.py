@@ -1,0 +1,255 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer results are compared bit-exactly: compressed results by their header
+and canonical payload bytes, vectors element by element.  Small cases span
+several tiles and ragged tails; the workload-sized cases are checked on
+sampled rows and entries the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+
+import ccm_workloads as W
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "gpu tests need a GPU"
+    import paper_1303_0270_amd  # noqa: F401  (fails loudly without libccm.so)
+
+
+def ccm():
+    import paper_1303_0270_amd as c
+    return c
+
+
+def dev(a, dtype=torch.int64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def rand_matrix(rng, rows, cols, b, signed):
+    lo, hi = ((-(1 << (b - 1)), (1 << (b - 1)) - 1) if signed else (0, (1 << b) - 1))
+    m = rng.integers(lo, hi, size=(rows, cols), endpoint=True, dtype=np.int64)
+    flat = m.reshape(-1)
+    flat[int(rng.integers(0, flat.size))] = hi
+    if signed:
+        flat[int(rng.integers(0, flat.size))] = lo
+    return m
+
+
+def assert_same_packed(gpu, ref):
+    assert gpu.header() == oracle.header(ref)
+    assert gpu.payload_bytes() == ref.payload_bytes()
+    # every byte of the capacity past the canonical payload is written as zero
+    tail = gpu.payload[8 * gpu.words:].cpu().numpy()
+    assert not tail.any()
+
+
+SHAPES = [(1, 1), (1, 33), (3, 37), (65, 33), (130, 257), (7, 1000)]
+
+
+@pytest.mark.parametrize("b", list(range(1, 65)))
+def test_compress_decompress_all_widths(b):
+    c = ccm()
+    rng = np.random.default_rng(100 + b)
+    for signed in ((False, True) if b < 64 else (True,)):
+        for rows, cols in SHAPES[: 3 + b % 4]:
+            if signed and b == 1 and rows * cols < 2:
+                continue
+            m = rand_matrix(rng, rows, cols, b, signed)
+            ref = oracle.compress(m)
+            g = c.compress(dev(m))
+            assert_same_packed(g, ref)
+            assert np.array_equal(c.decompress(g).cpu().numpy(), oracle.decompress(ref))
+            if b <= 31:
+                g32 = c.compress(dev(m, torch.int32))
+                assert_same_packed(g32, ref)
+
+
+def test_worked_example_on_gpu():
+    c = ccm()
+    vals = np.array([[900, 1023, 721, 256, 1, 10, 700, 20]])
+    g = c.compress(dev(vals))
+    ref = oracle.compress(vals)
+    assert_same_packed(g, ref)
+    assert [c.get(g, 0, j) for j in range(8)] == vals[0].tolist()
+
+
+def test_get_and_gather():
+    c = ccm()
+    rng = np.random.default_rng(7)
+    for b, signed in ((3, False), (10, False), (33, True), (64, True), (17, True)):
+        m = rand_matrix(rng, 45, 71, b, signed)
+        ref = oracle.compress(m)
+        g = c.compress(dev(m))
+        for _ in range(20):
+            i, j = int(rng.integers(0, 45)), int(rng.integers(0, 71))
+            assert c.get(g, i, j) == oracle.get(ref, i, j)
+        ii = rng.integers(0, 45, size=1000)
+        jj = rng.integers(0, 71, size=1000)
+        vals, bad = c.gather(g, dev(ii), dev(jj))
+        assert not bad
+        assert vals.cpu().numpy().tolist() == [oracle.get(ref, int(i), int(j))
+                                               for i, j in zip(ii, jj)]
+        vals, bad = c.gather(g, dev(np.array([0, 45, 3])), dev(np.array([0, 0, -1])))
+        assert bad and vals.cpu().numpy().tolist()[1:] == [0, 0]
+        with pytest.raises(c.CcmError):
+            c.get(g, 45, 0)
+        with pytest.raises(c.CcmError):
+            c.get(g, 0, -1)
+
+
+ADD_CASES = [(1, False, 1, False), (3, True, 5, False), (10, False, 10, False),
+             (12, True, 12, True), (31, True, 30, False), (33, False, 2, True),
+             (40, True, 63, False), (64, True, 7, True), (62, False, 62, False)]
+
+
+@pytest.mark.parametrize("ba,sa,bb,sb", ADD_CASES)
+def test_add_matches_oracle(ba, sa, bb, sb):
+    c = ccm()
+    rng = np.random.default_rng(ba * 100 + bb)
+    for rows, cols in ((1, 1), (5, 77), (70, 130)):
+        A = rand_matrix(rng, rows, cols, ba, sa)
+        B = rand_matrix(rng, rows, cols, bb, sb)
+        try:
+            ref = oracle.add(oracle.compress(A), oracle.compress(B))
+        except oracle.OracleError as e:
+            assert e.code == oracle.E_OVERFLOW
+            with pytest.raises(c.CcmError) as ei:
+                c.add(c.compress(dev(A)), c.compress(dev(B)))
+            assert ei.value.status == c._lib.E_OVERFLOW
+            continue
+        assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B))), ref)
+
+
+def test_add_overflow_and_shape():
+    c = ccm()
+    a = c.compress(dev(np.array([[2**63 - 1, 0]])))
+    one = c.compress(dev(np.array([[1, 0]])))
+    with pytest.raises(c.CcmError) as ei:
+        c.add(a, one)
+    assert ei.value.status == c._lib.E_OVERFLOW
+    with pytest.raises(c.CcmError) as ei:
+        c.add(a, c.compress(dev(np.array([[1], [0]]))))
+    assert ei.value.status == c._lib.E_SHAPE
+
+
+@pytest.mark.parametrize("b,signed", [(1, False), (4, True), (13, False), (31, True),
+                                      (40, False), (64, True)])
+def test_scale_matches_oracle(b, signed):
+    c = ccm()
+    rng = np.random.default_rng(b)
+    A = rand_matrix(rng, 33, 65, b, signed)
+    pa = oracle.compress(A)
+    ga = c.compress(dev(A))
+    for s in (0, 1, -1, 7, -3, 2**20, -(2**30)):
+        try:
+            ref = oracle.scale(pa, s)
+        except oracle.OracleError as e:
+            assert e.code == oracle.E_OVERFLOW
+            with pytest.raises(c.CcmError):
+                c.scale(ga, s)
+            continue
+        assert_same_packed(c.scale(ga, s), ref)
+
+
+MV_SHAPES = [(1, 1), (1, 40), (17, 31), (33, 96), (100, 257), (3, 9000), (70, 16500)]
+
+
+@pytest.mark.parametrize("b", list(range(1, 65)))
+def test_matvec_all_widths(b):
+    c = ccm()
+    rng = np.random.default_rng(1000 + b)
+    for signed in ((False, True) if b < 64 else (True,)):
+        shapes = MV_SHAPES if b in (1, 3, 7, 10, 12, 17, 31, 32, 33, 64) else MV_SHAPES[:5]
+        for rows, cols in shapes:
+            if signed and b == 1 and rows * cols < 2:
+                continue
+            A = rand_matrix(rng, rows, cols, b, signed)
+            pa = oracle.compress(A)
+            g = c.compress(dev(A))
+            x16 = rng.integers(-(1 << 15), 1 << 15, size=cols)
+            x32 = rng.integers(-(1 << 31), 1 << 31, size=cols)
+            x64 = rng.integers(-(1 << 63), (1 << 63) - 1, size=cols, endpoint=True)
+            for x, dt in ((x16, torch.int32), (x32, torch.int32), (x64, torch.int64)):
+                y = c.matvec(g, dev(x, dt)).cpu().numpy()
+                assert np.array_equal(y, oracle.matvec(pa, x)), (b, signed, rows, cols, dt)
+
+
+@pytest.mark.parametrize("ba,sa,bb,sb", [(10, False, 10, False), (6, False, 4, True),
+                                         (1, False, 1, True), (20, True, 17, False),
+                                         (33, True, 20, False), (8, False, 8, True)])
+def test_matmul_matches_oracle(ba, sa, bb, sb):
+    c = ccm()
+    rng = np.random.default_rng(ba * 7 + bb)
+    for M, K, N in ((1, 1, 1), (5, 7, 3), (65, 33, 70), (130, 100, 129)):
+        A = rand_matrix(rng, M, K, ba, sa)
+        B = rand_matrix(rng, K, N, bb, sb)
+        pa, pb = oracle.compress(A), oracle.compress(B)
+        ref = oracle.matmul(pa, pb)
+        assert_same_packed(c.matmul(c.compress(dev(A)), c.compress(dev(B))), ref)
+
+
+def test_matmul_overflow_rule():
+    c = ccm()
+    a = c.compress(dev(np.array([[2**31, 2**31]])))
+    b = c.compress(dev(np.array([[2**31], [-2**31]])))
+    with pytest.raises(c.CcmError) as ei:
+        c.matmul(a, b)
+    assert ei.value.status == c._lib.E_OVERFLOW
+    with pytest.raises(c.CcmError) as ei:
+        c.matmul(a, a)
+    assert ei.value.status == c._lib.E_SHAPE
+
+
+def test_serialize_round_trip():
+    c = ccm()
+    rng = np.random.default_rng(5)
+    A = rand_matrix(rng, 19, 23, 21, True)
+    g = c.compress(dev(A))
+    blob = g.serialize()
+    assert blob == oracle.header(oracle.compress(A)) + oracle.compress(A).payload_bytes()
+    back = c.from_serialized(blob)
+    assert np.array_equal(c.decompress(back).cpu().numpy(), A)
+
+
+def test_device_generator_matches_host_twin():
+    c = ccm()
+    for dt, lo, hi in ((torch.int64, -(1 << 31), 1 << 31), (torch.int32, -(1 << 15), 1 << 15),
+                       (torch.int64, 0, 1 << 32), (torch.int64, 5, 6), (torch.int32, 0, 1000)):
+        t = torch.empty(100003, dtype=dt, device="cuda")
+        c.fill_uniform(t, lo, hi, seed=W.seed_for(9, 1), stream_id=3, start=17)
+        want = W.uniform(W.seed_for(9, 1), 3, 17, 100003, lo, hi)
+        assert np.array_equal(t.cpu().numpy().astype(np.int64), want)
+    m = c.generate(301, 77, -100, 1 << 20, seed=W.seed_for(9, 2), stream_id=5)
+    ref = oracle.compress(W.uniform_matrix(W.seed_for(9, 2), 5, 301, 77, -100, 1 << 20))
+    assert_same_packed(m, ref)
+
+
+def test_small_plain_workload_full():
+    """256x256 in [0, 2^10): every operation checked in full."""
+    c = ccm()
+    a_s, b_s, x_s, s = W.small_plain()
+    A, B, x = a_s.dense(), b_s.dense(), x_s.dense()
+    pa, pb = oracle.compress(A), oracle.compress(B)
+    ga, gb = c.compress(dev(A)), c.compress(dev(B))
+    assert ga.bits == 10
+    assert_same_packed(ga, pa)
+    assert_same_packed(gb, pb)
+    assert np.array_equal(c.decompress(ga).cpu().numpy(), A)
+    rng = np.random.default_rng(W.seed_for(1, 3))
+    ii, jj = rng.integers(0, 256, 1000), rng.integers(0, 256, 1000)
+    vals, bad = c.gather(ga, dev(ii), dev(jj))
+    assert not bad and vals.cpu().numpy().tolist() == [oracle.get(pa, int(i), int(j))
+                                                       for i, j in zip(ii, jj)]
+    assert np.array_equal(c.matvec(ga, dev(x)).cpu().numpy(), oracle.matvec(pa, x))
+    assert_same_packed(c.add(ga, gb), oracle.add(pa, pb))
+    assert_same_packed(c.scale(ga, s), oracle.scale(pa, s))
+    gm = c.matmul(ga, gb)
+    assert_same_packed(gm, oracle.matmul(pa, pb))
+    # the same values as plain int64 arithmetic
+    assert np.array_equal(c.decompress(gm).cpu().numpy(), A @ B)
