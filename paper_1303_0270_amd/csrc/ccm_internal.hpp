@@ -37,6 +37,16 @@ __host__ __device__ inline uint32_t mask32(int bits) {
   return bits >= 32 ? ~0u : ((1u << bits) - 1u);
 }
 
+// Returns v unchanged (no instruction) but hides how it was computed from the
+// optimizer.  Used on sign-extended bit-field extracts (v_bfe_i32): when such a
+// value feeds a 64-bit multiply-accumulate chain, the compiler has been seen
+// to drop the sign(a)*x correction term of the 64-bit product, as if the
+// extract were non-negative.
+__device__ __forceinline__ int32_t opaque_i32(int32_t v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
 // Two's-complement sign extension of the low `bits` bits.
 __host__ __device__ inline int64_t sext64(uint64_t u, int bits) {
   const int s = 64 - bits;

@@ -62,7 +62,7 @@ __device__ __forceinline__ int64_t group_field(const uint32_t *w, int i) {
       o2 = 0;
     }
     if constexpr (SGN)
-      return (int64_t)__builtin_amdgcn_sbfe((int32_t)src, o2, B);
+      return (int64_t)opaque_i32(__builtin_amdgcn_sbfe((int32_t)src, o2, B));
     else
       return (int64_t)__builtin_amdgcn_ubfe(src, o2, B);
   } else if constexpr (B == 32) {
@@ -82,7 +82,7 @@ __device__ __forceinline__ int64_t group_field(const uint32_t *w, int i) {
     if constexpr (B == 64)
       h = (int64_t)(int32_t)hi;
     else if constexpr (SGN)
-      h = (int64_t)__builtin_amdgcn_sbfe((int32_t)hi, 0, B - 32);
+      h = (int64_t)opaque_i32(__builtin_amdgcn_sbfe((int32_t)hi, 0, B - 32));
     else
       h = (int64_t)__builtin_amdgcn_ubfe(hi, 0, B - 32);
     return (int64_t)(((uint64_t)h << 32) | (uint64_t)lo);
