@@ -1,0 +1,331 @@
+"""Benchmark of the compressed-matrix hot path on one MI355X.
+
+Workload: the bandwidth sweep -- 16384 x 16384 matrices uniform in [0, 2^k)
+and in [-2^(k-1), 2^(k-1)) for k in {1, 3, 7, 12, 17, 31} (twelve matrices),
+a second matrix of each kind for add, and an int32 x uniform in
+[-2^15, 2^15).  All inputs are seeded synthetic data generated on the device
+(SplitMix64) and resident in HBM before the timed region.
+
+One step runs every operation of the path over the twelve matrices, in
+phases: width + compress (from the dense int64 input), matvec, add (range
+pass + pack), scale by 7, decompress and 1000 element gets.  The reported
+value is the packed-matvec bandwidth: the packed bytes of A (8*W per matrix)
+over the matvec kernels' time, taken with HIP events on the launch stream
+inside the timed steps.  Each phase touches gigabytes before a matrix is read
+again, so the 256 MB last-level cache does not hold A between its compression
+and its matvec.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-extras] [--profile]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+METRIC = ("packed-matvec HBM GB/s (% peak) + Gelem/s vs dense int32; "
+          "batched p50/p99 latency")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: matvec sweep and a calibration copy only")
+    return ap.parse_args()
+
+
+class Timer:
+    """HIP events on the current stream, accumulated per label."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pending = []
+
+    def span(self, label):
+        torch = self.torch
+        timer = self
+
+        class _S:
+            def __enter__(self_):
+                self_.a = torch.cuda.Event(enable_timing=True)
+                self_.b = torch.cuda.Event(enable_timing=True)
+                self_.a.record()
+
+            def __exit__(self_, *exc):
+                self_.b.record()
+                timer.pending.append((label, self_.a, self_.b))
+        return _S()
+
+    def collect(self):
+        out = {}
+        for label, a, b in self.pending:
+            out.setdefault(label, []).append(a.elapsed_time(b) * 1e-3)
+        self.pending = []
+        return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import ccm_workloads as W
+    import paper_1303_0270_amd as ccm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    bench_lib = ctypes.CDLL(os.path.join(ROOT, "paper_1303_0270_amd", "libccm_bench.so"))
+    bench_lib.ccmb_dense_matvec_i32.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                                ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p]
+    bench_lib.ccmb_read_bytes.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                          ctypes.c_void_p]
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    n = args.n
+
+    # ---- resident inputs -------------------------------------------------
+    cases = []
+    x_spec = None
+    for k in W.SWEEP_WIDTHS:
+        for signed in (False, True):
+            a_s, b_s, x_s, s = W.sweep(k, signed, n)
+            x_spec = x_s
+            dense = torch.empty((n, n), dtype=torch.int64, device="cuda")
+            ccm.fill_uniform(dense, a_s.lo, a_s.hi, a_s.seed, a_s.stream)
+            bden = torch.empty((n, n), dtype=torch.int64, device="cuda")
+            ccm.fill_uniform(bden, b_s.lo, b_s.hi, b_s.seed, b_s.stream)
+            bpk = ccm.compress(bden)
+            del bden
+            cases.append({"k": k, "signed": signed, "spec": a_s, "dense": dense, "B": bpk,
+                          "scale": s})
+    x = torch.empty(n, dtype=torch.int32, device="cuda")
+    ccm.fill_uniform(x, x_spec.lo, x_spec.hi, x_spec.seed, x_spec.stream)
+    y = torch.empty(n, dtype=torch.int64, device="cuda")
+    dec = torch.empty((n, n), dtype=torch.int64, device="cuda")
+    rng = np.random.default_rng(W.seed_for(2, 3))
+    gi = torch.from_numpy(rng.integers(0, n, 1000)).cuda()
+    gj = torch.from_numpy(rng.integers(0, n, 1000)).cuda()
+    torch.cuda.synchronize()
+    log("inputs resident")
+
+    timer = Timer(torch)
+
+    def step(profile=False):
+        packed = []
+        for c in cases:
+            with timer.span(f"compress:{c['k']}:{int(c['signed'])}"):
+                a = ccm.compress(c["dense"])
+            packed.append(a)
+        for c, a in zip(cases, packed):
+            with timer.span(f"matvec:{c['k']}:{int(c['signed'])}"):
+                ccm.matvec(a, x, y)
+        if profile:
+            return packed
+        for c, a in zip(cases, packed):
+            with timer.span(f"add:{c['k']}:{int(c['signed'])}"):
+                c["sum"] = ccm.add(a, c["B"])
+        for c, a in zip(cases, packed):
+            with timer.span(f"scale:{c['k']}:{int(c['signed'])}"):
+                c["scaled"] = ccm.scale(a, c["scale"])
+        for c, a in zip(cases, packed):
+            with timer.span(f"decompress:{c['k']}:{int(c['signed'])}"):
+                ccm.decompress(a, out=dec)
+            with timer.span(f"get:{c['k']}:{int(c['signed'])}"):
+                ccm.gather(a, gi, gj)
+        return packed
+
+    for _ in range(args.warmup):
+        step(args.profile)
+    torch.cuda.synchronize()
+    timer.collect()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        packed = step(args.profile)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    times = timer.collect()
+    log(f"{args.steps} timed steps: {wall / args.steps * 1e3:.1f} ms/step")
+
+    # ---- matvec roofline -------------------------------------------------
+    per_width = []
+    tot_bytes = tot_t = 0.0
+    for c, a in zip(cases, packed):
+        ts = times[f"matvec:{c['k']}:{int(c['signed'])}"]
+        t = float(np.mean(ts))
+        nbytes = 8 * a.words
+        tot_bytes += nbytes * len(ts)
+        tot_t += sum(ts)
+        per_width.append({"k": c["k"], "signed": c["signed"], "bits": a.bits,
+                          "packed_bytes": nbytes, "matvec_us": round(t * 1e6, 2),
+                          "gbs": round(nbytes / t / 1e9, 1),
+                          "frac_hbm": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
+                          "gelem_s": round(n * n / t / 1e9, 1)})
+    value = tot_bytes / tot_t / 1e9
+
+    # ---- the other operations (algorithmic bytes, SURVEY per-op units) ---
+    def op_stats(prefix, bytes_fn):
+        tt = bb = 0.0
+        for c, a in zip(cases, packed):
+            ts = times.get(f"{prefix}:{c['k']}:{int(c['signed'])}")
+            if not ts:
+                return None
+            tt += sum(ts)
+            bb += bytes_fn(c, a) * len(ts)
+        return {"ms_per_sweep": round(tt / args.steps * 1e3, 3),
+                "us_per_call": round(tt / args.steps / len(cases) * 1e6, 2),
+                "alg_gbs": round(bb / tt / 1e9, 1)}
+
+    ops = {"matvec": {"ms_per_sweep": round(tot_t / args.steps * 1e3, 3),
+                      "alg_gbs": round(value, 1)}}
+    ops["compress"] = op_stats("compress", lambda c, a: 16 * n * n + 8 * a.words)
+    if not args.profile:
+        ops["add"] = op_stats("add", lambda c, a: 8 * (a.words + c["B"].words + c["sum"].words))
+        ops["scale"] = op_stats("scale", lambda c, a: 8 * (a.words + c["scaled"].words))
+        ops["decompress"] = op_stats("decompress", lambda c, a: 8 * a.words + 8 * n * n)
+        ops["get_1000"] = op_stats("get", lambda c, a: 1000 * 8)
+
+    # ---- dense int32 comparison and HBM read probe -----------------------
+    del dec
+    for c in cases:
+        c["dense"] = None
+    torch.cuda.empty_cache()
+    dense32 = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    ccm.fill_uniform(dense32, -(1 << 15), 1 << 15, W.seed_for(2, 4), 0)
+    copies32 = [dense32]
+    for _ in range(1):
+        copies32.append(dense32.clone())
+    for i in range(3):
+        bench_lib.ccmb_dense_matvec_i32(ctypes.c_void_p(copies32[i % 2].data_ptr()), n, n,
+                                        ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(y.data_ptr()), sp)
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        bench_lib.ccmb_dense_matvec_i32(ctypes.c_void_p(copies32[i % 2].data_ptr()), n, n,
+                                        ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(y.data_ptr()), sp)
+    e1.record()
+    torch.cuda.synchronize()
+    td = e0.elapsed_time(e1) * 1e-3 / reps
+    dense_i32 = {"matvec_us": round(td * 1e6, 2), "gelem_s": round(n * n / td / 1e9, 1),
+                 "gbs": round(4 * n * n / td / 1e9, 1)}
+    del copies32, dense32
+    torch.cuda.empty_cache()
+
+    big = torch.empty(4 << 30, dtype=torch.uint8, device="cuda")
+    big.fill_(1)
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        bench_lib.ccmb_read_bytes(ctypes.c_void_p(big.data_ptr()), big.numel(),
+                                  ctypes.c_void_p(sink.data_ptr()), sp)
+    e0.record()
+    for _ in range(5):
+        bench_lib.ccmb_read_bytes(ctypes.c_void_p(big.data_ptr()), big.numel(),
+                                  ctypes.c_void_p(sink.data_ptr()), sp)
+    e1.record()
+    torch.cuda.synchronize()
+    read_peak = big.numel() / (e0.elapsed_time(e1) * 1e-3 / 5) / 1e9
+    # plain copy of known size (calibrates the FETCH_SIZE / WRITE_SIZE counters)
+    half = big[: 1 << 30]
+    big[2 << 30: 3 << 30].copy_(half)
+    torch.cuda.synchronize()
+    del big, half
+
+    ref_t = sum(p["matvec_us"] for p in per_width)
+    result = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic (seeded SplitMix64, generated on device, resident in HBM)",
+        "config": {"workload": f"bandwidth sweep: {n}x{n}, k in {list(W.SWEEP_WIDTHS)}, "
+                               "unsigned and signed, int32 x in [-2^15, 2^15)",
+                   "rows": n, "cols": n, "matrices": len(cases),
+                   "step": "compress, matvec, add, scale(7), decompress, 1000 gets; "
+                           "all twelve matrices" if not args.profile else "compress, matvec"},
+        "roofline": {"bound": "hbm", "achieved": round(value, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(value / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_matvec (all widths of the sweep)",
+                     "alg_bytes_per_launch": "8*W packed bytes of A (x and y reported apart)"},
+        "per_width": per_width,
+        "ops": ops,
+        "gelem_s_packed": round(len(per_width) * n * n / (ref_t * 1e-6) / 1e9, 1),
+        "dense_i32": dense_i32,
+        "hbm_read_probe_gbs": round(read_peak, 1),
+    }
+
+    log("dense int32 and read probe done")
+    if not args.no_extras and not args.profile:
+        from bench_extras import run_extras
+        result["extras"] = run_extras(torch, ccm)
+
+    if not args.no_cpu_baseline and not args.profile:
+        log("extras done; timing the oracle")
+        result["cpu_baseline"] = cpu_baseline(W)
+
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(W):
+    """The oracle's matvec on the first rows of every sweep matrix (host cores)."""
+    import numpy as np
+
+    import oracle
+    rows = 512
+    total_bytes = 0.0
+    total_t = 0.0
+    for k in W.SWEEP_WIDTHS:
+        for signed in (False, True):
+            a_s, b_s, x_s, s = W.sweep(k, signed)
+            vals = a_s.rows_slice(0, rows)
+            bits, sgn = oracle.width(a_s.lo, a_s.hi - 1)
+            p = oracle.Packed(rows, a_s.cols, int(vals.min()), int(vals.max()), bits, sgn,
+                              oracle.encode_run(vals, bits))
+            xv = x_s.dense()
+            t0 = time.perf_counter()
+            oracle.matvec(p, xv)
+            total_t += time.perf_counter() - t0
+            total_bytes += rows * a_s.cols * bits / 8
+    return {"value": round(total_bytes / total_t / 1e9, 4), "unit": "GB/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"oracle matvec on rows 0..{rows - 1} of each of the 12 sweep matrices "
+                      f"({12 * rows} rows x 16384), bytes = packed bits / 8",
+            "seconds": round(total_t, 2)}
+
+
+if __name__ == "__main__":
+    main()

@@ -15,7 +15,7 @@ from ._lib import (E_INVAL, E_NOMEM, E_OVERFLOW, E_RANGE, E_SHAPE, E_UNSUPPORTED
                    OK, CcmError, Desc, check, lib)
 
 __all__ = ["CMatrix", "CcmError", "compress", "decompress", "get", "gather", "add", "scale",
-           "matvec", "matmul", "fill_uniform", "generate", "from_serialized", "words",
+           "matvec", "matmul", "matmul_plan", "matmul_pack", "fill_uniform", "generate", "from_serialized", "words",
            "packed_bytes", "payload_capacity", "width", "Batch"]
 
 
@@ -138,8 +138,11 @@ def compress(dense: torch.Tensor, stream=None) -> CMatrix:
     return m
 
 
-def decompress(m: CMatrix, stream=None) -> torch.Tensor:
-    out = torch.empty((m.rows, m.cols), dtype=torch.int64, device=m.payload.device)
+def decompress(m: CMatrix, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty((m.rows, m.cols), dtype=torch.int64, device=m.payload.device)
+    elif out.dtype != torch.int64 or out.numel() != m.rows * m.cols or not out.is_contiguous():
+        raise CcmError(E_INVAL, "decompress: out")
     check(lib.ccm_decompress(ctypes.byref(m.desc), _ptr(out), _stream(stream)), "ccm_decompress")
     return out
 
@@ -199,7 +202,9 @@ def matmul_scratch_bytes(a: CMatrix, b: CMatrix) -> int:
     return int(lib.ccm_matmul_scratch_bytes(ctypes.byref(a.desc), ctypes.byref(b.desc)))
 
 
-def matmul(a: CMatrix, b: CMatrix, scratch: torch.Tensor | None = None, stream=None) -> CMatrix:
+def matmul_plan(a: CMatrix, b: CMatrix, scratch: torch.Tensor | None = None, stream=None):
+    """Range pass of C = A B: computes C into scratch and returns (C, scratch), C
+    allocated at its final width but not yet packed."""
     if a.cols != b.rows:
         raise CcmError(E_SHAPE, "matmul")
     need = matmul_scratch_bytes(a, b)
@@ -208,14 +213,22 @@ def matmul(a: CMatrix, b: CMatrix, scratch: torch.Tensor | None = None, stream=N
         need = 8
     if scratch is None or scratch.numel() < need:
         scratch = torch.empty(need, dtype=torch.uint8, device=a.payload.device)
-    s = _stream(stream)
     d = Desc()
     check(lib.ccm_matmul_plan(ctypes.byref(a.desc), ctypes.byref(b.desc), ctypes.byref(d),
-                              _ptr(scratch), scratch.numel(), s), "ccm_matmul_plan")
-    c = CMatrix(d, device=a.payload.device)
+                              _ptr(scratch), scratch.numel(), _stream(stream)), "ccm_matmul_plan")
+    return CMatrix(d, device=a.payload.device), scratch
+
+
+def matmul_pack(a: CMatrix, b: CMatrix, c: CMatrix, scratch: torch.Tensor, stream=None):
+    """Packing pass of C = A B from the scratch its plan filled."""
     check(lib.ccm_matmul(ctypes.byref(a.desc), ctypes.byref(b.desc), ctypes.byref(c.desc),
-                         _ptr(scratch), scratch.numel(), s), "ccm_matmul")
+                         _ptr(scratch), scratch.numel(), _stream(stream)), "ccm_matmul")
     return c
+
+
+def matmul(a: CMatrix, b: CMatrix, scratch: torch.Tensor | None = None, stream=None) -> CMatrix:
+    c, scratch = matmul_plan(a, b, scratch, stream)
+    return matmul_pack(a, b, c, scratch, stream)
 
 
 def fill_uniform(t: torch.Tensor, lo: int, hi: int, seed: int, stream_id: int = 0,

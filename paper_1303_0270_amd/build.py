@@ -12,6 +12,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libccm.so")
+BENCH_SRC = os.path.join(PKG, "csrc_bench")
+BENCH_LIB = os.path.join(PKG, "libccm_bench.so")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -34,18 +36,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build_library(jobs: int | None = None) -> str:
-    os.makedirs(OBJ, exist_ok=True)
-    srcs = _sources()
-    jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
-    with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+def _link(objs, out):
+    tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build_library(jobs: int | None = None) -> str:
+    """Builds libccm.so and the benchmark's comparison kernels, libccm_bench.so."""
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = _sources()
+    bench_srcs = sorted(glob.glob(os.path.join(BENCH_SRC, "*.hip")))
+    jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(_compile, srcs + bench_srcs))
+    _link(objs[: len(srcs)], LIB)
+    _link(objs[len(srcs):], BENCH_LIB)
     return LIB
 
 
