@@ -49,7 +49,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile", action="store_true",
-                    help="short run for rocprofv3: matvec sweep and a calibration copy only")
+                    help="short run for rocprofv3: compress and matvec sweep, comparisons")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="counter runs: the twelve packed matrices generated directly on the "
+                         "device, K matvec sweeps, then a 1 GiB calibration copy")
     return ap.parse_args()
 
 
@@ -97,6 +100,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.matvec_only:
+        matvec_only(args, torch, W, ccm)
+        return
     bench_lib = ctypes.CDLL(os.path.join(ROOT, "paper_1303_0270_amd", "libccm_bench.so"))
     bench_lib.ccmb_dense_matvec_i32.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                                 ctypes.c_void_p, ctypes.c_void_p,
@@ -155,7 +161,7 @@ def main():
             with timer.span(f"decompress:{c['k']}:{int(c['signed'])}"):
                 ccm.decompress(a, out=dec)
             with timer.span(f"get:{c['k']}:{int(c['signed'])}"):
-                ccm.gather(a, gi, gj)
+                ccm.gather(a, gi, gj, sync=False)
         return packed
 
     for _ in range(args.warmup):
@@ -298,6 +304,29 @@ def main():
         result["cpu_baseline"] = cpu_baseline(W)
 
     print(json.dumps(result), flush=True)
+
+
+def matvec_only(args, torch, W, ccm):
+    """Matvec sweeps alone, for hardware-counter runs (one kernel per width)."""
+    n = args.n
+    mats = []
+    x_spec = None
+    for k in W.SWEEP_WIDTHS:
+        for signed in (False, True):
+            a_s, _, x_spec, _ = W.sweep(k, signed, n)
+            mats.append(ccm.generate(n, n, a_s.lo, a_s.hi, a_s.seed, a_s.stream))
+    x = torch.empty(n, dtype=torch.int32, device="cuda")
+    ccm.fill_uniform(x, x_spec.lo, x_spec.hi, x_spec.seed, x_spec.stream)
+    y = torch.empty(n, dtype=torch.int64, device="cuda")
+    for _ in range(args.warmup + args.steps):
+        for m in mats:
+            ccm.matvec(m, x, y)
+    src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"matvec_only": True, "matrices": len(mats),
+                      "packed_bytes": [8 * m.words for m in mats]}), flush=True)
 
 
 def cpu_baseline(W):

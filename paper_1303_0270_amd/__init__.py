@@ -153,15 +153,16 @@ def get(m: CMatrix, i: int, j: int, stream=None) -> int:
     return int(v.value)
 
 
-def gather(m: CMatrix, ii: torch.Tensor, jj: torch.Tensor, stream=None):
-    """Elements (ii[t], jj[t]); returns (values, any_out_of_range)."""
+def gather(m: CMatrix, ii: torch.Tensor, jj: torch.Tensor, stream=None, sync: bool = True):
+    """Elements (ii[t], jj[t]); returns (values, any_out_of_range).  With
+    sync=False the second item is the device flag tensor (no host wait)."""
     ii = _device_tensor(ii.to(torch.int64), "ii")
     jj = _device_tensor(jj.to(torch.int64), "jj")
     out = torch.empty(ii.numel(), dtype=torch.int64, device=ii.device)
     bad = torch.zeros(1, dtype=torch.int32, device=ii.device)
     check(lib.ccm_gather(ctypes.byref(m.desc), _ptr(ii), _ptr(jj), ii.numel(), _ptr(out),
                          _ptr(bad), _stream(stream)), "ccm_gather")
-    return out, bool(bad.item())
+    return out, (bool(bad.item()) if sync else bad)
 
 
 def add(a: CMatrix, b: CMatrix, stream=None) -> CMatrix:

@@ -3,20 +3,28 @@
 // Work layout (gfx950, 64-lane waves, 256-lane blocks):
 //   * A block owns a column panel of x, staged once into LDS (zero-padded to
 //     whole groups, with a 4-dword skew per group so 16-byte LDS reads of
-//     consecutive groups hit distinct banks), and loops over row blocks.
-//   * Each wave owns R rows at a time.  Lane l walks groups l, l+64, ... of
-//     those rows: for every group it reads 32 x values from LDS once and
-//     reuses them for all R rows (x traffic per element falls as 1/R).
+//     consecutive groups hit distinct banks), and one block of 4*R rows.
+//   * Each wave owns R rows.  Lane l walks groups l, l+64, ... of those rows:
+//     for every group it reads its 32 x values from LDS once and reuses them
+//     for all R rows.  The next group's words are fetched before the current
+//     group is decoded.
 //   * A row's group j starts at stream bit (r*cols + c0 + 32j)*b.  The word
 //     offset differs per row but the bit shift s = (r*cols + c0)*b mod 32 is
 //     the same for every group of the row (wave-uniform), so one funnel shift
 //     (v_alignbit_b32) per word re-aligns the group and every field is then
-//     extracted at a compile-time offset with one v_bfe (two when it
-//     straddles a word).
-//   * Products accumulate exactly in int64 (mod 2^64).  When the block finds
-//     every x of its panel in int16 range and b <= 10, 32 products of a group
-//     are summed in int32 with 24-bit multiply-adds first: |sum| < 32 * 2^10
-//     * 2^15 = 2^30, so the int32 partial is exact.
+//     extracted at a compile-time offset with one v_bfe (two instructions when
+//     it straddles a word).
+//   * Exact arithmetic.  When the block finds its whole x panel in int16
+//     range, products are summed in int32 over runs short enough that the
+//     partial sum cannot overflow (fixed per width at compile time: max|a| *
+//     2^15 * run < 2^31) with 24-bit multiply-adds, then widened to int64.
+//     Otherwise products are formed in 64 bits, accumulated in four
+//     independent chains, modulo 2^64.
+//   * b = 1 with int16-range x uses nibble dot products: x' = x + 2^15 is
+//     split into four 4-bit digits, arranged per group so that
+//     v_dot8_u32_u4 multiplies eight 1-bit fields (spread to nibbles with a
+//     shift and a mask) by eight digits at once; the row result is
+//     sum_d 16^d acc_d - 2^15 * popcount, negated for signed fields.
 //   * Row results are reduced across the wave with shuffles; with several
 //     column panels the partial row sums are combined with int64 atomics.
 #pragma once
@@ -42,11 +50,23 @@ struct XLayout<int64_t> {
   static constexpr int kPanel = 4096;
 };
 
-constexpr int rows_per_wave(int b) { return b <= 4 ? 16 : b <= 8 ? 8 : b <= 16 ? 4 : b <= 32 ? 2 : 1; }
+// Digit words of the b = 1 path: 16 per group (+4 skew).
+constexpr int kDigitPitch = 20;
 
-// Field i (compile-time after unrolling) of a re-aligned group of b-bit
-// fields held in w[0..b].  b <= 32: the value as int64.
-template <int B, bool SGN>
+constexpr int rows_per_wave(int b) { return b <= 10 ? 4 : b <= 16 ? 2 : 1; }
+
+// Elements per exact int32 partial sum on the int16-x path (0: use int64).
+constexpr int run_len(int b, bool sgn) {
+  if (b > 16) return 0;
+  const long long maxa = sgn ? (1ll << (b - 1)) : ((1ll << b) - 1);
+  const long long t = ((1ll << 31) - 1) / (maxa * 32768ll);
+  return t >= 32 ? 32 : (t >= 16 ? 16 : (t >= 8 ? 8 : (t >= 4 ? 4 : (t >= 2 ? 2 : (t >= 1 ? 1 : 0)))));
+}
+
+// Field i (compile-time after unrolling) of a re-aligned group held in w[].
+// OPQ hides signed extracts from the optimizer; only the 64-bit product
+// chains need it (see opaque_i32).
+template <int B, bool SGN, bool OPQ = true>
 __device__ __forceinline__ int64_t group_field(const uint32_t *w, int i) {
   const int p = i * B;
   const int k = p >> 5;
@@ -61,10 +81,12 @@ __device__ __forceinline__ int64_t group_field(const uint32_t *w, int i) {
       src = __builtin_amdgcn_alignbit(w[k + 1], w[k], off);
       o2 = 0;
     }
-    if constexpr (SGN)
-      return (int64_t)opaque_i32(__builtin_amdgcn_sbfe((int32_t)src, o2, B));
-    else
+    if constexpr (SGN) {
+      const int32_t v = __builtin_amdgcn_sbfe((int32_t)src, o2, B);
+      return (int64_t)(OPQ ? opaque_i32(v) : v);
+    } else {
       return (int64_t)__builtin_amdgcn_ubfe(src, o2, B);
+    }
   } else if constexpr (B == 32) {
     const uint32_t src = w[k];
     if constexpr (SGN)
@@ -89,14 +111,8 @@ __device__ __forceinline__ int64_t group_field(const uint32_t *w, int i) {
   }
 }
 
-// 24-bit signed field for the int32 fast path (b <= 10).
-template <int B, bool SGN>
-__device__ __forceinline__ int32_t group_field24(const uint32_t *w, int i) {
-  return (int32_t)group_field<B, SGN>(w, i);
-}
-
 // a * x modulo 2^64.  With b <= 32 and int32 x the product is exact in int64
-// (|a x| < 2^63), which lets the compiler use one v_mad_i64_i32 per element.
+// (|a x| < 2^63), so the compiler can use one v_mad_i64_i32 per element.
 template <int B, typename XT>
 __device__ __forceinline__ uint64_t mul_mod64(int64_t a, XT x) {
   if constexpr (sizeof(XT) == 4 && B <= 32)
@@ -105,39 +121,63 @@ __device__ __forceinline__ uint64_t mul_mod64(int64_t a, XT x) {
     return (uint64_t)a * (uint64_t)(int64_t)x;
 }
 
+// d = a * b + c on the low 24 bits of a and b (v_mad_i32_i24).  Written as one
+// instruction: left to itself the compiler re-associates such chains into a
+// 24-bit multiply plus a three-input add per element pair (1.5 instructions
+// per element instead of 1).
+__device__ __forceinline__ int32_t mad24(int32_t a, int32_t b, int32_t c) {
+  int32_t d;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
+// Dot product of one group with int16-range x (exact; int32 runs).
+template <int B, bool SGN>
+__device__ __forceinline__ uint64_t group_dot_small(const uint32_t *w, const int32_t *xv) {
+  constexpr int T = run_len(B, SGN);
+  uint64_t acc = 0;
+#pragma unroll
+  for (int r0 = 0; r0 < kGroup; r0 += T) {
+    int32_t part = 0;
+#pragma unroll
+    for (int i = r0; i < r0 + T; ++i)
+      part = mad24((int32_t)group_field<B, SGN, false>(w, i), xv[i], part);
+    acc += (uint64_t)(int64_t)part;
+  }
+  return acc;
+}
+
+// Dot product of one group, general x (64-bit products, four chains).
+// Scheduling barriers every 8 elements bound the live ranges (the 64-bit
+// products otherwise get hoisted together and cost occupancy).
 template <int B, bool SGN, typename XT>
-__global__ __launch_bounds__(kThreads, 2) void k_matvec(const uint32_t *__restrict__ A,
-                                                        int64_t rows, int64_t cols,
-                                                        const XT *__restrict__ x,
-                                                        int64_t *__restrict__ y,
-                                                        int atomic_out) {
+__device__ __forceinline__ uint64_t group_dot_wide(const uint32_t *w, const XT *xv) {
+  uint64_t c[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < kGroup; ++i) {
+    c[i & 3] += mul_mod64<B, XT>(group_field<B, SGN>(w, i), xv[i]);
+    if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+  }
+  return (c[0] + c[1]) + (c[2] + c[3]);
+}
+
+// Row-block loop of the general kernel for one arithmetic mode (0: 64-bit
+// products; 1: int16-range x, exact int32 runs; 2: b = 1 digit dot
+// products).  Instantiated per mode so each loop gets its own registers.
+template <int B, bool SGN, typename XT, int MODE>
+__device__ __forceinline__ void mv_rows(const uint32_t *__restrict__ A, int64_t rows,
+                                        int64_t cols, int64_t c0, int ng, const XT *xs,
+                                        const uint32_t *xd, int64_t *__restrict__ y,
+                                        int atomic_out) {
   constexpr int R = rows_per_wave(B);
   constexpr int P = XLayout<XT>::kPitch;
   constexpr int NW = B + 1;  // words fetched per group (one extra for the funnel shift)
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  XT *xs = reinterpret_cast<XT *>(smem_raw);
-
-  const int64_t c0 = (int64_t)blockIdx.y * XLayout<XT>::kPanel;
-  const int64_t pc = cols - c0 < XLayout<XT>::kPanel ? cols - c0 : XLayout<XT>::kPanel;
-  const int ng = (int)((pc + kGroup - 1) / kGroup);
-
-  // stage the x panel, zero-padded to whole groups
-  int small = 1;
-  for (int q = threadIdx.x; q < ng * kGroup; q += kThreads) {
-    const XT v = q < pc ? x[c0 + q] : XT(0);
-    xs[(q >> 5) * P + (q & 31)] = v;
-    small &= (v >= -32768 && v <= 32767);
-  }
-  const bool fast = (B <= 10) && (sizeof(XT) == 4) && __syncthreads_and(small);
-  if (!(B <= 10 && sizeof(XT) == 4)) __syncthreads();
-
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nrb = (rows + kWaves * R - 1) / (kWaves * R);
-
   for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
     const int64_t r0 = rb * (kWaves * R) + (int64_t)wave * R;
     const int nv = rows - r0 >= R ? R : (rows - r0 > 0 ? (int)(rows - r0) : 0);
-    if (nv == 0) continue;  // wave-uniform
+    if (nv == 0) continue;  // wave-uniform; no block barrier inside this loop
 
     const uint32_t *rowp[R];
     int shift[R];
@@ -148,48 +188,81 @@ __global__ __launch_bounds__(kThreads, 2) void k_matvec(const uint32_t *__restri
       rowp[rr] = A + (bit >> 5);
       shift[rr] = (int)(bit & 31u);
     }
+
     uint64_t acc[R];
+    uint32_t dacc[R][5];
 #pragma unroll
-    for (int rr = 0; rr < R; ++rr) acc[rr] = 0;
-
-    for (int j = lane; j < ng; j += 64) {
-      XT xv[kGroup];
-      const XT *xg = xs + j * P;
+    for (int rr = 0; rr < R; ++rr) {
+      acc[rr] = 0;
 #pragma unroll
-      for (int i = 0; i < kGroup; ++i) xv[i] = xg[i];
+      for (int d = 0; d < 5; ++d) dacc[rr][d] = 0;
+    }
 
-      uint32_t w[R][NW];
+    uint32_t wn[R][NW];
+    auto fetch = [&](int j) {
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) {
         if (rr < nv) {
           const uint32_t *gp = rowp[rr] + (uint64_t)j * B;
 #pragma unroll
-          for (int k = 0; k < NW; ++k) w[rr][k] = gp[k];
+          for (int k = 0; k < NW; ++k) wn[rr][k] = gp[k];
         }
       }
+    };
+    if (lane < ng) fetch(lane);
+
+    for (int j = lane; j < ng; j += 64) {
+      uint32_t w[R][NW];
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int k = 0; k < NW; ++k) w[rr][k] = wn[rr][k];
+      if (j + 64 < ng) fetch(j + 64);
+
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) {
         if (rr < nv) {
           const int s = shift[rr];
           if (s != 0) {
 #pragma unroll
-            for (int k = 0; k < B; ++k) w[rr][k] = __builtin_amdgcn_alignbit(w[rr][k + 1], w[rr][k], s);
+            for (int k = 0; k < B; ++k)
+              w[rr][k] = __builtin_amdgcn_alignbit(w[rr][k + 1], w[rr][k], s);
           }
-          if constexpr (B <= 10 && sizeof(XT) == 4) {
-            if (fast) {
-              int32_t part = 0;
+        }
+      }
+
+      if constexpr (MODE == 2) {
+        const uint4 *dg = reinterpret_cast<const uint4 *>(xd + j * kDigitPitch);
+        const uint4 d0 = dg[0], d1 = dg[1], d2 = dg[2], d3 = dg[3];
+        const uint32_t X[16] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w,
+                                d2.x, d2.y, d2.z, d2.w, d3.x, d3.y, d3.z, d3.w};
 #pragma unroll
-              for (int i = 0; i < kGroup; ++i)
-                part = __mul24(group_field24<B, SGN>(w[rr], i), (int32_t)xv[i]) + part;
-              acc[rr] += (uint64_t)(int64_t)part;
-              continue;
+        for (int rr = 0; rr < R; ++rr) {
+          if (rr < nv) {
+            const uint32_t a = w[rr][0];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+              const uint32_t an = (a >> s4) & 0x11111111u;
+#pragma unroll
+              for (int d = 0; d < 4; ++d)
+                dacc[rr][d] = __builtin_amdgcn_udot8(an, X[d * 4 + s4], dacc[rr][d], false);
             }
+            dacc[rr][4] += (uint32_t)__builtin_popcount(a);
           }
-          uint64_t a64 = 0;
+        }
+      } else {
+        XT xv[kGroup];
+        const XT *xg = xs + j * P;
 #pragma unroll
-          for (int i = 0; i < kGroup; ++i)
-            a64 += mul_mod64<B, XT>(group_field<B, SGN>(w[rr], i), xv[i]);
-          acc[rr] += a64;
+        for (int i = 0; i < kGroup; ++i) xv[i] = xg[i];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+          if (rr < nv) {
+            if constexpr (MODE == 1)
+              acc[rr] += group_dot_small<B, SGN>(w[rr], reinterpret_cast<const int32_t *>(xv));
+            else
+              acc[rr] += group_dot_wide<B, SGN, XT>(w[rr], xv);
+          }
         }
       }
     }
@@ -197,16 +270,139 @@ __global__ __launch_bounds__(kThreads, 2) void k_matvec(const uint32_t *__restri
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
       if (rr < nv) {
-        const int64_t v = wave_sum((int64_t)acc[rr]);
+        uint64_t v = acc[rr];
+        if constexpr (MODE == 2) {
+          const int64_t t = (int64_t)dacc[rr][0] + ((int64_t)dacc[rr][1] << 4) +
+                            ((int64_t)dacc[rr][2] << 8) + ((int64_t)dacc[rr][3] << 12) -
+                            ((int64_t)dacc[rr][4] << 15);
+          v = (uint64_t)(SGN ? -t : t);
+        }
+        const int64_t sum = wave_sum((int64_t)v);
         if (lane == 0) {
           if (atomic_out)
-            atomicAdd((unsigned long long *)&y[r0 + rr], (unsigned long long)v);
+            atomicAdd((unsigned long long *)&y[r0 + rr], (unsigned long long)sum);
           else
-            y[r0 + rr] = v;
+            y[r0 + rr] = sum;
         }
       }
     }
   }
+}
+
+template <int B, bool SGN, typename XT>
+__global__ __launch_bounds__(kThreads) void k_matvec(const uint32_t *__restrict__ A,
+                                                     int64_t rows, int64_t cols,
+                                                     const XT *__restrict__ x,
+                                                     int64_t *__restrict__ y, int atomic_out,
+                                                     int x_aligned16) {
+  constexpr int P = XLayout<XT>::kPitch;
+  constexpr bool kSmallPath = (B <= 16) && (sizeof(XT) == 4);
+  constexpr bool kDigits = (B == 1) && (sizeof(XT) == 4);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  XT *xs = reinterpret_cast<XT *>(smem_raw);
+
+  const int64_t c0 = (int64_t)blockIdx.y * XLayout<XT>::kPanel;
+  const int64_t pc = cols - c0 < XLayout<XT>::kPanel ? cols - c0 : XLayout<XT>::kPanel;
+  const int ng = (int)((pc + kGroup - 1) / kGroup);
+
+  // stage the x panel, zero-padded to whole groups: 16-byte chunks, eight
+  // independent loads in flight per lane
+  int small = 1;
+  {
+    constexpr int PER = 16 / sizeof(XT);
+    constexpr int UNR = 8;
+    const int nchunk = ng * kGroup / PER;
+    for (int q0 = threadIdx.x; q0 < nchunk; q0 += kThreads * UNR) {
+      XT v[UNR][PER];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * kThreads;
+        const int e = q * PER;
+        if (q < nchunk && x_aligned16 && e + PER <= pc) {
+          const uint4 t = *reinterpret_cast<const uint4 *>(x + c0 + e);
+          const XT *tv = reinterpret_cast<const XT *>(&t);
+#pragma unroll
+          for (int k = 0; k < PER; ++k) v[u][k] = tv[k];
+        } else {
+#pragma unroll
+          for (int k = 0; k < PER; ++k) v[u][k] = (q < nchunk && e + k < pc) ? x[c0 + e + k] : XT(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * kThreads;
+        if (q < nchunk) {
+          const int e = q * PER;
+          XT *dst = xs + (e >> 5) * P + (e & 31);
+#pragma unroll
+          for (int k = 0; k < PER; ++k) {
+            dst[k] = v[u][k];
+            small &= (v[u][k] >= -32768 && v[u][k] <= 32767);
+          }
+        }
+      }
+    }
+  }
+  bool fast = false;
+  if constexpr (kSmallPath)
+    fast = __syncthreads_and(small);
+  else
+    __syncthreads();
+
+  uint32_t *xd = nullptr;
+  if constexpr (kDigits) {
+    // digit words: X[d][s] nibble q = digit d of x'_{4q+s}, x' = x + 2^15
+    xd = reinterpret_cast<uint32_t *>(xs + ng * P);
+    if (fast) {
+      for (int j = threadIdx.x; j < ng; j += kThreads) {
+        const int32_t *xg = reinterpret_cast<const int32_t *>(xs) + j * P;
+        uint32_t dw[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) dw[t] = 0;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+          const uint32_t u = (uint32_t)(xg[i] + 32768);
+          const int s = i & 3, q = i >> 2;
+#pragma unroll
+          for (int d = 0; d < 4; ++d) dw[d * 4 + s] |= ((u >> (4 * d)) & 15u) << (4 * q);
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) xd[j * kDigitPitch + t] = dw[t];
+      }
+      __syncthreads();
+    }
+  }
+
+  if constexpr (kSmallPath) {
+    if (fast) {
+      if constexpr (kDigits)
+        mv_rows<B, SGN, XT, 2>(A, rows, cols, c0, ng, xs, xd, y, atomic_out);
+      else
+        mv_rows<B, SGN, XT, 1>(A, rows, cols, c0, ng, xs, xd, y, atomic_out);
+      return;
+    }
+  }
+  mv_rows<B, SGN, XT, 0>(A, rows, cols, c0, ng, xs, xd, y, atomic_out);
+}
+
+// Blocks per CU that fit at once (from the occupancy API), cached per
+// instantiation.
+template <int B, bool SGN, typename XT>
+int resident_blocks(size_t lds) {
+  static int cached = 0;
+  if (cached == 0) {
+    int occ = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_matvec<B, SGN, XT>, kThreads, lds) !=
+            hipSuccess ||
+        occ < 1)
+      occ = 1;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    cached = occ * cus;
+  }
+  return cached;
 }
 
 template <int B, bool SGN, typename XT>
@@ -215,23 +411,288 @@ hipError_t launch_one(const uint32_t *w, int64_t rows, int64_t cols, const XT *x
   constexpr int R = rows_per_wave(B);
   const int64_t npanels = (cols + XLayout<XT>::kPanel - 1) / XLayout<XT>::kPanel;
   const int64_t nrb = (rows + kWaves * R - 1) / (kWaves * R);
-  int64_t gx = nrb < 1024 ? nrb : 1024;
+  if (nrb > 0x7fffffffll || npanels > 65535) return hipErrorInvalidValue;
   if (npanels > 1) {
-    const int64_t cap = 2048 / npanels > 1 ? 2048 / npanels : 1;
-    gx = gx < cap ? gx : cap;
     hipError_t e = launch_fill_i64(y, (uint64_t)rows, 0, s);
     if (e != hipSuccess) return e;
   }
   const int64_t pcols = cols < XLayout<XT>::kPanel ? cols : XLayout<XT>::kPanel;
-  const size_t lds = (size_t)((pcols + kGroup - 1) / kGroup) * XLayout<XT>::kPitch * sizeof(XT);
+  const int64_t ngp = (pcols + kGroup - 1) / kGroup;
+  size_t lds = (size_t)ngp * XLayout<XT>::kPitch * sizeof(XT);
+  if (B == 1 && sizeof(XT) == 4) lds += (size_t)ngp * kDigitPitch * sizeof(uint32_t);
+  // persistent blocks: as many as are resident at once, split over the panels
+  int64_t gx = resident_blocks<B, SGN, XT>(lds) / npanels;
+  gx = gx < 1 ? 1 : (gx > nrb ? nrb : gx);
   dim3 grid((unsigned)gx, (unsigned)npanels);
-  k_matvec<B, SGN, XT><<<grid, kThreads, lds, s>>>(w, rows, cols, x, y, npanels > 1 ? 1 : 0);
+  const int al = ((uintptr_t)x % 16) == 0;
+  k_matvec<B, SGN, XT><<<grid, kThreads, lds, s>>>(w, rows, cols, x, y, npanels > 1 ? 1 : 0, al);
+  return hipGetLastError();
+}
+
+// Aligned variant for b <= 16 and int32 x: rows start on 16-byte boundaries
+// (cols % 128 == 0, so r*cols*b/32 is a multiple of 4 words) and every panel
+// holds whole quads of groups.  Lane l owns the four consecutive groups
+// 4l..4l+3 of the panel ("quad" l), i.e. 4b contiguous words that it fetches
+// with b 16-byte loads per row; a wave covers the 8192-column panel in one
+// pass.  RA rows per wave keep enough bytes in flight for the small widths.
+// LDS keeps each quad's x values (128 int32) or digit words (64) contiguous
+// plus a 4-dword skew, so the 16-byte LDS reads of neighbouring lanes fall in
+// distinct banks.
+constexpr int rows_per_wave_al(int b) { return b <= 4 ? 4 : b <= 8 ? 2 : 1; }
+constexpr int kQuadX = 4 * kGroup + 4;  // int32 per quad of groups
+constexpr int kQuadD = 4 * 16 + 4;      // digit words per quad of groups
+
+template <int B, bool SGN>
+__global__ __launch_bounds__(kThreads) void k_matvec_al(const uint32_t *__restrict__ A,
+                                                        int64_t rows, int64_t cols,
+                                                        const int32_t *__restrict__ x,
+                                                        int64_t *__restrict__ y, int atomic_out,
+                                                        int x_aligned16) {
+  constexpr int R = rows_per_wave_al(B);
+  constexpr bool kDigits = (B == 1);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int32_t *xs = reinterpret_cast<int32_t *>(smem_raw);
+
+  const int64_t c0 = (int64_t)blockIdx.y * XLayout<int32_t>::kPanel;
+  const int64_t pc = cols - c0 < XLayout<int32_t>::kPanel ? cols - c0 : XLayout<int32_t>::kPanel;
+  const int ng = (int)(pc / kGroup);  // a multiple of 4
+  const int nq = ng / 4;
+
+  // stage x: column e of the panel goes to xs[e + 4*(e/128)]
+  int small = 1;
+  {
+    constexpr int UNR = 8;
+    const int nchunk = ng * kGroup / 4;
+    for (int q0 = threadIdx.x; q0 < nchunk; q0 += kThreads * UNR) {
+      int4 v[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * kThreads;
+        if (q < nchunk) {
+          if (x_aligned16)
+            v[u] = *reinterpret_cast<const int4 *>(x + c0 + 4 * q);
+          else
+            v[u] = make_int4(x[c0 + 4 * q], x[c0 + 4 * q + 1], x[c0 + 4 * q + 2],
+                             x[c0 + 4 * q + 3]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * kThreads;
+        if (q < nchunk) {
+          const int e = 4 * q;
+          *reinterpret_cast<int4 *>(xs + e + 4 * (e >> 7)) = v[u];
+          small &= (v[u].x >= -32768 && v[u].x <= 32767) & (v[u].y >= -32768 && v[u].y <= 32767) &
+                   (v[u].z >= -32768 && v[u].z <= 32767) & (v[u].w >= -32768 && v[u].w <= 32767);
+        }
+      }
+    }
+  }
+  const bool fast = __syncthreads_and(small);
+
+  // digit words of group j: xd[(j/4)*kQuadD + (j%4)*16 + 4d + s], nibble q =
+  // digit d of x'_{32j + 4q + s}, x' = x + 2^15
+  uint32_t *xd = reinterpret_cast<uint32_t *>(xs + nq * kQuadX);
+  if constexpr (kDigits) {
+    if (fast) {
+      for (int j = threadIdx.x; j < ng; j += kThreads) {
+        const int32_t *xg = xs + (j >> 2) * kQuadX + (j & 3) * kGroup;
+        uint32_t dw[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) dw[t] = 0;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+          const uint32_t u = (uint32_t)(xg[i] + 32768);
+          const int s4 = i & 3, q = i >> 2;
+#pragma unroll
+          for (int d = 0; d < 4; ++d) dw[d * 4 + s4] |= ((u >> (4 * d)) & 15u) << (4 * q);
+        }
+        uint32_t *dst = xd + (j >> 2) * kQuadD + (j & 3) * 16;
+#pragma unroll
+        for (int t = 0; t < 16; t += 4)
+          *reinterpret_cast<uint4 *>(dst + t) = make_uint4(dw[t], dw[t + 1], dw[t + 2], dw[t + 3]);
+      }
+      __syncthreads();
+    }
+  }
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nrb = (rows + kWaves * R - 1) / (kWaves * R);
+  const bool active = lane < nq;
+  const uint64_t row_words = (uint64_t)cols * B / 32;  // a multiple of 4
+  const uint64_t lane_word = (uint64_t)c0 * B / 32 + (uint64_t)lane * 4 * B;
+
+  if (!fast) {
+    // general x: 64-bit products, one row and one group at a time (a loop of
+    // its own, so the int16 path below keeps its registers and occupancy)
+    for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
+      const int64_t r0 = rb * (kWaves * R) + (int64_t)wave * R;
+      const int nv = rows - r0 >= R ? R : (rows - r0 > 0 ? (int)(rows - r0) : 0);
+#pragma unroll 1
+      for (int rr = 0; rr < nv; ++rr) {
+        uint64_t a = 0;
+        if (active) {
+          const uint32_t *src = A + (uint64_t)(r0 + rr) * row_words + lane_word;
+#pragma unroll 1
+          for (int t = 0; t < 4; ++t) {
+            uint32_t w[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) w[k] = src[t * B + k];
+            a += group_dot_wide<B, SGN, int32_t>(w, xs + lane * kQuadX + t * kGroup);
+          }
+        }
+        const int64_t sum = wave_sum((int64_t)a);
+        if (lane == 0) {
+          if (atomic_out)
+            atomicAdd((unsigned long long *)&y[r0 + rr], (unsigned long long)sum);
+          else
+            y[r0 + rr] = sum;
+        }
+      }
+    }
+    return;
+  }
+
+  for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
+    const int64_t r0 = rb * (kWaves * R) + (int64_t)wave * R;
+    const int nv = rows - r0 >= R ? R : (rows - r0 > 0 ? (int)(rows - r0) : 0);
+    if (nv == 0) continue;
+
+    uint32_t w[R][4 * B];
+    if (active) {
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        if (rr < nv) {
+          const uint4 *src =
+              reinterpret_cast<const uint4 *>(A + (uint64_t)(r0 + rr) * row_words + lane_word);
+#pragma unroll
+          for (int u = 0; u < B; ++u) {
+            const uint4 t = src[u];
+            w[rr][4 * u] = t.x;
+            w[rr][4 * u + 1] = t.y;
+            w[rr][4 * u + 2] = t.z;
+            w[rr][4 * u + 3] = t.w;
+          }
+        }
+      }
+    }
+
+    uint64_t acc[R];
+    uint32_t dacc[R][5];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      acc[rr] = 0;
+#pragma unroll
+      for (int d = 0; d < 5; ++d) dacc[rr][d] = 0;
+    }
+
+    if (active) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if constexpr (kDigits) {
+          const uint4 *dg = reinterpret_cast<const uint4 *>(xd + lane * kQuadD + t * 16);
+          const uint4 d0 = dg[0], d1 = dg[1], d2 = dg[2], d3 = dg[3];
+          const uint32_t X[16] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w,
+                                  d2.x, d2.y, d2.z, d2.w, d3.x, d3.y, d3.z, d3.w};
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr) {
+            if (rr < nv) {
+              const uint32_t a = w[rr][t];
+#pragma unroll
+              for (int s4 = 0; s4 < 4; ++s4) {
+                const uint32_t an = (a >> s4) & 0x11111111u;
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+                  dacc[rr][d] = __builtin_amdgcn_udot8(an, X[d * 4 + s4], dacc[rr][d], false);
+              }
+              dacc[rr][4] += (uint32_t)__builtin_popcount(a);
+            }
+          }
+        } else {
+          int32_t xv[kGroup];
+          const int32_t *xg = xs + lane * kQuadX + t * kGroup;
+#pragma unroll
+          for (int i = 0; i < kGroup; ++i) xv[i] = xg[i];
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr)
+            if (rr < nv) acc[rr] += group_dot_small<B, SGN>(&w[rr][t * B], xv);
+        }
+        // keep each group's x values live for that group only
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      if (rr < nv) {
+        uint64_t v = acc[rr];
+        if constexpr (kDigits) {
+          const int64_t tt = (int64_t)dacc[rr][0] + ((int64_t)dacc[rr][1] << 4) +
+                             ((int64_t)dacc[rr][2] << 8) + ((int64_t)dacc[rr][3] << 12) -
+                             ((int64_t)dacc[rr][4] << 15);
+          v = (uint64_t)(SGN ? -tt : tt);
+        }
+        const int64_t sum = wave_sum((int64_t)v);
+        if (lane == 0) {
+          if (atomic_out)
+            atomicAdd((unsigned long long *)&y[r0 + rr], (unsigned long long)sum);
+          else
+            y[r0 + rr] = sum;
+        }
+      }
+    }
+  }
+}
+
+template <int B, bool SGN>
+int resident_blocks_al(size_t lds) {
+  static int cached = 0;
+  if (cached == 0) {
+    int occ = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_matvec_al<B, SGN>, kThreads, lds) !=
+            hipSuccess ||
+        occ < 1)
+      occ = 1;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    cached = occ * cus;
+  }
+  return cached;
+}
+
+template <int B, bool SGN>
+hipError_t launch_aligned(const uint32_t *w, int64_t rows, int64_t cols, const int32_t *x,
+                          int64_t *y, hipStream_t s) {
+  constexpr int R = rows_per_wave_al(B);
+  constexpr int PANEL = XLayout<int32_t>::kPanel;
+  const int64_t npanels = (cols + PANEL - 1) / PANEL;
+  const int64_t nrb = (rows + kWaves * R - 1) / (kWaves * R);
+  if (nrb > 0x7fffffffll || npanels > 65535) return hipErrorInvalidValue;
+  if (npanels > 1) {
+    hipError_t e = launch_fill_i64(y, (uint64_t)rows, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t nqp = (cols < PANEL ? cols : PANEL) / (4 * kGroup);
+  size_t lds = (size_t)nqp * kQuadX * sizeof(int32_t);
+  if (B == 1) lds += (size_t)nqp * kQuadD * sizeof(uint32_t);
+  int64_t gx = resident_blocks_al<B, SGN>(lds) / npanels;
+  gx = gx < 1 ? 1 : (gx > nrb ? nrb : gx);
+  const int al = ((uintptr_t)x % 16) == 0;
+  k_matvec_al<B, SGN><<<dim3((unsigned)gx, (unsigned)npanels), kThreads, lds, s>>>(
+      w, rows, cols, x, y, npanels > 1 ? 1 : 0, al);
   return hipGetLastError();
 }
 
 template <int B>
 hipError_t launch_width(const uint32_t *w, int64_t rows, int64_t cols, int sgn, const void *x,
                         int xdtype, int64_t *y, hipStream_t s) {
+  if constexpr (B <= 16) {
+    if (xdtype == CCM_I32 && cols % 128 == 0 && ((uintptr_t)w % 16) == 0)
+      return sgn ? launch_aligned<B, true>(w, rows, cols, (const int32_t *)x, y, s)
+                 : launch_aligned<B, false>(w, rows, cols, (const int32_t *)x, y, s);
+  }
   if (xdtype == CCM_I32) {
     return sgn ? launch_one<B, true, int32_t>(w, rows, cols, (const int32_t *)x, y, s)
                : launch_one<B, false, int32_t>(w, rows, cols, (const int32_t *)x, y, s);
@@ -239,9 +700,6 @@ hipError_t launch_width(const uint32_t *w, int64_t rows, int64_t cols, int sgn, 
   return sgn ? launch_one<B, true, int64_t>(w, rows, cols, (const int64_t *)x, y, s)
              : launch_one<B, false, int64_t>(w, rows, cols, (const int64_t *)x, y, s);
 }
-
-using LaunchFn = hipError_t (*)(const uint32_t *, int64_t, int64_t, int, const void *, int,
-                                int64_t *, hipStream_t);
 
 }  // namespace mv
 }  // namespace ccm

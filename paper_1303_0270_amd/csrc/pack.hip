@@ -9,6 +9,7 @@
 // runtime-width reader/writer branch-uniform.  Dense operands are staged
 // through LDS so that HBM reads and writes stay coalesced.
 #include "ccm_internal.hpp"
+#include "group_codec.hpp"
 
 namespace ccm {
 namespace {
@@ -26,40 +27,92 @@ __global__ void k_range_init(RangeSlot *slot) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_range_dense(const T *__restrict__ d, uint64_t n,
-                                                     RangeSlot *slot) {
+                                                     RangeSlot *slot, int aligned16) {
+  constexpr int PER = 16 / sizeof(T);  // elements per 16-byte load
+  constexpr int UNR = 4;
   int64_t lo = INT64_MAX, hi = INT64_MIN;
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-    const int64_t v = (int64_t)d[e];
-    lo = v < lo ? v : lo;
-    hi = v > hi ? v : hi;
+  uint64_t done = 0;
+  if (aligned16) {
+    const uint64_t n16 = n / PER;
+    const uint4 *v = reinterpret_cast<const uint4 *>(d);
+    uint64_t i = tid;
+    for (; i + (UNR - 1) * stride < n16; i += UNR * stride) {
+      uint4 r[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) r[u] = v[i + u * stride];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const T *t = reinterpret_cast<const T *>(&r[u]);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int64_t x = (int64_t)t[q];
+          lo = x < lo ? x : lo;
+          hi = x > hi ? x : hi;
+        }
+      }
+    }
+    for (; i < n16; i += stride) {
+      const uint4 r = v[i];
+      const T *t = reinterpret_cast<const T *>(&r);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int64_t x = (int64_t)t[q];
+        lo = x < lo ? x : lo;
+        hi = x > hi ? x : hi;
+      }
+    }
+    done = n16 * PER;
+  }
+  for (uint64_t e = done + tid; e < n; e += stride) {
+    const int64_t x = (int64_t)d[e];
+    lo = x < lo ? x : lo;
+    hi = x > hi ? x : hi;
   }
   block_range_commit(lo, hi, 0, slot);
 }
 
 // dense (n values) -> packed words [0, cap32): lane g writes words [g*b, g*b+b).
+// The block's 32*128 elements are first staged through LDS with 16-byte
+// loads, all issued before any is consumed.
 template <typename T>
 __global__ __launch_bounds__(kTileThreads) void k_compress(const T *__restrict__ d, uint64_t n,
                                                            int bits, uint32_t *__restrict__ out,
-                                                           uint64_t cap32, uint64_t ngroups) {
+                                                           uint64_t cap32, uint64_t ngroups,
+                                                           int aligned16) {
+  constexpr int PER = 16 / sizeof(T);
+  constexpr int NLOAD = kTileElems / (kTileThreads * PER);
   __shared__ T tile[kTileThreads * kPad];
   const uint64_t g0 = (uint64_t)blockIdx.x * kTileThreads;
   const uint64_t e0 = g0 * kGroup;
-  if (e0 < n) {
+  if (aligned16 && e0 + kTileElems <= n) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(d + e0);
+    uint4 r[NLOAD];
+#pragma unroll
+    for (int j = 0; j < NLOAD; ++j) r[j] = src[threadIdx.x + j * kTileThreads];
+#pragma unroll
+    for (int j = 0; j < NLOAD; ++j) {
+      const int q = (threadIdx.x + j * kTileThreads) * PER;
+      const T *t = reinterpret_cast<const T *>(&r[j]);
+#pragma unroll
+      for (int u = 0; u < PER; ++u) tile[q + u + (q >> 5)] = t[u];
+    }
+  } else {
     for (int q = threadIdx.x; q < kTileElems; q += kTileThreads) {
       const uint64_t e = e0 + q;
       tile[q + (q >> 5)] = e < n ? d[e] : T(0);
     }
-  } else {
-    for (int q = threadIdx.x; q < kTileElems; q += kTileThreads) tile[q + (q >> 5)] = T(0);
   }
   __syncthreads();
   const uint64_t g = g0 + threadIdx.x;
   if (g >= ngroups) return;
-  BitWriter w(out, g * (uint64_t)bits, cap32);
-  const T *src = tile + threadIdx.x * kPad;
-#pragma unroll 4
-  for (int i = 0; i < kGroup; ++i) w.field((uint64_t)(int64_t)src[i], bits);
+  int64_t v[kGroup];
+  const T *row = tile + threadIdx.x * kPad;
+#pragma unroll
+  for (int i = 0; i < kGroup; ++i) v[i] = (int64_t)row[i];
+  const uint64_t w0 = g * (uint64_t)bits;
+  codec::encode_rt(v, bits, out + w0, cap32 - w0);
 }
 
 // packed -> dense int64 (n values)
@@ -71,13 +124,11 @@ __global__ __launch_bounds__(kTileThreads) void k_decompress(const uint32_t *__r
   const uint64_t g = g0 + threadIdx.x;
   const uint64_t ngroups = (n + kGroup - 1) / kGroup;
   if (g < ngroups) {
-    BitReader r(wds + g * (uint64_t)bits);
+    int64_t v[kGroup];
+    codec::decode_rt(wds + g * (uint64_t)bits, bits, sgn, v);
     int64_t *dst = tile + threadIdx.x * kPad;
-#pragma unroll 4
-    for (int i = 0; i < kGroup; ++i) {
-      const uint64_t u = r.field(bits);
-      dst[i] = sgn ? sext64(u, bits) : (int64_t)u;
-    }
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) dst[i] = v[i];
   }
   __syncthreads();
   const uint64_t e0 = g0 * kGroup;
@@ -128,20 +179,14 @@ __global__ __launch_bounds__(256) void k_ewise_range(int op, PackedOperand a, Pa
   const uint64_t ngroups = (n + kGroup - 1) / kGroup;
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g < ngroups) {
-    BitReader ra(a.w + g * (uint64_t)a.bits);
-    BitReader rb(op == EW_ADD ? b.w + g * (uint64_t)b.bits : a.w);
+    int64_t va[kGroup], vb[kGroup];
+    codec::decode_rt(a.w + g * (uint64_t)a.bits, a.bits, a.sgn, va);
+    if (op == EW_ADD) codec::decode_rt(b.w + g * (uint64_t)b.bits, b.bits, b.sgn, vb);
     const uint64_t e0 = g * kGroup;
-#pragma unroll 2
+#pragma unroll
     for (int i = 0; i < kGroup; ++i) {
-      const uint64_t ua = ra.field(a.bits);
-      const int64_t va = a.sgn ? sext64(ua, a.bits) : (int64_t)ua;
-      int64_t vb = 0;
-      if (op == EW_ADD) {
-        const uint64_t ub = rb.field(b.bits);
-        vb = b.sgn ? sext64(ub, b.bits) : (int64_t)ub;
-      }
       if (e0 + i < n) {
-        const int64_t c = ewise_value(op, va, vb, scalar, &ovf);
+        const int64_t c = ewise_value(op, va[i], op == EW_ADD ? vb[i] : 0, scalar, &ovf);
         lo = c < lo ? c : lo;
         hi = c > hi ? c : hi;
       }
@@ -158,28 +203,23 @@ __global__ __launch_bounds__(256) void k_ewise_pack(int op, PackedOperand a, Pac
                                                     uint64_t ngroups_out) {
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ngroups_out) return;
-  BitWriter w(out, g * (uint64_t)out_bits, cap32);
+  const uint64_t w0 = g * (uint64_t)out_bits;
   const uint64_t ngroups_in = (n + kGroup - 1) / kGroup;
+  int64_t vc[kGroup];
   if (g >= ngroups_in) {
-    for (int i = 0; i < out_bits; ++i) w.put(0u, 32);
-    return;
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) vc[i] = 0;
+  } else {
+    int64_t va[kGroup], vb[kGroup];
+    codec::decode_rt(a.w + g * (uint64_t)a.bits, a.bits, a.sgn, va);
+    if (op == EW_ADD) codec::decode_rt(b.w + g * (uint64_t)b.bits, b.bits, b.sgn, vb);
+    const uint64_t e0 = g * kGroup;
+    int ovf = 0;
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i)
+      vc[i] = e0 + i < n ? ewise_value(op, va[i], op == EW_ADD ? vb[i] : 0, scalar, &ovf) : 0;
   }
-  BitReader ra(a.w + g * (uint64_t)a.bits);
-  BitReader rb(op == EW_ADD ? b.w + g * (uint64_t)b.bits : a.w);
-  const uint64_t e0 = g * kGroup;
-  int ovf = 0;
-#pragma unroll 2
-  for (int i = 0; i < kGroup; ++i) {
-    const uint64_t ua = ra.field(a.bits);
-    const int64_t va = a.sgn ? sext64(ua, a.bits) : (int64_t)ua;
-    int64_t vb = 0;
-    if (op == EW_ADD) {
-      const uint64_t ub = rb.field(b.bits);
-      vb = b.sgn ? sext64(ub, b.bits) : (int64_t)ub;
-    }
-    const int64_t c = e0 + i < n ? ewise_value(op, va, vb, scalar, &ovf) : 0;
-    w.field((uint64_t)c, out_bits);
-  }
+  codec::encode_rt(vc, out_bits, out + w0, cap32 - w0);
 }
 
 __global__ void k_fill_i64(int64_t *p, uint64_t n, int64_t v) {
@@ -217,14 +257,15 @@ __global__ __launch_bounds__(256) void k_gen_pack(uint64_t n, int64_t lo, uint64
                                                   uint64_t ngroups_out) {
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ngroups_out) return;
-  BitWriter w(out, g * (uint64_t)bits, cap32);
   const uint64_t e0 = g * kGroup;
-#pragma unroll 4
+  int64_t v[kGroup];
+#pragma unroll
   for (int i = 0; i < kGroup; ++i) {
     const uint64_t e = e0 + i;
-    const int64_t v = e < n ? uniform_at(seed, sid, e, lo, span) : 0;
-    w.field((uint64_t)v, bits);
+    v[i] = e < n ? uniform_at(seed, sid, e, lo, span) : 0;
   }
+  const uint64_t w0 = g * (uint64_t)bits;
+  codec::encode_rt(v, bits, out + w0, cap32 - w0);
 }
 
 inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap = 1u << 20) {
@@ -244,10 +285,11 @@ hipError_t launch_range_init(RangeSlot *slot, hipStream_t s) {
 hipError_t launch_range_dense(const void *dense, int dtype, uint64_t n, RangeSlot *slot,
                               hipStream_t s) {
   const unsigned grid = grid_for(n, 256 * 16, 4096);
+  const int al = ((uintptr_t)dense % 16) == 0;
   if (dtype == CCM_I64)
-    k_range_dense<int64_t><<<grid, 256, 0, s>>>((const int64_t *)dense, n, slot);
+    k_range_dense<int64_t><<<grid, 256, 0, s>>>((const int64_t *)dense, n, slot, al);
   else
-    k_range_dense<int32_t><<<grid, 256, 0, s>>>((const int32_t *)dense, n, slot);
+    k_range_dense<int32_t><<<grid, 256, 0, s>>>((const int32_t *)dense, n, slot, al);
   return hipGetLastError();
 }
 
@@ -255,12 +297,13 @@ hipError_t launch_compress(const void *dense, int dtype, uint64_t n, int bits, u
                            uint64_t cap32, hipStream_t s) {
   const uint64_t ngroups = (cap32 + bits - 1) / bits;
   const unsigned grid = grid_for(ngroups, kTileThreads, 0x7fffffffu);
+  const int al = ((uintptr_t)dense % 16) == 0;
   if (dtype == CCM_I64)
     k_compress<int64_t><<<grid, kTileThreads, 0, s>>>((const int64_t *)dense, n, bits, out,
-                                                       cap32, ngroups);
+                                                       cap32, ngroups, al);
   else
     k_compress<int32_t><<<grid, kTileThreads, 0, s>>>((const int32_t *)dense, n, bits, out,
-                                                       cap32, ngroups);
+                                                       cap32, ngroups, al);
   return hipGetLastError();
 }
 

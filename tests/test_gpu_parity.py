@@ -158,6 +158,9 @@ def test_scale_matches_oracle(b, signed):
 
 
 MV_SHAPES = [(1, 1), (1, 40), (17, 31), (33, 96), (100, 257), (3, 9000), (70, 16500)]
+# cols % 128 == 0: rows start on 16-byte boundaries (the aligned b <= 16 path);
+# 8320 = 8192 + 128 spans two column panels
+MV_ALIGNED = [(5, 128), (37, 256), (130, 1024), (9, 8320)]
 
 
 @pytest.mark.parametrize("b", list(range(1, 65)))
@@ -166,6 +169,7 @@ def test_matvec_all_widths(b):
     rng = np.random.default_rng(1000 + b)
     for signed in ((False, True) if b < 64 else (True,)):
         shapes = MV_SHAPES if b in (1, 3, 7, 10, 12, 17, 31, 32, 33, 64) else MV_SHAPES[:5]
+        shapes = shapes + (MV_ALIGNED if b <= 16 else MV_ALIGNED[:1])
         for rows, cols in shapes:
             if signed and b == 1 and rows * cols < 2:
                 continue
