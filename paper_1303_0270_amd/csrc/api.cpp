@@ -385,35 +385,51 @@ int ccm_matvec(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, voi
   return CCM_OK;
 }
 
+// Scratch layout of a matmul: dense C (int32 when the bound allows, else
+// int64), rounded up to 256 bytes, then -- on the int8 MFMA path -- B
+// re-packed column-major.  The MFMA path is taken when both operands' values
+// fit int8 and the bound K*max|A|*max|B| < 2^31 keeps int32 sums exact.
+struct MatmulPlan {
+  int out32, use_i8;
+  uint64_t c_bytes, total;
+};
+
+static bool matmul_layout(const ccm_desc *a, const ccm_desc *b, MatmulPlan *p) {
+  unsigned __int128 bound = 0;
+  if (!matmul_bound(a, b, &bound)) return false;
+  p->out32 = bound < ((unsigned __int128)1 << 31) ? 1 : 0;
+  p->use_i8 = (p->out32 && fits_i8(a) && fits_i8(b)) ? 1 : 0;
+  const uint64_t c = (p->out32 ? 4u : 8u) * (uint64_t)a->rows * (uint64_t)b->cols;
+  p->c_bytes = (c + 255u) / 256u * 256u;
+  p->total = p->c_bytes + (p->use_i8 ? 4u * ccm::matmul_bt_words32(b->rows, b->cols, b->bits) : 0u);
+  return true;
+}
+
 uint64_t ccm_matmul_scratch_bytes(const ccm_desc *a, const ccm_desc *b) {
   if (check_desc(a, false) != CCM_OK || check_desc(b, false) != CCM_OK) return 0;
   if (a->cols != b->rows) return 0;
-  unsigned __int128 bound = 0;
-  if (!matmul_bound(a, b, &bound)) return 0;
-  const uint64_t per = bound < ((unsigned __int128)1 << 31) ? 4u : 8u;
-  return per * (uint64_t)a->rows * (uint64_t)b->cols;
+  MatmulPlan p;
+  if (!matmul_layout(a, b, &p)) return 0;
+  return p.total;
 }
 
 static int matmul_common(const ccm_desc *a, const ccm_desc *b, uint64_t scratch_bytes,
-                         const void *scratch, int *out32) {
+                         const void *scratch, MatmulPlan *p) {
   int rc = check_desc(a, true);
   if (rc == CCM_OK) rc = check_desc(b, true);
   if (rc != CCM_OK) return rc;
   if (a->cols != b->rows) return CCM_E_SHAPE;
   if (!shape_ok(a->rows, b->cols)) return CCM_E_INVAL;
-  unsigned __int128 bound = 0;
-  if (!matmul_bound(a, b, &bound)) return CCM_E_OVERFLOW;
+  if (!matmul_layout(a, b, p)) return CCM_E_OVERFLOW;
   if (!scratch) return CCM_E_INVAL;
-  *out32 = bound < ((unsigned __int128)1 << 31) ? 1 : 0;
-  const uint64_t need = (*out32 ? 4u : 8u) * (uint64_t)a->rows * (uint64_t)b->cols;
-  if (scratch_bytes < need) return CCM_E_NOMEM;
+  if (scratch_bytes < p->total) return CCM_E_NOMEM;
   return CCM_OK;
 }
 
 int ccm_matmul_plan(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *scratch,
                     uint64_t scratch_bytes, void *stream) {
-  int out32 = 0;
-  int rc = matmul_common(a, b, scratch_bytes, scratch, &out32);
+  MatmulPlan mp;
+  int rc = matmul_common(a, b, scratch_bytes, scratch, &mp);
   if (rc != CCM_OK) return rc;
   if (!out) return CCM_E_INVAL;
   hipStream_t s = (hipStream_t)stream;
@@ -422,10 +438,9 @@ int ccm_matmul_plan(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *s
   rc = device_ctx(&c);
   if (rc != CCM_OK) return rc;
   CCM_HIP(ccm::launch_range_init(c->slot, s));
-  const int use_i8 = fits_i8(a) && fits_i8(b);
   CCM_HIP(ccm::launch_matmul((const uint32_t *)a->payload, a->bits, a->is_signed,
                              (const uint32_t *)b->payload, b->bits, b->is_signed, a->rows,
-                             a->cols, b->cols, use_i8, out32, scratch, c->slot, s));
+                             a->cols, b->cols, mp.use_i8, mp.out32, scratch, c->slot, s));
   ccm::RangeSlot r;
   rc = read_slot(c, s, &r);
   if (rc != CCM_OK) return rc;
@@ -434,13 +449,13 @@ int ccm_matmul_plan(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *s
 
 int ccm_matmul(const ccm_desc *a, const ccm_desc *b, const ccm_desc *out, const void *scratch,
                uint64_t scratch_bytes, void *stream) {
-  int out32 = 0;
-  int rc = matmul_common(a, b, scratch_bytes, scratch, &out32);
+  MatmulPlan mp;
+  int rc = matmul_common(a, b, scratch_bytes, scratch, &mp);
   if (rc != CCM_OK) return rc;
   rc = check_result(out, a->rows, b->cols);
   if (rc != CCM_OK) return rc;
   const uint64_t n = nelem(out);
-  CCM_HIP(ccm::launch_compress(scratch, out32 ? CCM_I32 : CCM_I64, n, out->bits,
+  CCM_HIP(ccm::launch_compress(scratch, mp.out32 ? CCM_I32 : CCM_I64, n, out->bits,
                                (uint32_t *)out->payload, ccm::cap_words32(n, out->bits),
                                (hipStream_t)stream));
   return CCM_OK;

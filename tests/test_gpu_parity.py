@@ -184,13 +184,17 @@ def test_matvec_all_widths(b):
                 assert np.array_equal(y, oracle.matvec(pa, x)), (b, signed, rows, cols, dt)
 
 
+# operands whose values fit int8 take the MFMA path (unsigned b <= 7, signed b <= 8)
 @pytest.mark.parametrize("ba,sa,bb,sb", [(10, False, 10, False), (6, False, 4, True),
                                          (1, False, 1, True), (20, True, 17, False),
-                                         (33, True, 20, False), (8, False, 8, True)])
+                                         (33, True, 20, False), (8, False, 8, True),
+                                         (7, False, 8, True), (8, True, 3, False),
+                                         (2, True, 5, True)])
 def test_matmul_matches_oracle(ba, sa, bb, sb):
     c = ccm()
     rng = np.random.default_rng(ba * 7 + bb)
-    for M, K, N in ((1, 1, 1), (5, 7, 3), (65, 33, 70), (130, 100, 129)):
+    for M, K, N in ((1, 1, 1), (5, 7, 3), (65, 33, 70), (130, 100, 129), (257, 300, 131),
+                    (128, 64, 128)):
         A = rand_matrix(rng, M, K, ba, sa)
         B = rand_matrix(rng, K, N, bb, sb)
         pa, pb = oracle.compress(A), oracle.compress(B)
