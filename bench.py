@@ -297,7 +297,7 @@ def main():
     log("dense int32 and read probe done")
     if not args.no_extras and not args.profile:
         from bench_extras import run_extras
-        result["extras"] = run_extras(torch, ccm)
+        result["extras"] = run_extras(torch, ccm, log)
 
     if not args.no_cpu_baseline and not args.profile:
         log("extras done; timing the oracle")

@@ -37,10 +37,119 @@ def gemm(torch, ccm, n=8192, reps=3):
             "frac_i8_mfma": round(ops / tp / 1e12 / I8_PEAK_TOPS, 4)}
 
 
-def run_extras(torch, ccm):
+def batched(torch, ccm, reps=30):
+    """4096 matrices (32..2048 x 32..2048, widths 1..24): one captured graph
+    launch of the persistent batched kernel vs 4096 per-call launches."""
+    import numpy as np
+    items = W.batched()
+    mats = [ccm.generate(it.a.rows, it.a.cols, it.a.lo, it.a.hi, it.a.seed, it.a.stream)
+            for it in items]
+    xs, ys = [], []
+    for it in items:
+        x = torch.empty(it.x.n, dtype=torch.int32, device="cuda")
+        ccm.fill_uniform(x, it.x.lo, it.x.hi, it.x.seed, it.x.stream)
+        xs.append(x)
+        ys.append(torch.empty(it.a.rows, dtype=torch.int64, device="cuda"))
+    batch = ccm.Batch(mats)
+    batch.set_io(xs, ys)
+    info = batch.info()
+    for _ in range(3):
+        batch.run(use_graph=True)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        batch.run(use_graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        lat.append(e0.elapsed_time(e1) * 1e-3)
+    # the plain per-call path: one ccm_matvec launch per matrix
+    for m, x, y in zip(mats[:64], xs[:64], ys[:64]):
+        ccm.matvec(m, x, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record()
+    for m, x, y in zip(mats, xs, ys):
+        ccm.matvec(m, x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    per_call_gpu = e0.elapsed_time(e1) * 1e-3
+    nbytes = info["packed_bytes"]
+    p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+    out = {"workload": f"{len(items)} matrices, rows/cols 32..2048, widths 1..24, int32 x",
+           "packed_bytes": nbytes, "items": info["items"],
+           "graph_launch_p50_ms": round(p50 * 1e3, 3), "graph_launch_p99_ms": round(p99 * 1e3, 3),
+           "graph_gbs": round(nbytes / p50 / 1e9, 1),
+           "graph_frac_hbm": round(nbytes / p50 / 1e9 / 8000.0, 4),
+           "per_call_wall_ms": round(wall * 1e3, 3), "per_call_gpu_ms": round(per_call_gpu * 1e3, 3),
+           "per_call_gbs": round(nbytes / wall / 1e9, 1),
+           "speedup_vs_per_call": round(wall / p50, 2)}
+    batch.close()
+    return out
+
+
+def serving(torch, ccm, target_bytes=200e9, count=2000, log=None):
+    """Resident pool (~200 GB packed, 1e4..1e9 elements, widths 1..20),
+    requests 90% matvec / 10% small matmul: saturation throughput from a
+    burst, then Poisson arrivals at 50/80/95% of it."""
+    from paper_1303_0270_amd import serve
+    specs = W.serving_pool(target_bytes)
+    t0 = time.perf_counter()
+    pool = serve.make_pool(specs)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    packed = sum(64 + 8 * m.words for m in pool)
+    as_int32 = sum(4 * m.rows * m.cols for m in pool)
+    if log:
+        log(f"pool: {len(pool)} matrices, {packed / 1e9:.1f} GB packed, generated in {gen_s:.1f} s")
+    free, total = torch.cuda.mem_get_info()
+    arena = max(1 << 30, free - (16 << 30))
+    srv = serve.Server(pool, arena_bytes=arena, streams=4, max_inflight=512, max_batch=256)
+    seed = W.seed_for(5, 2)
+    warm = serve.make_requests(pool, 200, None, seed, first_rid=10_000_000)
+    srv.run(warm)
+    burst = serve.make_requests(pool, count, None, seed)
+    sat = srv.run(burst)
+    del burst
+    out = {"pool_matrices": len(pool), "pool_packed_gb": round(packed / 1e9, 2),
+           "pool_as_int32_gb": round(as_int32 / 1e9, 2), "arena_gb": round(arena / 1e9, 1),
+           "saturation": sat, "load": {}}
+    for frac in (0.5, 0.8, 0.95):
+        qps = frac * sat["throughput_rps"]
+        reqs = serve.make_requests(pool, count, qps, seed + int(frac * 100),
+                                   first_rid=int(frac * 1_000_000))
+        st = srv.run(reqs)
+        st["offered_qps"] = round(qps, 1)
+        out["load"][f"{int(frac * 100)}%"] = st
+        if log:
+            log(f"serving at {frac:.0%}: p50 {st['p50_ms']} ms p99 {st['p99_ms']} ms")
+        del reqs
+    srv.close()
+    del pool
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_extras(torch, ccm, log=None):
     out = {}
     t0 = time.perf_counter()
     out["gemm"] = gemm(torch, ccm)
     out["gemm"]["wall_s"] = round(time.perf_counter() - t0, 2)
     torch.cuda.empty_cache()
+    if log:
+        log("gemm done")
+    t0 = time.perf_counter()
+    out["batched"] = batched(torch, ccm)
+    out["batched"]["wall_s"] = round(time.perf_counter() - t0, 2)
+    torch.cuda.empty_cache()
+    if log:
+        log("batched done")
+    t0 = time.perf_counter()
+    out["serving"] = serving(torch, ccm, log=log)
+    out["serving"]["wall_s"] = round(time.perf_counter() - t0, 2)
+    if log:
+        log("serving done")
     return out

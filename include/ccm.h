@@ -210,6 +210,24 @@ int ccm_batch_info(const ccm_batch *b, int64_t *items, uint64_t *packed_bytes,
 
 int ccm_batch_destroy(ccm_batch *b);
 
+/* Dynamic batches (the matrices change on every launch, as in a serving
+ * loop).  A workspace holds `slots` sets of pinned host staging and device
+ * tables for up to max_mats matrices and max_items work items; launches use
+ * the slots in turn, and a slot is reused only after its previous launch has
+ * completed (the call waits for that if needed).  Library-owned memory,
+ * released by ccm_batch_ws_destroy. */
+typedef struct ccm_batch_ws ccm_batch_ws;
+
+int ccm_batch_ws_create(int32_t max_mats, int64_t max_items, int32_t slots,
+                        const char *tune_json, ccm_batch_ws **out);
+int ccm_batch_ws_destroy(ccm_batch_ws *w);
+
+/* y_t = A_t x_t for the n matrices given (x int32), planned on the host and
+ * run as one persistent launch on `stream`.  CCM_E_NOMEM if n or the work
+ * list exceeds the workspace.  Async (one host-to-device table copy). */
+int ccm_batch_matvec_dyn(ccm_batch_ws *w, const ccm_desc *as, const void *const *xs,
+                         int64_t *const *ys, int32_t n, void *stream);
+
 /* ---- seeded synthetic data (SplitMix64, counter-based) ------------------ */
 
 /* dense[t] = draw number (stream_id << 40) + start + t of SplitMix64 from

@@ -16,7 +16,7 @@ from ._lib import (E_INVAL, E_NOMEM, E_OVERFLOW, E_RANGE, E_SHAPE, E_UNSUPPORTED
 
 __all__ = ["CMatrix", "CcmError", "compress", "decompress", "get", "gather", "add", "scale",
            "matvec", "matmul", "matmul_plan", "matmul_pack", "fill_uniform", "generate", "from_serialized", "words",
-           "packed_bytes", "payload_capacity", "width", "Batch"]
+           "packed_bytes", "payload_capacity", "width", "Batch", "DynBatch"]
 
 
 def _stream(stream=None) -> ctypes.c_void_p:
@@ -254,4 +254,4 @@ def generate(rows: int, cols: int, lo: int, hi: int, seed: int, stream_id: int =
     return m
 
 
-from .batch import Batch  # noqa: E402
+from .batch import Batch, DynBatch  # noqa: E402

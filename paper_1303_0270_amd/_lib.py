@@ -69,6 +69,11 @@ SIGNATURES = {
     "ccm_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_u64),
                                       ctypes.POINTER(_i32)]),
     "ccm_batch_destroy": (ctypes.c_int, [_vp]),
+    "ccm_batch_ws_create": (ctypes.c_int, [_i32, _i64, _i32, ctypes.c_char_p,
+                                           ctypes.POINTER(_vp)]),
+    "ccm_batch_ws_destroy": (ctypes.c_int, [_vp]),
+    "ccm_batch_matvec_dyn": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                            _i32, _vp]),
     "ccm_fill_uniform": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i64, _u64, _u64, _u64, _vp]),
     "ccm_generate_plan": (ctypes.c_int, [_i64, _i64, _i64, _i64, _u64, _u64, _dp, _vp]),
     "ccm_generate": (ctypes.c_int, [_dp, _i64, _i64, _u64, _u64, _vp]),

@@ -1,0 +1,236 @@
+"""Serving loop over a pool of compressed matrices resident in HBM.
+
+Requests (matvec with an int32 x, or matmul with a small compressed B) arrive
+over time.  The loop runs continuous batching on a few HIP streams:
+
+* admission: a request is admitted when a slot is free (at most `max_inflight`
+  requests admitted and not finished) and its memory footprint (x and y, or B,
+  the result at its bound width and the matmul scratch) fits in the arena left
+  after the pool;
+* every admitted matvec not yet launched goes into the next batched launch
+  (one persistent kernel over all of them, ccm_batch_matvec_dyn) on the next
+  free stream -- matrices wider than the batched kernel's x staging take the
+  single-matrix kernel in the same launch; a matmul runs on a free stream of
+  its own;
+* launches on different streams overlap on the device; requests that arrive
+  while others run are admitted as slots and memory free up and join the next
+  launch;
+* completion is read from a GPU event per launch; latency is completion time
+  minus arrival time, both on the run's clock (the GPU timestamps are taken
+  relative to an event recorded when the run starts).
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import (CMatrix, generate, matmul_pack, matmul_plan, matmul_scratch_bytes, matvec,
+               payload_capacity)
+from . import width as width_rule
+from .batch import BATCH_MAX_COLS, DynBatch
+
+
+@dataclass
+class Request:
+    rid: int
+    kind: str  # "mv" or "mm"
+    mat: int  # index into the pool
+    arrival: float  # seconds after the start of the run
+    x: torch.Tensor | None = None  # matvec input (int32)
+    b: CMatrix | None = None  # matmul right operand
+    footprint: int = 0
+    y: torch.Tensor | None = None  # matvec result
+    c: CMatrix | None = None  # matmul result
+    done: float = math.nan  # completion, seconds after the start of the run
+    launch: int = -1  # id of the launch that served it
+
+
+@dataclass
+class _Launch:
+    lid: int
+    stream_idx: int
+    event: torch.cuda.Event
+    requests: list
+    scratch: list = field(default_factory=list)
+
+
+def request_footprint(req: Request, pool) -> int:
+    """Device bytes a request holds while in flight."""
+    a = pool[req.mat]
+    if req.kind == "mv":
+        return 4 * a.cols + 8 * a.rows
+    b = req.b
+    bound = a.cols * max(abs(a.vmin), abs(a.vmax)) * max(abs(b.vmin), abs(b.vmax))
+    cb, _ = width_rule(-bound, bound) if bound < (1 << 63) else (64, True)
+    return (payload_capacity(b.rows, b.cols, b.bits) + payload_capacity(a.rows, b.cols, cb) +
+            matmul_scratch_bytes(a, b))
+
+
+class Server:
+    def __init__(self, pool, arena_bytes: int, streams: int = 4, max_inflight: int = 256,
+                 max_batch: int = 512):
+        self.pool = pool
+        self.arena = int(arena_bytes)
+        self.max_inflight = max_inflight
+        self.max_batch = max_batch
+        self.streams = [torch.cuda.Stream() for _ in range(streams)]
+        self.dyn = [DynBatch(max_mats=max_batch, max_items=1 << 17, slots=4)
+                    for _ in range(streams)]
+
+    def close(self):
+        for d in self.dyn:
+            d.close()
+
+    def run(self, requests, poll_sleep: float = 0.0):
+        """Serves `requests` (sorted by arrival); returns summary statistics.
+        Each request's result is left in req.y / req.c."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        for r in reqs:
+            r.footprint = request_footprint(r, self.pool)
+            if r.footprint > self.arena:
+                raise ValueError(f"request {r.rid} needs {r.footprint} bytes, arena {self.arena}")
+        waiting = collections.deque()
+        pending_mv, pending_mm = [], []
+        inflight: list[_Launch] = []
+        free_streams = list(range(len(self.streams)))
+        used_bytes = 0
+        admitted = 0
+        lid = 0
+        nxt = 0
+        n = len(reqs)
+        finished = 0
+        launches = []
+        torch.cuda.synchronize()
+        start_evt = torch.cuda.Event(enable_timing=True)
+        start_evt.record()
+        t0 = time.perf_counter()
+        while finished < n:
+            now = time.perf_counter() - t0
+            while nxt < n and reqs[nxt].arrival <= now:
+                waiting.append(reqs[nxt])
+                nxt += 1
+            # completions
+            still = []
+            for L in inflight:
+                if L.event.query():
+                    t_done = start_evt.elapsed_time(L.event) * 1e-3
+                    for r in L.requests:
+                        r.done = t_done
+                        used_bytes -= r.footprint
+                        admitted -= 1
+                        finished += 1
+                    free_streams.append(L.stream_idx)
+                    L.scratch.clear()
+                else:
+                    still.append(L)
+            inflight = still
+            # admission
+            while waiting and admitted < self.max_inflight and \
+                    used_bytes + waiting[0].footprint <= self.arena:
+                r = waiting.popleft()
+                used_bytes += r.footprint
+                admitted += 1
+                (pending_mv if r.kind == "mv" else pending_mm).append(r)
+            # launches
+            while free_streams and (pending_mv or pending_mm):
+                si = free_streams.pop(0)
+                stream = self.streams[si]
+                evt = torch.cuda.Event(enable_timing=True)
+                L = _Launch(lid, si, evt, [])
+                with torch.cuda.stream(stream):
+                    if pending_mm and (not pending_mv or len(pending_mm) * 8 >= len(pending_mv)):
+                        r = pending_mm.pop(0)
+                        a = self.pool[r.mat]
+                        c, scratch = matmul_plan(a, r.b, stream=stream)
+                        matmul_pack(a, r.b, c, scratch, stream=stream)
+                        r.c = c
+                        L.requests.append(r)
+                        L.scratch.append(scratch)
+                    else:
+                        group = pending_mv[: self.max_batch]
+                        del pending_mv[: len(group)]
+                        narrow = []
+                        for r in group:
+                            a = self.pool[r.mat]
+                            r.y = torch.empty(a.rows, dtype=torch.int64, device="cuda")
+                            if a.cols <= BATCH_MAX_COLS:
+                                narrow.append(r)
+                            else:
+                                matvec(a, r.x, r.y, stream=stream)
+                        if narrow:
+                            self.dyn[si].matvec([self.pool[r.mat] for r in narrow],
+                                                [r.x for r in narrow], [r.y for r in narrow],
+                                                stream=stream)
+                        L.requests.extend(group)
+                    evt.record(stream)
+                for r in L.requests:
+                    r.launch = lid
+                inflight.append(L)
+                launches.append(len(L.requests))
+                lid += 1
+            if poll_sleep:
+                time.sleep(poll_sleep)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([r.done - r.arrival for r in reqs])
+        span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+        touched = sum(8 * self.pool[r.mat].words for r in reqs)
+        return {"requests": n, "launches": lid,
+                "mean_batch": round(float(np.mean(launches)), 2) if launches else 0.0,
+                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                "mean_ms": round(float(lat.mean()) * 1e3, 3),
+                "throughput_rps": round(n / span, 1),
+                "throughput_gbs": round(touched / span / 1e9, 1),
+                "wall_s": round(wall, 4)}
+
+
+def make_pool(specs):
+    """Generates the pool on the device (no dense copies)."""
+    return [generate(p.rows, p.cols, p.spec.lo, p.spec.hi, p.spec.seed, p.spec.stream)
+            for p in specs]
+
+
+# generator streams of the per-request inputs: x of request rid uses stream
+# X_STREAM + rid, B uses B_STREAM + rid (same seed as the request mix)
+X_STREAM = 1 << 20
+B_STREAM = 1 << 21
+
+
+def make_requests(pool, count: int, qps: float | None, seed: int, mm_frac: float = 0.1,
+                  mm_max_elems: int = 1 << 20, first_rid: int = 0):
+    """Seeded request mix: 90% matvec on a uniformly chosen pool matrix with
+    int32 x in [-2^15, 2^15); 10% matmul of a pool matrix with <= 2^20
+    elements by a compressed B (cols x n, n in [2, 64], signed, width 1..8).
+    qps=None: every request arrives at t = 0 (saturation)."""
+    from . import fill_uniform
+    rng = np.random.default_rng(seed)
+    small = [i for i, m in enumerate(pool) if m.rows * m.cols <= mm_max_elems]
+    out = []
+    t = 0.0
+    for k in range(count):
+        if qps:
+            t += float(rng.exponential(1.0 / qps))
+        rid = first_rid + k
+        if small and rng.random() < mm_frac:
+            mi = int(small[int(rng.integers(0, len(small)))])
+            a = pool[mi]
+            ncol = int(rng.integers(2, 65))
+            bw = int(rng.integers(1, 9))
+            lo, hi = -(1 << (bw - 1)), (1 << (bw - 1)) if bw > 1 else 1
+            if bw == 1:
+                lo, hi = -1, 1
+            b = generate(a.cols, ncol, lo, hi, seed, B_STREAM + rid)
+            out.append(Request(rid, "mm", mi, t, b=b))
+        else:
+            mi = int(rng.integers(0, len(pool)))
+            x = torch.empty(pool[mi].cols, dtype=torch.int32, device="cuda")
+            fill_uniform(x, -(1 << 15), 1 << 15, seed, X_STREAM + rid)
+            out.append(Request(rid, "mv", mi, t, x=x))
+    torch.cuda.synchronize()
+    return out
