@@ -138,11 +138,32 @@ __device__ __forceinline__ int64_t value_at(const uint32_t *w, uint64_t e, int b
 // ---------------------------------------------------------------------------
 
 // Sum over the wave modulo 2^64.
+// One 64-bit add of a DPP-permuted copy (CTRL: a GFX9 DPP control word).
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_add64(uint64_t v) {
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  const uint32_t lo2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, CTRL, 0xf, 0xf, true);
+  const uint32_t hi2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, CTRL, 0xf, 0xf, true);
+  const uint32_t s = lo + lo2;
+  return ((uint64_t)(hi + hi2 + (s < lo ? 1u : 0u)) << 32) | s;
+}
+
+// Sum over the 64 lanes of a wave, mod 2^64; every lane must be active.  Four
+// DPP steps leave each 16-lane row's sum in all of its lanes (quad swaps, then
+// the half-row and row mirrors); the four row sums are read out as scalars.
 __device__ __forceinline__ int64_t wave_sum(int64_t v) {
   uint64_t u = (uint64_t)v;
+  u = dpp_add64<0xB1>(u);   // quad_perm [1,0,3,2]
+  u = dpp_add64<0x4E>(u);   // quad_perm [2,3,0,1]
+  u = dpp_add64<0x141>(u);  // row_half_mirror
+  u = dpp_add64<0x140>(u);  // row_mirror
+  const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+  uint64_t t = 0;
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) u += (uint64_t)__shfl_xor((int64_t)u, m, 64);
-  return (int64_t)u;
+  for (int r = 0; r < 4; ++r)
+    t += ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi, 16 * r) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane(lo, 16 * r);
+  return (int64_t)t;
 }
 
 __device__ __forceinline__ int64_t wave_min(int64_t v) {

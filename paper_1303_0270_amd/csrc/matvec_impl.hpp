@@ -429,116 +429,226 @@ hipError_t launch_one(const uint32_t *w, int64_t rows, int64_t cols, const XT *x
   return hipGetLastError();
 }
 
-// Aligned variant for b <= 16 and int32 x: rows start on 16-byte boundaries
-// (cols % 128 == 0, so r*cols*b/32 is a multiple of 4 words) and every panel
-// holds whole quads of groups.  Lane l owns the four consecutive groups
-// 4l..4l+3 of the panel ("quad" l), i.e. 4b contiguous words that it fetches
-// with b 16-byte loads per row; a wave covers the 8192-column panel in one
-// pass.  RA rows per wave keep enough bytes in flight for the small widths.
-// LDS keeps each quad's x values (128 int32) or digit words (64) contiguous
-// plus a 4-dword skew, so the 16-byte LDS reads of neighbouring lanes fall in
-// distinct banks.
-constexpr int rows_per_wave_al(int b) { return b <= 4 ? 4 : b <= 8 ? 2 : 1; }
+// Aligned variant for b <= 15, int32 x on a 16-byte boundary: rows start on
+// 16-byte boundaries (cols % 128 == 0, so r*cols*b/32 is a multiple of 4
+// words) and every panel holds whole quads of groups.  Quad q of a row panel
+// is the four groups 4q..4q+3, i.e. 4b contiguous words fetched with b
+// 16-byte loads.
+//   * 512-lane blocks, 16384-column panels (67.6 KB of LDS: two blocks per
+//     CU), so a matrix up to 16384 columns wide is one panel: each row sum is
+//     stored once, with no zero-fill pass and no atomics.
+//   * A wave owns R rows of a row block; lane l owns quads l and l+64 of the
+//     panel.  One "unit" is (row block, quad slot): R*b 16-byte loads per lane.
+//   * With PF the next unit's words are requested before the current one is
+//     decoded (two register sets, used alternately).  Every unit issues the
+//     same loads -- addresses past the last row or quad are clamped to valid
+//     ones, and past the last unit the current one is fetched again (a cache
+//     hit) -- so the compiler can wait for exactly the older unit's loads
+//     (the load counter is in order) instead of draining the queue.  The x
+//     panel is requested first, then the first unit, so the unit's latency
+//     overlaps the LDS staging.
+//   * LDS keeps each quad's x values (128 int32) or b = 1 digit words (64)
+//     contiguous plus a 4-dword skew, so the 16-byte LDS reads of neighbouring
+//     lanes fall in distinct banks.
+//   * b = 1: lane g builds the digit words of group g straight from its 32 x
+//     values (byte permutes and nibble masks), with no int32 copy of x.
+constexpr int kThreadsAl = 512;
+constexpr int kWavesAl = kThreadsAl / 64;
+constexpr int kPanelAl = 16384;
 constexpr int kQuadX = 4 * kGroup + 4;  // int32 per quad of groups
 constexpr int kQuadD = 4 * 16 + 4;      // digit words per quad of groups
 
+template <int B>
+struct AlCfg {
+  static constexpr int R = B <= 2 ? 4 : B <= 4 ? 2 : 1;  // rows per wave and unit
+  static constexpr bool PF = B <= 9;                     // double-buffered units
+};
+
+// Stages x[c0, c0+pc) (pc a multiple of 128) into xs (quad-skewed), general
+// loop for the slow path; returns whether this thread saw only int16-range
+// values.
+__device__ __forceinline__ int stage_x_al(const int32_t *__restrict__ x, int64_t c0, int pc,
+                                          int32_t *xs) {
+  uint32_t m = 0;
+  const int nchunk = pc / 4;
+  for (int q = threadIdx.x; q < nchunk; q += kThreadsAl) {
+    const int4 v = *reinterpret_cast<const int4 *>(x + c0 + 4 * q);
+    const int e = 4 * q;
+    *reinterpret_cast<int4 *>(xs + e + 4 * (e >> 7)) = v;
+    m |= ((uint32_t)v.x + 32768u) | ((uint32_t)v.y + 32768u) | ((uint32_t)v.z + 32768u) |
+         ((uint32_t)v.w + 32768u);
+  }
+  return (m >> 16) == 0;
+}
+
+// b = 1: digit words of group g from its 32 x values v[] (already offset by
+// 2^15).  Word xd[(g/4)*kQuadD + (g%4)*16 + 4d + s] holds in nibble q digit d
+// of x'_{32g + 4q + s}, x' = x + 2^15.
+__device__ __forceinline__ void store_digits_al(const uint32_t *v, int g, uint32_t *xd) {
+  uint32_t D[4][4];  // [digit][s]
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    // values u_q = x'_{4q+s}, q = 0..7; byte 0 holds digits 0,1, byte 1 digits 2,3
+    const uint32_t *u = v + s;
+    // v_perm_b32: selector bytes 0-3 pick the second operand's bytes, 4-7 the
+    // first's; t02 = [u0.b0, u2.b0, u0.b1, u2.b1] and the like
+    const uint32_t t02 = __builtin_amdgcn_perm(u[8], u[0], 0x05010400u);
+    const uint32_t t46 = __builtin_amdgcn_perm(u[24], u[16], 0x05010400u);
+    const uint32_t t13 = __builtin_amdgcn_perm(u[12], u[4], 0x05010400u);
+    const uint32_t t57 = __builtin_amdgcn_perm(u[28], u[20], 0x05010400u);
+    const uint32_t le = __builtin_amdgcn_perm(t46, t02, 0x05040100u);  // byte 0 of u0,u2,u4,u6
+    const uint32_t he = __builtin_amdgcn_perm(t46, t02, 0x07060302u);  // byte 1
+    const uint32_t lo = __builtin_amdgcn_perm(t57, t13, 0x05040100u);  // byte 0 of u1,u3,u5,u7
+    const uint32_t ho = __builtin_amdgcn_perm(t57, t13, 0x07060302u);
+    // byte k of digit word d: low nibble from u_{2k}, high nibble from u_{2k+1}
+    D[0][s] = (le & 0x0F0F0F0Fu) | ((lo & 0x0F0F0F0Fu) << 4);
+    D[1][s] = ((le >> 4) & 0x0F0F0F0Fu) | (lo & 0xF0F0F0F0u);
+    D[2][s] = (he & 0x0F0F0F0Fu) | ((ho & 0x0F0F0F0Fu) << 4);
+    D[3][s] = ((he >> 4) & 0x0F0F0F0Fu) | (ho & 0xF0F0F0F0u);
+  }
+  uint32_t *dst = xd + (g >> 2) * kQuadD + (g & 3) * 16;
+#pragma unroll
+  for (int d = 0; d < 4; ++d)
+    *reinterpret_cast<uint4 *>(dst + 4 * d) = make_uint4(D[d][0], D[d][1], D[d][2], D[d][3]);
+}
+
 template <int B, bool SGN>
-__global__ __launch_bounds__(kThreads) void k_matvec_al(const uint32_t *__restrict__ A,
-                                                        int64_t rows, int64_t cols,
-                                                        const int32_t *__restrict__ x,
-                                                        int64_t *__restrict__ y, int atomic_out,
-                                                        int x_aligned16) {
-  constexpr int R = rows_per_wave_al(B);
-  constexpr bool kDigits = (B == 1);
+__global__ __launch_bounds__(kThreadsAl) __attribute__((amdgpu_waves_per_eu(4))) void
+k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
+            const int32_t *__restrict__ x, int64_t *__restrict__ y, int atomic_out) {
+  constexpr int R = AlCfg<B>::R;
+  constexpr bool PF = AlCfg<B>::PF;
+  constexpr int NWD = 4 * B;  // words per (row, quad)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int32_t *xs = reinterpret_cast<int32_t *>(smem_raw);
+  uint32_t *xd = reinterpret_cast<uint32_t *>(smem_raw);  // b = 1 fast path only
 
-  const int64_t c0 = (int64_t)blockIdx.y * XLayout<int32_t>::kPanel;
-  const int64_t pc = cols - c0 < XLayout<int32_t>::kPanel ? cols - c0 : XLayout<int32_t>::kPanel;
-  const int ng = (int)(pc / kGroup);  // a multiple of 4
-  const int nq = ng / 4;
-
-  // stage x: column e of the panel goes to xs[e + 4*(e/128)]
-  int small = 1;
-  {
-    constexpr int UNR = 8;
-    const int nchunk = ng * kGroup / 4;
-    for (int q0 = threadIdx.x; q0 < nchunk; q0 += kThreads * UNR) {
-      int4 v[UNR];
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int q = q0 + u * kThreads;
-        if (q < nchunk) {
-          if (x_aligned16)
-            v[u] = *reinterpret_cast<const int4 *>(x + c0 + 4 * q);
-          else
-            v[u] = make_int4(x[c0 + 4 * q], x[c0 + 4 * q + 1], x[c0 + 4 * q + 2],
-                             x[c0 + 4 * q + 3]);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int q = q0 + u * kThreads;
-        if (q < nchunk) {
-          const int e = 4 * q;
-          *reinterpret_cast<int4 *>(xs + e + 4 * (e >> 7)) = v[u];
-          small &= (v[u].x >= -32768 && v[u].x <= 32767) & (v[u].y >= -32768 && v[u].y <= 32767) &
-                   (v[u].z >= -32768 && v[u].z <= 32767) & (v[u].w >= -32768 && v[u].w <= 32767);
-        }
-      }
-    }
-  }
-  const bool fast = __syncthreads_and(small);
-
-  // digit words of group j: xd[(j/4)*kQuadD + (j%4)*16 + 4d + s], nibble q =
-  // digit d of x'_{32j + 4q + s}, x' = x + 2^15
-  uint32_t *xd = reinterpret_cast<uint32_t *>(xs + nq * kQuadX);
-  if constexpr (kDigits) {
-    if (fast) {
-      for (int j = threadIdx.x; j < ng; j += kThreads) {
-        const int32_t *xg = xs + (j >> 2) * kQuadX + (j & 3) * kGroup;
-        uint32_t dw[16];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) dw[t] = 0;
-#pragma unroll
-        for (int i = 0; i < kGroup; ++i) {
-          const uint32_t u = (uint32_t)(xg[i] + 32768);
-          const int s4 = i & 3, q = i >> 2;
-#pragma unroll
-          for (int d = 0; d < 4; ++d) dw[d * 4 + s4] |= ((u >> (4 * d)) & 15u) << (4 * q);
-        }
-        uint32_t *dst = xd + (j >> 2) * kQuadD + (j & 3) * 16;
-#pragma unroll
-        for (int t = 0; t < 16; t += 4)
-          *reinterpret_cast<uint4 *>(dst + t) = make_uint4(dw[t], dw[t + 1], dw[t + 2], dw[t + 3]);
-      }
-      __syncthreads();
-    }
-  }
+  const int64_t c0 = (int64_t)blockIdx.y * kPanelAl;
+  const int pc = (int)(cols - c0 < kPanelAl ? cols - c0 : kPanelAl);  // a multiple of 128
+  const int nq = pc / (4 * kGroup);
+  const int nslot = (nq + 63) / 64;  // quad slots per lane: 1 or 2 (wave-uniform)
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t nrb = (rows + kWaves * R - 1) / (kWaves * R);
-  const bool active = lane < nq;
+  const int64_t nrb = (rows + kWavesAl * R - 1) / (kWavesAl * R);  // > blockIdx.x
   const uint64_t row_words = (uint64_t)cols * B / 32;  // a multiple of 4
-  const uint64_t lane_word = (uint64_t)c0 * B / 32 + (uint64_t)lane * 4 * B;
+  const uint64_t panel_word = (uint64_t)c0 * B / 32;
+
+  // rows r0 .. r0+nv-1 of row block rb belong to this wave
+  auto rows_of = [&](int64_t rb, int64_t &r0) -> int {
+    r0 = rb * (kWavesAl * R) + (int64_t)wave * R;
+    const int64_t left = rows - r0;
+    return left >= R ? R : (left > 0 ? (int)left : 0);
+  };
+  // the unit's words; rows and quads past the end are clamped to the last one
+  auto load_unit = [&](uint32_t (&w)[R][NWD], int64_t rb, int h) {
+    const int64_t r0 = rb * (kWavesAl * R) + (int64_t)wave * R;
+    const int qq = lane + 64 * h;
+    const int q = qq < nq ? qq : nq - 1;
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      const int64_t r = r0 + rr < rows ? r0 + rr : rows - 1;
+      const uint4 *src = reinterpret_cast<const uint4 *>(A + (uint64_t)r * row_words + panel_word +
+                                                         (uint64_t)q * NWD);
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const uint4 t = src[u];
+        w[rr][4 * u] = t.x;
+        w[rr][4 * u + 1] = t.y;
+        w[rr][4 * u + 2] = t.z;
+        w[rr][4 * u + 3] = t.w;
+      }
+    }
+  };
+  auto store_rows = [&](const uint64_t (&acc)[R], int64_t rb) {
+    int64_t r0;
+    const int nv = rows_of(rb, r0);
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      if (rr < nv) {
+        const int64_t sum = wave_sum((int64_t)acc[rr]);
+        if (lane == 0) {
+          if (atomic_out)
+            atomicAdd((unsigned long long *)&y[r0 + rr], (unsigned long long)sum);
+          else
+            y[r0 + rr] = sum;
+        }
+      }
+    }
+  };
+
+  // request x (clamped, fixed count), then the first unit, then consume x
+  const int4 *x4 = reinterpret_cast<const int4 *>(x + c0);
+  int4 xv[8];
+  if constexpr (B == 1) {
+    // lane g: the 32 values of group g (pc <= 16384: one group per lane)
+    const int ng = pc / kGroup;
+    const int g = (int)threadIdx.x < ng ? (int)threadIdx.x : ng - 1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) xv[i] = x4[8 * g + i];
+  } else {
+    // lane t: 16-byte chunks t, t+512, ... (pc/4 <= 4096 chunks: one round)
+    const int nchunk = pc / 4;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = (int)threadIdx.x + kThreadsAl * u;
+      xv[u] = x4[q < nchunk ? q : nchunk - 1];
+    }
+  }
+  uint32_t w0[R][NWD], w1[R][NWD];
+  int64_t rb = blockIdx.x;
+  __builtin_amdgcn_sched_barrier(0);  // x requests first
+  if constexpr (PF) load_unit(w0, rb, 0);
+
+  uint32_t m = 0;
+  if constexpr (B == 1) {
+    uint32_t v[kGroup];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      v[4 * i] = (uint32_t)xv[i].x + 32768u;
+      v[4 * i + 1] = (uint32_t)xv[i].y + 32768u;
+      v[4 * i + 2] = (uint32_t)xv[i].z + 32768u;
+      v[4 * i + 3] = (uint32_t)xv[i].w + 32768u;
+    }
+#pragma unroll
+    for (int i = 0; i < kGroup; i += 2) m |= v[i] | v[i + 1];
+    if ((int)threadIdx.x < pc / kGroup) store_digits_al(v, threadIdx.x, xd);
+  } else {
+    const int nchunk = pc / 4;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = (int)threadIdx.x + kThreadsAl * u;
+      if (q < nchunk) {
+        const int e = 4 * q;
+        *reinterpret_cast<int4 *>(xs + e + 4 * (e >> 7)) = xv[u];
+      }
+      // x in [-2^15, 2^15) iff x + 2^15 < 2^16 as unsigned (clamped chunks repeat valid ones)
+      m |= ((uint32_t)xv[u].x + 32768u) | ((uint32_t)xv[u].y + 32768u) |
+           ((uint32_t)xv[u].z + 32768u) | ((uint32_t)xv[u].w + 32768u);
+    }
+  }
+  const bool fast = __syncthreads_and((m >> 16) == 0);
 
   if (!fast) {
-    // general x: 64-bit products, one row and one group at a time (a loop of
-    // its own, so the int16 path below keeps its registers and occupancy)
-    for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
-      const int64_t r0 = rb * (kWaves * R) + (int64_t)wave * R;
-      const int nv = rows - r0 >= R ? R : (rows - r0 > 0 ? (int)(rows - r0) : 0);
+    // general x: 64-bit products, one row and one group at a time
+    if constexpr (B == 1) {
+      (void)stage_x_al(x, c0, pc, xs);
+      __syncthreads();
+    }
+    for (; rb < nrb; rb += gridDim.x) {
+      int64_t r0;
+      const int nv = rows_of(rb, r0);
 #pragma unroll 1
       for (int rr = 0; rr < nv; ++rr) {
         uint64_t a = 0;
-        if (active) {
-          const uint32_t *src = A + (uint64_t)(r0 + rr) * row_words + lane_word;
+#pragma unroll 1
+        for (int q = lane; q < nq; q += 64) {
+          const uint32_t *src = A + (uint64_t)(r0 + rr) * row_words + panel_word + (uint64_t)q * NWD;
 #pragma unroll 1
           for (int t = 0; t < 4; ++t) {
             uint32_t w[B];
 #pragma unroll
             for (int k = 0; k < B; ++k) w[k] = src[t * B + k];
-            a += group_dot_wide<B, SGN, int32_t>(w, xs + lane * kQuadX + t * kGroup);
+            a += group_dot_wide<B, SGN, int32_t>(w, xs + q * kQuadX + t * kGroup);
           }
         }
         const int64_t sum = wave_sum((int64_t)a);
@@ -553,93 +663,104 @@ __global__ __launch_bounds__(kThreads) void k_matvec_al(const uint32_t *__restri
     return;
   }
 
-  for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
-    const int64_t r0 = rb * (kWaves * R) + (int64_t)wave * R;
-    const int nv = rows - r0 >= R ? R : (rows - r0 > 0 ? (int)(rows - r0) : 0);
-    if (nv == 0) continue;
+  uint64_t acc[R];
+#pragma unroll
+  for (int rr = 0; rr < R; ++rr) acc[rr] = 0;
 
-    uint32_t w[R][4 * B];
-    if (active) {
+  // decode one unit (quad slot h of the wave's R rows) held in w into acc.
+  // Branch-free: lanes past the last quad decode the clamped copy and add
+  // nothing, rows past the end are decoded and never stored -- so every path
+  // waits for the unit's loads at the same point.
+  auto compute_unit = [&](const uint32_t (&w)[R][NWD], int h) {
+    const int qq = lane + 64 * h;
+    const bool live = qq < nq;
+    const int q = live ? qq : nq - 1;
+    if constexpr (B == 1) {
+      uint32_t dacc[R][5];
 #pragma unroll
-      for (int rr = 0; rr < R; ++rr) {
-        if (rr < nv) {
-          const uint4 *src =
-              reinterpret_cast<const uint4 *>(A + (uint64_t)(r0 + rr) * row_words + lane_word);
+      for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-          for (int u = 0; u < B; ++u) {
-            const uint4 t = src[u];
-            w[rr][4 * u] = t.x;
-            w[rr][4 * u + 1] = t.y;
-            w[rr][4 * u + 2] = t.z;
-            w[rr][4 * u + 3] = t.w;
-          }
-        }
-      }
-    }
-
-    uint64_t acc[R];
-    uint32_t dacc[R][5];
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-      acc[rr] = 0;
-#pragma unroll
-      for (int d = 0; d < 5; ++d) dacc[rr][d] = 0;
-    }
-
-    if (active) {
+        for (int d = 0; d < 5; ++d) dacc[rr][d] = 0;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        if constexpr (kDigits) {
-          const uint4 *dg = reinterpret_cast<const uint4 *>(xd + lane * kQuadD + t * 16);
-          const uint4 d0 = dg[0], d1 = dg[1], d2 = dg[2], d3 = dg[3];
-          const uint32_t X[16] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w,
-                                  d2.x, d2.y, d2.z, d2.w, d3.x, d3.y, d3.z, d3.w};
+        const uint4 *dg = reinterpret_cast<const uint4 *>(xd + q * kQuadD + t * 16);
+        const uint4 d0 = dg[0], d1 = dg[1], d2 = dg[2], d3 = dg[3];
+        const uint32_t X[16] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w,
+                                d2.x, d2.y, d2.z, d2.w, d3.x, d3.y, d3.z, d3.w};
 #pragma unroll
-          for (int rr = 0; rr < R; ++rr) {
-            if (rr < nv) {
-              const uint32_t a = w[rr][t];
+        for (int rr = 0; rr < R; ++rr) {
+          const uint32_t a = w[rr][t];
 #pragma unroll
-              for (int s4 = 0; s4 < 4; ++s4) {
-                const uint32_t an = (a >> s4) & 0x11111111u;
+          for (int s = 0; s < 4; ++s) {
+            const uint32_t an = (a >> s) & 0x11111111u;
 #pragma unroll
-                for (int d = 0; d < 4; ++d)
-                  dacc[rr][d] = __builtin_amdgcn_udot8(an, X[d * 4 + s4], dacc[rr][d], false);
-              }
-              dacc[rr][4] += (uint32_t)__builtin_popcount(a);
-            }
+            for (int d = 0; d < 4; ++d)
+              dacc[rr][d] = __builtin_amdgcn_udot8(an, X[d * 4 + s], dacc[rr][d], false);
           }
-        } else {
-          int32_t xv[kGroup];
-          const int32_t *xg = xs + lane * kQuadX + t * kGroup;
-#pragma unroll
-          for (int i = 0; i < kGroup; ++i) xv[i] = xg[i];
-#pragma unroll
-          for (int rr = 0; rr < R; ++rr)
-            if (rr < nv) acc[rr] += group_dot_small<B, SGN>(&w[rr][t * B], xv);
+          dacc[rr][4] += (uint32_t)__builtin_popcount(a);
         }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const int64_t tt = (int64_t)dacc[rr][0] + ((int64_t)dacc[rr][1] << 4) +
+                           ((int64_t)dacc[rr][2] << 8) + ((int64_t)dacc[rr][3] << 12) -
+                           ((int64_t)dacc[rr][4] << 15);
+        acc[rr] += live ? (uint64_t)(SGN ? -tt : tt) : 0u;
+      }
+    } else {
+      uint64_t part[R];
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) part[rr] = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        int32_t xg[kGroup];
+        const int32_t *xp = xs + q * kQuadX + t * kGroup;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) xg[i] = xp[i];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) part[rr] += group_dot_small<B, SGN>(&w[rr][t * B], xg);
         // keep each group's x values live for that group only
         __builtin_amdgcn_sched_barrier(0);
       }
-    }
-
 #pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-      if (rr < nv) {
-        uint64_t v = acc[rr];
-        if constexpr (kDigits) {
-          const int64_t tt = (int64_t)dacc[rr][0] + ((int64_t)dacc[rr][1] << 4) +
-                             ((int64_t)dacc[rr][2] << 8) + ((int64_t)dacc[rr][3] << 12) -
-                             ((int64_t)dacc[rr][4] << 15);
-          v = (uint64_t)(SGN ? -tt : tt);
-        }
-        const int64_t sum = wave_sum((int64_t)v);
-        if (lane == 0) {
-          if (atomic_out)
-            atomicAdd((unsigned long long *)&y[r0 + rr], (unsigned long long)sum);
-          else
-            y[r0 + rr] = sum;
-        }
+      for (int rr = 0; rr < R; ++rr) acc[rr] += live ? part[rr] : 0u;
+    }
+  };
+
+  if constexpr (PF) {
+    // units in order (rb, 0), (rb, 1), ..., (rb + gridDim.x, 0), ...
+    int h = 0;
+    auto step = [&](const uint32_t (&cur)[R][NWD], uint32_t (&nxt)[R][NWD]) -> bool {
+      int64_t rb2 = rb;
+      int h2 = h + 1;
+      if (h2 == nslot) {
+        h2 = 0;
+        rb2 += gridDim.x;
       }
+      const bool more = rb2 < nrb;
+      load_unit(nxt, more ? rb2 : rb, more ? h2 : h);
+      compute_unit(cur, h);
+      if (h == nslot - 1) {
+        store_rows(acc, rb);
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) acc[rr] = 0;
+      }
+      rb = rb2;
+      h = h2;
+      return more;
+    };
+    while (step(w0, w1) && step(w1, w0)) {
+    }
+  } else {
+    for (; rb < nrb; rb += gridDim.x) {
+      for (int h = 0; h < nslot; ++h) {
+        load_unit(w0, rb, h);
+        compute_unit(w0, h);
+      }
+      store_rows(acc, rb);
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) acc[rr] = 0;
     }
   }
 }
@@ -649,8 +770,10 @@ int resident_blocks_al(size_t lds) {
   static int cached = 0;
   if (cached == 0) {
     int occ = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_matvec_al<B, SGN>, kThreads, lds) !=
-            hipSuccess ||
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_matvec_al<B, SGN>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_matvec_al<B, SGN>, kThreadsAl,
+                                                     lds) != hipSuccess ||
         occ < 1)
       occ = 1;
     (void)hipGetDevice(&dev);
@@ -665,31 +788,31 @@ int resident_blocks_al(size_t lds) {
 template <int B, bool SGN>
 hipError_t launch_aligned(const uint32_t *w, int64_t rows, int64_t cols, const int32_t *x,
                           int64_t *y, hipStream_t s) {
-  constexpr int R = rows_per_wave_al(B);
-  constexpr int PANEL = XLayout<int32_t>::kPanel;
-  const int64_t npanels = (cols + PANEL - 1) / PANEL;
-  const int64_t nrb = (rows + kWaves * R - 1) / (kWaves * R);
+  constexpr int R = AlCfg<B>::R;
+  const int64_t npanels = (cols + kPanelAl - 1) / kPanelAl;
+  const int64_t nrb = (rows + kWavesAl * R - 1) / (kWavesAl * R);
   if (nrb > 0x7fffffffll || npanels > 65535) return hipErrorInvalidValue;
   if (npanels > 1) {
     hipError_t e = launch_fill_i64(y, (uint64_t)rows, 0, s);
     if (e != hipSuccess) return e;
   }
-  const int64_t nqp = (cols < PANEL ? cols : PANEL) / (4 * kGroup);
-  size_t lds = (size_t)nqp * kQuadX * sizeof(int32_t);
-  if (B == 1) lds += (size_t)nqp * kQuadD * sizeof(uint32_t);
-  int64_t gx = resident_blocks_al<B, SGN>(lds) / npanels;
-  gx = gx < 1 ? 1 : (gx > nrb ? nrb : gx);
-  const int al = ((uintptr_t)x % 16) == 0;
-  k_matvec_al<B, SGN><<<dim3((unsigned)gx, (unsigned)npanels), kThreads, lds, s>>>(
-      w, rows, cols, x, y, npanels > 1 ? 1 : 0, al);
+  const int64_t nqp = (cols < kPanelAl ? cols : kPanelAl) / (4 * kGroup);
+  const size_t lds = (size_t)nqp * kQuadX * sizeof(int32_t);  // >= the digit words
+  int64_t gx = resident_blocks_al<B, SGN>((size_t)(kPanelAl / (4 * kGroup)) * kQuadX * 4) / npanels;
+  gx = gx < 1 ? 1 : (gx > nrb ? nrb : gx);  // every block owns at least one row block
+  k_matvec_al<B, SGN><<<dim3((unsigned)gx, (unsigned)npanels), kThreadsAl, lds, s>>>(
+      w, rows, cols, x, y, npanels > 1 ? 1 : 0);
   return hipGetLastError();
 }
 
 template <int B>
 hipError_t launch_width(const uint32_t *w, int64_t rows, int64_t cols, int sgn, const void *x,
                         int xdtype, int64_t *y, hipStream_t s) {
-  if constexpr (B <= 16) {
-    if (xdtype == CCM_I32 && cols % 128 == 0 && ((uintptr_t)w % 16) == 0)
+  // b = 16 needs 64-bit products even for int16 x (no room for int32 runs)
+  // and more registers than the aligned kernel's occupancy target allows
+  if constexpr (B <= 15) {
+    if (xdtype == CCM_I32 && cols % 128 == 0 && ((uintptr_t)w % 16) == 0 &&
+        ((uintptr_t)x % 16) == 0)
       return sgn ? launch_aligned<B, true>(w, rows, cols, (const int32_t *)x, y, s)
                  : launch_aligned<B, false>(w, rows, cols, (const int32_t *)x, y, s);
   }

@@ -158,9 +158,10 @@ def test_scale_matches_oracle(b, signed):
 
 
 MV_SHAPES = [(1, 1), (1, 40), (17, 31), (33, 96), (100, 257), (3, 9000), (70, 16500)]
-# cols % 128 == 0: rows start on 16-byte boundaries (the aligned b <= 16 path);
-# 8320 = 8192 + 128 spans two column panels
-MV_ALIGNED = [(5, 128), (37, 256), (130, 1024), (9, 8320)]
+# cols % 128 == 0: rows start on 16-byte boundaries (the aligned b <= 15 path);
+# 8320 leaves one lane a second quad of groups, 16384 is one full panel with
+# two quads per lane, 16512 = 16384 + 128 spans two column panels
+MV_ALIGNED = [(5, 128), (37, 256), (130, 1024), (9, 8320), (3, 16384), (11, 16512)]
 
 
 @pytest.mark.parametrize("b", list(range(1, 65)))
