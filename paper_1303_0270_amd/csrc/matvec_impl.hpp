@@ -559,23 +559,6 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
       }
     }
   };
-  auto store_rows = [&](const uint64_t (&acc)[R], int64_t rb) {
-    int64_t r0;
-    const int nv = rows_of(rb, r0);
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-      if (rr < nv) {
-        const int64_t sum = wave_sum((int64_t)acc[rr]);
-        if (lane == 0) {
-          if (atomic_out)
-            atomicAdd((unsigned long long *)&y[r0 + rr], (unsigned long long)sum);
-          else
-            y[r0 + rr] = sum;
-        }
-      }
-    }
-  };
-
   // request x (clamped, fixed count), then the first unit, then consume x
   const int4 *x4 = reinterpret_cast<const int4 *>(x + c0);
   int4 xv[8];
@@ -728,10 +711,47 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
     }
   };
 
+  // Row sums of the fast path wait in a register: lane j holds entry j of the
+  // wave's current batch (row j % R of the wave's rows in row block first_rb +
+  // (j / R) * gridDim.x), written with one store per 64 entries.  A store's
+  // address and data registers may only be reused once it has completed, and
+  // the load counter is in order, so a store issued after a unit's loads
+  // would make the next reuse wait for those loads as well: the batch store is
+  // therefore issued at the start of a step, before that step's loads, and
+  // its address register stays reserved (ydst) until the next batch.
+  uint64_t ybuf = 0;
+  int nst = 0;
+  int64_t first_rb = rb;
+  int64_t *ydst = y;
+  auto flush = [&]() {
+    const int64_t rbj = first_rb + (int64_t)(lane / R) * gridDim.x;
+    const int64_t row = rbj * (kWavesAl * R) + (int64_t)wave * R + lane % R;
+    const bool ok = lane < nst && row < rows;
+    ydst = y + (ok ? row : 0);
+    if (ok) {
+      if (atomic_out)
+        atomicAdd((unsigned long long *)ydst, (unsigned long long)ybuf);
+      else
+        *ydst = (int64_t)ybuf;
+    }
+    nst = 0;
+  };
+  auto collect = [&](int64_t rb_) {
+    if (nst == 0) first_rb = rb_;
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      const uint64_t sum = (uint64_t)wave_sum((int64_t)acc[rr]);
+      ybuf = lane == nst + rr ? sum : ybuf;
+      acc[rr] = 0;
+    }
+    nst += R;
+  };
+
   if constexpr (PF) {
     // units in order (rb, 0), (rb, 1), ..., (rb + gridDim.x, 0), ...
     int h = 0;
     auto step = [&](const uint32_t (&cur)[R][NWD], uint32_t (&nxt)[R][NWD]) -> bool {
+      if (nst == 64) flush();
       int64_t rb2 = rb;
       int h2 = h + 1;
       if (h2 == nslot) {
@@ -741,28 +761,37 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
       const bool more = rb2 < nrb;
       load_unit(nxt, more ? rb2 : rb, more ? h2 : h);
       compute_unit(cur, h);
-      if (h == nslot - 1) {
-        store_rows(acc, rb);
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) acc[rr] = 0;
-      }
+      if (h == nslot - 1) collect(rb);
       rb = rb2;
       h = h2;
+      asm volatile("" ::"v"(ydst));
       return more;
     };
     while (step(w0, w1) && step(w1, w0)) {
     }
   } else {
+    // one unit at a time: row sums are stored as they complete
     for (; rb < nrb; rb += gridDim.x) {
       for (int h = 0; h < nslot; ++h) {
         load_unit(w0, rb, h);
         compute_unit(w0, h);
       }
-      store_rows(acc, rb);
+      int64_t r0;
+      const int nv = rows_of(rb, r0);
 #pragma unroll
-      for (int rr = 0; rr < R; ++rr) acc[rr] = 0;
+      for (int rr = 0; rr < R; ++rr) {
+        const int64_t sum = wave_sum((int64_t)acc[rr]);
+        acc[rr] = 0;
+        if (lane == 0 && rr < nv) {
+          if (atomic_out)
+            atomicAdd((unsigned long long *)&y[r0 + rr], (unsigned long long)sum);
+          else
+            y[r0 + rr] = sum;
+        }
+      }
     }
   }
+  if (nst > 0) flush();
 }
 
 template <int B, bool SGN>
