@@ -53,7 +53,111 @@ def parse():
     ap.add_argument("--matvec-only", action="store_true",
                     help="counter runs: the twelve packed matrices generated directly on the "
                          "device, K matvec sweeps, then a 1 GiB calibration copy")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="write the HBM-traffic summary of two rocprofv3 --pmc runs of "
+                         "--matvec-only (DIR/fetch, DIR/write) to --counters-out; no GPU use")
+    ap.add_argument("--counters-out", default=os.path.join("profiles",
+                                                           "matvec_sweep_hbm_counters.md"))
     return ap.parse_args()
+
+
+# Sources whose change makes recorded hardware counters of the matvec kernels stale.
+MATVEC_SOURCES = ["paper_1303_0270_amd/csrc/matvec_impl.hpp", "paper_1303_0270_amd/csrc/matvec.hip",
+                  "paper_1303_0270_amd/csrc/matvec_w1.hip", "paper_1303_0270_amd/csrc/matvec_w2.hip",
+                  "paper_1303_0270_amd/csrc/matvec_w3.hip", "paper_1303_0270_amd/csrc/matvec_w4.hip",
+                  "paper_1303_0270_amd/csrc/ccm_internal.hpp",
+                  "paper_1303_0270_amd/csrc/group_codec.hpp", "paper_1303_0270_amd/build.py"]
+COUNTERS_MD = os.path.join(ROOT, "profiles", "matvec_sweep_hbm_counters.md")
+# FETCH_SIZE / WRITE_SIZE (KiB) per byte moved, from a plain 1 GiB device copy in the same run
+# (reads 2^30 bytes, writes 2^30 bytes): the factors turn the counters into bytes.
+
+
+def matvec_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in MATVEC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per matvec launch of the sweep, from the committed counter
+    summary; None when there is none or the matvec sources changed since."""
+    import re
+    if not os.path.exists(COUNTERS_MD):
+        return None
+    text = open(COUNTERS_MD).read()
+    m = re.search(r"matvec source hash: `([0-9a-f]+)`", text)
+    t = re.search(r"HBM bytes per launch \(mean over the sweep\): ([0-9.]+)", text)
+    if not m or not t or m.group(1) != matvec_source_hash():
+        return None
+    return float(t.group(1))
+
+
+def summarize_counters(src_dir, out_path):
+    """Builds the counter summary from rocprofv3 --pmc FETCH_SIZE and
+    WRITE_SIZE runs of `bench.py --matvec-only` (CSV output under
+    src_dir/fetch and src_dir/write)."""
+    import csv
+    import glob
+
+    def per_kernel(sub, counter):
+        vals = {}
+        for f in glob.glob(os.path.join(src_dir, sub, "**", "*counter_collection.csv"),
+                           recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    fetch = per_kernel("fetch", "FETCH_SIZE")
+    write = per_kernel("write", "WRITE_SIZE")
+    copy_f = [v for k, vs in fetch.items() if "copyBuffer" in k for v in vs]
+    copy_w = [v for k, vs in write.items() if "copyBuffer" in k for v in vs]
+    gib_kib = float(1 << 20)
+    ff = gib_kib / max(copy_f) if copy_f else None  # bytes read per FETCH_SIZE KiB / 1024
+    fw = gib_kib / max(copy_w) if copy_w else None
+    rows = []
+    for name in sorted(fetch):
+        if "k_matvec" not in name:
+            continue
+        f_kib = sum(fetch[name]) / len(fetch[name])
+        w_kib = sum(write.get(name, [0.0])) / max(1, len(write.get(name, [])))
+        rows.append((name.split("(")[0].replace("void ", ""), len(fetch[name]), f_kib, w_kib,
+                     1024 * (f_kib * ff + w_kib * fw)))
+    mean = sum(r[4] for r in rows) / len(rows)
+    lines = [
+        "# HBM traffic of the matvec kernels: 16384 x 16384 bandwidth sweep",
+        "",
+        "Commands (repo root on the MI355X box; rocprofv3 run from /tmp with TMPDIR=/tmp):",
+        "",
+        "    timeout -s KILL 60 rocprofv3 --pmc FETCH_SIZE -d gpurun_out/ctr/fetch -o fetch \\",
+        "        --output-format csv -- python3 bench.py --matvec-only --steps 1 --warmup 0",
+        "    timeout -s KILL 60 rocprofv3 --pmc WRITE_SIZE -d gpurun_out/ctr/write -o write \\",
+        "        --output-format csv -- python3 bench.py --matvec-only --steps 1 --warmup 0",
+        "    python3 bench.py --summarize-counters gpurun_out/ctr",
+        "",
+        "`--matvec-only` generates the twelve packed sweep matrices (k in {1,3,7,12,17,31}, "
+        "unsigned and signed) on the device, runs one matvec per matrix, then a plain 1 GiB "
+        "device copy used to calibrate the counters.",
+        "",
+        f"Calibration: the 1 GiB copy reads FETCH_SIZE {max(copy_f):.0f} KiB and writes WRITE_SIZE "
+        f"{max(copy_w):.0f} KiB; bytes = KiB x 1024 x {ff:.3f} (fetch) and x {fw:.3f} (write).",
+        "",
+        f"matvec source hash: `{matvec_source_hash()}` (sha256 prefix of the matvec sources; "
+        "bench.py reports `roofline.traffic` only while it matches)",
+        "",
+        "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (calibrated) |",
+        "|---|---|---|---|---|",
+    ]
+    for r in rows:
+        lines.append(f"| `{r[0]}` | {r[1]} | {r[2]:.0f} | {r[3]:.0f} | {r[4]:.0f} |")
+    lines += ["", f"HBM bytes per launch (mean over the sweep): {mean:.0f}", ""]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines))
+    print(out_path)
 
 
 class Timer:
@@ -88,6 +192,9 @@ class Timer:
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.counters_out)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -284,9 +391,12 @@ def main():
                    "step": "compress, matvec, add, scale(7), decompress, 1000 gets; "
                            "all twelve matrices" if not args.profile else "compress, matvec"},
         "roofline": {"bound": "hbm", "achieved": round(value, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(value / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_matvec (all widths of the sweep)",
-                     "alg_bytes_per_launch": "8*W packed bytes of A (x and y reported apart)"},
+                     "unit": "GB/s", "frac": round(value / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic(),
+                     "kernel": "matvec (one launch per sweep matrix)",
+                     "alg_bytes_per_launch": round(sum(p["packed_bytes"] for p in per_width) /
+                                                   len(per_width)),
+                     "alg_bytes": "8*W packed bytes of A per launch (x and y not counted)"},
         "per_width": per_width,
         "ops": ops,
         "gelem_s_packed": round(len(per_width) * n * n / (ref_t * 1e-6) / 1e9, 1),

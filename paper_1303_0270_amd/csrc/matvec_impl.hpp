@@ -458,10 +458,14 @@ constexpr int kPanelAl = 16384;
 constexpr int kQuadX = 4 * kGroup + 4;  // int32 per quad of groups
 constexpr int kQuadD = 4 * 16 + 4;      // digit words per quad of groups
 
+// PF: the next unit is loaded into a second register set while the current
+// one is decoded.  Measured on the 16384^2 sweep, it pays for b <= 4 only;
+// wider fields issue enough bytes per unit for the other waves to hide the
+// latency.
 template <int B>
 struct AlCfg {
-  static constexpr int R = B <= 2 ? 4 : B <= 4 ? 2 : 1;  // rows per wave and unit
-  static constexpr bool PF = B <= 9;                     // double-buffered units
+  static constexpr int R = B == 1 ? 4 : B <= 4 ? 2 : 1;  // rows per wave and unit
+  static constexpr bool PF = B <= 4;
 };
 
 // Stages x[c0, c0+pc) (pc a multiple of 128) into xs (quad-skewed), general
@@ -580,7 +584,9 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   uint32_t w0[R][NWD], w1[R][NWD];
   int64_t rb = blockIdx.x;
   __builtin_amdgcn_sched_barrier(0);  // x requests first
-  if constexpr (PF) load_unit(w0, rb, 0);
+  // the first unit overlaps the staging (measured: a loss for b > 8)
+  constexpr bool kEarly = PF || B <= 8;
+  if constexpr (kEarly) load_unit(w0, rb, 0);
 
   uint32_t m = 0;
   if constexpr (B == 1) {
@@ -747,10 +753,10 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
     nst += R;
   };
 
+  // units in order (rb, 0), (rb, 1), ..., (rb + gridDim.x, 0), ...
+  int h = 0;
   if constexpr (PF) {
-    // units in order (rb, 0), (rb, 1), ..., (rb + gridDim.x, 0), ...
-    int h = 0;
-    auto step = [&](const uint32_t (&cur)[R][NWD], uint32_t (&nxt)[R][NWD]) -> bool {
+    auto step = [&](uint32_t (&cur)[R][NWD], uint32_t (&nxt)[R][NWD]) -> bool {
       if (nst == 64) flush();
       int64_t rb2 = rb;
       int h2 = h + 1;
@@ -772,8 +778,8 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   } else {
     // one unit at a time: row sums are stored as they complete
     for (; rb < nrb; rb += gridDim.x) {
-      for (int h = 0; h < nslot; ++h) {
-        load_unit(w0, rb, h);
+      for (h = 0; h < nslot; ++h) {
+        if (!kEarly || h > 0 || rb != (int64_t)blockIdx.x) load_unit(w0, rb, h);
         compute_unit(w0, h);
       }
       int64_t r0;
@@ -834,6 +840,200 @@ hipError_t launch_aligned(const uint32_t *w, int64_t rows, int64_t cols, const i
   return hipGetLastError();
 }
 
+// Wide-field variant for b >= 16 and int32 x, any row alignment.  Same
+// pipeline as the aligned kernel: 512-lane blocks over 16384-column panels
+// (a 73.7 KB x panel, two blocks per CU), one row per wave, lane l owns
+// groups l, l+64, ... of the panel; a unit is (row, group slot), b+1 words per
+// lane (the extra word feeds the funnel shift of rows that start inside a
+// word).  With PF the next unit's words are in flight while the current one
+// is decoded; loads are issued in fixed count (clamped addresses) so the
+// compiler waits only for the older unit.  Products are 64-bit (int16-range
+// runs would be one element long at these widths).
+constexpr int kThreadsW = 512;
+constexpr int kWavesW = kThreadsW / 64;
+constexpr int kPanelW = 16384;
+constexpr int kPitchW = kGroup + 4;  // int32 per staged group
+
+template <int B>
+struct WCfg {
+  static constexpr bool PF = B <= 24;  // measured: larger widths run faster without
+};
+
+template <int B, bool SGN>
+__global__ __launch_bounds__(kThreadsW) __attribute__((amdgpu_waves_per_eu(4))) void
+k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
+           const int32_t *__restrict__ x, int64_t *__restrict__ y, int atomic_out,
+           int x_aligned16) {
+  constexpr bool PF = WCfg<B>::PF;
+  constexpr int NWG = B + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int32_t *xs = reinterpret_cast<int32_t *>(smem_raw);
+
+  const int64_t c0 = (int64_t)blockIdx.y * kPanelW;
+  const int pc = (int)(cols - c0 < kPanelW ? cols - c0 : kPanelW);
+  const int ng = (pc + kGroup - 1) / kGroup;
+  const int nslot = (ng + 63) / 64;  // wave-uniform
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nrb = (rows + kWavesW - 1) / kWavesW;  // > blockIdx.x
+
+  // the unit's words and the row's funnel shift (the same for every group of
+  // a row); rows past the end and groups past the last are clamped
+  auto load_unit = [&](uint32_t (&w)[NWG], int64_t rb, int h, int &shift) {
+    const int64_t r0 = rb * kWavesW + wave;
+    const int64_t r = r0 < rows ? r0 : rows - 1;
+    const int jj = lane + 64 * h;
+    const int j = jj < ng ? jj : ng - 1;
+    const uint64_t bit = ((uint64_t)r * (uint64_t)cols + (uint64_t)c0) * (uint64_t)B;
+    shift = (int)(bit & 31u);
+    const uint32_t *gp = A + (bit >> 5) + (uint64_t)j * B;
+#pragma unroll
+    for (int k = 0; k < NWG; ++k) w[k] = gp[k];
+  };
+
+  uint32_t w0[NWG], w1[NWG];
+  int s0 = 0, s1 = 0;
+  int64_t rb = blockIdx.x;
+
+  // stage the x panel, zero-padded to whole groups
+  {
+    const int nchunk = ng * kGroup / 4;
+    for (int q = threadIdx.x; q < nchunk; q += kThreadsW) {
+      const int e = 4 * q;
+      int4 v;
+      if (x_aligned16 && e + 4 <= pc)
+        v = *reinterpret_cast<const int4 *>(x + c0 + e);
+      else
+        v = make_int4(e < pc ? x[c0 + e] : 0, e + 1 < pc ? x[c0 + e + 1] : 0,
+                      e + 2 < pc ? x[c0 + e + 2] : 0, e + 3 < pc ? x[c0 + e + 3] : 0);
+      *reinterpret_cast<int4 *>(xs + (e >> 5) * kPitchW + (e & 31)) = v;
+    }
+  }
+  if constexpr (PF) load_unit(w0, rb, 0, s0);  // in flight across the barrier
+  __syncthreads();
+
+  uint64_t acc = 0;
+  auto compute_unit = [&](uint32_t (&w)[NWG], int shift, int h) {
+    const int jj = lane + 64 * h;
+    const bool live = jj < ng;
+    const int j = live ? jj : ng - 1;
+    // consume every word before the (wave-uniform) shift test, so that all
+    // paths wait for the unit's loads at the same point
+#pragma unroll
+    for (int k = 0; k < NWG; ++k) asm volatile("" ::"v"(w[k]));
+    if (shift != 0) {
+#pragma unroll
+      for (int k = 0; k < B; ++k) w[k] = __builtin_amdgcn_alignbit(w[k + 1], w[k], shift);
+    }
+    const uint64_t d = group_dot_wide<B, SGN, int32_t>(w, xs + j * kPitchW);
+    acc += live ? d : 0u;
+  };
+
+  if constexpr (PF) {
+    // row sums wait in a register (lane j: entry j of the batch, row
+    // first_rb + j * gridDim.x of this wave) and are stored once per 64 rows,
+    // before a step's loads (see the aligned kernel)
+    uint64_t ybuf = 0;
+    int nst = 0;
+    int64_t first_rb = rb;
+    int64_t *ydst = y;
+    auto flush = [&]() {
+      const int64_t row = (first_rb + (int64_t)lane * gridDim.x) * kWavesW + wave;
+      const bool ok = lane < nst && row < rows;
+      ydst = y + (ok ? row : 0);
+      if (ok) {
+        if (atomic_out)
+          atomicAdd((unsigned long long *)ydst, (unsigned long long)ybuf);
+        else
+          *ydst = (int64_t)ybuf;
+      }
+      nst = 0;
+    };
+    int h = 0;
+    auto step = [&](uint32_t (&cur)[NWG], int &scur, uint32_t (&nxt)[NWG], int &snxt) -> bool {
+      if (nst == 64) flush();
+      int64_t rb2 = rb;
+      int h2 = h + 1;
+      if (h2 == nslot) {
+        h2 = 0;
+        rb2 += gridDim.x;
+      }
+      const bool more = rb2 < nrb;
+      load_unit(nxt, more ? rb2 : rb, more ? h2 : h, snxt);
+      compute_unit(cur, scur, h);
+      if (h == nslot - 1) {
+        if (nst == 0) first_rb = rb;
+        const uint64_t sum = (uint64_t)wave_sum((int64_t)acc);
+        ybuf = lane == nst ? sum : ybuf;
+        acc = 0;
+        ++nst;
+      }
+      rb = rb2;
+      h = h2;
+      asm volatile("" ::"v"(ydst));
+      return more;
+    };
+    while (step(w0, s0, w1, s1) && step(w1, s1, w0, s0)) {
+    }
+    if (nst > 0) flush();
+  } else {
+    for (; rb < nrb; rb += gridDim.x) {
+      for (int h = 0; h < nslot; ++h) {
+        load_unit(w0, rb, h, s0);
+        compute_unit(w0, s0, h);
+      }
+      const int64_t sum = wave_sum((int64_t)acc);
+      acc = 0;
+      const int64_t r = rb * kWavesW + wave;
+      if (lane == 0 && r < rows) {
+        if (atomic_out)
+          atomicAdd((unsigned long long *)&y[r], (unsigned long long)sum);
+        else
+          y[r] = sum;
+      }
+    }
+  }
+}
+
+template <int B, bool SGN>
+int resident_blocks_w(size_t lds) {
+  static int cached = 0;
+  if (cached == 0) {
+    int occ = 0, dev = 0, cus = 0;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_matvec_w<B, SGN>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_matvec_w<B, SGN>, kThreadsW, lds) !=
+            hipSuccess ||
+        occ < 1)
+      occ = 1;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    cached = occ * cus;
+  }
+  return cached;
+}
+
+template <int B, bool SGN>
+hipError_t launch_wide(const uint32_t *w, int64_t rows, int64_t cols, const int32_t *x,
+                       int64_t *y, hipStream_t s) {
+  const int64_t npanels = (cols + kPanelW - 1) / kPanelW;
+  const int64_t nrb = (rows + kWavesW - 1) / kWavesW;
+  if (nrb > 0x7fffffffll || npanels > 65535) return hipErrorInvalidValue;
+  if (npanels > 1) {
+    hipError_t e = launch_fill_i64(y, (uint64_t)rows, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t ngp = ((cols < kPanelW ? cols : kPanelW) + kGroup - 1) / kGroup;
+  const size_t lds = (size_t)ngp * kPitchW * sizeof(int32_t);
+  int64_t gx = resident_blocks_w<B, SGN>((size_t)(kPanelW / kGroup) * kPitchW * 4) / npanels;
+  gx = gx < 1 ? 1 : (gx > nrb ? nrb : gx);  // every block owns at least one row
+  const int al = ((uintptr_t)x % 16) == 0;
+  k_matvec_w<B, SGN><<<dim3((unsigned)gx, (unsigned)npanels), kThreadsW, lds, s>>>(
+      w, rows, cols, x, y, npanels > 1 ? 1 : 0, al);
+  return hipGetLastError();
+}
+
 template <int B>
 hipError_t launch_width(const uint32_t *w, int64_t rows, int64_t cols, int sgn, const void *x,
                         int xdtype, int64_t *y, hipStream_t s) {
@@ -844,6 +1044,11 @@ hipError_t launch_width(const uint32_t *w, int64_t rows, int64_t cols, int sgn, 
         ((uintptr_t)x % 16) == 0)
       return sgn ? launch_aligned<B, true>(w, rows, cols, (const int32_t *)x, y, s)
                  : launch_aligned<B, false>(w, rows, cols, (const int32_t *)x, y, s);
+  }
+  if constexpr (B >= 16) {
+    if (xdtype == CCM_I32)
+      return sgn ? launch_wide<B, true>(w, rows, cols, (const int32_t *)x, y, s)
+                 : launch_wide<B, false>(w, rows, cols, (const int32_t *)x, y, s);
   }
   if (xdtype == CCM_I32) {
     return sgn ? launch_one<B, true, int32_t>(w, rows, cols, (const int32_t *)x, y, s)
