@@ -10,10 +10,12 @@ One step runs every operation of the path over the twelve matrices, in
 phases: width + compress (from the dense int64 input), matvec, add (range
 pass + pack), scale by 7, decompress and 1000 element gets.  The reported
 value is the packed-matvec bandwidth: the packed bytes of A (8*W per matrix)
-over the matvec kernels' time, taken with HIP events on the launch stream
-inside the timed steps.  Each phase touches gigabytes before a matrix is read
-again, so the 256 MB last-level cache does not hold A between its compression
-and its matvec.
+over the time of the matvec phase, taken with a pair of HIP events on the
+launch stream around the twelve back-to-back launches (even steps); odd steps
+put one event between neighbouring launches for the per-width breakdown, and
+each such marker adds a few microseconds to its interval.  Each phase touches
+gigabytes before a matrix is read again, so the 256 MB last-level cache does
+not hold A between its compression and its matvec.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--no-extras] [--profile]
@@ -58,6 +60,13 @@ def parse():
                          "--matvec-only (DIR/fetch, DIR/write) to --counters-out; no GPU use")
     ap.add_argument("--counters-out", default=os.path.join("profiles",
                                                            "matvec_sweep_hbm_counters.md"))
+    ap.add_argument("--summarize-trace", metavar="CSV",
+                    help="write the kernel-time summary of a rocprofv3 --kernel-trace --stats "
+                         "run of this benchmark (its kernel_stats.csv) to --trace-out; no GPU use")
+    ap.add_argument("--trace-json", metavar="FILE",
+                    help="the JSON line the profiled run printed (matvec event times, compared)")
+    ap.add_argument("--trace-cmd", default="", help="the profiled command, recorded in the summary")
+    ap.add_argument("--trace-out", default=os.path.join("profiles", "sweep_step_kernels.md"))
     return ap.parse_args()
 
 
@@ -160,6 +169,53 @@ def summarize_counters(src_dir, out_path):
     print(out_path)
 
 
+def summarize_trace(stats_csv, out_path, bench_json=None, cmd=""):
+    """Kernel-time table of a rocprofv3 --kernel-trace --stats run of this
+    benchmark; with the run's JSON line, the matvec kernels' trace averages
+    next to the HIP-event times bench.py measured in the same run."""
+    import csv
+    import re
+
+    def short(name):
+        if "FillFunctor" in name:
+            return "torch fill_"
+        return name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = ["# Kernel times: one benchmark step over the 16384 x 16384 bandwidth sweep", "",
+             "Command (repo root on the MI355X box; rocprofv3 run from /tmp with TMPDIR=/tmp):", "",
+             "    " + cmd, "",
+             "A step runs width + compress, matvec, add (range + pack), scale by 7, decompress and "
+             "1000 gets over the twelve sweep matrices (k in {1,3,7,12,17,31}, unsigned and "
+             "signed); the dense int32 comparison, the read probe and a 1 GiB copy follow.", "",
+             "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    if bench_json:
+        d = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        lines += ["", "Matvec kernels: rocprofv3 average against the HIP-event time bench.py took "
+                  "in the same run (`per_width[].matvec_us`).", "",
+                  "| width | signed | trace avg us | bench event us |", "|---|---|---|---|"]
+        for pw in d["per_width"]:
+            sg = "true" if pw["signed"] else "false"
+            pat = re.compile(r"k_matvec\w*<%d, %s" % (pw["bits"], sg))
+            tr = [float(r["AverageNs"]) / 1e3 for r in rows if pat.search(r["Name"])]
+            lines.append(f"| {pw['bits']} | {sg} | {tr[0]:.1f} | {pw['matvec_us']:.1f} |" if tr
+                         else f"| {pw['bits']} | {sg} | - | {pw['matvec_us']:.1f} |")
+        mv = [float(r["AverageNs"]) / 1e3 for r in rows if "k_matvec" in r["Name"]]
+        lines += ["", "Per-width event intervals each include one event marker; the value "
+                  "uses the even steps' pair of events around all twelve launches instead:", "",
+                  f"* sum of the matvec kernels' trace averages: {sum(mv):.1f} us per sweep",
+                  f"* bench matvec phase (event pair): {d['ops']['matvec']['ms_per_sweep'] * 1e3:.1f}"
+                  f" us per sweep",
+                  f"* bench value: {d['value']} GB/s (roofline frac {d['roofline']['frac']})"]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out_path)
+
+
 class Timer:
     """HIP events on the current stream, accumulated per label."""
 
@@ -182,6 +238,31 @@ class Timer:
                 timer.pending.append((label, self_.a, self_.b))
         return _S()
 
+    def chain(self, labels_and_calls):
+        """Launches back to back with one event between neighbours: launch i
+        is timed from the event before it to the event after it.  The events
+        are created and the launches marshalled before the first record, so
+        the host enqueues faster than the kernels run and no host gap lands
+        inside an interval."""
+        torch = self.torch
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(labels_and_calls) + 1)]
+        evs[0].record()
+        for i, (label, call) in enumerate(labels_and_calls):
+            call()
+            evs[i + 1].record()
+            self.pending.append((label, evs[i], evs[i + 1]))
+
+    def phase(self, label, calls):
+        """Launches back to back between one pair of events (no marker between
+        the kernels)."""
+        torch = self.torch
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for call in calls:
+            call()
+        b.record()
+        self.pending.append((label, a, b))
+
     def collect(self):
         out = {}
         for label, a, b in self.pending:
@@ -194,6 +275,9 @@ def main():
     args = parse()
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, args.counters_out)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.trace_out, args.trace_json, args.trace_cmd)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -247,15 +331,24 @@ def main():
 
     timer = Timer(torch)
 
+    nstep = [0]
+
     def step(profile=False):
         packed = []
         for c in cases:
             with timer.span(f"compress:{c['k']}:{int(c['signed'])}"):
                 a = ccm.compress(c["dense"])
             packed.append(a)
-        for c, a in zip(cases, packed):
-            with timer.span(f"matvec:{c['k']}:{int(c['signed'])}"):
-                ccm.matvec(a, x, y)
+        # Even steps time the twelve back-to-back launches as one phase (the
+        # value); odd steps put one event between neighbouring launches for the
+        # per-width breakdown -- each marker adds a few us to its interval.
+        launches = [(f"matvec:{c['k']}:{int(c['signed'])}", ccm.matvec_launcher(a, x, y, stream))
+                    for c, a in zip(cases, packed)]
+        if nstep[0] % 2 == 0:
+            timer.phase("matvec_phase", [go for _, go in launches])
+        else:
+            timer.chain(launches)
+        nstep[0] += 1
         if profile:
             return packed
         for c, a in zip(cases, packed):
@@ -287,19 +380,23 @@ def main():
 
     # ---- matvec roofline -------------------------------------------------
     per_width = []
-    tot_bytes = tot_t = 0.0
+    sweep_bytes = 0.0
     for c, a in zip(cases, packed):
-        ts = times[f"matvec:{c['k']}:{int(c['signed'])}"]
+        ts = times.get(f"matvec:{c['k']}:{int(c['signed'])}", [float("nan")])
         t = float(np.mean(ts))
         nbytes = 8 * a.words
-        tot_bytes += nbytes * len(ts)
-        tot_t += sum(ts)
+        sweep_bytes += nbytes
         per_width.append({"k": c["k"], "signed": c["signed"], "bits": a.bits,
                           "packed_bytes": nbytes, "matvec_us": round(t * 1e6, 2),
                           "gbs": round(nbytes / t / 1e9, 1),
                           "frac_hbm": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
                           "gelem_s": round(n * n / t / 1e9, 1)})
-    value = tot_bytes / tot_t / 1e9
+    phases = times.get("matvec_phase")
+    if not phases:  # a single timed step: sum its per-launch intervals
+        phases = [sum(float(np.sum(times[f"matvec:{c['k']}:{int(c['signed'])}"]))
+                      for c in cases)]
+    tot_t = float(np.sum(phases))
+    value = sweep_bytes * len(phases) / tot_t / 1e9
 
     # ---- the other operations (algorithmic bytes, SURVEY per-op units) ---
     def op_stats(prefix, bytes_fn):
@@ -314,7 +411,7 @@ def main():
                 "us_per_call": round(tt / args.steps / len(cases) * 1e6, 2),
                 "alg_gbs": round(bb / tt / 1e9, 1)}
 
-    ops = {"matvec": {"ms_per_sweep": round(tot_t / args.steps * 1e3, 3),
+    ops = {"matvec": {"ms_per_sweep": round(tot_t / len(phases) * 1e3, 3),
                       "alg_gbs": round(value, 1)}}
     ops["compress"] = op_stats("compress", lambda c, a: 16 * n * n + 8 * a.words)
     if not args.profile:
@@ -371,7 +468,7 @@ def main():
     torch.cuda.synchronize()
     del big, half
 
-    ref_t = sum(p["matvec_us"] for p in per_width)
+    sweep_t = tot_t / len(phases)
     result = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -399,7 +496,7 @@ def main():
                      "alg_bytes": "8*W packed bytes of A per launch (x and y not counted)"},
         "per_width": per_width,
         "ops": ops,
-        "gelem_s_packed": round(len(per_width) * n * n / (ref_t * 1e-6) / 1e9, 1),
+        "gelem_s_packed": round(len(per_width) * n * n / sweep_t / 1e9, 1),
         "dense_i32": dense_i32,
         "hbm_read_probe_gbs": round(read_peak, 1),
     }

@@ -15,6 +15,7 @@ from ._lib import (E_INVAL, E_NOMEM, E_OVERFLOW, E_RANGE, E_SHAPE, E_UNSUPPORTED
                    OK, CcmError, Desc, check, lib)
 
 __all__ = ["CMatrix", "CcmError", "compress", "decompress", "get", "gather", "add", "scale",
+           "matvec_launcher",
            "matvec", "matmul", "matmul_plan", "matmul_pack", "fill_uniform", "generate", "from_serialized", "words",
            "packed_bytes", "payload_capacity", "width", "Batch", "DynBatch"]
 
@@ -197,6 +198,26 @@ def matvec(a: CMatrix, x: torch.Tensor, y: torch.Tensor | None = None, stream=No
     check(lib.ccm_matvec(ctypes.byref(a.desc), _ptr(x), _dtype_code(x), _ptr(y),
                          _stream(stream)), "ccm_matvec")
     return y
+
+
+def matvec_launcher(a: CMatrix, x: torch.Tensor, y: torch.Tensor, stream=None):
+    """Marshals the arguments of y = A x once and returns a callable that
+    launches it with no further Python work (for back-to-back launches whose
+    kernels are shorter than the per-call marshalling).  a, x and y must stay
+    alive while the callable is used."""
+    x = _device_tensor(x, "x")
+    if x.numel() != a.cols:
+        raise CcmError(E_SHAPE, "matvec")
+    if y.dtype != torch.int64 or y.numel() != a.rows or not y.is_contiguous():
+        raise CcmError(E_INVAL, "matvec: y")
+    fn = lib.ccm_matvec
+    args = (ctypes.byref(a.desc), _ptr(x), _dtype_code(x), _ptr(y), _stream(stream))
+
+    def launch():
+        rc = fn(*args)
+        if rc != 0:
+            raise CcmError(rc, "ccm_matvec")
+    return launch
 
 
 def matmul_scratch_bytes(a: CMatrix, b: CMatrix) -> int:

@@ -48,21 +48,29 @@ int device_ctx(DeviceCtx **out) {
   DeviceCtx &c = g_ctx[(size_t)dev];
   if (!c.slot) {
     void *p = nullptr;
-    CCM_HIP(hipMalloc(&p, 256));
+    CCM_HIP(hipMalloc(&p, ccm::kRangeBytes + 256));
     c.slot = (ccm::RangeSlot *)p;
-    c.one = (int64_t *)((char *)p + 64);
+    c.one = (int64_t *)((char *)p + ccm::kRangeBytes);
     void *h = nullptr;
-    CCM_HIP(hipHostMalloc(&h, sizeof(ccm::RangeSlot) + 64, hipHostMallocDefault));
+    CCM_HIP(hipHostMalloc(&h, ccm::kRangeBytes + 64, hipHostMallocDefault));
     c.host = (ccm::RangeSlot *)h;
   }
   *out = &c;
   return CCM_OK;
 }
 
+// Copies the spread range slots back and folds them into one result.
 int read_slot(DeviceCtx *c, hipStream_t s, ccm::RangeSlot *res) {
-  CCM_HIP(hipMemcpyAsync(c->host, c->slot, sizeof(ccm::RangeSlot), hipMemcpyDeviceToHost, s));
+  CCM_HIP(hipMemcpyAsync(c->host, c->slot, ccm::kRangeBytes, hipMemcpyDeviceToHost, s));
   CCM_HIP(hipStreamSynchronize(s));
-  *res = *c->host;
+  ccm::RangeSlot r = c->host[0];
+  for (int i = 1; i < ccm::kRangeSpread; ++i) {
+    const ccm::RangeSlot &t = c->host[ccm::kRangeStride * i];
+    r.vmin = t.vmin < r.vmin ? t.vmin : r.vmin;
+    r.vmax = t.vmax > r.vmax ? t.vmax : r.vmax;
+    r.flag |= t.flag;
+  }
+  *res = r;
   return CCM_OK;
 }
 
@@ -290,7 +298,7 @@ int ccm_get(const ccm_desc *a, int64_t i, int64_t j, int64_t *value, void *strea
   if (rc != CCM_OK) return rc;
   CCM_HIP(ccm::launch_get_one((const uint32_t *)a->payload, (uint64_t)(i * a->cols + j), a->bits,
                               a->is_signed, c->one, s));
-  int64_t *h = (int64_t *)((char *)c->host + sizeof(ccm::RangeSlot));
+  int64_t *h = (int64_t *)((char *)c->host + ccm::kRangeBytes);
   CCM_HIP(hipMemcpyAsync(h, c->one, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   CCM_HIP(hipStreamSynchronize(s));
   *value = *h;
@@ -307,6 +315,29 @@ int ccm_gather(const ccm_desc *a, const int64_t *ii, const int64_t *jj, int64_t 
   return CCM_OK;
 }
 
+// Value class of an elementwise pass from the operands' exact ranges: 32-bit
+// arithmetic when every operand value and every possible result fits.
+static bool in_i32(__int128 v) { return v >= (__int128)INT32_MIN && v <= (__int128)INT32_MAX; }
+
+static int add_class(const ccm_desc *a, const ccm_desc *b) {
+  const __int128 lo = (__int128)a->vmin + b->vmin, hi = (__int128)a->vmax + b->vmax;
+  if (in_i32(a->vmin) && in_i32(a->vmax) && in_i32(b->vmin) && in_i32(b->vmax) && in_i32(lo) &&
+      in_i32(hi))
+    return ccm::EW_I32;
+  if (a->vmin >= 0 && b->vmin >= 0 && hi <= (__int128)UINT32_MAX) return ccm::EW_U32;
+  return ccm::EW_I64;
+}
+
+static int scale_class(const ccm_desc *a, int64_t s) {
+  const __int128 p = (__int128)a->vmin * s, q = (__int128)a->vmax * s;
+  const __int128 lo = p < q ? p : q, hi = p < q ? q : p;
+  if (in_i32(a->vmin) && in_i32(a->vmax) && in_i32(s) && in_i32(lo) && in_i32(hi))
+    return ccm::EW_I32;
+  if (a->vmin >= 0 && s >= 0 && s <= (int64_t)UINT32_MAX && hi <= (__int128)UINT32_MAX)
+    return ccm::EW_U32;
+  return ccm::EW_I64;
+}
+
 int ccm_add_plan(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *stream) {
   int rc = check_desc(a, true);
   if (rc == CCM_OK) rc = check_desc(b, true);
@@ -319,7 +350,8 @@ int ccm_add_plan(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *stre
   rc = device_ctx(&c);
   if (rc != CCM_OK) return rc;
   CCM_HIP(ccm::launch_range_init(c->slot, s));
-  CCM_HIP(ccm::launch_ewise_range(ccm::EW_ADD, operand(a), operand(b), 0, nelem(a), c->slot, s));
+  CCM_HIP(ccm::launch_ewise_range(ccm::EW_ADD, operand(a), operand(b), 0, nelem(a),
+                                  add_class(a, b), c->slot, s));
   ccm::RangeSlot r;
   rc = read_slot(c, s, &r);
   if (rc != CCM_OK) return rc;
@@ -342,7 +374,8 @@ int ccm_add(const ccm_desc *a, const ccm_desc *b, const ccm_desc *out, void *str
   rc = check_result(out, a->rows, a->cols);
   if (rc != CCM_OK) return rc;
   const uint64_t n = nelem(a);
-  CCM_HIP(ccm::launch_ewise_pack(ccm::EW_ADD, operand(a), operand(b), 0, n, out->bits,
+  CCM_HIP(ccm::launch_ewise_pack(ccm::EW_ADD, operand(a), operand(b), 0, n, add_class(a, b),
+                                 out->bits,
                                  (uint32_t *)out->payload, ccm::cap_words32(n, out->bits),
                                  (hipStream_t)stream));
   return CCM_OK;
@@ -370,7 +403,8 @@ int ccm_scale(const ccm_desc *a, int64_t s, const ccm_desc *out, void *stream) {
     return CCM_E_INVAL;
   const uint64_t n = nelem(a);
   ccm::PackedOperand none{nullptr, 0, 0};
-  CCM_HIP(ccm::launch_ewise_pack(ccm::EW_SCALE, operand(a), none, s, n, out->bits,
+  CCM_HIP(ccm::launch_ewise_pack(ccm::EW_SCALE, operand(a), none, s, n, scale_class(a, s),
+                                 out->bits,
                                  (uint32_t *)out->payload, ccm::cap_words32(n, out->bits),
                                  (hipStream_t)stream));
   return CCM_OK;

@@ -192,8 +192,17 @@ struct RangeSlot {
   int32_t pad;
 };
 
-// Block-wide (min, max, flag) folded into *slot with one atomic each per
-// block.  Every thread of the block must call it.
+// A range result lives in kRangeSpread slots, one 128-byte line apart: block
+// i folds into slot i % kRangeSpread, so a few thousand blocks do not
+// serialize on one address (same-address device atomics cost tens of ns
+// each); the host folds the slots after the copy back.
+constexpr int kRangeSpread = 64;
+constexpr int kRangeStride = 4;  // RangeSlot units per slot (128 bytes)
+constexpr size_t kRangeBytes = sizeof(RangeSlot) * kRangeStride * kRangeSpread;
+
+// Block-wide (min, max, flag) folded into the block's slot of a spread range
+// result with one atomic each per block.  Every thread of the block must call
+// it.
 __device__ inline void block_range_commit(int64_t lo, int64_t hi, int flag, RangeSlot *slot) {
   __shared__ int64_t s_lo[16], s_hi[16];
   __shared__ int s_flag[16];
@@ -208,6 +217,7 @@ __device__ inline void block_range_commit(int64_t lo, int64_t hi, int flag, Rang
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    slot += kRangeStride * ((blockIdx.x + blockIdx.y * gridDim.x) % kRangeSpread);
     const int nw = (blockDim.x + 63) >> 6;
     for (int w = 1; w < nw; ++w) {
       lo = s_lo[w] < lo ? s_lo[w] : lo;
@@ -240,15 +250,19 @@ hipError_t launch_gather(const uint32_t *w, int64_t rows, int64_t cols, int bits
 
 // Elementwise ops on two packed operands (b may be null for unary ops).
 enum EwiseOp { EW_ADD = 0, EW_SCALE = 1 };
+// Value class of an elementwise pass: every operand value and every result
+// fits int32 / uint32 (exact 32-bit arithmetic), or general int64 with
+// overflow detection.
+enum EwiseClass { EW_I64 = 0, EW_I32 = 1, EW_U32 = 2 };
 struct PackedOperand {
   const uint32_t *w;
   int bits;
   int sgn;
 };
 hipError_t launch_ewise_range(int op, PackedOperand a, PackedOperand b, int64_t scalar,
-                              uint64_t n, RangeSlot *slot, hipStream_t s);
+                              uint64_t n, int vclass, RangeSlot *slot, hipStream_t s);
 hipError_t launch_ewise_pack(int op, PackedOperand a, PackedOperand b, int64_t scalar,
-                             uint64_t n, int out_bits, uint32_t *out, uint64_t cap32,
+                             uint64_t n, int vclass, int out_bits, uint32_t *out, uint64_t cap32,
                              hipStream_t s);
 
 hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t s);

@@ -87,6 +87,61 @@ __device__ __forceinline__ void encode(const int64_t *v, uint32_t *__restrict__ 
   }
 }
 
+// 32-bit values (b <= 32): fields zero-extended, or sign-extended when sgn.
+template <int B>
+__device__ __forceinline__ void decode32(const uint32_t *__restrict__ p, int sgn, uint32_t *v) {
+  static_assert(B <= 32, "32-bit decode");
+  uint32_t w[B];
+#pragma unroll
+  for (int k = 0; k < B; ++k) w[k] = p[k];
+#pragma unroll
+  for (int i = 0; i < kGroup; ++i) {
+    const uint32_t u = (uint32_t)field<B>(w, i);
+    v[i] = (sgn && B < 32) ? (uint32_t)(((int32_t)(u << (32 - B))) >> (32 - B)) : u;
+  }
+}
+
+template <int B>
+__device__ __forceinline__ void encode32(const uint32_t *v, uint32_t *__restrict__ out,
+                                         uint64_t limit) {
+  static_assert(B <= 32, "32-bit encode");
+  uint32_t w[B];
+#pragma unroll
+  for (int k = 0; k < B; ++k) w[k] = 0;
+#pragma unroll
+  for (int i = 0; i < kGroup; ++i) {
+    const uint32_t u = B == 32 ? v[i] : (v[i] & ((1u << (B & 31)) - 1u));
+    const int p = i * B;
+    const int k = p >> 5;
+    const int off = p & 31;
+    w[k] |= u << off;
+    if (off + B > 32) w[k + 1] |= u >> (32 - off);
+  }
+  if (limit >= (uint64_t)B) {
+    if constexpr (B % 4 == 0) {
+#pragma unroll
+      for (int k = 0; k < B; k += 4)
+        *reinterpret_cast<uint4 *>(out + k) = make_uint4(w[k], w[k + 1], w[k + 2], w[k + 3]);
+    } else if constexpr (B % 2 == 0) {
+#pragma unroll
+      for (int k = 0; k < B; k += 2)
+        *reinterpret_cast<uint2 *>(out + k) = make_uint2(w[k], w[k + 1]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < B; ++k) out[k] = w[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if ((uint64_t)k < limit) out[k] = w[k];
+  }
+}
+
+#define CCM_WIDTH_CASES_32(X)                                                                \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)   \
+  X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30)      \
+  X(31) X(32)
+
 #define CCM_WIDTH_CASES(X)                                                                   \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)   \
   X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30)      \
@@ -118,6 +173,34 @@ __device__ __forceinline__ void encode_rt(const int64_t *v, int bits, uint32_t *
     break;
     CCM_WIDTH_CASES(CCM_ENC_CASE)
 #undef CCM_ENC_CASE
+    default:
+      break;
+  }
+}
+
+__device__ __forceinline__ void decode32_rt(const uint32_t *__restrict__ p, int bits, int sgn,
+                                            uint32_t *v) {
+  switch (bits) {
+#define CCM_DEC32_CASE(b)    \
+  case b:                    \
+    decode32<b>(p, sgn, v);  \
+    break;
+    CCM_WIDTH_CASES_32(CCM_DEC32_CASE)
+#undef CCM_DEC32_CASE
+    default:
+      break;
+  }
+}
+
+__device__ __forceinline__ void encode32_rt(const uint32_t *v, int bits, uint32_t *__restrict__ out,
+                                            uint64_t limit) {
+  switch (bits) {
+#define CCM_ENC32_CASE(b)         \
+  case b:                         \
+    encode32<b>(v, out, limit);   \
+    break;
+    CCM_WIDTH_CASES_32(CCM_ENC32_CASE)
+#undef CCM_ENC32_CASE
     default:
       break;
   }

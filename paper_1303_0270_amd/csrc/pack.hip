@@ -11,6 +11,8 @@
 #include "ccm_internal.hpp"
 #include "group_codec.hpp"
 
+#include <limits>
+
 namespace ccm {
 namespace {
 
@@ -19,10 +21,13 @@ constexpr int kTileElems = kTileThreads * kGroup;
 constexpr int kPad = kGroup + 1;            // LDS row pitch (elements) of a lane's group
 
 __global__ void k_range_init(RangeSlot *slot) {
-  slot->vmin = INT64_MAX;
-  slot->vmax = INT64_MIN;
-  slot->flag = 0;
-  slot->pad = 0;
+  if (threadIdx.x < kRangeSpread) {
+    RangeSlot *r = slot + kRangeStride * threadIdx.x;
+    r->vmin = INT64_MAX;
+    r->vmax = INT64_MIN;
+    r->flag = 0;
+    r->pad = 0;
+  }
 }
 
 template <typename T>
@@ -170,15 +175,17 @@ __device__ __forceinline__ int64_t ewise_value(int op, int64_t a, int64_t b, int
   return p;
 }
 
-// Range pass of an elementwise result: one group of 32 elements per lane.
+// Range pass of an elementwise result: one group of 32 elements per lane and
+// step, grid-stride over the groups (a bounded grid keeps the per-block
+// atomics on the one result slot few).
 __global__ __launch_bounds__(256) void k_ewise_range(int op, PackedOperand a, PackedOperand b,
                                                      int64_t scalar, uint64_t n,
                                                      RangeSlot *slot) {
   int64_t lo = INT64_MAX, hi = INT64_MIN;
   int ovf = 0;
   const uint64_t ngroups = (n + kGroup - 1) / kGroup;
-  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < ngroups) {
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups;
+       g += (uint64_t)gridDim.x * blockDim.x) {
     int64_t va[kGroup], vb[kGroup];
     codec::decode_rt(a.w + g * (uint64_t)a.bits, a.bits, a.sgn, va);
     if (op == EW_ADD) codec::decode_rt(b.w + g * (uint64_t)b.bits, b.bits, b.sgn, vb);
@@ -220,6 +227,68 @@ __global__ __launch_bounds__(256) void k_ewise_pack(int op, PackedOperand a, Pac
       vc[i] = e0 + i < n ? ewise_value(op, va[i], op == EW_ADD ? vb[i] : 0, scalar, &ovf) : 0;
   }
   codec::encode_rt(vc, out_bits, out + w0, cap32 - w0);
+}
+
+// 32-bit variants, taken when the operands' and the result's exact ranges
+// (from the headers) all fit the value type VT (int32_t or uint32_t): the sum
+// or product is then exact in VT and cannot overflow, so every element costs
+// a few 32-bit instructions instead of 64-bit arithmetic with overflow tests.
+template <typename VT>
+__device__ __forceinline__ VT ewise_value32(int op, VT a, VT b, VT scalar) {
+  return op == EW_ADD ? (VT)(a + b) : (VT)(a * scalar);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_ewise_range32(int op, PackedOperand a, PackedOperand b,
+                                                       int64_t scalar, uint64_t n,
+                                                       RangeSlot *slot) {
+  VT lo = std::numeric_limits<VT>::max(), hi = std::numeric_limits<VT>::min();
+  const VT sc = (VT)scalar;
+  const uint64_t ngroups = (n + kGroup - 1) / kGroup;
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups;
+       g += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t va[kGroup], vb[kGroup];
+    codec::decode32_rt(a.w + g * (uint64_t)a.bits, a.bits, a.sgn, va);
+    if (op == EW_ADD) codec::decode32_rt(b.w + g * (uint64_t)b.bits, b.bits, b.sgn, vb);
+    const uint64_t e0 = g * kGroup;
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) {
+      if (e0 + i < n) {
+        const VT c = ewise_value32<VT>(op, (VT)va[i], op == EW_ADD ? (VT)vb[i] : (VT)0, sc);
+        lo = c < lo ? c : lo;
+        hi = c > hi ? c : hi;
+      }
+    }
+  }
+  block_range_commit((int64_t)lo, (int64_t)hi, 0, slot);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_ewise_pack32(int op, PackedOperand a, PackedOperand b,
+                                                      int64_t scalar, uint64_t n, int out_bits,
+                                                      uint32_t *__restrict__ out, uint64_t cap32,
+                                                      uint64_t ngroups_out) {
+  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroups_out) return;
+  const uint64_t w0 = g * (uint64_t)out_bits;
+  const uint64_t ngroups_in = (n + kGroup - 1) / kGroup;
+  uint32_t vc[kGroup];
+  if (g >= ngroups_in) {
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) vc[i] = 0;
+  } else {
+    uint32_t vb[kGroup];
+    codec::decode32_rt(a.w + g * (uint64_t)a.bits, a.bits, a.sgn, vc);
+    if (op == EW_ADD) codec::decode32_rt(b.w + g * (uint64_t)b.bits, b.bits, b.sgn, vb);
+    const uint64_t e0 = g * kGroup;
+    const VT sc = (VT)scalar;
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i)
+      vc[i] = e0 + i < n ? (uint32_t)ewise_value32<VT>(op, (VT)vc[i],
+                                                        op == EW_ADD ? (VT)vb[i] : (VT)0, sc)
+                         : 0u;
+  }
+  codec::encode32_rt(vc, out_bits, out + w0, cap32 - w0);
 }
 
 __global__ void k_fill_i64(int64_t *p, uint64_t n, int64_t v) {
@@ -278,7 +347,7 @@ inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap = 1u <<
 }  // namespace
 
 hipError_t launch_range_init(RangeSlot *slot, hipStream_t s) {
-  k_range_init<<<1, 1, 0, s>>>(slot);
+  k_range_init<<<1, kRangeSpread, 0, s>>>(slot);
   return hipGetLastError();
 }
 
@@ -331,18 +400,31 @@ hipError_t launch_get_one(const uint32_t *w, uint64_t e, int bits, int sgn, int6
 }
 
 hipError_t launch_ewise_range(int op, PackedOperand a, PackedOperand b, int64_t scalar,
-                              uint64_t n, RangeSlot *slot, hipStream_t s) {
+                              uint64_t n, int vclass, RangeSlot *slot, hipStream_t s) {
   const uint64_t ngroups = (n + kGroup - 1) / kGroup;
-  k_ewise_range<<<grid_for(ngroups, 256, 0x7fffffffu), 256, 0, s>>>(op, a, b, scalar, n, slot);
+  const unsigned grid = grid_for(ngroups, 256, 2048);
+  if (vclass == EW_I32)
+    k_ewise_range32<int32_t><<<grid, 256, 0, s>>>(op, a, b, scalar, n, slot);
+  else if (vclass == EW_U32)
+    k_ewise_range32<uint32_t><<<grid, 256, 0, s>>>(op, a, b, scalar, n, slot);
+  else
+    k_ewise_range<<<grid, 256, 0, s>>>(op, a, b, scalar, n, slot);
   return hipGetLastError();
 }
 
 hipError_t launch_ewise_pack(int op, PackedOperand a, PackedOperand b, int64_t scalar,
-                             uint64_t n, int out_bits, uint32_t *out, uint64_t cap32,
+                             uint64_t n, int vclass, int out_bits, uint32_t *out, uint64_t cap32,
                              hipStream_t s) {
   const uint64_t ngroups_out = (cap32 + out_bits - 1) / out_bits;
-  k_ewise_pack<<<grid_for(ngroups_out, 256, 0x7fffffffu), 256, 0, s>>>(
-      op, a, b, scalar, n, out_bits, out, cap32, ngroups_out);
+  const unsigned grid = grid_for(ngroups_out, 256, 0x7fffffffu);
+  if (vclass == EW_I32 && out_bits <= 32)
+    k_ewise_pack32<int32_t><<<grid, 256, 0, s>>>(op, a, b, scalar, n, out_bits, out, cap32,
+                                                  ngroups_out);
+  else if (vclass == EW_U32 && out_bits <= 32)
+    k_ewise_pack32<uint32_t><<<grid, 256, 0, s>>>(op, a, b, scalar, n, out_bits, out, cap32,
+                                                   ngroups_out);
+  else
+    k_ewise_pack<<<grid, 256, 0, s>>>(op, a, b, scalar, n, out_bits, out, cap32, ngroups_out);
   return hipGetLastError();
 }
 
@@ -368,7 +450,7 @@ hipError_t launch_fill_uniform(void *dense, int dtype, uint64_t n, int64_t lo, u
 
 hipError_t launch_gen_range(uint64_t n, int64_t lo, uint64_t span, uint64_t seed,
                             uint64_t stream_id, RangeSlot *slot, hipStream_t s) {
-  k_gen_range<<<grid_for(n, 256 * 16, 8192), 256, 0, s>>>(n, lo, span, seed, stream_id, slot);
+  k_gen_range<<<grid_for(n, 256 * 16, 2048), 256, 0, s>>>(n, lo, span, seed, stream_id, slot);
   return hipGetLastError();
 }
 

@@ -126,6 +126,45 @@ def test_add_matches_oracle(ba, sa, bb, sb):
         assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B))), ref)
 
 
+# Operand ranges at the edges of the 32-bit elementwise classes (every operand
+# and result in int32, or all non-negative with results below 2^32) and just
+# past them, so each class and the int64 path meet their boundary values.
+EDGE_PAIRS = [
+    ((-2**31, 0), (0, 2**31 - 1)),            # int32 class, result spans int32
+    ((-2**31, -1), (-1, 0)),                  # result reaches -2^31 - 1: int64
+    ((0, 2**32 - 1), (0, 0)),                 # uint32 class, result up to 2^32 - 1
+    ((0, 2**31), (0, 2**31 - 1)),             # uint32 class, result 2^32 - 1
+    ((0, 2**32 - 1), (0, 1)),                 # result 2^32: int64
+    ((-5, 2**31 - 1), (0, 1)),                # result 2^31 with a signed operand: int64
+]
+
+
+@pytest.mark.parametrize("ra,rb", EDGE_PAIRS)
+def test_add_class_edges(ra, rb):
+    c = ccm()
+    rng = np.random.default_rng(abs(ra[0]) % 97 + rb[1] % 89)
+    for rows, cols in ((3, 40), (65, 97)):
+        A = rng.integers(ra[0], ra[1], size=(rows, cols), endpoint=True, dtype=np.int64)
+        B = rng.integers(rb[0], rb[1], size=(rows, cols), endpoint=True, dtype=np.int64)
+        # both extremes of each operand, paired so the result extremes occur too
+        A.flat[0], B.flat[0] = ra[0], rb[0]
+        A.flat[1], B.flat[1] = ra[1], rb[1]
+        ref = oracle.add(oracle.compress(A), oracle.compress(B))
+        assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B))), ref)
+
+
+@pytest.mark.parametrize("r,s", [((-2**31, 2**31 - 1), 1), ((-2**31, 2**31 - 1), -1),
+                                 ((-2**15, 2**15 - 1), 2**16), ((0, 2**16 - 1), 2**16 + 1),
+                                 ((0, 2**31 - 1), 2), ((0, 2**32 - 1), 1), ((-7, 9), -(2**28))])
+def test_scale_class_edges(r, s):
+    c = ccm()
+    rng = np.random.default_rng(r[1] % 1000 + abs(s) % 1000)
+    A = rng.integers(r[0], r[1], size=(17, 70), endpoint=True, dtype=np.int64)
+    A.flat[0], A.flat[1] = r[0], r[1]
+    ref = oracle.scale(oracle.compress(A), s)
+    assert_same_packed(c.scale(c.compress(dev(A)), s), ref)
+
+
 def test_add_overflow_and_shape():
     c = ccm()
     a = c.compress(dev(np.array([[2**63 - 1, 0]])))
