@@ -109,6 +109,15 @@ def serving(torch, ccm, target_bytes=200e9, count=2000, log=None):
     arena = max(1 << 30, free - (16 << 30))
     srv = serve.Server(pool, arena_bytes=arena, streams=4, max_inflight=512, max_batch=256)
     seed = W.seed_for(5, 2)
+    # warm-up, untimed: one matvec per pool matrix (loads every kernel the
+    # pool's shapes and widths use, as a server does at start), then a short
+    # burst through the serving loop
+    xw = torch.ones(max(m.cols for m in pool), dtype=torch.int32, device="cuda")
+    yw = torch.empty(max(m.rows for m in pool), dtype=torch.int64, device="cuda")
+    for m in pool:
+        ccm.matvec(m, xw[: m.cols], yw[: m.rows])
+    torch.cuda.synchronize()
+    del xw, yw
     warm = serve.make_requests(pool, 200, None, seed, first_rid=10_000_000)
     srv.run(warm)
     burst = serve.make_requests(pool, count, None, seed)

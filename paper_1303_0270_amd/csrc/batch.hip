@@ -52,17 +52,11 @@ struct Item {
   int32_t rif;  // rows in flight per lane (1 or 2)
 };
 
-// Sum over aligned segments of L lanes (L a power of two, wave-uniform, all
-// lanes active); every lane of a segment gets its total.  Up to 16 lanes the
-// steps are DPP swaps inside a 16-lane row (quad swaps, half-row and row
-// mirrors); wider segments finish with shuffles.
+// Sum over aligned segments of L lanes (L a power of two); lane j%L == 0
+// holds the segment's total.
 __device__ __forceinline__ int64_t seg_sum(int64_t v, int L) {
   uint64_t u = (uint64_t)v;
-  if (L > 1) u = dpp_add64<0xB1>(u);   // quad_perm [1,0,3,2]
-  if (L > 2) u = dpp_add64<0x4E>(u);   // quad_perm [2,3,0,1]
-  if (L > 4) u = dpp_add64<0x141>(u);  // row_half_mirror
-  if (L > 8) u = dpp_add64<0x140>(u);  // row_mirror
-  for (int m = 16; m < L; m <<= 1) u += (uint64_t)__shfl_xor((int64_t)u, m, 64);
+  for (int m = 1; m < L; m <<= 1) u += (uint64_t)__shfl_xor((int64_t)u, m, 64);
   return (int64_t)u;
 }
 
