@@ -171,7 +171,8 @@ int ccm_matvec(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, voi
  * through int8 MFMA tiles with exact integer accumulation; others through an
  * exact int64 path.
  *   scratch_bytes: device scratch the two calls need (dense C at 4 or 8 bytes
- *     per entry).
+ *     per entry; on the int8 path also A and B^T decoded to int8, K padded
+ *     to a multiple of 128).
  *   plan: computes C into scratch and its exact range, fills out (payload
  *     NULL).  Blocking.
  *   op: packs the scratch into out->payload.  Async.

@@ -420,8 +420,8 @@ int ccm_matvec(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, voi
 }
 
 // Scratch layout of a matmul: dense C (int32 when the bound allows, else
-// int64), rounded up to 256 bytes, then -- on the int8 MFMA path -- B
-// re-packed column-major.  The MFMA path is taken when both operands' values
+// int64), rounded up to 256 bytes, then -- on the int8 MFMA path -- A and
+// B^T decoded to int8.  The MFMA path is taken when both operands' values
 // fit int8 and the bound K*max|A|*max|B| < 2^31 keeps int32 sums exact.
 struct MatmulPlan {
   int out32, use_i8;
@@ -435,7 +435,7 @@ static bool matmul_layout(const ccm_desc *a, const ccm_desc *b, MatmulPlan *p) {
   p->use_i8 = (p->out32 && fits_i8(a) && fits_i8(b)) ? 1 : 0;
   const uint64_t c = (p->out32 ? 4u : 8u) * (uint64_t)a->rows * (uint64_t)b->cols;
   p->c_bytes = (c + 255u) / 256u * 256u;
-  p->total = p->c_bytes + (p->use_i8 ? 4u * ccm::matmul_bt_words32(b->rows, b->cols, b->bits) : 0u);
+  p->total = p->c_bytes + (p->use_i8 ? ccm::matmul_i8_bytes(a->rows, a->cols, b->cols) : 0u);
   return true;
 }
 

@@ -277,12 +277,12 @@ hipError_t launch_matmul(const uint32_t *aw, int abits, int asgn, const uint32_t
                          int out32, void *scratch, RangeSlot *slot, hipStream_t s);
 
 // int8 MFMA matmul (operands whose values fit int8, K*max|A|*max|B| < 2^31):
-// B is re-packed column-major into scratch_bt (matmul_bt_words32 words).
-uint64_t matmul_bt_words32(int64_t K, int64_t N, int bbits);
+// The int8 MFMA path decodes A (M x K) and B^T (N x K) into int8 scratch,
+// K padded to a multiple of 128: matmul_i8_bytes bytes.
+uint64_t matmul_i8_bytes(int64_t M, int64_t K, int64_t N);
 hipError_t launch_matmul_i8(const uint32_t *aw, int abits, int asgn, const uint32_t *bw,
                             int bbits, int bsgn, int64_t M, int64_t K, int64_t N, int out32,
-                            void *scratch_c, uint32_t *scratch_bt, RangeSlot *slot,
-                            hipStream_t s);
+                            void *scratch_c, int8_t *scratch_i8, RangeSlot *slot, hipStream_t s);
 
 // synthetic data
 hipError_t launch_fill_uniform(void *dense, int dtype, uint64_t n, int64_t lo, uint64_t span,

@@ -90,156 +90,202 @@ hipError_t launch_generic(const uint32_t *aw, int abits, int asgn, const uint32_
 
 // ---- int8 MFMA path --------------------------------------------------------
 //
-// B (K x N, row-major) is first re-packed column-major at the same width (the
-// other unravel order the paper allows), so that both operands hold K
-// contiguously: A as M rows of K, Bt as N rows of K.  Every K-chunk of a
-// 128 x 128 output tile is then decoded from the packed fields straight into
-// int8 LDS tiles and multiplied with v_mfma_i32_32x32x32_i8.  A and B operand
-// lanes use the same assignment of the 32 K values of a step to (lane half,
-// byte), so the products summed per output are exactly those of the dot
-// product.  int32 accumulation is exact because the host only takes this
-// path when K * max|A| * max|B| < 2^31.
+// Both operands are first decoded once into int8 scratch with K contiguous
+// and zero-padded to a multiple of the K chunk: A as M rows, B transposed as N rows
+// (B^T, the paper's other unravel order).  Decoding inside the GEMM's K loop
+// would redo it for every output tile (N/256 times per A element) and read
+// the packed rows one lane per row, which the memory pipeline serves one
+// cache line per lane; decoded once, the tiles stream with coalesced 16-byte
+// loads.  The GEMM then multiplies 256x256 output tiles per 1024-lane block
+// (sixteen waves, each a 64x64 block of 2x2 32x32 accumulators) with
+// v_mfma_i32_32x32x32_i8 over double-buffered LDS tiles, K in chunks of 128:
+// the next chunk is loaded into registers before the current chunk's MFMAs
+// and stored to the other buffer after them (tile shape, wave shape and chunk
+// length measured against 128x64 waves and 64-byte chunks on the 8192^3
+// product).  A and B operand lanes use the same assignment of
+// the 32 K values of a step to (lane half, byte), so the products summed per
+// output are exactly those of the dot product.  int32 accumulation is exact
+// because the host only takes this path when K * max|A| * max|B| < 2^31.
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
-// Bt[n][k] = B[k][n]: lane g builds output group g of the column-major stream
-// (elements 32g..32g+31, walking k within column n and wrapping to n+1).
-__global__ __launch_bounds__(256) void k_transpose_packed(const uint32_t *__restrict__ bw,
-                                                          int bits, int sgn, int64_t K,
-                                                          int64_t N, uint32_t *__restrict__ out,
-                                                          uint64_t cap32, uint64_t ngroups_out) {
-  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ngroups_out) return;
-  const uint64_t n_elems = (uint64_t)K * (uint64_t)N;
-  uint64_t e = g * kGroup;
-  int64_t n = (int64_t)(e / (uint64_t)K), k = (int64_t)(e % (uint64_t)K);
-  int64_t v[kGroup];
-#pragma unroll
-  for (int i = 0; i < kGroup; ++i) {
-    v[i] = (e + i < n_elems) ? value_at(bw, (uint64_t)(k * N + n), bits, sgn) : 0;
-    if (++k == K) {
-      k = 0;
-      ++n;
-    }
-  }
-  const uint64_t w0 = g * (uint64_t)bits;
-  codec::encode_rt(v, bits, out + w0, cap32 - w0);
+constexpr int kBM = 256, kBN = 256, kBK = 128, kPitch8 = kBK + 16;  // LDS row pitch, bytes
+constexpr int kWM = 64, kWN = 64;  // output rows and columns per wave
+constexpr int kFM = kWM / 32, kFN = kWN / 32;  // 32x32 accumulator blocks per wave
+constexpr int kGemmThreads = 64 * (kBM / kWM) * (kBN / kWN);
+constexpr size_t kGemmLds = 2u * (kBM + kBN) * kPitch8;  // two buffers of A and B tiles
+
+__host__ __device__ inline int64_t padded_k(int64_t K) { return (K + kBK - 1) / kBK * kBK; }
+
+// Four int8 fields (values fit int8) into one word, byte i = field i.
+__device__ __forceinline__ uint32_t bytes4(int32_t a, int32_t b, int32_t c, int32_t d) {
+  return (uint32_t)(a & 0xff) | ((uint32_t)(b & 0xff) << 8) | ((uint32_t)(c & 0xff) << 16) |
+         ((uint32_t)(d & 0xff) << 24);
 }
 
-constexpr int kMT = 128, kNT = 128, kKT = 64, kLdsPitch = kKT + 16;  // bytes per tile row
-
-// Decodes row `row` (global index r of a rows x K stream), K-chunk [k0, k0+64)
-// into 64 int8 values at dst.  Elements past K or rows past `rows` are zero.
+// out[row][c .. c+32) = A[row][c .. c+32) as int8 (zero at or past K); one
+// block per row, lane j takes columns 32j..32j+31 (one group's worth of fields,
+// re-aligned with a funnel shift when the row starts inside a word).
 template <int B>
-__device__ __forceinline__ void decode_row_chunk(const uint32_t *__restrict__ w, int sgn,
-                                                 int64_t r, int64_t rows, int64_t K, int64_t k0,
-                                                 int8_t *dst) {
-  uint32_t packed[16];
+__global__ __launch_bounds__(256) void k_decode_rows_i8(const uint32_t *__restrict__ w,
+                                                        uint64_t cap, int sgn, int64_t K,
+                                                        int64_t ldk, int8_t *__restrict__ out) {
+  const int64_t row = blockIdx.x;
+  for (int64_t c = 32 * (int64_t)threadIdx.x; c < ldk; c += 32 * 256) {
+    uint32_t o[8];
+    if (c < K) {
+      const uint64_t bit = ((uint64_t)row * (uint64_t)K + (uint64_t)c) * B;
+      const uint64_t w0 = bit >> 5;
+      const int sh = (int)(bit & 31u);
+      uint32_t ww[B + 1];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) packed[q] = 0;
-  if (r < rows) {
+      for (int q = 0; q <= B; ++q) ww[q] = w[w0 + q < cap ? w0 + q : cap - 1];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t kb = k0 + 32 * h;
-      if (kb < K) {
-        const uint64_t bit = ((uint64_t)r * (uint64_t)K + (uint64_t)kb) * (uint64_t)B;
-        const uint32_t *p = w + (bit >> 5);
-        const int s = (int)(bit & 31u);
-        uint32_t ww[B + 1];
+      for (int q = 0; q < B; ++q) ww[q] = __builtin_amdgcn_alignbit(ww[q + 1], ww[q], sh);
+      const int lim = K - c < 32 ? (int)(K - c) : 32;
+      int32_t v[32];
 #pragma unroll
-        for (int q = 0; q <= B; ++q) ww[q] = p[q];
-        if (s != 0) {
-#pragma unroll
-          for (int q = 0; q < B; ++q) ww[q] = __builtin_amdgcn_alignbit(ww[q + 1], ww[q], s);
-        }
-        const int lim = K - kb < 32 ? (int)(K - kb) : 32;
-#pragma unroll
-        for (int i = 0; i < 32; ++i) {
-          const uint64_t u = codec::field<B>(ww, i);
-          int32_t v = sgn ? (int32_t)sext64(u, B) : (int32_t)u;
-          if (i >= lim) v = 0;
-          packed[8 * h + i / 4] |= ((uint32_t)v & 0xffu) << (8 * (i % 4));
-        }
+      for (int i = 0; i < 32; ++i) {
+        const uint64_t u = codec::field<B>(ww, i);
+        v[i] = i < lim ? (sgn ? (int32_t)sext64(u, B) : (int32_t)u) : 0;
       }
-    }
-  }
-  uint4 *d = reinterpret_cast<uint4 *>(dst);
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    d[q] = make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
+      for (int q = 0; q < 8; ++q) o[q] = bytes4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) o[q] = 0;
+    }
+    uint4 *d = reinterpret_cast<uint4 *>(out + row * ldk + c);
+    d[0] = make_uint4(o[0], o[1], o[2], o[3]);
+    d[1] = make_uint4(o[4], o[5], o[6], o[7]);
+  }
 }
 
-__device__ __forceinline__ void decode_row_chunk_rt(const uint32_t *w, int bits, int sgn,
-                                                    int64_t r, int64_t rows, int64_t K,
-                                                    int64_t k0, int8_t *dst) {
-  switch (bits) {
-    case 1: decode_row_chunk<1>(w, sgn, r, rows, K, k0, dst); break;
-    case 2: decode_row_chunk<2>(w, sgn, r, rows, K, k0, dst); break;
-    case 3: decode_row_chunk<3>(w, sgn, r, rows, K, k0, dst); break;
-    case 4: decode_row_chunk<4>(w, sgn, r, rows, K, k0, dst); break;
-    case 5: decode_row_chunk<5>(w, sgn, r, rows, K, k0, dst); break;
-    case 6: decode_row_chunk<6>(w, sgn, r, rows, K, k0, dst); break;
-    case 7: decode_row_chunk<7>(w, sgn, r, rows, K, k0, dst); break;
-    default: decode_row_chunk<8>(w, sgn, r, rows, K, k0, dst); break;
+// out[n][k] = B[k][n] as int8 (zero at or past K): lane l of a wave takes
+// column n0 + l, so each step reads 64 neighbouring fields of one row of B;
+// the wave's 32 consecutive k are packed into 32 bytes.
+template <int B>
+__global__ __launch_bounds__(256) void k_decode_cols_i8(const uint32_t *__restrict__ w,
+                                                        uint64_t cap, int sgn, int64_t K,
+                                                        int64_t N, int64_t ldk,
+                                                        int8_t *__restrict__ out) {
+  const int64_t n = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int64_t k0 = (int64_t)blockIdx.y * 128 + 32 * (threadIdx.x >> 6);
+  if (n >= N || k0 >= ldk) return;
+  int32_t v[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const int64_t k = k0 + i;
+    v[i] = 0;
+    if (k < K) {
+      const uint64_t bit = ((uint64_t)k * (uint64_t)N + (uint64_t)n) * B;
+      const uint64_t w0 = bit >> 5;
+      uint32_t u;
+      if constexpr (32 % B == 0) {  // fields never straddle a word
+        u = (w[w0] >> (bit & 31u)) & ((1u << B) - 1u);
+      } else {
+        const uint32_t lo = w[w0], hi = w[w0 + 1 < cap ? w0 + 1 : cap - 1];
+        u = __builtin_amdgcn_alignbit(hi, lo, (int)(bit & 31u)) & ((1u << B) - 1u);
+      }
+      v[i] = sgn ? ((int32_t)(u << (32 - B)) >> (32 - B)) : (int32_t)u;
+    }
   }
+  uint4 *d = reinterpret_cast<uint4 *>(out + n * ldk + k0);
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+    d[q] = make_uint4(bytes4(v[16 * q], v[16 * q + 1], v[16 * q + 2], v[16 * q + 3]),
+                      bytes4(v[16 * q + 4], v[16 * q + 5], v[16 * q + 6], v[16 * q + 7]),
+                      bytes4(v[16 * q + 8], v[16 * q + 9], v[16 * q + 10], v[16 * q + 11]),
+                      bytes4(v[16 * q + 12], v[16 * q + 13], v[16 * q + 14], v[16 * q + 15]));
 }
 
 template <typename OT>
-__global__ __launch_bounds__(256) void k_gemm_i8(const uint32_t *__restrict__ aw, int abits,
-                                                 int asgn, const uint32_t *__restrict__ btw,
-                                                 int bbits, int bsgn, int64_t M, int64_t K,
-                                                 int64_t N, OT *__restrict__ C, RangeSlot *slot) {
-  __shared__ __align__(16) int8_t As[kMT * kLdsPitch];
-  __shared__ __align__(16) int8_t Bs[kNT * kLdsPitch];
-  const int64_t m0 = (int64_t)blockIdx.y * kMT, n0 = (int64_t)blockIdx.x * kNT;
+__global__ __launch_bounds__(kGemmThreads) void k_gemm_i8(const int8_t *__restrict__ A,
+                                                          const int8_t *__restrict__ Bt, int64_t M,
+                                                          int64_t N, int64_t ldk,
+                                                          OT *__restrict__ C, RangeSlot *slot) {
+  extern __shared__ __align__(16) int8_t gemm_lds[];
+  // buffer b: A tile at b * (kBM + kBN) * kPitch8, then the B tile
+  auto tile = [&](int b, int opnd) {
+    return gemm_lds + b * (kBM + kBN) * kPitch8 + opnd * kBM * kPitch8;
+  };
+  const int64_t m0 = (int64_t)blockIdx.y * kBM, n0 = (int64_t)blockIdx.x * kBN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;  // 64 x 64 quadrant of the tile
-  v16i acc[2][2];
+  const int wm = wave / (kBN / kWN), wn = wave % (kBN / kWN);  // the wave's kWM x kWN block
+
+  // tile loads: 2 operands x 256 rows x kBK/16 pieces of 16 bytes, NP per
+  // lane: lane t takes piece t % kPR of rows t / kPR + kRP * j; rows past the
+  // end read the last row (their products land only in outputs not stored)
+  constexpr int kPR = kBK / 16, kRP = kGemmThreads / kPR, kNP = 2 * kBM / kRP;
+  const int prow = tid / kPR, pq = tid % kPR;
+  const int lds0 = prow * kPitch8 + 16 * pq;
+  v4u pre[kNP];  // native vectors: an array of uint4 structs is not kept in registers
+#define CCM_GEMM_LOAD(k0)                                                               \
+  _Pragma("unroll") for (int j = 0; j < kNP; ++j) {                                     \
+    const int opnd = j / (kBM / kRP);                                                   \
+    const int64_t r = (opnd ? n0 : m0) + prow + kRP * (j % (kBM / kRP));                \
+    const int64_t lim = opnd ? N : M;                                                   \
+    pre[j] = *reinterpret_cast<const v4u *>((opnd ? Bt : A) + (r < lim ? r : lim - 1) * ldk + \
+                                              16 * pq + (k0));                          \
+  }
+#define CCM_GEMM_STORE(b)                                                               \
+  _Pragma("unroll") for (int j = 0; j < kNP; ++j) {                                     \
+    const int opnd = j / (kBM / kRP);                                                   \
+    *reinterpret_cast<v4u *>(gemm_lds + (b) * (kBM + kBN) * kPitch8 + opnd * kBM * kPitch8 + \
+                               lds0 + kRP * (j % (kBM / kRP)) * kPitch8) = pre[j];      \
+  }
+
+  v16i acc[kFM][kFN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < kFM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < kFN; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
 
-  for (int64_t k0 = 0; k0 < K; k0 += kKT) {
-    // 256 lanes decode 128 A rows and 128 Bt rows, one 64-element chunk each
-    if (tid < 128)
-      decode_row_chunk_rt(aw, abits, asgn, m0 + tid, M, K, k0, As + tid * kLdsPitch);
-    else
-      decode_row_chunk_rt(btw, bbits, bsgn, n0 + (tid - 128), N, K, k0,
-                          Bs + (tid - 128) * kLdsPitch);
-    __syncthreads();
+  const int64_t nk = ldk / kBK;
+  CCM_GEMM_LOAD(0);
+  CCM_GEMM_STORE(0);
+  __syncthreads();
+  for (int64_t kc = 0; kc < nk; ++kc) {
+    const int cur = (int)(kc & 1);
+    if (kc + 1 < nk) CCM_GEMM_LOAD((kc + 1) * kBK);  // in flight during the MFMAs
+    const int8_t *as = tile(cur, 0), *bs = tile(cur, 1);
 #pragma unroll
-    for (int kk = 0; kk < kKT; kk += 32) {
+    for (int kk = 0; kk < kBK; kk += 32) {
       const int koff = kk + 16 * (lane >> 5);
-      v4i a[2], b[2];
+      v4i a[kFM], b[kFN];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[t] = *reinterpret_cast<const v4i *>(As + (wm * 64 + t * 32 + (lane & 31)) * kLdsPitch + koff);
-        b[t] = *reinterpret_cast<const v4i *>(Bs + (wn * 64 + t * 32 + (lane & 31)) * kLdsPitch + koff);
-      }
+      for (int t = 0; t < kFM; ++t)
+        a[t] = *reinterpret_cast<const v4i *>(as + (wm * kWM + t * 32 + (lane & 31)) * kPitch8 + koff);
 #pragma unroll
-      for (int ta = 0; ta < 2; ++ta)
+      for (int t = 0; t < kFN; ++t)
+        b[t] = *reinterpret_cast<const v4i *>(bs + (wn * kWN + t * 32 + (lane & 31)) * kPitch8 + koff);
 #pragma unroll
-        for (int tb = 0; tb < 2; ++tb)
+      for (int ta = 0; ta < kFM; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < kFN; ++tb)
           acc[ta][tb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
     }
-    __syncthreads();
+    if (kc + 1 < nk) CCM_GEMM_STORE(cur ^ 1);
+    __syncthreads();  // the next buffer is written and this one is read
   }
+#undef CCM_GEMM_LOAD
+#undef CCM_GEMM_STORE
 
   // 32x32 accumulator layout: lane l, register r -> column l%32,
   // row 8*(r/4) + 4*(l/32) + r%4
   int64_t lo = INT64_MAX, hi = INT64_MIN;
 #pragma unroll
-  for (int ta = 0; ta < 2; ++ta)
+  for (int ta = 0; ta < kFM; ++ta)
 #pragma unroll
-    for (int tb = 0; tb < 2; ++tb)
+    for (int tb = 0; tb < kFN; ++tb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int64_t i = m0 + wm * 64 + ta * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-        const int64_t j = n0 + wn * 64 + tb * 32 + (lane & 31);
+        const int64_t i = m0 + wm * kWM + ta * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+        const int64_t j = n0 + wn * kWN + tb * 32 + (lane & 31);
         if (i < M && j < N) {
           const int64_t v = acc[ta][tb][r];
           C[i * N + j] = (OT)v;
@@ -252,27 +298,58 @@ __global__ __launch_bounds__(256) void k_gemm_i8(const uint32_t *__restrict__ aw
 
 }  // namespace
 
-uint64_t matmul_bt_words32(int64_t K, int64_t N, int bbits) {
-  return cap_words32((uint64_t)K * (uint64_t)N, bbits);
+uint64_t matmul_i8_bytes(int64_t M, int64_t K, int64_t N) {
+  return ((uint64_t)(M + N) * (uint64_t)padded_k(K) + 255u) / 256u * 256u;
 }
 
 hipError_t launch_matmul_i8(const uint32_t *aw, int abits, int asgn, const uint32_t *bw,
                             int bbits, int bsgn, int64_t M, int64_t K, int64_t N, int out32,
-                            void *scratch_c, uint32_t *scratch_bt, RangeSlot *slot,
-                            hipStream_t s) {
-  const uint64_t cap = matmul_bt_words32(K, N, bbits);
-  const uint64_t ngroups = (cap + bbits - 1) / bbits;
-  k_transpose_packed<<<(unsigned)((ngroups + 255) / 256), 256, 0, s>>>(bw, bbits, bsgn, K, N,
-                                                                       scratch_bt, cap, ngroups);
+                            void *scratch_c, int8_t *scratch_i8, RangeSlot *slot, hipStream_t s) {
+  const int64_t ldk = padded_k(K);
+  if (M > 0x7fffffffll || (N + 63) / 64 > 0x7fffffffll || ldk / 128 + 1 > 65535 ||
+      (N + kBN - 1) / kBN > 0x7fffffffll || (M + kBM - 1) / kBM > 65535)
+    return hipErrorInvalidValue;
+  int8_t *ai8 = scratch_i8, *bti8 = scratch_i8 + M * ldk;
+  const uint64_t acap = cap_words32((uint64_t)M * (uint64_t)K, abits);
+  const uint64_t bcap = cap_words32((uint64_t)K * (uint64_t)N, bbits);
+  const dim3 cgrid((unsigned)((N + 63) / 64), (unsigned)((ldk + 127) / 128));
+  switch (abits) {
+#define CCM_DEC_A(b)                                                                              \
+  case b:                                                                                         \
+    k_decode_rows_i8<b><<<(unsigned)M, 256, 0, s>>>(aw, acap, asgn, K, ldk, ai8);                 \
+    break;
+    CCM_DEC_A(1) CCM_DEC_A(2) CCM_DEC_A(3) CCM_DEC_A(4) CCM_DEC_A(5) CCM_DEC_A(6) CCM_DEC_A(7)
+    CCM_DEC_A(8)
+#undef CCM_DEC_A
+    default: return hipErrorInvalidValue;
+  }
+  switch (bbits) {
+#define CCM_DEC_B(b)                                                                            \
+  case b:                                                                                       \
+    k_decode_cols_i8<b><<<cgrid, 256, 0, s>>>(bw, bcap, bsgn, K, N, ldk, bti8);                 \
+    break;
+    CCM_DEC_B(1) CCM_DEC_B(2) CCM_DEC_B(3) CCM_DEC_B(4) CCM_DEC_B(5) CCM_DEC_B(6) CCM_DEC_B(7)
+    CCM_DEC_B(8)
+#undef CCM_DEC_B
+    default: return hipErrorInvalidValue;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  dim3 grid((unsigned)((N + kNT - 1) / kNT), (unsigned)((M + kMT - 1) / kMT));
+  dim3 grid((unsigned)((N + kBN - 1) / kBN), (unsigned)((M + kBM - 1) / kBM));
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_gemm_i8<int32_t>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_gemm_i8<int64_t>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds);
+    attr = true;
+  }
   if (out32)
-    k_gemm_i8<int32_t><<<grid, 256, 0, s>>>(aw, abits, asgn, scratch_bt, bbits, bsgn, M, K, N,
-                                            (int32_t *)scratch_c, slot);
+    k_gemm_i8<int32_t><<<grid, kGemmThreads, kGemmLds, s>>>(ai8, bti8, M, N, ldk,
+                                                             (int32_t *)scratch_c, slot);
   else
-    k_gemm_i8<int64_t><<<grid, 256, 0, s>>>(aw, abits, asgn, scratch_bt, bbits, bsgn, M, K, N,
-                                            (int64_t *)scratch_c, slot);
+    k_gemm_i8<int64_t><<<grid, kGemmThreads, kGemmLds, s>>>(ai8, bti8, M, N, ldk,
+                                                             (int64_t *)scratch_c, slot);
   return hipGetLastError();
 }
 
@@ -280,10 +357,10 @@ hipError_t launch_matmul(const uint32_t *aw, int abits, int asgn, const uint32_t
                          int bbits, int bsgn, int64_t M, int64_t K, int64_t N, int use_i8,
                          int out32, void *scratch, RangeSlot *slot, hipStream_t s) {
   if (use_i8) {
-    // scratch = [dense C, rounded up to 256 bytes][column-major B payload]
+    // scratch = [dense C, rounded up to 256 bytes][A as int8][B^T as int8]
     const uint64_t cbytes = ((out32 ? 4u : 8u) * (uint64_t)M * (uint64_t)N + 255u) / 256u * 256u;
     return launch_matmul_i8(aw, abits, asgn, bw, bbits, bsgn, M, K, N, out32, scratch,
-                            (uint32_t *)((char *)scratch + cbytes), slot, s);
+                            (int8_t *)scratch + cbytes, slot, s);
   }
   // Operands that fit in 32 bits are staged as int32 (products stay exact in
   // int64); wider ones as int64.

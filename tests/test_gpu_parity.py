@@ -233,13 +233,32 @@ def test_matvec_all_widths(b):
 def test_matmul_matches_oracle(ba, sa, bb, sb):
     c = ccm()
     rng = np.random.default_rng(ba * 7 + bb)
+    # ragged in every dimension, up to several 256 x 256 tiles and K chunks of 64
     for M, K, N in ((1, 1, 1), (5, 7, 3), (65, 33, 70), (130, 100, 129), (257, 300, 131),
-                    (128, 64, 128)):
+                    (128, 64, 128), (300, 200, 520), (513, 130, 257)):
         A = rand_matrix(rng, M, K, ba, sa)
         B = rand_matrix(rng, K, N, bb, sb)
         pa, pb = oracle.compress(A), oracle.compress(B)
         ref = oracle.matmul(pa, pb)
         assert_same_packed(c.matmul(c.compress(dev(A)), c.compress(dev(B))), ref)
+
+
+# every operand width and sign the int8 MFMA path decodes (values fit int8:
+# unsigned b <= 7, signed b <= 8), on both sides of the product
+I8_WIDTHS = [(b, False) for b in range(1, 8)] + [(b, True) for b in range(1, 9)]
+
+
+@pytest.mark.parametrize("b,signed", I8_WIDTHS)
+def test_matmul_i8_every_width(b, signed):
+    c = ccm()
+    rng = np.random.default_rng(500 + 2 * b + signed)
+    ob, osg = I8_WIDTHS[(I8_WIDTHS.index((b, signed)) + 5) % len(I8_WIDTHS)]
+    for M, K, N in ((70, 150, 90), (33, 64, 260)):
+        for A, B in ((rand_matrix(rng, M, K, b, signed), rand_matrix(rng, K, N, ob, osg)),
+                     (rand_matrix(rng, M, K, ob, osg), rand_matrix(rng, K, N, b, signed))):
+            pa, pb = oracle.compress(A), oracle.compress(B)
+            assert_same_packed(c.matmul(c.compress(dev(A)), c.compress(dev(B))),
+                               oracle.matmul(pa, pb))
 
 
 def test_matmul_overflow_rule():
