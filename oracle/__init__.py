@@ -42,9 +42,18 @@ class _Matrix(ctypes.Structure):
                 ("words", ctypes.c_uint64), ("payload", ctypes.c_void_p)]
 
 
+class _Vlb(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("vmin", ctypes.c_int64), ("vmax", ctypes.c_int64),
+                ("k", ctypes.c_int32), ("is_signed", ctypes.c_int32),
+                ("nbits", ctypes.c_uint64), ("words", ctypes.c_uint64),
+                ("payload", ctypes.c_void_p)]
+
+
 _I64P = ctypes.POINTER(ctypes.c_int64)
 _U64P = ctypes.POINTER(ctypes.c_uint64)
 _MP = ctypes.POINTER(_Matrix)
+_VP = ctypes.POINTER(_Vlb)
 _SIGNATURES = {
     "ccmref_bitlen": (ctypes.c_int, [ctypes.c_uint64]),
     "ccmref_sm_width": (ctypes.c_int, [ctypes.c_uint64]),
@@ -65,6 +74,12 @@ _SIGNATURES = {
     "ccmref_matmul_check": (ctypes.c_int, [_MP, _MP]),
     "ccmref_matmul_dense": (ctypes.c_int, [_MP, _MP, _I64P]),
     "ccmref_matmul_entries": (ctypes.c_int, [_MP, _MP, _I64P, _I64P, ctypes.c_int64, _I64P]),
+    "ccmref_vlb_width": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32]),
+    "ccmref_vlb_plan": (ctypes.c_int, [_I64P, ctypes.c_int64, ctypes.c_int64, _VP]),
+    "ccmref_vlb_compress": (ctypes.c_int, [_I64P, _VP]),
+    "ccmref_vlb_decompress": (ctypes.c_int, [_VP, _I64P]),
+    "ccmref_vlb_get": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _I64P]),
+    "ccmref_vlb_matvec": (ctypes.c_int, [_VP, _I64P, _I64P]),
 }
 
 
@@ -103,6 +118,29 @@ class Packed:
 
     def payload_bytes(self) -> bytes:
         return self.payload.astype("<u8").tobytes()
+
+
+@dataclass
+class VlbPacked:
+    """The oracle's Method 2 (VLB) matrix: k-bit length fields, each followed by
+    its element's own minimal width."""
+    rows: int
+    cols: int
+    vmin: int
+    vmax: int
+    k: int
+    is_signed: bool
+    nbits: int
+    payload: np.ndarray  # uint64 bitstrings, floor(nbits/64)+1 of them
+
+    @property
+    def words(self) -> int:
+        return int(self.payload.size)
+
+    def _struct(self) -> _Vlb:
+        return _Vlb(self.rows, self.cols, self.vmin, self.vmax, self.k,
+                    1 if self.is_signed else 0, self.nbits, self.words,
+                    self.payload.ctypes.data_as(ctypes.c_void_p))
 
 
 class Oracle:
@@ -241,6 +279,44 @@ class Oracle:
         return out
 
 
+    # -- Method 2 (VLB) -------------------------------------------------------
+    def vlb_width(self, v: int, is_signed: bool) -> int:
+        return int(self._lib.ccmref_vlb_width(v, 1 if is_signed else 0))
+
+    def vlb_compress(self, dense) -> VlbPacked:
+        d = np.ascontiguousarray(np.asarray(dense, dtype=np.int64))
+        if d.ndim != 2:
+            raise OracleError(E_INVAL)
+        m = _Vlb()
+        _check(self._lib.ccmref_vlb_plan(_i64(d), d.shape[0], d.shape[1], ctypes.byref(m)))
+        payload = np.zeros(int(m.words), dtype=np.uint64)
+        m.payload = payload.ctypes.data_as(ctypes.c_void_p)
+        _check(self._lib.ccmref_vlb_compress(_i64(d), ctypes.byref(m)))
+        return VlbPacked(int(m.rows), int(m.cols), int(m.vmin), int(m.vmax), int(m.k),
+                         bool(m.is_signed), int(m.nbits), payload)
+
+    def vlb_decompress(self, p: VlbPacked) -> np.ndarray:
+        m = p._struct()
+        out = np.empty((p.rows, p.cols), dtype=np.int64)
+        _check(self._lib.ccmref_vlb_decompress(ctypes.byref(m), _i64(out)))
+        return out
+
+    def vlb_get(self, p: VlbPacked, i: int, j: int) -> int:
+        m = p._struct()
+        v = ctypes.c_int64()
+        _check(self._lib.ccmref_vlb_get(ctypes.byref(m), i, j, ctypes.byref(v)))
+        return int(v.value)
+
+    def vlb_matvec(self, p: VlbPacked, x) -> np.ndarray:
+        m = p._struct()
+        xv = np.ascontiguousarray(np.asarray(x, dtype=np.int64))
+        if xv.size != p.cols:
+            raise OracleError(E_SHAPE)
+        y = np.empty(p.rows, dtype=np.int64)
+        _check(self._lib.ccmref_vlb_matvec(ctypes.byref(m), _i64(xv), _i64(y)))
+        return y
+
+
 def _default() -> Oracle:
     path = library_path()
     if not os.path.exists(path):
@@ -270,6 +346,11 @@ matmul_check = _ORACLE.matmul_check
 matmul_dense = _ORACLE.matmul_dense
 matmul = _ORACLE.matmul
 matmul_entries = _ORACLE.matmul_entries
+vlb_width = _ORACLE.vlb_width
+vlb_compress = _ORACLE.vlb_compress
+vlb_decompress = _ORACLE.vlb_decompress
+vlb_get = _ORACLE.vlb_get
+vlb_matvec = _ORACLE.vlb_matvec
 
 
 def threads() -> int:

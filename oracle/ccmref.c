@@ -245,3 +245,110 @@ int ccmref_matmul_entries(const ccmref_matrix *a, const ccmref_matrix *b, const 
   for (t = 0; t < n; t++) out[t] = matmul_entry(a, b, ii[t], jj[t]);
   return CCMREF_OK;
 }
+
+/* ---- Method 2: Variable Length Blocks ----------------------------------- */
+
+int ccmref_vlb_width(int64_t v, int32_t is_signed) {
+  if (!is_signed) return ccmref_sm_width((uint64_t)v); /* Eq. 1 on the element */
+  int32_t b = 0, s = 0;
+  /* the width of the one-value range [v, v] in two's complement, with the
+   * sign bit even for v >= 0 */
+  if (v < 0) {
+    ccmref_width(v, v, &b, &s);
+  } else {
+    b = 1 + ccmref_bitlen((uint64_t)v);
+  }
+  return b;
+}
+
+/* Bits [p, p+bits) of the stream get the low bits of u. */
+static void put_bits(uint64_t *words, uint64_t p, int32_t bits, uint64_t u) {
+  for (int t = 0; t < bits; t++) put_bit(words, p + (uint64_t)t, (int)((u >> t) & 1u));
+}
+
+static uint64_t get_bits(const uint64_t *words, uint64_t p, int32_t bits) {
+  uint64_t u = 0;
+  for (int t = 0; t < bits; t++) u |= (uint64_t)get_bit(words, p + (uint64_t)t) << t;
+  return u;
+}
+
+int ccmref_vlb_plan(const int64_t *dense, int64_t rows, int64_t cols, ccmref_vlb *m) {
+  if (!dense || !m || rows < 1 || cols < 1) return CCMREF_E_INVAL;
+  int64_t n = rows * cols;
+  int64_t lo = dense[0], hi = dense[0];
+  for (int64_t e = 1; e < n; e++) {
+    if (dense[e] < lo) lo = dense[e];
+    if (dense[e] > hi) hi = dense[e];
+  }
+  m->rows = rows;
+  m->cols = cols;
+  m->vmin = lo;
+  m->vmax = hi;
+  m->is_signed = lo < 0;
+  int32_t bmax = 1;
+  uint64_t sum_b = 0;
+  for (int64_t e = 0; e < n; e++) {
+    int32_t b = ccmref_vlb_width(dense[e], m->is_signed);
+    if (b > bmax) bmax = b;
+    sum_b += (uint64_t)b;
+  }
+  m->k = ccmref_bitlen((uint64_t)bmax);
+  m->nbits = (uint64_t)n * (uint64_t)m->k + sum_b;
+  m->words = m->nbits / 64u + 1u;
+  return CCMREF_OK;
+}
+
+int ccmref_vlb_compress(const int64_t *dense, ccmref_vlb *m) {
+  if (!dense || !m || !m->payload) return CCMREF_E_INVAL;
+  memset(m->payload, 0, m->words * sizeof(uint64_t));
+  uint64_t p = 0;
+  for (int64_t e = 0; e < m->rows * m->cols; e++) {
+    int32_t b = ccmref_vlb_width(dense[e], m->is_signed);
+    put_bits(m->payload, p, m->k, (uint64_t)b); /* the fixed-size length chunk */
+    p += (uint64_t)m->k;
+    put_bits(m->payload, p, b, (uint64_t)dense[e]); /* then the element itself */
+    p += (uint64_t)b;
+  }
+  return CCMREF_OK;
+}
+
+/* Decodes the element starting at stream bit *p and advances *p. */
+static int64_t vlb_next(const ccmref_vlb *m, uint64_t *p) {
+  int32_t b = (int32_t)get_bits(m->payload, *p, m->k);
+  *p += (uint64_t)m->k;
+  uint64_t u = get_bits(m->payload, *p, b);
+  *p += (uint64_t)b;
+  if (m->is_signed && ((u >> (b - 1)) & 1u) && b < 64) u -= (uint64_t)1 << b;
+  return (int64_t)u;
+}
+
+int ccmref_vlb_decompress(const ccmref_vlb *m, int64_t *dense) {
+  if (!m || !dense || !m->payload) return CCMREF_E_INVAL;
+  uint64_t p = 0;
+  for (int64_t e = 0; e < m->rows * m->cols; e++) dense[e] = vlb_next(m, &p);
+  return CCMREF_OK;
+}
+
+int ccmref_vlb_get(const ccmref_vlb *m, int64_t i, int64_t j, int64_t *out) {
+  if (!m || !out || !m->payload) return CCMREF_E_INVAL;
+  if (i < 0 || i >= m->rows || j < 0 || j >= m->cols) return CCMREF_E_RANGE;
+  uint64_t p = 0;
+  int64_t v = 0;
+  for (int64_t e = 0; e <= i * m->cols + j; e++) v = vlb_next(m, &p);
+  *out = v;
+  return CCMREF_OK;
+}
+
+int ccmref_vlb_matvec(const ccmref_vlb *m, const int64_t *x, int64_t *y) {
+  if (!m || !x || !y || !m->payload) return CCMREF_E_INVAL;
+  uint64_t p = 0;
+  for (int64_t i = 0; i < m->rows; i++) {
+    unsigned __int128 acc = 0;
+    for (int64_t j = 0; j < m->cols; j++) {
+      int64_t a = vlb_next(m, &p);
+      acc += (unsigned __int128)((__int128)a * (__int128)x[j]);
+    }
+    y[i] = (int64_t)(uint64_t)acc;
+  }
+  return CCMREF_OK;
+}

@@ -124,6 +124,54 @@ int ccmref_matmul_dense(const ccmref_matrix *a, const ccmref_matrix *b, int64_t 
 int ccmref_matmul_entries(const ccmref_matrix *a, const ccmref_matrix *b, const int64_t *ii,
                           const int64_t *jj, int64_t n, int64_t *out);
 
+/* ---- Method 2: Variable Length Blocks (VLB) ----------------------------
+ *
+ * Each element gets its own minimal width b_e, stored in a length field of a
+ * fixed k bits that precedes the element's b_e value bits; k is the
+ * bit-length of the largest b_e (Methods, "Method 2": the fixed chunk holds
+ * the bit-length of sup M, 10 -> 4 bits in the worked example).  Elements are
+ * adjacent in row-major order, least significant bit first, fields
+ * straddling bitstrings exactly as in Method 1.
+ *
+ * Readings where the paper is silent:
+ *   - b_e is Eq. 1 applied to the single element (0 and 1 take one bit); for
+ *     a matrix with a negative element every b_e is a two's complement width
+ *     (one bit more than the magnitude's bit-length), decoded by sign
+ *     extension from b_e bits;
+ *   - the length field holds b_e itself (1..64), so k = bitlen(max b_e) <= 7;
+ *   - floor(total_bits / 64) + 1 bitstrings, as for Method 1; bits past the
+ *     last field are zero;
+ *   - random access (get) is a scan from the first element: the paper gives
+ *     no index.
+ * Pins: the worked example's two bitstrings (the layout gives 91 bits; the
+ * paper's text says 87), round trips, the closed-form bit count, brute force.
+ */
+typedef struct {
+  int64_t rows, cols;
+  int64_t vmin, vmax;
+  int32_t k;          /* length-field width */
+  int32_t is_signed;  /* 1 iff vmin < 0 */
+  uint64_t nbits;     /* sum over elements of k + b_e */
+  uint64_t words;     /* floor(nbits / 64) + 1 */
+  uint64_t *payload;
+} ccmref_vlb;
+
+/* b_e of one value under the matrix's signedness. */
+int ccmref_vlb_width(int64_t v, int32_t is_signed);
+
+/* Fills everything but payload. */
+int ccmref_vlb_plan(const int64_t *dense, int64_t rows, int64_t cols, ccmref_vlb *m);
+
+/* Writes m->payload (m->words bitstrings, caller-allocated) after ccmref_vlb_plan. */
+int ccmref_vlb_compress(const int64_t *dense, ccmref_vlb *m);
+
+int ccmref_vlb_decompress(const ccmref_vlb *m, int64_t *dense);
+
+int ccmref_vlb_get(const ccmref_vlb *m, int64_t i, int64_t j, int64_t *out);
+
+/* y[i] = sum_j a[i][j] * x[j] modulo 2^64 for every row. */
+int ccmref_vlb_matvec(const ccmref_vlb *m, const int64_t *x, int64_t *y);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,8 +3,8 @@
 Each ``pin_*`` function takes an ``oracle.Oracle`` and raises AssertionError if
 the oracle disagrees with what the paper or the mathematics fixes:
 
-* values the paper prints (Table 1, Eq. 1, the worked example of Method 1 and
-  the bitstring count), read from ``tests/golden/``;
+* values the paper prints (Table 1, Eq. 1, the worked examples of Method 1
+  and Method 2 and the bitstring count), read from ``tests/golden/``;
 * closed forms (the word count, Eq. 15's bits-used relation);
 * invariants (round trips, minimality of the width, zero padding, locality of
   the encoding);
@@ -408,7 +408,146 @@ def pin_overflow_rules(o):
     assert raises(lambda: o.add(a1, a2)) == _mod.E_SHAPE
 
 
+# ---------------------------------------------------------------------------
+# Method 2 (Variable Length Blocks)
+# ---------------------------------------------------------------------------
+
+def _vlb_elem_width(v: int, signed: bool) -> int:
+    """Fewest bits holding v alone: Eq. 1 on the element when unsigned; the
+    smallest two's complement width, found by search, when signed."""
+    if not signed:
+        return max(1, v.bit_length())
+    for b in range(1, 65):
+        if -(1 << (b - 1)) <= v < (1 << (b - 1)):
+            return b
+    raise AssertionError(v)
+
+
+def _vlb_read(payload, n: int, k: int, signed: bool):
+    """Reads n (length, value) pairs from the bitstrings, least significant bit
+    first, straddling freely; returns the values, the widths and the bits used."""
+    stream = 0
+    for i, w in enumerate(payload):
+        stream |= int(w) << (64 * i)
+    p, vals, widths = 0, [], []
+    for _ in range(n):
+        b = (stream >> p) & ((1 << k) - 1)
+        p += k
+        u = (stream >> p) & ((1 << b) - 1)
+        p += b
+        if signed and b and (u >> (b - 1)) & 1:
+            u -= 1 << b
+        vals.append(u)
+        widths.append(b)
+    return vals, widths, p, stream
+
+
+def pin_vlb_worked_example(o):
+    """Method 2's worked example: the states after steps 1-3 and the two final
+    bitstrings, k = 4 and the 91 bits the printed layout uses."""
+    g = _golden_kv("vlb_worked_example.txt")
+    vals = [int(v) for v in g["values"].split()]
+    w0 = int(g["bitstring_1"].replace(" ", ""), 2)
+    w1 = int(g["bitstring_2"].replace(" ", ""), 2)
+    p = o.vlb_compress(np.array([vals], dtype=np.int64))
+    assert p.k == int(g["k"]) and not p.is_signed
+    assert p.nbits == int(g["nbits"]) and p.words == int(g["words"])
+    assert [int(w) for w in p.payload] == [w0, w1]
+    for s in (1, 2, 3):
+        q = o.vlb_compress(np.array([vals[:s]], dtype=np.int64))
+        assert q.k == 4 and q.words == 1
+        assert int(q.payload[0]) == int(g["step_%d" % s].replace(" ", ""), 2)
+    assert o.vlb_decompress(p).tolist() == [vals]
+    assert [o.vlb_get(p, 0, j) for j in range(8)] == vals
+    # Eq. 16 with these frequencies: every element's k + b_i bits
+    assert p.nbits == sum(4 + bl for _, _, bl in _table1())
+
+
+def pin_vlb_layout(o):
+    """Every stream read back by an independent sequential reader: the length
+    chunk holds the element's minimal width, k = b(b(max)) (Eq. 16's k) for
+    non-negative matrices, bits used = sum of k + b_i (Eq. 16), floor(bits/64)
+    + 1 bitstrings with zero padding; signed matrices use minimal two's
+    complement widths."""
+    rng = np.random.default_rng(21)
+    shapes = [(1, 1), (1, 7), (3, 5), (4, 33), (9, 64), (17, 31)]
+    for t in range(60):
+        r, c = shapes[t % len(shapes)]
+        signed = t % 3 == 2
+        top = int(rng.integers(1, 64))
+        lens = rng.integers(0, top + 1, size=r * c)
+        mag = np.array([int(rng.integers(0, 1 << int(L))) if L else 0 for L in lens],
+                       dtype=np.uint64)
+        v = mag.astype(np.int64)
+        if signed:
+            neg = rng.random(r * c) < 0.5
+            v = np.where(neg, -v - 1, v)
+        A = v.reshape(r, c)
+        p = o.vlb_compress(A)
+        flat = [int(e) for e in A.ravel()]
+        is_signed = min(flat) < 0
+        assert p.is_signed == is_signed
+        widths = [_vlb_elem_width(e, is_signed) for e in flat]
+        k = max(widths).bit_length()
+        if not is_signed:
+            assert k == max(1, max(flat).bit_length()).bit_length()
+        assert p.k == k
+        assert p.nbits == sum(k + b for b in widths)
+        assert p.words == p.nbits // 64 + 1
+        got, got_w, used, stream = _vlb_read(p.payload, r * c, k, is_signed)
+        assert got == flat and got_w == widths and used == p.nbits
+        assert stream >> p.nbits == 0
+        assert o.vlb_decompress(p).tolist() == A.tolist()
+
+
+def pin_vlb_extremes(o):
+    """The widest elements (64-bit, 7-bit length chunks) and the narrowest (all
+    zeros: one bit each, k = 1)."""
+    A = np.array([[-2**63, 2**63 - 1, 0, -1, 1]], dtype=np.int64)
+    p = o.vlb_compress(A)
+    assert p.is_signed and p.k == 7
+    got, widths, used, _ = _vlb_read(p.payload, 5, 7, True)
+    assert got == A.ravel().tolist() and widths == [64, 64, 1, 1, 2] and used == p.nbits
+    z = o.vlb_compress(np.zeros((3, 70), dtype=np.int64))
+    assert z.k == 1 and z.nbits == 3 * 70 * 2 and not z.is_signed
+    # each element: length chunk "1", value "0"
+    stream = sum(int(w) << (64 * i) for i, w in enumerate(z.payload))
+    assert stream == sum(1 << (2 * e) for e in range(210))
+    u = o.vlb_compress(np.array([[2**63 - 1, 1, 0]], dtype=np.int64))
+    assert not u.is_signed and u.k == 6 and u.nbits == 3 * 6 + 63 + 1 + 1
+
+
+def pin_vlb_ops_bruteforce(o):
+    """get and matvec on Method 2 matrices against Python integers (mod 2^64)."""
+    rng = np.random.default_rng(23)
+    for t in range(30):
+        r, c = int(rng.integers(1, 12)), int(rng.integers(1, 40))
+        top = [3, 10, 20, 40, 62][t % 5]
+        A = rng.integers(-(1 << top) if t % 2 else 0, 1 << top, size=(r, c), dtype=np.int64)
+        x = rng.integers(-2**62, 2**62, size=c, dtype=np.int64)
+        p = o.vlb_compress(A)
+        want = [_to_signed64(sum(int(a) * int(b) for a, b in zip(row, x))) for row in A.tolist()]
+        assert o.vlb_matvec(p, x).tolist() == want
+        for _ in range(5):
+            i, j = int(rng.integers(0, r)), int(rng.integers(0, c))
+            assert o.vlb_get(p, i, j) == int(A[i, j])
+
+
+def pin_vlb_exhaustive_small(o):
+    """Every 1 x 3 matrix with entries in [-4, 7]: stream read back exactly."""
+    for vals in itertools.product(range(-4, 8), repeat=3):
+        A = np.array([vals], dtype=np.int64)
+        p = o.vlb_compress(A)
+        signed = min(vals) < 0
+        widths = [_vlb_elem_width(v, signed) for v in vals]
+        k = max(widths).bit_length()
+        got, got_w, used, stream = _vlb_read(p.payload, 3, k, signed)
+        assert (p.k, p.nbits) == (k, used)
+        assert got == list(vals) and got_w == widths and stream >> used == 0
+
+
 ALL_PINS = [pin_table1, pin_eq1_special_case, pin_bitlen_bruteforce, pin_width_bruteforce,
             pin_worked_example, pin_word_count, pin_round_trip, pin_signed_small_bruteforce,
             pin_locality, pin_get, pin_ops_bruteforce, pin_ops_exhaustive_2x2, pin_identities,
-            pin_overflow_rules]
+            pin_overflow_rules, pin_vlb_worked_example, pin_vlb_layout, pin_vlb_extremes,
+            pin_vlb_ops_bruteforce, pin_vlb_exhaustive_small]

@@ -48,6 +48,29 @@ MUTANTS = {
                       "if (p * (unsigned __int128)(uint64_t)a->cols > lim)")],
     # signed flag ignored when decoding
     "decode_unsigned": [("if (is_signed && ((u >> (bits - 1)) & 1u)) {", "if (0) {")],
+    # Method 2: the element written before its length chunk
+    "vlb_value_first": [("put_bits(m->payload, p, m->k, (uint64_t)b); /* the fixed-size length chunk */\n"
+                         "    p += (uint64_t)m->k;\n"
+                         "    put_bits(m->payload, p, b, (uint64_t)dense[e]); /* then the element itself */\n"
+                         "    p += (uint64_t)b;",
+                         "put_bits(m->payload, p, b, (uint64_t)dense[e]);\n"
+                         "    p += (uint64_t)b;\n"
+                         "    put_bits(m->payload, p, m->k, (uint64_t)b);\n"
+                         "    p += (uint64_t)m->k;")],
+    # Method 2: k taken from the largest value instead of the largest width
+    "vlb_k_of_value": [("m->k = ccmref_bitlen((uint64_t)bmax);",
+                        "m->k = ccmref_bitlen((uint64_t)bmax) + (hi > 1);")],
+    # Method 2: the length chunk holds b - 1
+    "vlb_length_minus_one": [("put_bits(m->payload, p, m->k, (uint64_t)b);",
+                              "put_bits(m->payload, p, m->k, (uint64_t)(b - 1));")],
+    # Method 2: no sign extension on decode
+    "vlb_no_sign_extend": [("if (m->is_signed && ((u >> (b - 1)) & 1u) && b < 64)", "if (0)")],
+    # Method 2: the sign bit left out of non-negative elements of a signed matrix
+    "vlb_signed_width": [("b = 1 + ccmref_bitlen((uint64_t)v);", "b = ccmref_bitlen((uint64_t)v) + (v == 0);")],
+    # Method 2: matvec skips the last column
+    "vlb_matvec_last": [("for (int64_t j = 0; j < m->cols; j++) {\n      int64_t a = vlb_next(m, &p);",
+                         "for (int64_t j = 0; j < m->cols; j++) {\n      int64_t a = vlb_next(m, &p);\n"
+                         "      if (j == m->cols - 1) a = 0;")],
 }
 
 
