@@ -188,3 +188,91 @@ def serving_pool(target_bytes: float, max_elems: float = 1e9, max_bits: int = 20
         total += 64 + 8 * ((rows * cols * b) // 64 + 1)
         t += 1
     return out
+
+
+# ---------------------------------------------------------------------------
+# Method 2 workloads: element bit-lengths drawn from the paper's Beta
+# distributions mapped to [1, 64] (Results, "Random Matrix Generation", Eq. 18:
+# L = floor(64 x) + 1), then a value of exactly that bit-length.
+# ---------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class VlbSpec:
+    """rows x cols matrix whose element bit-lengths follow
+    (1 - w) Beta(a1, b1) + w Beta(a2, b2) on [1, 64] (w = 0: one Beta).
+
+    Element idx draws u = uniform(seed, 3*stream, idx, 0, 2^32); its bit-length
+    is L = 1 + #{l in 1..62 : u >= t_l} with t_l = floor(2^32 P(L <= l)), so
+    lengths 63 and 64 both give 63 (the largest non-negative int64 length).
+    Its value takes the low L-1 bits of r = (h << 32) | g, with h and g draws
+    of streams 3*stream + 1 and 3*stream + 2 in [0, 2^32), and sets bit L-1
+    (L = 1: the value is r & 1, i.e. 0 or 1)."""
+    rows: int
+    cols: int
+    a1: float
+    b1: float
+    seed: int
+    stream: int = 0
+    a2: float = 1.0
+    b2: float = 1.0
+    w: float = 0.0
+
+    def thresholds(self) -> np.ndarray:
+        from scipy.special import betainc
+        edges = np.arange(1, 63, dtype=np.float64) / 64.0
+        cdf = (1.0 - self.w) * betainc(self.a1, self.b1, edges)
+        if self.w:
+            cdf = cdf + self.w * betainc(self.a2, self.b2, edges)
+        t = np.floor(np.clip(cdf, 0.0, 1.0) * float(1 << 32))
+        return np.maximum.accumulate(t.astype(np.uint64))
+
+    def values(self, start: int, count: int) -> np.ndarray:
+        u = uniform(self.seed, 3 * self.stream, start, count, 0, 1 << 32).astype(np.uint64)
+        L = 1 + np.searchsorted(self.thresholds(), u, side="right").astype(np.int64)
+        h = uniform(self.seed, 3 * self.stream + 1, start, count, 0, 1 << 32).astype(np.uint64)
+        g = uniform(self.seed, 3 * self.stream + 2, start, count, 0, 1 << 32).astype(np.uint64)
+        r = (h << np.uint64(32)) | g
+        top = np.left_shift(np.uint64(1), (L - 1).astype(np.uint64))
+        v = np.where(L == 1, r & np.uint64(1), top | (r & (top - np.uint64(1))))
+        return v.astype(np.int64)
+
+    def rows_slice(self, r0: int, r1: int) -> np.ndarray:
+        return self.values(r0 * self.cols, (r1 - r0) * self.cols).reshape(r1 - r0, self.cols)
+
+    def dense(self) -> np.ndarray:
+        return self.rows_slice(0, self.rows)
+
+    def dense_device(self, fill_uniform, torch):
+        """The same matrix built on the GPU: fill_uniform(tensor, lo, hi, seed,
+        stream, start) must draw uniform(seed, stream, start + ., ., lo, hi)
+        into an int64 device tensor (the GPU library's generator does)."""
+        n = self.rows * self.cols
+        dev = torch.device("cuda")
+        u = fill_uniform(torch.empty(n, dtype=torch.int64, device=dev), 0, 1 << 32, self.seed,
+                         3 * self.stream, 0)
+        thr = torch.from_numpy(self.thresholds().astype(np.int64)).to(dev)
+        L = 1 + torch.searchsorted(thr, u, right=True)
+        del u
+        h = fill_uniform(torch.empty(n, dtype=torch.int64, device=dev), 0, 1 << 32, self.seed,
+                         3 * self.stream + 1, 0)
+        g = fill_uniform(torch.empty(n, dtype=torch.int64, device=dev), 0, 1 << 32, self.seed,
+                         3 * self.stream + 2, 0)
+        r = torch.bitwise_or(torch.bitwise_left_shift(h, 32), g)
+        del h, g
+        top = torch.bitwise_left_shift(torch.ones_like(L), L - 1)
+        v = torch.where(L == 1, r & 1, top | (r & (top - 1)))
+        return v.view(self.rows, self.cols)
+
+
+# Method 2 bandwidth workloads, n x n: bit-lengths from Beta(1, 32) (short,
+# mean about 3 bits), Beta(5, 33) (mean about 9.4 bits) and Beta(1, 1) (uniform
+# over 1..64); int32 x in [-2^15, 2^15).
+VLB_BETAS = {"beta_1_32": (1.0, 32.0), "beta_5_33": (5.0, 33.0), "beta_1_1": (1.0, 1.0)}
+
+
+def vlb_sweep(name: str, n: int = 16384):
+    a1, b1 = VLB_BETAS[name]
+    stream = sorted(VLB_BETAS).index(name)
+    a = VlbSpec(n, n, a1, b1, seed_for(6, 0), stream)
+    x = VectorSpec(n, -(1 << 15), 1 << 15, seed_for(6, 2), stream)
+    return a, x

@@ -245,6 +245,72 @@ int ccm_generate_plan(int64_t rows, int64_t cols, int64_t lo, int64_t hi, uint64
 int ccm_generate(const ccm_desc *out, int64_t lo, int64_t hi, uint64_t seed,
                  uint64_t stream_id, void *stream);
 
+/* ---- Method 2: Variable Length Blocks (Methods, "Method 2"; Eq. 16) ------
+ *
+ * Encoding: every element e has its own width b_e -- Eq. 1 applied to the
+ * element when the matrix has no negative value, else the smallest two's
+ * complement width holding it (the same sign reading as Method 1).  The
+ * stream holds, for each element in row-major order, a k-bit length field
+ * with the value b_e followed by the low b_e bits of the element, least
+ * significant bit first and straddling 64-bit bitstrings exactly as in
+ * Method 1; k is the bit-length of the largest b_e (for the worked example,
+ * largest value 1023 -> b = 10 -> k = 4).  nbits = sum over elements of
+ * (k + b_e) (Eq. 16's bits used); the canonical payload is floor(nbits/64) + 1
+ * little-endian bitstrings with every bit past nbits zero (the same count
+ * rule as Method 1).
+ *
+ * Index (this library's; the paper gives none, and the stream alone can only
+ * be read from its start): a device buffer of ccm_vlb_index_bytes(rows, cols)
+ * bytes holding row_bit[rows + 1] (uint64 at offset 0: stream bit where row i
+ * starts; row_bit[rows] = nbits) and, from the next 256-byte boundary,
+ * grp_off[rows][ceil(cols/32)] (uint32: bit offset of element (i, 32g) from
+ * row i's start).  It costs 32 bits per 32 elements plus 64 bits per row and
+ * is what lets the GPU decode groups of 32 elements in parallel and get one
+ * element by reading at most 32 pairs.  A row may hold at most 2^32 - 1 bits:
+ * cols * (k + max b_e) < 2^32, else CCM_E_UNSUPPORTED. */
+typedef struct ccm_vlb_desc {
+  int64_t rows, cols;
+  int64_t vmin, vmax;  /* exact extremes of the values */
+  int32_t k;           /* length-field width, 1..7 */
+  int32_t is_signed;   /* 1 iff vmin < 0 */
+  uint64_t nbits;      /* sum of k + b_e over the elements */
+  uint64_t words;      /* floor(nbits / 64) + 1 */
+  uint64_t gmax;       /* bits of the longest group of 32 elements of a row (sizes the
+                          matvec's staging) */
+  void *payload;       /* device, caller-owned, >= ccm_vlb_payload_capacity(nbits) bytes */
+  void *index;         /* device, caller-owned, ccm_vlb_index_bytes(rows, cols) bytes */
+} ccm_vlb_desc;
+
+/* Sizes of the caller-allocated buffers (host only; 0 for an invalid shape).
+ * The payload capacity adds guard words that kernels may read past the last
+ * field, rounded up to 256 bytes. */
+uint64_t ccm_vlb_index_bytes(int64_t rows, int64_t cols);
+uint64_t ccm_vlb_payload_capacity(uint64_t nbits);
+
+/* Plan: range pass over dense (device, rows x cols of dtype), then the index:
+ * per-group bit counts and their scans, written into `index` (device, caller
+ * allocated).  Fills every field of out (payload NULL, index = index) and
+ * reads nbits back.  Blocking. */
+int ccm_vlb_compress_plan(const void *dense, int32_t dtype, int64_t rows, int64_t cols,
+                          void *index, ccm_vlb_desc *out, void *stream);
+
+/* Packs dense into out->payload (set by the caller), zeroing its whole
+ * capacity first.  `out` must come from ccm_vlb_compress_plan over the same
+ * values.  Async. */
+int ccm_vlb_compress(const void *dense, int32_t dtype, const ccm_vlb_desc *out, void *stream);
+
+/* Every element into dense_out (device, rows*cols int64).  Async. */
+int ccm_vlb_decompress(const ccm_vlb_desc *a, int64_t *dense_out, void *stream);
+
+/* Element (i, j) into *value (host); CCM_E_RANGE outside the matrix.
+ * Blocking. */
+int ccm_vlb_get(const ccm_vlb_desc *a, int64_t i, int64_t j, int64_t *value, void *stream);
+
+/* y = A x modulo 2^64, as ccm_matvec.  x: device, cols values of xdtype;
+ * y: device, rows int64.  Async. */
+int ccm_vlb_matvec(const ccm_vlb_desc *a, const void *x, int32_t xdtype, int64_t *y,
+                   void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -80,6 +80,7 @@ _SIGNATURES = {
     "ccmref_vlb_decompress": (ctypes.c_int, [_VP, _I64P]),
     "ccmref_vlb_get": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _I64P]),
     "ccmref_vlb_matvec": (ctypes.c_int, [_VP, _I64P, _I64P]),
+    "ccmref_vlb_offsets": (ctypes.c_int, [_VP, ctypes.c_int64, _U64P]),
 }
 
 
@@ -307,6 +308,16 @@ class Oracle:
         _check(self._lib.ccmref_vlb_get(ctypes.byref(m), i, j, ctypes.byref(v)))
         return int(v.value)
 
+    def vlb_offsets(self, p: VlbPacked, group: int = 32) -> np.ndarray:
+        """Start bit of every element (i, j) with j % group == 0, as a
+        rows x ceil(cols/group) array."""
+        m = p._struct()
+        ng = (p.cols + group - 1) // group
+        out = np.empty((p.rows, ng), dtype=np.uint64)
+        _check(self._lib.ccmref_vlb_offsets(ctypes.byref(m), group,
+                                            out.ctypes.data_as(_U64P)))
+        return out
+
     def vlb_matvec(self, p: VlbPacked, x) -> np.ndarray:
         m = p._struct()
         xv = np.ascontiguousarray(np.asarray(x, dtype=np.int64))
@@ -351,6 +362,7 @@ vlb_compress = _ORACLE.vlb_compress
 vlb_decompress = _ORACLE.vlb_decompress
 vlb_get = _ORACLE.vlb_get
 vlb_matvec = _ORACLE.vlb_matvec
+vlb_offsets = _ORACLE.vlb_offsets
 
 
 def threads() -> int:

@@ -339,6 +339,18 @@ int ccmref_vlb_get(const ccmref_vlb *m, int64_t i, int64_t j, int64_t *out) {
   return CCMREF_OK;
 }
 
+int ccmref_vlb_offsets(const ccmref_vlb *m, int64_t group, uint64_t *out) {
+  if (!m || !out || !m->payload || group < 1) return CCMREF_E_INVAL;
+  uint64_t p = 0;
+  int64_t t = 0;
+  for (int64_t i = 0; i < m->rows; i++)
+    for (int64_t j = 0; j < m->cols; j++) {
+      if (j % group == 0) out[t++] = p;
+      (void)vlb_next(m, &p);
+    }
+  return CCMREF_OK;
+}
+
 int ccmref_vlb_matvec(const ccmref_vlb *m, const int64_t *x, int64_t *y) {
   if (!m || !x || !y || !m->payload) return CCMREF_E_INVAL;
   uint64_t p = 0;

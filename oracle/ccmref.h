@@ -169,6 +169,11 @@ int ccmref_vlb_decompress(const ccmref_vlb *m, int64_t *dense);
 
 int ccmref_vlb_get(const ccmref_vlb *m, int64_t i, int64_t j, int64_t *out);
 
+/* Stream bit where element (i, j) starts, for every i and every j that is a
+ * multiple of `group` (row-major over (i, j / group)); out holds
+ * rows * ceil(cols / group) entries.  Used to check the GPU's index. */
+int ccmref_vlb_offsets(const ccmref_vlb *m, int64_t group, uint64_t *out);
+
 /* y[i] = sum_j a[i][j] * x[j] modulo 2^64 for every row. */
 int ccmref_vlb_matvec(const ccmref_vlb *m, const int64_t *x, int64_t *y);
 

@@ -12,12 +12,14 @@ import ctypes
 import torch
 
 from ._lib import (E_INVAL, E_NOMEM, E_OVERFLOW, E_RANGE, E_SHAPE, E_UNSUPPORTED, I32, I64,
-                   OK, CcmError, Desc, check, lib)
+                   OK, CcmError, Desc, VlbDesc, check, lib)
 
 __all__ = ["CMatrix", "CcmError", "compress", "decompress", "get", "gather", "add", "scale",
            "matvec_launcher",
            "matvec", "matmul", "matmul_plan", "matmul_pack", "fill_uniform", "generate", "from_serialized", "words",
-           "packed_bytes", "payload_capacity", "width", "Batch", "DynBatch"]
+           "packed_bytes", "payload_capacity", "width", "Batch", "DynBatch",
+           "VlbMatrix", "vlb_compress", "vlb_decompress", "vlb_get", "vlb_matvec",
+           "vlb_matvec_launcher"]
 
 
 def _stream(stream=None) -> ctypes.c_void_p:
@@ -251,6 +253,127 @@ def matmul_pack(a: CMatrix, b: CMatrix, c: CMatrix, scratch: torch.Tensor, strea
 def matmul(a: CMatrix, b: CMatrix, scratch: torch.Tensor | None = None, stream=None) -> CMatrix:
     c, scratch = matmul_plan(a, b, scratch, stream)
     return matmul_pack(a, b, c, scratch, stream)
+
+
+class VlbMatrix:
+    """A Method 2 (variable length blocks) matrix: descriptor, device stream
+    and device index (row starts, group offsets)."""
+
+    def __init__(self, desc: VlbDesc, index: torch.Tensor, payload: torch.Tensor | None = None):
+        self.desc = desc
+        self.index = index
+        if payload is None:
+            cap = int(lib.ccm_vlb_payload_capacity(desc.nbits))
+            payload = torch.empty(cap, dtype=torch.uint8, device=index.device)
+        self.payload = payload
+        self.desc.payload = payload.data_ptr()
+        self.desc.index = index.data_ptr()
+
+    rows = property(lambda self: int(self.desc.rows))
+    cols = property(lambda self: int(self.desc.cols))
+    vmin = property(lambda self: int(self.desc.vmin))
+    vmax = property(lambda self: int(self.desc.vmax))
+    k = property(lambda self: int(self.desc.k))
+    is_signed = property(lambda self: bool(self.desc.is_signed))
+    nbits = property(lambda self: int(self.desc.nbits))
+    words = property(lambda self: int(self.desc.words))
+    gmax = property(lambda self: int(self.desc.gmax))
+
+    @property
+    def shape(self):
+        return (self.rows, self.cols)
+
+    @property
+    def index_bytes(self) -> int:
+        return int(self.index.numel())
+
+    def payload_words(self) -> torch.Tensor:
+        """The canonical payload (floor(nbits/64) + 1 bitstrings) as int64 (host)."""
+        torch.cuda.current_stream().synchronize()
+        return self.payload[: 8 * self.words].view(torch.int64).cpu()
+
+    def row_bits(self) -> torch.Tensor:
+        """row_bit[0..rows] (host int64 copy of the index's uint64 row starts)."""
+        torch.cuda.current_stream().synchronize()
+        return self.index[: 8 * (self.rows + 1)].view(torch.int64).cpu()
+
+    def group_offsets(self) -> torch.Tensor:
+        """grp_off[rows][ceil(cols/32)] (host int64 copy)."""
+        torch.cuda.current_stream().synchronize()
+        off = ((self.rows + 1) * 8 + 255) // 256 * 256
+        ngr = (self.cols + 31) // 32
+        g = self.index[off: off + 4 * self.rows * ngr].view(torch.int32).cpu()
+        return (g.to(torch.int64) & 0xFFFFFFFF).view(self.rows, ngr)
+
+    def __repr__(self):
+        return (f"VlbMatrix({self.rows}x{self.cols}, k={self.k}, signed={self.is_signed}, "
+                f"nbits={self.nbits})")
+
+
+def vlb_compress(dense: torch.Tensor, stream=None) -> VlbMatrix:
+    """Method 2-compress a 2-D int32/int64 device tensor (range pass, index
+    passes, then packing)."""
+    t = _device_tensor(dense, "dense")
+    if t.dim() != 2:
+        raise ValueError("2-D tensor expected")
+    code = _dtype_code(t)
+    s = _stream(stream)
+    rows, cols = t.shape
+    nidx = int(lib.ccm_vlb_index_bytes(rows, cols))
+    if nidx == 0:
+        raise CcmError(E_INVAL, "vlb_compress: shape")
+    index = torch.empty(nidx, dtype=torch.uint8, device=t.device)
+    d = VlbDesc()
+    check(lib.ccm_vlb_compress_plan(_ptr(t), code, rows, cols, _ptr(index), ctypes.byref(d), s),
+          "ccm_vlb_compress_plan")
+    m = VlbMatrix(d, index)
+    check(lib.ccm_vlb_compress(_ptr(t), code, ctypes.byref(m.desc), s), "ccm_vlb_compress")
+    return m
+
+
+def vlb_decompress(m: VlbMatrix, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty((m.rows, m.cols), dtype=torch.int64, device=m.payload.device)
+    elif out.dtype != torch.int64 or out.numel() != m.rows * m.cols or not out.is_contiguous():
+        raise CcmError(E_INVAL, "vlb_decompress: out")
+    check(lib.ccm_vlb_decompress(ctypes.byref(m.desc), _ptr(out), _stream(stream)),
+          "ccm_vlb_decompress")
+    return out
+
+
+def vlb_get(m: VlbMatrix, i: int, j: int, stream=None) -> int:
+    v = ctypes.c_int64()
+    check(lib.ccm_vlb_get(ctypes.byref(m.desc), i, j, ctypes.byref(v), _stream(stream)),
+          "ccm_vlb_get")
+    return int(v.value)
+
+
+def vlb_matvec(m: VlbMatrix, x: torch.Tensor, y: torch.Tensor | None = None, stream=None):
+    x = _device_tensor(x, "x")
+    if x.numel() != m.cols:
+        raise CcmError(E_SHAPE, "vlb_matvec: x")
+    if y is None:
+        y = torch.empty(m.rows, dtype=torch.int64, device=x.device)
+    elif y.dtype != torch.int64 or y.numel() != m.rows or not y.is_contiguous():
+        raise CcmError(E_INVAL, "vlb_matvec: y")
+    check(lib.ccm_vlb_matvec(ctypes.byref(m.desc), _ptr(x), _dtype_code(x), _ptr(y),
+                             _stream(stream)), "ccm_vlb_matvec")
+    return y
+
+
+def vlb_matvec_launcher(m: VlbMatrix, x: torch.Tensor, y: torch.Tensor, stream=None):
+    """A zero-argument callable that enqueues y = A x with every argument
+    marshalled once (for timing loops)."""
+    x = _device_tensor(x, "x")
+    if x.numel() != m.cols or y.dtype != torch.int64 or y.numel() != m.rows:
+        raise CcmError(E_SHAPE, "vlb_matvec_launcher")
+    fn = lib.ccm_vlb_matvec
+    args = (ctypes.byref(m.desc), _ptr(x), _dtype_code(x), _ptr(y), _stream(stream))
+
+    def launch():
+        check(fn(*args), "ccm_vlb_matvec")
+
+    return launch
 
 
 def fill_uniform(t: torch.Tensor, lo: int, hi: int, seed: int, stream_id: int = 0,

@@ -32,11 +32,22 @@ class Desc(ctypes.Structure):
                 ("words", ctypes.c_uint64), ("payload", ctypes.c_void_p)]
 
 
+class VlbDesc(ctypes.Structure):
+    """Mirror of ccm_vlb_desc."""
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("vmin", ctypes.c_int64), ("vmax", ctypes.c_int64),
+                ("k", ctypes.c_int32), ("is_signed", ctypes.c_int32),
+                ("nbits", ctypes.c_uint64), ("words", ctypes.c_uint64),
+                ("gmax", ctypes.c_uint64),
+                ("payload", ctypes.c_void_p), ("index", ctypes.c_void_p)]
+
+
 _i64 = ctypes.c_int64
 _u64 = ctypes.c_uint64
 _i32 = ctypes.c_int32
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(Desc)
+_vdp = ctypes.POINTER(VlbDesc)
 
 SIGNATURES = {
     "ccm_version": (ctypes.c_int, []),
@@ -77,6 +88,13 @@ SIGNATURES = {
     "ccm_fill_uniform": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i64, _u64, _u64, _u64, _vp]),
     "ccm_generate_plan": (ctypes.c_int, [_i64, _i64, _i64, _i64, _u64, _u64, _dp, _vp]),
     "ccm_generate": (ctypes.c_int, [_dp, _i64, _i64, _u64, _u64, _vp]),
+    "ccm_vlb_index_bytes": (_u64, [_i64, _i64]),
+    "ccm_vlb_payload_capacity": (_u64, [_u64]),
+    "ccm_vlb_compress_plan": (ctypes.c_int, [_vp, _i32, _i64, _i64, _vp, _vdp, _vp]),
+    "ccm_vlb_compress": (ctypes.c_int, [_vp, _i32, _vdp, _vp]),
+    "ccm_vlb_decompress": (ctypes.c_int, [_vdp, _vp, _vp]),
+    "ccm_vlb_get": (ctypes.c_int, [_vdp, _i64, _i64, ctypes.POINTER(_i64), _vp]),
+    "ccm_vlb_matvec": (ctypes.c_int, [_vdp, _vp, _i32, _vp, _vp]),
 }
 
 

@@ -540,4 +540,169 @@ int ccm_generate(const ccm_desc *out, int64_t lo, int64_t hi, uint64_t seed,
   return CCM_OK;
 }
 
+// ---- Method 2: variable length blocks -----------------------------------
+
+}  // extern "C"
+
+namespace {
+
+int bitlen_u(uint64_t u) {
+  int L = 0;
+  while (L < 64 && (u >> L) != 0) ++L;
+  return L;
+}
+
+// Largest element width of a matrix with range [vmin, vmax] (widths grow with
+// |v| on each side of zero, so an extreme has it) and the length-field width
+// k = its bit-length.
+void vlb_widths(int64_t vmin, int64_t vmax, int32_t *bmax, int32_t *k) {
+  int b;
+  if (vmin >= 0) {
+    b = vmax <= 1 ? 1 : bitlen_u((uint64_t)vmax);
+  } else {
+    const int lo = 1 + bitlen_u(~(uint64_t)vmin);
+    const int hi = 1 + bitlen_u(vmax < 0 ? ~(uint64_t)vmax : (uint64_t)vmax);
+    b = lo > hi ? lo : hi;
+  }
+  *bmax = b;
+  *k = bitlen_u((uint64_t)b);
+}
+
+constexpr int kVlbGroup = 32;
+
+uint64_t vlb_grp_offset(int64_t rows) { return ((uint64_t)(rows + 1) * 8u + 255u) / 256u * 256u; }
+
+uint64_t vlb_cap32(uint64_t nbits) { return ((nbits + 31u) / 32u + 16u + 63u) / 64u * 64u; }
+
+int check_vlb(const ccm_vlb_desc *d) {
+  if (!d || !d->payload || !d->index) return CCM_E_INVAL;
+  if (!shape_ok(d->rows, d->cols) || d->vmin > d->vmax) return CCM_E_INVAL;
+  if (d->is_signed != (d->vmin < 0 ? 1 : 0)) return CCM_E_INVAL;
+  int32_t bmax = 0, k = 0;
+  vlb_widths(d->vmin, d->vmax, &bmax, &k);
+  if (k != d->k) return CCM_E_INVAL;
+  const unsigned __int128 n = (unsigned __int128)d->rows * (unsigned __int128)d->cols;
+  if ((unsigned __int128)d->nbits < n * (unsigned __int128)(k + 1) ||
+      (unsigned __int128)d->nbits > n * (unsigned __int128)(k + bmax))
+    return CCM_E_INVAL;
+  if (d->words != d->nbits / 64u + 1u) return CCM_E_INVAL;
+  if (d->gmax < (uint64_t)(k + 1) || d->gmax > (uint64_t)kVlbGroup * (uint64_t)(k + bmax) ||
+      d->gmax > d->nbits)
+    return CCM_E_INVAL;
+  return CCM_OK;
+}
+
+ccm::VlbView vlb_view(const ccm_vlb_desc *d) {
+  ccm::VlbView v;
+  v.w = (const uint32_t *)d->payload;
+  v.row_bit = (const uint64_t *)d->index;
+  v.grp = (const uint32_t *)((const char *)d->index + vlb_grp_offset(d->rows));
+  v.rows = d->rows;
+  v.cols = d->cols;
+  v.ngr = (int64_t)ccm::vlb_ngr(d->cols);
+  int32_t bmax = 0, k = 0;
+  vlb_widths(d->vmin, d->vmax, &bmax, &k);
+  v.k = k;
+  v.bmax = bmax;
+  v.sgn = d->is_signed;
+  v.gmax = d->gmax;
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t ccm_vlb_index_bytes(int64_t rows, int64_t cols) {
+  if (!shape_ok(rows, cols)) return 0;
+  const uint64_t g = (uint64_t)rows * ccm::vlb_ngr(cols) * 4u;
+  return vlb_grp_offset(rows) + (g + 255u) / 256u * 256u;
+}
+
+uint64_t ccm_vlb_payload_capacity(uint64_t nbits) { return vlb_cap32(nbits) * 4u; }
+
+int ccm_vlb_compress_plan(const void *dense, int32_t dtype, int64_t rows, int64_t cols,
+                          void *index, ccm_vlb_desc *out, void *stream) {
+  if (!out || !index || !shape_ok(rows, cols)) return CCM_E_INVAL;
+  int64_t lo = 0, hi = 0;
+  int rc = ccm_range(dense, dtype, rows * cols, &lo, &hi, stream);
+  if (rc != CCM_OK) return rc;
+  int32_t bmax = 0, k = 0;
+  vlb_widths(lo, hi, &bmax, &k);
+  // group offsets within a row are 32-bit
+  if ((unsigned __int128)cols * (unsigned __int128)(k + bmax) >= ((unsigned __int128)1 << 32))
+    return CCM_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  uint64_t *row_bit = (uint64_t *)index;
+  uint32_t *grp = (uint32_t *)((char *)index + vlb_grp_offset(rows));
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx *c = nullptr;
+  rc = device_ctx(&c);
+  if (rc != CCM_OK) return rc;
+  CCM_HIP(ccm::launch_range_init(c->slot, s));
+  CCM_HIP(ccm::launch_vlb_sizes(dense, dtype, rows, cols, k, lo < 0 ? 1 : 0, grp, c->slot, s));
+  CCM_HIP(ccm::launch_vlb_scan(rows, cols, grp, row_bit, s));
+  uint64_t *h = (uint64_t *)((char *)c->host + ccm::kRangeBytes);
+  CCM_HIP(hipMemcpyAsync(h, row_bit + rows, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  ccm::RangeSlot gr;
+  rc = read_slot(c, s, &gr);  // synchronizes the stream
+  if (rc != CCM_OK) return rc;
+  out->rows = rows;
+  out->cols = cols;
+  out->vmin = lo;
+  out->vmax = hi;
+  out->k = k;
+  out->is_signed = lo < 0 ? 1 : 0;
+  out->nbits = *h;
+  out->words = out->nbits / 64u + 1u;
+  out->gmax = (uint64_t)gr.vmax;
+  out->payload = nullptr;
+  out->index = index;
+  return CCM_OK;
+}
+
+int ccm_vlb_compress(const void *dense, int32_t dtype, const ccm_vlb_desc *out, void *stream) {
+  if (!dense || (dtype != CCM_I32 && dtype != CCM_I64)) return CCM_E_INVAL;
+  int rc = check_vlb(out);
+  if (rc != CCM_OK) return rc;
+  CCM_HIP(ccm::launch_vlb_pack(dense, dtype, vlb_view(out), (uint32_t *)out->payload,
+                               vlb_cap32(out->nbits), (hipStream_t)stream));
+  return CCM_OK;
+}
+
+int ccm_vlb_decompress(const ccm_vlb_desc *a, int64_t *dense_out, void *stream) {
+  int rc = check_vlb(a);
+  if (rc != CCM_OK) return rc;
+  if (!dense_out) return CCM_E_INVAL;
+  CCM_HIP(ccm::launch_vlb_decode(vlb_view(a), dense_out, (hipStream_t)stream));
+  return CCM_OK;
+}
+
+int ccm_vlb_get(const ccm_vlb_desc *a, int64_t i, int64_t j, int64_t *value, void *stream) {
+  int rc = check_vlb(a);
+  if (rc != CCM_OK) return rc;
+  if (!value) return CCM_E_INVAL;
+  if (i < 0 || i >= a->rows || j < 0 || j >= a->cols) return CCM_E_RANGE;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx *c = nullptr;
+  rc = device_ctx(&c);
+  if (rc != CCM_OK) return rc;
+  CCM_HIP(ccm::launch_vlb_get(vlb_view(a), i, j, c->one, s));
+  int64_t *h = (int64_t *)((char *)c->host + ccm::kRangeBytes);
+  CCM_HIP(hipMemcpyAsync(h, c->one, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  CCM_HIP(hipStreamSynchronize(s));
+  *value = *h;
+  return CCM_OK;
+}
+
+int ccm_vlb_matvec(const ccm_vlb_desc *a, const void *x, int32_t xdtype, int64_t *y,
+                   void *stream) {
+  int rc = check_vlb(a);
+  if (rc != CCM_OK) return rc;
+  if (!x || !y || (xdtype != CCM_I32 && xdtype != CCM_I64)) return CCM_E_INVAL;
+  CCM_HIP(ccm::launch_vlb_matvec(vlb_view(a), x, xdtype, y, (hipStream_t)stream));
+  return CCM_OK;
+}
+
 }  // extern "C"

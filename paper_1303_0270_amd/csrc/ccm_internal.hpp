@@ -284,6 +284,33 @@ hipError_t launch_matmul_i8(const uint32_t *aw, int abits, int asgn, const uint3
                             int bbits, int bsgn, int64_t M, int64_t K, int64_t N, int out32,
                             void *scratch_c, int8_t *scratch_i8, RangeSlot *slot, hipStream_t s);
 
+// Method 2 (variable length blocks): stream, index and shape of one matrix.
+struct VlbView {
+  const uint32_t *w;        // the stream as 32-bit words
+  const uint64_t *row_bit;  // rows + 1 row start bits
+  const uint32_t *grp;      // rows x ngr group offsets within the row
+  int64_t rows, cols, ngr;  // ngr = ceil(cols / 32)
+  int k;                    // length-field width
+  int bmax;                 // largest element width
+  int sgn;
+  uint64_t gmax;            // bits of the longest group
+};
+uint64_t vlb_ngr(int64_t cols);
+// pass 1: grp[i][g] = bits of group g of row i (sum of k + b_e); the largest
+// folds into slot's vmax (slot initialised by launch_range_init)
+hipError_t launch_vlb_sizes(const void *dense, int dtype, int64_t rows, int64_t cols, int k,
+                            int sgn, uint32_t *grp, RangeSlot *slot, hipStream_t s);
+// pass 2: counts -> offsets within rows, row starts and the total in row_bit
+hipError_t launch_vlb_scan(int64_t rows, int64_t cols, uint32_t *grp, uint64_t *row_bit,
+                           hipStream_t s);
+// pass 3: the stream (zeroes cap32 words first)
+hipError_t launch_vlb_pack(const void *dense, int dtype, const VlbView &a, uint32_t *out,
+                           uint64_t cap32, hipStream_t s);
+hipError_t launch_vlb_decode(const VlbView &a, int64_t *out, hipStream_t s);
+hipError_t launch_vlb_get(const VlbView &a, int64_t i, int64_t j, int64_t *out, hipStream_t s);
+hipError_t launch_vlb_matvec(const VlbView &a, const void *x, int xdtype, int64_t *y,
+                             hipStream_t s);
+
 // synthetic data
 hipError_t launch_fill_uniform(void *dense, int dtype, uint64_t n, int64_t lo, uint64_t span,
                                uint64_t seed, uint64_t stream_id, uint64_t start,

@@ -1,0 +1,615 @@
+// Method 2 of the paper (Variable Length Blocks): every element is stored in
+// its own minimal width b_e, preceded by a fixed k-bit length field holding
+// b_e, with k the bit-length of the largest b_e (Methods, "Method 2"; Eq. 16
+// counts the bits).  Elements follow each other in row-major order, least
+// significant bit first, straddling 64-bit bitstrings as in Method 1.
+//
+// The stream alone can only be read from its start.  For random access and
+// data-parallel decoding the library keeps an index beside it:
+//   row_bit[i]   (uint64, rows + 1 entries): stream bit where row i starts;
+//                row_bit[rows] is the total bit count;
+//   grp_off[i][g] (uint32, rows x ceil(cols/32)): bit offset of element
+//                (i, 32g) from the start of row i.
+// A "group" is 32 consecutive elements of one row (the last group of a row
+// may be shorter).  A lane that owns a group knows where it starts and walks
+// its 32 (length, value) pairs; where the next one starts depends on the
+// length just read, so the walk is serial within a group and parallel across
+// groups.
+//
+// Encoding runs in three passes: group bit counts (sum of k + b_e), scans
+// (within rows, then over rows) that turn the counts into the index, and the
+// packing pass, where each lane writes its group's bits: the words its group
+// covers entirely with plain stores, the at most two it shares with a
+// neighbour with atomic ORs into the zeroed payload.
+#include <hip/hip_runtime.h>
+
+#include "ccm_internal.hpp"
+
+namespace ccm {
+namespace {
+
+constexpr int kVG = 32;          // elements per index group
+constexpr int kVThreads = 256;   // threads per block of every VLB kernel
+
+__device__ __forceinline__ int bitlen64(uint64_t u) { return u ? 64 - __clzll((long long)u) : 0; }
+
+// b_e of one value: Eq. 1 on the element when the matrix has no negative
+// value; otherwise the smallest two's complement width holding it.
+__device__ __forceinline__ int elem_width(int64_t v, int sgn) {
+  if (!sgn) {
+    const int L = bitlen64((uint64_t)v);
+    return L > 1 ? L : 1;
+  }
+  const uint64_t m = v < 0 ? ~(uint64_t)v : (uint64_t)v;
+  return 1 + bitlen64(m);
+}
+
+template <typename T>
+__device__ __forceinline__ int64_t load_dense(const T *d, uint64_t e) {
+  return (int64_t)d[e];
+}
+
+// nb (1..64) stream bits starting at bit p, zero-extended.  Reads words
+// p/32 .. p/32 + 2, which stay inside the payload capacity for any field
+// that starts inside the stream.
+__device__ __forceinline__ uint64_t bits_at(const uint32_t *w, uint64_t p, int nb) {
+  const uint64_t q = p >> 5;
+  const int off = (int)(p & 31u);
+  uint64_t v = ((uint64_t)w[q] | ((uint64_t)w[q + 1] << 32)) >> off;
+  if (off + nb > 64) v |= (uint64_t)w[q + 2] << (64 - off);
+  return v & mask64(nb);
+}
+
+// Start bit (absolute) and end bit of group g of row i.
+__device__ __forceinline__ void group_span(const uint64_t *row_bit, const uint32_t *grp,
+                                           int64_t i, int64_t g, int64_t ngr, uint64_t *s,
+                                           uint64_t *e) {
+  const uint64_t base = row_bit[i];
+  *s = base + grp[(uint64_t)i * (uint64_t)ngr + (uint64_t)g];
+  *e = g + 1 < ngr ? base + grp[(uint64_t)i * (uint64_t)ngr + (uint64_t)g + 1] : row_bit[i + 1];
+}
+
+// ---- pass 1: bits per group --------------------------------------------
+
+// Half-wave h of a wave owns one group: lane l reads element 32g + l, and the
+// 32 lanes sum k + b_e.  The grid-stride step is a multiple of 32 and the
+// total a multiple of 32, so a group's lanes are always active together.
+template <typename T>
+__global__ __launch_bounds__(kVThreads) void k_vlb_sizes(const T *__restrict__ dense, int64_t rows,
+                                                         int64_t cols, int64_t ngr, int k, int sgn,
+                                                         uint32_t *__restrict__ grp,
+                                                         RangeSlot *slot) {
+  const uint64_t total = (uint64_t)rows * (uint64_t)ngr * kVG;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint32_t gmax = 0;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    const uint64_t gi = t >> 5;
+    const int l = (int)(t & 31u);
+    const uint64_t i = gi / (uint64_t)ngr;
+    const uint64_t g = gi - i * (uint64_t)ngr;
+    const uint64_t j = g * kVG + (uint64_t)l;
+    uint32_t nb = 0;
+    if (j < (uint64_t)cols) nb = (uint32_t)(k + elem_width(load_dense(dense, i * cols + j), sgn));
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) nb += (uint32_t)__shfl_xor((int)nb, m, 32);
+    if (l == 0) grp[gi] = nb;
+    gmax = nb > gmax ? nb : gmax;
+  }
+  // the longest group (sizes the staging buffers of the matvec kernel)
+  block_range_commit(0, (int64_t)gmax, 0, slot);
+}
+
+// ---- pass 2: scans ----------------------------------------------------------
+
+// Inclusive block-wide scan of one value per thread (uint64), with the block
+// total.  Every thread must call it.
+__device__ __forceinline__ uint64_t block_scan_incl(uint64_t v, uint64_t *total) {
+  __shared__ uint64_t s_wave[kVThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  if (lane == 63) s_wave[wave] = v;
+  __syncthreads();
+  uint64_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kVThreads / 64; ++w) {
+    const uint64_t s = s_wave[w];
+    before += w < wave ? s : 0;
+    all += s;
+  }
+  __syncthreads();  // s_wave is reused by the next call
+  *total = all;
+  return v + before;
+}
+
+// Row i's group counts become exclusive offsets from the row start; the row's
+// total goes to row_bit[i + 1] (pass 3 turns those into starts).
+__global__ __launch_bounds__(kVThreads) void k_vlb_row_scan(int64_t rows, int64_t ngr,
+                                                            uint32_t *__restrict__ grp,
+                                                            uint64_t *__restrict__ row_bit) {
+  for (int64_t i = blockIdx.x; i < rows; i += gridDim.x) {
+    uint32_t *gp = grp + (uint64_t)i * (uint64_t)ngr;
+    uint64_t carry = 0;
+    for (int64_t c0 = 0; c0 < ngr; c0 += kVThreads) {
+      const int64_t g = c0 + threadIdx.x;
+      const uint64_t v = g < ngr ? gp[g] : 0;
+      uint64_t tot = 0;
+      const uint64_t inc = block_scan_incl(v, &tot);
+      if (g < ngr) gp[g] = (uint32_t)(carry + inc - v);
+      carry += tot;
+    }
+    if (threadIdx.x == 0) row_bit[i + 1] = carry;
+  }
+}
+
+// row_bit[0] = 0 and row_bit[i + 1] = sum of the first i + 1 row totals.  One
+// block.
+__global__ __launch_bounds__(kVThreads) void k_vlb_rows_scan(int64_t rows,
+                                                             uint64_t *__restrict__ row_bit) {
+  uint64_t carry = 0;
+  for (int64_t c0 = 0; c0 < rows; c0 += kVThreads) {
+    const int64_t i = c0 + threadIdx.x;
+    const uint64_t v = i < rows ? row_bit[i + 1] : 0;
+    uint64_t tot = 0;
+    const uint64_t inc = block_scan_incl(v, &tot);
+    if (i < rows) row_bit[i + 1] = carry + inc;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) row_bit[0] = 0;
+}
+
+// ---- pass 3: packing -----------------------------------------------------------
+
+__global__ void k_zero_u32(uint32_t *p, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) p[e] = 0;
+}
+
+// Bit writer for one group's span [s, e) of the stream.  Words entirely inside
+// the span belong to this group alone and are stored; a word shared with a
+// neighbouring group is ORed into the zeroed payload.
+struct SpanWriter {
+  uint32_t *w;
+  uint64_t s, e;
+  uint64_t q;    // word being filled
+  uint64_t buf;  // its pending bits, starting at bit 0 of word q
+  int used;      // bits of word q accounted for (including those before s)
+
+  __device__ SpanWriter(uint32_t *words, uint64_t start, uint64_t end)
+      : w(words), s(start), e(end), q(start >> 5), buf(0), used((int)(start & 31u)) {}
+
+  __device__ __forceinline__ void flush_word() {
+    const uint32_t v = (uint32_t)buf;
+    const uint64_t lo = q * 32u;
+    if (lo >= s && lo + 32u <= e)
+      w[q] = v;
+    else if (v != 0)
+      atomicOr(&w[q], v);
+  }
+
+  // nb (1..32) bits
+  __device__ __forceinline__ void put32(uint32_t v, int nb) {
+    buf |= (uint64_t)(v & mask32(nb)) << used;
+    used += nb;
+    if (used >= 32) {
+      flush_word();
+      ++q;
+      buf >>= 32;
+      used -= 32;
+    }
+  }
+
+  __device__ __forceinline__ void put(uint64_t v, int nb) {
+    if (nb <= 32) {
+      put32((uint32_t)v, nb);
+    } else {
+      put32((uint32_t)v, 32);
+      put32((uint32_t)(v >> 32), nb - 32);
+    }
+  }
+
+  __device__ __forceinline__ void finish() {
+    if (used > 0) flush_word();
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kVThreads) void k_vlb_pack(const T *__restrict__ dense, int64_t rows,
+                                                        int64_t cols, int64_t ngr, int k, int sgn,
+                                                        const uint64_t *__restrict__ row_bit,
+                                                        const uint32_t *__restrict__ grp,
+                                                        uint32_t *__restrict__ out) {
+  const uint64_t total = (uint64_t)rows * (uint64_t)ngr;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t gi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += stride) {
+    const int64_t i = (int64_t)(gi / (uint64_t)ngr);
+    const int64_t g = (int64_t)(gi - (uint64_t)i * (uint64_t)ngr);
+    uint64_t s, e;
+    group_span(row_bit, grp, i, g, ngr, &s, &e);
+    SpanWriter wr(out, s, e);
+    const int64_t j0 = g * kVG;
+    const int n = cols - j0 < kVG ? (int)(cols - j0) : kVG;
+    const T *src = dense + (uint64_t)i * (uint64_t)cols + (uint64_t)j0;
+    for (int l = 0; l < n; ++l) {
+      const int64_t v = load_dense(src, (uint64_t)l);
+      const int b = elem_width(v, sgn);
+      wr.put32((uint32_t)b, k);       // the length field
+      wr.put((uint64_t)v, b);         // then the value's low b bits
+    }
+    wr.finish();
+  }
+}
+
+// ---- decode, get ------------------------------------------------------------
+
+// One (length, value) pair at stream bit *p; advances *p.
+__device__ __forceinline__ int64_t vlb_read(const uint32_t *w, uint64_t *p, int k, int sgn) {
+  const int b = (int)bits_at(w, *p, k);
+  const uint64_t u = bits_at(w, *p + (uint64_t)k, b);
+  *p += (uint64_t)(k + b);
+  return sgn ? sext64(u, b) : (int64_t)u;
+}
+
+__global__ __launch_bounds__(kVThreads) void k_vlb_decode(const uint32_t *__restrict__ w,
+                                                          const uint64_t *__restrict__ row_bit,
+                                                          const uint32_t *__restrict__ grp,
+                                                          int64_t rows, int64_t cols, int64_t ngr,
+                                                          int k, int sgn, int64_t *__restrict__ out) {
+  const uint64_t total = (uint64_t)rows * (uint64_t)ngr;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t gi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += stride) {
+    const int64_t i = (int64_t)(gi / (uint64_t)ngr);
+    const int64_t g = (int64_t)(gi - (uint64_t)i * (uint64_t)ngr);
+    uint64_t p = row_bit[i] + grp[gi];
+    const int64_t j0 = g * kVG;
+    const int n = cols - j0 < kVG ? (int)(cols - j0) : kVG;
+    int64_t *dst = out + (uint64_t)i * (uint64_t)cols + (uint64_t)j0;
+    for (int l = 0; l < n; ++l) dst[l] = vlb_read(w, &p, k, sgn);
+  }
+}
+
+__global__ void k_vlb_get(const uint32_t *__restrict__ w, const uint64_t *__restrict__ row_bit,
+                          const uint32_t *__restrict__ grp, int64_t ngr, int64_t i, int64_t j,
+                          int k, int sgn, int64_t *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t g = j / kVG;
+  uint64_t p = row_bit[i] + grp[(uint64_t)i * (uint64_t)ngr + (uint64_t)g];
+  int64_t v = 0;
+  for (int64_t l = g * kVG; l <= j; ++l) v = vlb_read(w, &p, k, sgn);
+  *out = v;
+}
+
+// ---- matvec ------------------------------------------------------------------
+
+// General form: any k + b_e, int32 or int64 x.  Block (chunk c, row i) walks
+// groups 256c .. 256c + 255 of row i, one per lane, reading the stream
+// straight from memory; the block's sum goes to y[i] (atomically when a row
+// has more than one chunk; y was zeroed).
+template <typename XT>
+__global__ __launch_bounds__(kVThreads) void k_vlb_mv_gen(
+    const uint32_t *__restrict__ w, const uint64_t *__restrict__ row_bit,
+    const uint32_t *__restrict__ grp, int64_t rows, int64_t cols, int64_t ngr, int k, int sgn,
+    const XT *__restrict__ x, int64_t *__restrict__ y) {
+  __shared__ uint64_t s_part[kVThreads / 64];
+  const int64_t nchunk = (ngr + kVThreads - 1) / kVThreads;
+  const uint64_t nblk = (uint64_t)rows * (uint64_t)nchunk;
+  for (uint64_t bi = blockIdx.x; bi < nblk; bi += gridDim.x) {
+    const int64_t i = (int64_t)(bi / (uint64_t)nchunk);
+    const int64_t c = (int64_t)(bi - (uint64_t)i * (uint64_t)nchunk);
+    const int64_t g = c * kVThreads + threadIdx.x;
+    uint64_t acc = 0;
+    if (g < ngr) {
+      uint64_t p = row_bit[i] + grp[(uint64_t)i * (uint64_t)ngr + (uint64_t)g];
+      const int64_t j0 = g * kVG;
+      const int n = cols - j0 < kVG ? (int)(cols - j0) : kVG;
+      for (int l = 0; l < n; ++l) {
+        const int64_t a = vlb_read(w, &p, k, sgn);
+        acc += (uint64_t)a * (uint64_t)(int64_t)x[j0 + l];
+      }
+    }
+    const int64_t ws = wave_sum((int64_t)acc);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = (uint64_t)ws;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t t = 0;
+#pragma unroll
+      for (int v = 0; v < kVThreads / 64; ++v) t += s_part[v];
+      if (nchunk > 1)
+        atomicAdd((unsigned long long *)&y[i], (unsigned long long)t);
+      else
+        y[i] = (int64_t)t;
+    }
+    __syncthreads();
+  }
+}
+
+// 64 stream bits from bit pv of a staged stretch (reads three words).
+__device__ __forceinline__ uint64_t lds_bits64(const uint32_t *seg, uint32_t pv) {
+  const uint32_t q = pv >> 5;
+  const uint32_t w0 = seg[q], w1 = seg[q + 1], w2 = seg[q + 2];
+  const uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, pv & 31u);
+  const uint32_t hi = __builtin_amdgcn_alignbit(w2, w1, pv & 31u);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Staged form for int32 x on a 16-byte boundary, any widths.
+//   * Block (panel p, row slice) owns groups [256 GPT p, 256 GPT (p + 1)) of
+//     the rows it visits; lane t owns groups 256 GPT p + GPT t + u (u < GPT),
+//     GPT independent chains (instruction-level parallelism in the serial
+//     walks), and keeps their 32 GPT x values in registers for all rows.
+//   * Per row the block copies the panel's stretch of the stream (contiguous:
+//     the panel's groups follow each other) into LDS with 16-byte loads, then
+//     every lane walks its groups from LDS.  Per element: one two-word read
+//     and a funnel shift (v_alignbit) give the 32 bits at the pair's start;
+//     the length is their low k bits; when k + b_e <= 32 the value is one
+//     bit-field extract of the same word (sign-extending when signed) and the
+//     product one 32x32->64 multiply-add.  Longer pairs (rare in the paper's
+//     bit-length distributions) take a branch that reads 64 bits at the
+//     value's start.
+//   * Rows visited: blockIdx.y, blockIdx.y + gridDim.y, ... (resident
+//     blocks only, so x is loaded once per block).
+//   * CLAMP: some chain of the panel is shorter than 32 elements or absent
+//     (ragged row end, partial panel); its walk then continues through bits
+//     of the next group or past the stretch, with x = 0 for those elements,
+//     and the read position is clamped inside the staged buffer.
+template <bool SGN, int GPT, bool CLAMP>
+__global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
+    const uint32_t *__restrict__ w, const uint64_t *__restrict__ row_bit,
+    const uint32_t *__restrict__ grp, int64_t rows, int64_t cols, int64_t ngr, int k,
+    int seg_words, const int32_t *__restrict__ x, int64_t *__restrict__ y, int atomic_out) {
+  extern __shared__ uint4 seg4[];
+  uint32_t *seg = (uint32_t *)seg4;
+  // wave partial sums after the stream stretch, so the stretch starts at LDS
+  // address 0 and its reads need no base add
+  uint64_t *s_part = (uint64_t *)(seg + seg_words);
+  const int t = threadIdx.x;
+  const int64_t g0 = (int64_t)blockIdx.x * kVThreads * GPT;
+  const int64_t ge = g0 + kVThreads * GPT < ngr ? g0 + kVThreads * GPT : ngr;
+  const uint32_t kmask = (1u << k) - 1u;
+  const uint32_t pmax = (uint32_t)(seg_words - 4) * 32u;
+
+  int32_t xr[GPT][kVG];
+#pragma unroll
+  for (int u = 0; u < GPT; ++u) {
+    const int64_t c0 = (g0 + (int64_t)GPT * t + u) * kVG;
+    if (c0 + kVG <= cols) {
+      const int4 *xv = (const int4 *)(x + c0);
+#pragma unroll
+      for (int q = 0; q < kVG / 4; ++q) {
+        const int4 v = xv[q];
+        xr[u][4 * q] = v.x;
+        xr[u][4 * q + 1] = v.y;
+        xr[u][4 * q + 2] = v.z;
+        xr[u][4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kVG; ++j) xr[u][j] = c0 + j < cols ? x[c0 + j] : 0;
+    }
+  }
+
+  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+    // x stays in 32-bit registers: without this the compiler hoists the
+    // sign extensions out of the row loop and doubles the register count
+#pragma unroll
+    for (int u = 0; u < GPT; ++u)
+#pragma unroll
+      for (int j = 0; j < kVG; ++j) asm volatile("" : "+v"(xr[u][j]));
+
+    const uint64_t base = row_bit[r];
+    const uint32_t *gr = grp + (uint64_t)r * (uint64_t)ngr;
+    const uint64_t s = base + gr[g0];
+    const uint64_t e = ge < ngr ? base + gr[ge] : row_bit[r + 1];
+    const uint64_t ws = (s >> 5) & ~3ull;
+    const uint64_t we = ((e + 31u) >> 5) + 2u;  // two guard words for the 64-bit reads
+    const int nvec = (int)((we - ws + 3u) >> 2);
+    const uint4 *src = (const uint4 *)(w + ws);
+    for (int v = t; v < nvec; v += kVThreads) seg4[v] = src[v];
+
+    uint32_t p[GPT];
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+      const int64_t g = g0 + (int64_t)GPT * t + u;
+      p[u] = g < ngr ? (uint32_t)(base + gr[g] - ws * 32u) : 0u;
+    }
+    __syncthreads();
+
+    int64_t acc[GPT];
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) acc[u] = 0;
+#pragma unroll
+    for (int j = 0; j < kVG; ++j) {
+#pragma unroll
+      for (int u = 0; u < GPT; ++u) {
+        if (CLAMP) p[u] = p[u] < pmax ? p[u] : pmax;
+        const uint32_t q = p[u] >> 5;
+        const uint32_t lo = seg[q], hi = seg[q + 1];
+        const uint32_t wv = __builtin_amdgcn_alignbit(hi, lo, p[u] & 31u);
+        const uint32_t b = wv & kmask;
+        const uint32_t kb = (uint32_t)k + b;
+        int32_t a;
+        if (SGN)
+          a = opaque_i32(__builtin_amdgcn_sbfe((int32_t)wv, k, b));
+        else
+          a = (int32_t)__builtin_amdgcn_ubfe(wv, k, b);
+        acc[u] += (int64_t)a * (int64_t)xr[u][j];
+        if (__builtin_expect(kb > 32u, 0)) {
+          // the value runs past the 32 bits read: replace a by the full value
+          const int nb = b < 64u ? (int)b : 64;
+          uint64_t v = lds_bits64(seg, p[u] + (uint32_t)k) & mask64(nb);
+          if (SGN) v = (uint64_t)sext64(v, nb);
+          int32_t xw = xr[u][j];
+          asm volatile("" : "+v"(xw));  // sign-extend here, not hoisted
+          acc[u] += (int64_t)((v - (uint64_t)(int64_t)a) * (uint64_t)(int64_t)xw);
+        }
+        asm volatile("" : "+v"(acc[u]));  // accumulate in place, element by element
+        p[u] += kb;
+      }
+    }
+    int64_t tot = 0;
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) tot += acc[u];
+    tot = wave_sum(tot);
+    if ((t & 63) == 0) s_part[t >> 6] = (uint64_t)tot;
+    __syncthreads();
+    if (t == 0) {
+      uint64_t sum = 0;
+#pragma unroll
+      for (int v = 0; v < kVThreads / 64; ++v) sum += s_part[v];
+      if (atomic_out)
+        atomicAdd((unsigned long long *)&y[r], (unsigned long long)sum);
+      else
+        y[r] = (int64_t)sum;
+    }
+  }
+}
+
+int compute_units() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n < 1)
+      n = 256;
+    cus = n;
+  }
+  return cus;
+}
+
+// Blocks of the staged kernel resident at once for this staging size (the
+// size depends on the matrix, so it is not cached).
+template <bool SGN, int GPT, bool CLAMP>
+int resident_lds(size_t lds) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_vlb_mv_lds<SGN, GPT, CLAMP>,
+                                                   kVThreads, lds) != hipSuccess ||
+      occ < 1)
+    occ = 1;
+  return occ * compute_units();
+}
+
+template <bool SGN, int GPT, bool CLAMP>
+hipError_t launch_mv_lds(const VlbView &a, const int32_t *x, int64_t *y, hipStream_t s) {
+  const int64_t per_panel = (int64_t)kVThreads * GPT;
+  const int64_t npanels = (a.ngr + per_panel - 1) / per_panel;
+  if (npanels > 65535) return hipErrorInvalidValue;
+  // a panel's stretch: at most per_panel * gmax bits, plus the alignment of
+  // its first word down to 16 bytes, the two guard words after its last, the
+  // rounding to whole 16-byte vectors and the clamp margin
+  const int seg_words = (int)((per_panel * (int64_t)a.gmax + 31) / 32 + 16) & ~3;
+  const size_t lds = (size_t)seg_words * 4u + (kVThreads / 64) * 8u;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_vlb_mv_lds<SGN, GPT, CLAMP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  if (npanels > 1) {
+    hipError_t e = launch_fill_i64(y, (uint64_t)a.rows, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  int64_t gy = resident_lds<SGN, GPT, CLAMP>(lds) / npanels;
+  gy = gy < 1 ? 1 : (gy > a.rows ? a.rows : gy);
+  if (gy > 65535) gy = 65535;
+  dim3 grid((unsigned)npanels, (unsigned)gy);
+  k_vlb_mv_lds<SGN, GPT, CLAMP><<<grid, kVThreads, lds, s>>>(
+      a.w, a.row_bit, a.grp, a.rows, a.cols, a.ngr, a.k, seg_words, x, y, npanels > 1 ? 1 : 0);
+  return hipGetLastError();
+}
+
+unsigned vgrid(uint64_t work, uint64_t per_block, unsigned cap) {
+  uint64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+uint64_t vlb_ngr(int64_t cols) { return ((uint64_t)cols + kVG - 1) / kVG; }
+
+hipError_t launch_vlb_sizes(const void *dense, int dtype, int64_t rows, int64_t cols, int k,
+                            int sgn, uint32_t *grp, RangeSlot *slot, hipStream_t s) {
+  const int64_t ngr = (int64_t)vlb_ngr(cols);
+  const unsigned grid = vgrid((uint64_t)rows * (uint64_t)ngr * kVG, kVThreads * 4, 4096);
+  if (dtype == CCM_I64)
+    k_vlb_sizes<int64_t><<<grid, kVThreads, 0, s>>>((const int64_t *)dense, rows, cols, ngr, k,
+                                                    sgn, grp, slot);
+  else
+    k_vlb_sizes<int32_t><<<grid, kVThreads, 0, s>>>((const int32_t *)dense, rows, cols, ngr, k,
+                                                    sgn, grp, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_vlb_scan(int64_t rows, int64_t cols, uint32_t *grp, uint64_t *row_bit,
+                           hipStream_t s) {
+  const int64_t ngr = (int64_t)vlb_ngr(cols);
+  const unsigned grid = vgrid((uint64_t)rows, 1, 16384);
+  k_vlb_row_scan<<<grid, kVThreads, 0, s>>>(rows, ngr, grp, row_bit);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_vlb_rows_scan<<<1, kVThreads, 0, s>>>(rows, row_bit);
+  return hipGetLastError();
+}
+
+hipError_t launch_vlb_pack(const void *dense, int dtype, const VlbView &a, uint32_t *out,
+                           uint64_t cap32, hipStream_t s) {
+  k_zero_u32<<<vgrid(cap32, kVThreads * 8, 8192), kVThreads, 0, s>>>(out, cap32);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned grid = vgrid((uint64_t)a.rows * (uint64_t)a.ngr, kVThreads, 65536);
+  if (dtype == CCM_I64)
+    k_vlb_pack<int64_t><<<grid, kVThreads, 0, s>>>((const int64_t *)dense, a.rows, a.cols, a.ngr,
+                                                   a.k, a.sgn, a.row_bit, a.grp, out);
+  else
+    k_vlb_pack<int32_t><<<grid, kVThreads, 0, s>>>((const int32_t *)dense, a.rows, a.cols, a.ngr,
+                                                   a.k, a.sgn, a.row_bit, a.grp, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_vlb_decode(const VlbView &a, int64_t *out, hipStream_t s) {
+  const unsigned grid = vgrid((uint64_t)a.rows * (uint64_t)a.ngr, kVThreads, 65536);
+  k_vlb_decode<<<grid, kVThreads, 0, s>>>(a.w, a.row_bit, a.grp, a.rows, a.cols, a.ngr, a.k,
+                                          a.sgn, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_vlb_get(const VlbView &a, int64_t i, int64_t j, int64_t *out, hipStream_t s) {
+  k_vlb_get<<<1, 64, 0, s>>>(a.w, a.row_bit, a.grp, a.ngr, i, j, a.k, a.sgn, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_vlb_matvec(const VlbView &a, const void *x, int xdtype, int64_t *y,
+                             hipStream_t s) {
+  const bool staged = xdtype == CCM_I32 && ((uintptr_t)x % 16) == 0;
+  if (staged) {
+    constexpr int GPT = 2;
+    const bool clamp = (a.cols % ((int64_t)kVThreads * GPT * kVG)) != 0;
+    const int32_t *xi = (const int32_t *)x;
+    if (a.sgn)
+      return clamp ? launch_mv_lds<true, GPT, true>(a, xi, y, s)
+                   : launch_mv_lds<true, GPT, false>(a, xi, y, s);
+    return clamp ? launch_mv_lds<false, GPT, true>(a, xi, y, s)
+                 : launch_mv_lds<false, GPT, false>(a, xi, y, s);
+  }
+  const int64_t nchunk = (a.ngr + kVThreads - 1) / kVThreads;
+  if (nchunk > 1) {
+    hipError_t e = launch_fill_i64(y, (uint64_t)a.rows, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  const unsigned grid = vgrid((uint64_t)a.rows * (uint64_t)nchunk, 1, 65536);
+  if (xdtype == CCM_I64)
+    k_vlb_mv_gen<int64_t><<<grid, kVThreads, 0, s>>>(a.w, a.row_bit, a.grp, a.rows, a.cols, a.ngr,
+                                                     a.k, a.sgn, (const int64_t *)x, y);
+  else
+    k_vlb_mv_gen<int32_t><<<grid, kVThreads, 0, s>>>(a.w, a.row_bit, a.grp, a.rows, a.cols, a.ngr,
+                                                     a.k, a.sgn, (const int32_t *)x, y);
+  return hipGetLastError();
+}
+
+}  // namespace ccm

@@ -498,6 +498,10 @@ def pin_vlb_layout(o):
         assert got == flat and got_w == widths and used == p.nbits
         assert stream >> p.nbits == 0
         assert o.vlb_decompress(p).tolist() == A.tolist()
+        # element starts: prefix sums of k + b_e
+        starts = np.concatenate([[0], np.cumsum([k + b for b in widths])[:-1]]).reshape(r, c)
+        for grp in (1, 3, 32):
+            assert o.vlb_offsets(p, grp).tolist() == starts[:, ::grp].tolist()
 
 
 def pin_vlb_extremes(o):
