@@ -536,7 +536,7 @@ def matvec_only(args, torch, W, ccm):
                       "packed_bytes": [8 * m.words for m in mats]}), flush=True)
 
 
-def cpu_baseline(W, rows=192):
+def cpu_baseline(W, rows=192, vlb_rows=32):
     """The oracle on the host cores, on the first `rows` rows of each of the
     twelve sweep matrices: the same step as the GPU (compress A and B, matvec,
     add, scale by 7, decompress).  value = the oracle's packed-matvec GB/s."""
@@ -559,8 +559,23 @@ def cpu_baseline(W, rows=192):
             t_mv += t2 - t1
             t_step += t3 - t0
             mv_bytes += rows * a_s.cols * pa.bits / 8
+    # Method 2: the oracle's matvec on the first rows of each Beta workload
+    # (each row compressed on its own; its y entry is the same)
+    vlb = {}
+    for name in W.VLB_BETAS:
+        spec, x_s = W.vlb_sweep(name)
+        xv = x_s.dense()
+        packed = [oracle.vlb_compress(spec.rows_slice(r, r + 1)) for r in range(vlb_rows)]
+        t0 = time.perf_counter()
+        for p in packed:
+            oracle.vlb_matvec(p, xv)
+        dt = time.perf_counter() - t0
+        vlb[name] = {"gelem_s": round(vlb_rows * spec.cols / dt / 1e9, 5),
+                     "gb_s": round(sum(p.nbits for p in packed) / 8 / dt / 1e9, 5)}
     return {"value": round(mv_bytes / t_mv / 1e9, 4), "unit": "GB/s",
             "cores": oracle.threads(), "kind": "oracle",
+            "vlb_matvec": vlb, "vlb_sample": f"rows 0..{vlb_rows - 1} of each 16384 x 16384 "
+                                             "Beta workload, one thread",
             "sample": f"rows 0..{rows - 1} of each of the 12 sweep matrices ({12 * rows} x 16384 "
                       "elements): compress A and B, matvec, add, scale, decompress; value = "
                       "packed bytes of A over the oracle's matvec time",

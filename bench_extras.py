@@ -1,6 +1,7 @@
-"""Measurements beside the main benchmark line: the dense compressed GEMM
-(8192^3, A in [0, 2^6), B in [-2^3, 2^3)), the batched matvec and the serving
-loop.  Called by bench.py after its timed steps."""
+"""Measurements beside the main benchmark line: Method 2 (variable length
+blocks) matvec on the paper's Beta bit-length distributions, the dense
+compressed GEMM (8192^3, A in [0, 2^6), B in [-2^3, 2^3)), the batched matvec
+and the serving loop.  Called by bench.py after its timed steps."""
 from __future__ import annotations
 
 import time
@@ -142,8 +143,77 @@ def serving(torch, ccm, target_bytes=200e9, count=2000, log=None):
     return out
 
 
+# VALU instructions per element of the staged VLB walk when the pair fits 32
+# bits (funnel shift, length mask, extract, multiply-add, two position adds,
+# word index, window compare and select, width test, LDS address).
+VLB_VALU_PER_ELEM = 11
+VALU_LANE_OPS = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+
+
+def vlb(torch, ccm, reps=20):
+    """Method 2 matvec on 16384 x 16384 matrices whose bit-lengths follow the
+    paper's Beta distributions (two compressed copies used in turn, so the
+    256 MB last-level cache holds neither), with the Method 1 width of the
+    same matrix and both efficiencies (Eq. 15, Eq. 17)."""
+    import numpy as np
+    out = {}
+    for name in W.VLB_BETAS:
+        spec, xs = W.vlb_sweep(name)
+        A = spec.dense_device(ccm.fill_uniform, torch)
+        n = spec.rows * spec.cols
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        g0 = ccm.vlb_compress(A)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t_comp = ev[0].elapsed_time(ev[1]) * 1e-3
+        g1 = ccm.vlb_compress(A)
+        sm_bits, _ = ccm.width(int(g0.vmin), int(g0.vmax))
+        del A
+        x = torch.from_numpy(xs.dense()).to(torch.int32).cuda()
+        y = torch.empty(spec.rows, dtype=torch.int64, device="cuda")
+        go = [ccm.vlb_matvec_launcher(g, x, y) for g in (g0, g1)]
+        for i in range(4):
+            go[i % 2]()
+        torch.cuda.synchronize()
+        ts = []
+        for i in range(reps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record()
+            go[i % 2]()
+            e[1].record()
+            torch.cuda.synchronize()
+            ts.append(e[0].elapsed_time(e[1]) * 1e-3)
+        t = float(np.median(ts))
+        stream = 8 * g0.words
+        alu_t = n * VLB_VALU_PER_ELEM / VALU_LANE_OPS
+        out[name] = {
+            "workload": f"{spec.rows}x{spec.cols}, bit-lengths Beta({spec.a1:g}, {spec.b1:g}) on [1, 64]",
+            "k": g0.k, "avg_bits_per_elem": round(g0.nbits / n, 3), "gmax_bits": g0.gmax,
+            "eta2_vlb": round(1 - g0.nbits / (64 * n), 4), "eta1_sm": round(1 - sm_bits / 64, 4),
+            "index_bytes": g0.index_bytes, "stream_bytes": stream,
+            "compress_ms": round(t_comp * 1e3, 2),
+            "matvec_us": round(t * 1e6, 1),
+            "matvec_gb_s": round(stream / t / 1e9, 1),
+            "matvec_gb_s_with_index": round((stream + g0.index_bytes) / t / 1e9, 1),
+            "gelem_s": round(n / t / 1e9, 1),
+            "frac_hbm": round(stream / t / 8e12, 4),
+            "frac_alu_model": round(alu_t / t, 4),
+        }
+        del g0, g1, go
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_extras(torch, ccm, log=None):
     out = {}
+    t0 = time.perf_counter()
+    out["vlb"] = vlb(torch, ccm)
+    out["vlb"]["wall_s"] = round(time.perf_counter() - t0, 2)
+    torch.cuda.empty_cache()
+    if log:
+        log("vlb done")
     t0 = time.perf_counter()
     out["gemm"] = gemm(torch, ccm)
     out["gemm"]["wall_s"] = round(time.perf_counter() - t0, 2)

@@ -326,6 +326,18 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_mv_gen(
   }
 }
 
+// a == b ? x : y on registers.  Written as one compare and one v_cndmask:
+// as plain C the compiler turns the select of two values just read from LDS
+// into a select of their addresses and demotes the chain state to scratch.
+__device__ __forceinline__ uint32_t select_eq(uint32_t a, uint32_t b, uint32_t x, uint32_t y) {
+  uint32_t r;
+  asm("v_cmp_eq_u32 vcc, %1, %2\n\tv_cndmask_b32 %0, %4, %3, vcc"
+      : "=v"(r)
+      : "v"(a), "v"(b), "v"(x), "v"(y)
+      : "vcc");
+  return r;
+}
+
 // 64 stream bits from bit pv of a staged stretch (reads three words).
 __device__ __forceinline__ uint64_t lds_bits64(const uint32_t *seg, uint32_t pv) {
   const uint32_t q = pv >> 5;
@@ -341,35 +353,44 @@ __device__ __forceinline__ uint64_t lds_bits64(const uint32_t *seg, uint32_t pv)
 //     GPT independent chains (instruction-level parallelism in the serial
 //     walks), and keeps their 32 GPT x values in registers for all rows.
 //   * Per row the block copies the panel's stretch of the stream (contiguous:
-//     the panel's groups follow each other) into LDS with 16-byte loads, then
-//     every lane walks its groups from LDS.  Per element: one two-word read
-//     and a funnel shift (v_alignbit) give the 32 bits at the pair's start;
-//     the length is their low k bits; when k + b_e <= 32 the value is one
-//     bit-field extract of the same word (sign-extending when signed) and the
-//     product one 32x32->64 multiply-add.  Longer pairs (rare in the paper's
-//     bit-length distributions) take a branch that reads 64 bits at the
-//     value's start.
+//     the panel's groups follow each other) into LDS with 16-byte
+//     memory-to-LDS loads (global_load_lds_dwordx4, no registers), issued
+//     right after the walks of the previous row.  One buffer: a second one,
+//     filled a row ahead, measured slower, since it halves the blocks per CU
+//     and the other resident blocks already cover a block's copy.
+//   * A chain keeps the two stream words around its position in registers
+//     (w0 = word q, w1 = word q + 1).  Per element: a funnel shift
+//     (v_alignbit) gives the 32 bits at the pair's start; the length is their
+//     low k bits; the value is one bit-field extract of the same word
+//     (sign-extending when signed) and the product one 32x32->64
+//     multiply-add.  A pair of at most 32 bits moves the position by at most
+//     one word, so the window advances with a select and ONE new LDS word per
+//     element.  A longer pair (rare in the paper's bit-length distributions)
+//     takes a branch that reads the 64 bits at the value's start, corrects
+//     the product and reloads the window.
 //   * Rows visited: blockIdx.y, blockIdx.y + gridDim.y, ... (resident
-//     blocks only, so x is loaded once per block).
+//     blocks only, so x is loaded once per block).  Wave partial sums of row
+//     r are folded and stored after the barrier that opens row r + 1.
 //   * CLAMP: some chain of the panel is shorter than 32 elements or absent
 //     (ragged row end, partial panel); its walk then continues through bits
 //     of the next group or past the stretch, with x = 0 for those elements,
-//     and the read position is clamped inside the staged buffer.
+//     and its reads are clamped inside the staged buffer.
 template <bool SGN, int GPT, bool CLAMP>
 __global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
     const uint32_t *__restrict__ w, const uint64_t *__restrict__ row_bit,
     const uint32_t *__restrict__ grp, int64_t rows, int64_t cols, int64_t ngr, int k,
     int seg_words, const int32_t *__restrict__ x, int64_t *__restrict__ y, int atomic_out) {
   extern __shared__ uint4 seg4[];
-  uint32_t *seg = (uint32_t *)seg4;
-  // wave partial sums after the stream stretch, so the stretch starts at LDS
-  // address 0 and its reads need no base add
-  uint64_t *s_part = (uint64_t *)(seg + seg_words);
-  const int t = threadIdx.x;
+  // the stretch buffer (seg_words words), then the wave partial sums of two
+  // rows
+  uint64_t *s_part = (uint64_t *)((uint32_t *)seg4 + seg_words);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t g0 = (int64_t)blockIdx.x * kVThreads * GPT;
   const int64_t ge = g0 + kVThreads * GPT < ngr ? g0 + kVThreads * GPT : ngr;
   const uint32_t kmask = (1u << k) - 1u;
-  const uint32_t pmax = (uint32_t)(seg_words - 4) * 32u;
+  const uint32_t narrow = 32u - (uint32_t)k;  // largest b read from one 32-bit window
+  const uint32_t qmax = (uint32_t)seg_words - 4u;
+  const uint32_t pmax = qmax * 32u;
 
   int32_t xr[GPT][kVG];
 #pragma unroll
@@ -391,14 +412,12 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
     }
   }
 
-  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
-    // x stays in 32-bit registers: without this the compiler hoists the
-    // sign extensions out of the row loop and doubles the register count
-#pragma unroll
-    for (int u = 0; u < GPT; ++u)
-#pragma unroll
-      for (int j = 0; j < kVG; ++j) asm volatile("" : "+v"(xr[u][j]));
-
+  // Row r's stage: its start bit, first staged word (16-byte aligned) and
+  // 16-byte vector count; the lanes' raw group offsets (clamped loads,
+  // branch-free) and the copy of the stretch into the buffer.
+  uint64_t nb_base = 0, nb_ws = 0;
+  uint32_t graw[GPT];
+  auto stage = [&](int64_t r) {
     const uint64_t base = row_bit[r];
     const uint32_t *gr = grp + (uint64_t)r * (uint64_t)ngr;
     const uint64_t s = base + gr[g0];
@@ -406,64 +425,122 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
     const uint64_t ws = (s >> 5) & ~3ull;
     const uint64_t we = ((e + 31u) >> 5) + 2u;  // two guard words for the 64-bit reads
     const int nvec = (int)((we - ws + 3u) >> 2);
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+      int64_t g = g0 + (int64_t)GPT * t + u;
+      g = g < ngr ? g : ngr - 1;
+      graw[u] = gr[g];
+    }
     const uint4 *src = (const uint4 *)(w + ws);
-    for (int v = t; v < nvec; v += kVThreads) seg4[v] = src[v];
+    uint4 *dst = seg4;
+    for (int v0 = 0; v0 < nvec; v0 += kVThreads) {
+      const int v = v0 + t;
+      if (v < nvec)
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(src + v),
+            (__attribute__((address_space(3))) void *)(dst + v0 + 64 * wave), 16, 0, 0);
+    }
+    nb_base = base;
+    nb_ws = ws;
+  };
 
+  int64_t r = blockIdx.y;
+  if (r < rows) stage(r);
+  int cur = 0;
+  int64_t prev = -1;  // row whose wave sums wait in s_part[cur ^ 1]
+  while (r < rows) {
+    __builtin_amdgcn_s_waitcnt(0);  // all counters to zero: this lane's copies have landed
+    __syncthreads();                // everyone's copies have landed
+    if (prev >= 0 && t == 0) {
+      uint64_t sum = 0;
+#pragma unroll
+      for (int v = 0; v < kVThreads / 64; ++v) sum += s_part[4 * (cur ^ 1) + v];
+      if (atomic_out)
+        atomicAdd((unsigned long long *)&y[prev], (unsigned long long)sum);
+      else
+        y[prev] = (int64_t)sum;
+    }
     uint32_t p[GPT];
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
       const int64_t g = g0 + (int64_t)GPT * t + u;
-      p[u] = g < ngr ? (uint32_t)(base + gr[g] - ws * 32u) : 0u;
+      p[u] = g < ngr ? (uint32_t)(nb_base + graw[u] - nb_ws * 32u) : 0u;
     }
-    __syncthreads();
+    const int64_t rn = r + gridDim.y;
 
-    int64_t acc[GPT];
+    // x stays in 32-bit registers: without this the compiler hoists the
+    // sign extensions out of the row loop and doubles the register count
 #pragma unroll
-    for (int u = 0; u < GPT; ++u) acc[u] = 0;
+    for (int u = 0; u < GPT; ++u)
+#pragma unroll
+      for (int j = 0; j < kVG; ++j) asm volatile("" : "+v"(xr[u][j]));
+
+    const uint32_t *seg = (const uint32_t *)seg4;
+    int64_t acc[GPT];
+    uint32_t q[GPT], w0[GPT], w1[GPT];
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+      acc[u] = 0;
+      q[u] = p[u] >> 5;
+      w0[u] = seg[q[u]];
+      w1[u] = seg[q[u] + 1];
+    }
 #pragma unroll
     for (int j = 0; j < kVG; ++j) {
 #pragma unroll
       for (int u = 0; u < GPT; ++u) {
-        if (CLAMP) p[u] = p[u] < pmax ? p[u] : pmax;
-        const uint32_t q = p[u] >> 5;
-        const uint32_t lo = seg[q], hi = seg[q + 1];
-        const uint32_t wv = __builtin_amdgcn_alignbit(hi, lo, p[u] & 31u);
+        const uint32_t wv = __builtin_amdgcn_alignbit(w1[u], w0[u], p[u] & 31u);
         const uint32_t b = wv & kmask;
-        const uint32_t kb = (uint32_t)k + b;
         int32_t a;
         if (SGN)
           a = opaque_i32(__builtin_amdgcn_sbfe((int32_t)wv, k, b));
         else
           a = (int32_t)__builtin_amdgcn_ubfe(wv, k, b);
         acc[u] += (int64_t)a * (int64_t)xr[u][j];
-        if (__builtin_expect(kb > 32u, 0)) {
-          // the value runs past the 32 bits read: replace a by the full value
+        const uint32_t pn = p[u] + (uint32_t)k + b;
+        uint32_t qn = pn >> 5;
+        if (CLAMP) qn = qn < qmax ? qn : qmax;
+        uint32_t w0n = select_eq(qn, q[u], w0[u], w1[u]);
+        if (__builtin_expect(b > narrow, 0)) {
+          // the value runs past the 32 bits read: replace a by the full
+          // value, and reload the window where the next pair starts
+          uint32_t pv = p[u] + (uint32_t)k;
+          if (CLAMP) pv = pv < pmax ? pv : pmax;
           const int nb = b < 64u ? (int)b : 64;
-          uint64_t v = lds_bits64(seg, p[u] + (uint32_t)k) & mask64(nb);
+          uint64_t v = lds_bits64(seg, pv) & mask64(nb);
           if (SGN) v = (uint64_t)sext64(v, nb);
           int32_t xw = xr[u][j];
           asm volatile("" : "+v"(xw));  // sign-extend here, not hoisted
           acc[u] += (int64_t)((v - (uint64_t)(int64_t)a) * (uint64_t)(int64_t)xw);
+          w0n = seg[qn];
         }
         asm volatile("" : "+v"(acc[u]));  // accumulate in place, element by element
-        p[u] += kb;
+        w1[u] = seg[qn + 1];
+        w0[u] = w0n;
+        q[u] = qn;
+        p[u] = pn;
       }
     }
     int64_t tot = 0;
 #pragma unroll
     for (int u = 0; u < GPT; ++u) tot += acc[u];
     tot = wave_sum(tot);
-    if ((t & 63) == 0) s_part[t >> 6] = (uint64_t)tot;
-    __syncthreads();
-    if (t == 0) {
-      uint64_t sum = 0;
+    if (lane == 0) s_part[4 * cur + wave] = (uint64_t)tot;
+    __syncthreads();  // every walk is done before the copy overwrites the buffer
+    if (rn < rows) stage(rn);
+    prev = r;
+    r = rn;
+    cur ^= 1;
+  }
+  __syncthreads();
+  if (prev >= 0 && t == 0) {
+    uint64_t sum = 0;
 #pragma unroll
-      for (int v = 0; v < kVThreads / 64; ++v) sum += s_part[v];
-      if (atomic_out)
-        atomicAdd((unsigned long long *)&y[r], (unsigned long long)sum);
-      else
-        y[r] = (int64_t)sum;
-    }
+    for (int v = 0; v < kVThreads / 64; ++v) sum += s_part[4 * (cur ^ 1) + v];
+    if (atomic_out)
+      atomicAdd((unsigned long long *)&y[prev], (unsigned long long)sum);
+    else
+      y[prev] = (int64_t)sum;
   }
 }
 
@@ -480,8 +557,20 @@ int compute_units() {
   return cus;
 }
 
-// Blocks of the staged kernel resident at once for this staging size (the
-// size depends on the matrix, so it is not cached).
+constexpr size_t kMaxLds = 160 * 1024 - 64;
+
+// A panel's stretch: at most 256 GPT gmax bits, plus the alignment of its
+// first word down to 16 bytes, the two guard words after its last, the
+// rounding to whole 16-byte vectors and the clamp margin.
+int stage_words(uint64_t gmax, int gpt) {
+  return (int)(((uint64_t)kVThreads * gpt * gmax + 31u) / 32u + 16u) & ~3;
+}
+
+// The stretch buffer and the wave partial sums of two rows.
+size_t stage_lds(uint64_t gmax, int gpt) {
+  return (size_t)stage_words(gmax, gpt) * 4u + 2u * (kVThreads / 64) * 8u;
+}
+
 template <bool SGN, int GPT, bool CLAMP>
 int resident_lds(size_t lds) {
   int occ = 0;
@@ -497,15 +586,13 @@ hipError_t launch_mv_lds(const VlbView &a, const int32_t *x, int64_t *y, hipStre
   const int64_t per_panel = (int64_t)kVThreads * GPT;
   const int64_t npanels = (a.ngr + per_panel - 1) / per_panel;
   if (npanels > 65535) return hipErrorInvalidValue;
-  // a panel's stretch: at most per_panel * gmax bits, plus the alignment of
-  // its first word down to 16 bytes, the two guard words after its last, the
-  // rounding to whole 16-byte vectors and the clamp margin
-  const int seg_words = (int)((per_panel * (int64_t)a.gmax + 31) / 32 + 16) & ~3;
-  const size_t lds = (size_t)seg_words * 4u + (kVThreads / 64) * 8u;
+  const int seg_words = stage_words(a.gmax, GPT);
+  const size_t lds = stage_lds(a.gmax, GPT);
+  if (lds > kMaxLds) return hipErrorInvalidValue;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void *)k_vlb_mv_lds<SGN, GPT, CLAMP>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
     if (e != hipSuccess) return e;
     attr = true;
   }
@@ -520,6 +607,28 @@ hipError_t launch_mv_lds(const VlbView &a, const int32_t *x, int64_t *y, hipStre
   k_vlb_mv_lds<SGN, GPT, CLAMP><<<grid, kVThreads, lds, s>>>(
       a.w, a.row_bit, a.grp, a.rows, a.cols, a.ngr, a.k, seg_words, x, y, npanels > 1 ? 1 : 0);
   return hipGetLastError();
+}
+
+template <bool SGN, int GPT>
+hipError_t launch_mv_lds_c(const VlbView &a, const int32_t *x, int64_t *y, hipStream_t s) {
+  const bool clamp = (a.cols % ((int64_t)kVThreads * GPT * kVG)) != 0;
+  return clamp ? launch_mv_lds<SGN, GPT, true>(a, x, y, s)
+               : launch_mv_lds<SGN, GPT, false>(a, x, y, s);
+}
+
+// Staged matvec: one group per lane (256 groups of at most 32 * 71 bits
+// always fit in LDS), or two when that keeps strictly more chains resident
+// per CU (blocks per CU from registers and LDS, times 256 GPT).  At equal
+// chain counts one group per lane measured faster: twice the waves to hide
+// the LDS latency of the walks.
+template <bool SGN>
+hipError_t launch_mv_staged(const VlbView &a, const int32_t *x, int64_t *y, hipStream_t s) {
+  const int64_t chains1 = (int64_t)resident_lds<SGN, 1, true>(stage_lds(a.gmax, 1));
+  int64_t chains2 = 0;
+  if (stage_lds(a.gmax, 2) <= kMaxLds)
+    chains2 = 2 * (int64_t)resident_lds<SGN, 2, true>(stage_lds(a.gmax, 2));
+  return chains2 > chains1 ? launch_mv_lds_c<SGN, 2>(a, x, y, s)
+                           : launch_mv_lds_c<SGN, 1>(a, x, y, s);
 }
 
 unsigned vgrid(uint64_t work, uint64_t per_block, unsigned cap) {
@@ -588,14 +697,8 @@ hipError_t launch_vlb_matvec(const VlbView &a, const void *x, int xdtype, int64_
                              hipStream_t s) {
   const bool staged = xdtype == CCM_I32 && ((uintptr_t)x % 16) == 0;
   if (staged) {
-    constexpr int GPT = 2;
-    const bool clamp = (a.cols % ((int64_t)kVThreads * GPT * kVG)) != 0;
     const int32_t *xi = (const int32_t *)x;
-    if (a.sgn)
-      return clamp ? launch_mv_lds<true, GPT, true>(a, xi, y, s)
-                   : launch_mv_lds<true, GPT, false>(a, xi, y, s);
-    return clamp ? launch_mv_lds<false, GPT, true>(a, xi, y, s)
-                 : launch_mv_lds<false, GPT, false>(a, xi, y, s);
+    return a.sgn ? launch_mv_staged<true>(a, xi, y, s) : launch_mv_staged<false>(a, xi, y, s);
   }
   const int64_t nchunk = (a.ngr + kVThreads - 1) / kVThreads;
   if (nchunk > 1) {
