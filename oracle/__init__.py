@@ -74,6 +74,13 @@ _SIGNATURES = {
     "ccmref_matmul_check": (ctypes.c_int, [_MP, _MP]),
     "ccmref_matmul_dense": (ctypes.c_int, [_MP, _MP, _I64P]),
     "ccmref_matmul_entries": (ctypes.c_int, [_MP, _MP, _I64P, _I64P, ctypes.c_int64, _I64P]),
+    "ccmref_compress_cm": (ctypes.c_int, [_I64P, _MP]),
+    "ccmref_decompress_cm": (ctypes.c_int, [_MP, _I64P]),
+    "ccmref_get_cm": (ctypes.c_int, [_MP, ctypes.c_int64, ctypes.c_int64, _I64P]),
+    "ccmref_matvec_cm": (ctypes.c_int, [_MP, _I64P, _I64P]),
+    "ccmref_matvec_t": (ctypes.c_int, [_MP, _I64P, _I64P]),
+    "ccmref_matvec_t_cm": (ctypes.c_int, [_MP, _I64P, _I64P]),
+    "ccmref_header_cm": (None, [_MP, ctypes.POINTER(ctypes.c_uint8)]),
     "ccmref_vlb_width": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32]),
     "ccmref_vlb_plan": (ctypes.c_int, [_I64P, ctypes.c_int64, ctypes.c_int64, _VP]),
     "ccmref_vlb_compress": (ctypes.c_int, [_I64P, _VP]),
@@ -280,6 +287,60 @@ class Oracle:
         return out
 
 
+    # -- column-major unravel ---------------------------------------------------
+    # A column-major matrix is a Packed whose rows/cols are A's and whose
+    # stream holds element (i, j) at index j*rows + i.
+    def compress_cm(self, dense) -> Packed:
+        d = np.ascontiguousarray(np.asarray(dense, dtype=np.int64))
+        if d.ndim != 2:
+            raise OracleError(E_INVAL)
+        m = _Matrix()
+        _check(self._lib.ccmref_plan(_i64(d), d.shape[0], d.shape[1], ctypes.byref(m)))
+        payload = np.zeros(int(m.words), dtype=np.uint64)
+        m.payload = payload.ctypes.data_as(ctypes.c_void_p)
+        _check(self._lib.ccmref_compress_cm(_i64(d), ctypes.byref(m)))
+        return Packed(int(m.rows), int(m.cols), int(m.vmin), int(m.vmax), int(m.bits),
+                      bool(m.is_signed), payload)
+
+    def decompress_cm(self, p: Packed) -> np.ndarray:
+        out = np.empty((p.rows, p.cols), dtype=np.int64)
+        m = p._struct()
+        _check(self._lib.ccmref_decompress_cm(ctypes.byref(m), _i64(out)))
+        return out
+
+    def get_cm(self, p: Packed, i: int, j: int) -> int:
+        v = ctypes.c_int64()
+        m = p._struct()
+        _check(self._lib.ccmref_get_cm(ctypes.byref(m), i, j, ctypes.byref(v)))
+        return int(v.value)
+
+    def _mv(self, fn, a: Packed, x, nin: int, nout: int) -> np.ndarray:
+        xv = np.ascontiguousarray(np.asarray(x, dtype=np.int64).ravel())
+        if xv.size != nin:
+            raise OracleError(E_SHAPE)
+        y = np.empty(nout, dtype=np.int64)
+        ma = a._struct()
+        _check(fn(ctypes.byref(ma), _i64(xv), _i64(y)))
+        return y
+
+    def matvec_cm(self, a: Packed, x) -> np.ndarray:
+        """y = A x for a column-major A."""
+        return self._mv(self._lib.ccmref_matvec_cm, a, x, a.cols, a.rows)
+
+    def matvec_t(self, a: Packed, x) -> np.ndarray:
+        """y = A^T x for a row-major A (x: rows values)."""
+        return self._mv(self._lib.ccmref_matvec_t, a, x, a.rows, a.cols)
+
+    def matvec_t_cm(self, a: Packed, x) -> np.ndarray:
+        """y = A^T x for a column-major A."""
+        return self._mv(self._lib.ccmref_matvec_t_cm, a, x, a.rows, a.cols)
+
+    def header_cm(self, p: Packed) -> bytes:
+        buf = (ctypes.c_uint8 * 64)()
+        m = p._struct()
+        self._lib.ccmref_header_cm(ctypes.byref(m), buf)
+        return bytes(buf)
+
     # -- Method 2 (VLB) -------------------------------------------------------
     def vlb_width(self, v: int, is_signed: bool) -> int:
         return int(self._lib.ccmref_vlb_width(v, 1 if is_signed else 0))
@@ -357,6 +418,13 @@ matmul_check = _ORACLE.matmul_check
 matmul_dense = _ORACLE.matmul_dense
 matmul = _ORACLE.matmul
 matmul_entries = _ORACLE.matmul_entries
+compress_cm = _ORACLE.compress_cm
+decompress_cm = _ORACLE.decompress_cm
+get_cm = _ORACLE.get_cm
+matvec_cm = _ORACLE.matvec_cm
+matvec_t = _ORACLE.matvec_t
+matvec_t_cm = _ORACLE.matvec_t_cm
+header_cm = _ORACLE.header_cm
 vlb_width = _ORACLE.vlb_width
 vlb_compress = _ORACLE.vlb_compress
 vlb_decompress = _ORACLE.vlb_decompress

@@ -246,6 +246,87 @@ int ccmref_matmul_entries(const ccmref_matrix *a, const ccmref_matrix *b, const 
   return CCMREF_OK;
 }
 
+/* ---- column-major unravel ------------------------------------------------ */
+
+/* Stream index of element (i, j) when the matrix is unravelled by column. */
+static uint64_t cm_index(const ccmref_matrix *m, int64_t i, int64_t j) {
+  return (uint64_t)(j * m->rows + i);
+}
+
+int ccmref_compress_cm(const int64_t *dense, ccmref_matrix *m) {
+  if (!dense || !m || !m->payload) return CCMREF_E_INVAL;
+  memset(m->payload, 0, m->words * sizeof(uint64_t));
+  for (int64_t i = 0; i < m->rows; i++)
+    for (int64_t j = 0; j < m->cols; j++)
+      put_field(m->payload, cm_index(m, i, j), m->bits, dense[i * m->cols + j]);
+  return CCMREF_OK;
+}
+
+int ccmref_decompress_cm(const ccmref_matrix *m, int64_t *dense) {
+  if (!dense || !m || !m->payload) return CCMREF_E_INVAL;
+  for (int64_t i = 0; i < m->rows; i++)
+    for (int64_t j = 0; j < m->cols; j++)
+      dense[i * m->cols + j] = get_field(m->payload, cm_index(m, i, j), m->bits, m->is_signed);
+  return CCMREF_OK;
+}
+
+int ccmref_get_cm(const ccmref_matrix *m, int64_t i, int64_t j, int64_t *out) {
+  if (!m || !out || !m->payload) return CCMREF_E_INVAL;
+  if (i < 0 || i >= m->rows || j < 0 || j >= m->cols) return CCMREF_E_RANGE;
+  *out = get_field(m->payload, cm_index(m, i, j), m->bits, m->is_signed);
+  return CCMREF_OK;
+}
+
+int ccmref_matvec_cm(const ccmref_matrix *a, const int64_t *x, int64_t *y) {
+  if (!a || !x || !y || !a->payload) return CCMREF_E_INVAL;
+  int64_t i;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (i = 0; i < a->rows; i++) {
+    unsigned __int128 acc = 0;
+    for (int64_t j = 0; j < a->cols; j++) {
+      int64_t v = get_field(a->payload, cm_index(a, i, j), a->bits, a->is_signed);
+      acc += (unsigned __int128)((__int128)v * (__int128)x[j]);
+    }
+    y[i] = (int64_t)(uint64_t)acc;
+  }
+  return CCMREF_OK;
+}
+
+int ccmref_matvec_t(const ccmref_matrix *a, const int64_t *x, int64_t *y) {
+  if (!a || !x || !y || !a->payload) return CCMREF_E_INVAL;
+  int64_t j;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (j = 0; j < a->cols; j++) {
+    unsigned __int128 acc = 0;
+    for (int64_t i = 0; i < a->rows; i++) {
+      int64_t v = get_field(a->payload, (uint64_t)(i * a->cols + j), a->bits, a->is_signed);
+      acc += (unsigned __int128)((__int128)v * (__int128)x[i]);
+    }
+    y[j] = (int64_t)(uint64_t)acc;
+  }
+  return CCMREF_OK;
+}
+
+int ccmref_matvec_t_cm(const ccmref_matrix *a, const int64_t *x, int64_t *y) {
+  if (!a || !x || !y || !a->payload) return CCMREF_E_INVAL;
+  int64_t j;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (j = 0; j < a->cols; j++) {
+    unsigned __int128 acc = 0;
+    for (int64_t i = 0; i < a->rows; i++) {
+      int64_t v = get_field(a->payload, cm_index(a, i, j), a->bits, a->is_signed);
+      acc += (unsigned __int128)((__int128)v * (__int128)x[i]);
+    }
+    y[j] = (int64_t)(uint64_t)acc;
+  }
+  return CCMREF_OK;
+}
+
+void ccmref_header_cm(const ccmref_matrix *m, uint8_t out[64]) {
+  ccmref_header(m, out);
+  out[7] = (uint8_t)(out[7] | 2u);
+}
+
 /* ---- Method 2: Variable Length Blocks ----------------------------------- */
 
 int ccmref_vlb_width(int64_t v, int32_t is_signed) {

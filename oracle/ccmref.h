@@ -124,6 +124,28 @@ int ccmref_matmul_dense(const ccmref_matrix *a, const ccmref_matrix *b, int64_t 
 int ccmref_matmul_entries(const ccmref_matrix *a, const ccmref_matrix *b, const int64_t *ii,
                           const int64_t *jj, int64_t n, int64_t *out);
 
+/* ---- Column-major unravel ------------------------------------------------
+ *
+ * The matrix may be unravelled by column (Fortran order) instead of by row
+ * (Methods, "Matrix compression").  Same widths, fields, bit order and word
+ * count; element (i, j) is stream element j*rows + i.  rows and cols stay
+ * those of A; the header sets flags bit 1.  The y = A^T x products are the
+ * plain definition y[j] = sum_i a[i][j] * x[i] modulo 2^64.
+ */
+
+/* dense is row-major rows*cols (m from ccmref_plan over the same values). */
+int ccmref_compress_cm(const int64_t *dense, ccmref_matrix *m);
+/* Decode to row-major dense. */
+int ccmref_decompress_cm(const ccmref_matrix *m, int64_t *dense);
+int ccmref_get_cm(const ccmref_matrix *m, int64_t i, int64_t j, int64_t *out);
+/* y = A x (x: cols, y: rows) for a column-major matrix. */
+int ccmref_matvec_cm(const ccmref_matrix *a, const int64_t *x, int64_t *y);
+/* y = A^T x (x: rows, y: cols) for a row-major / column-major matrix. */
+int ccmref_matvec_t(const ccmref_matrix *a, const int64_t *x, int64_t *y);
+int ccmref_matvec_t_cm(const ccmref_matrix *a, const int64_t *x, int64_t *y);
+/* The header of a column-major matrix (flags bit 1 set). */
+void ccmref_header_cm(const ccmref_matrix *m, uint8_t out[64]);
+
 /* ---- Method 2: Variable Length Blocks (VLB) ----------------------------
  *
  * Each element gets its own minimal width b_e, stored in a length field of a

@@ -409,6 +409,71 @@ def pin_overflow_rules(o):
 
 
 # ---------------------------------------------------------------------------
+# Column-major unravel and y = A^T x
+# ---------------------------------------------------------------------------
+
+def pin_cm_worked_example(o):
+    """A single row or a single column unravels the same way by row or by
+    column: both give the worked example's bitstrings."""
+    g = _golden_kv("sm_worked_example.txt")
+    vals = [int(v) for v in g["values"].split()]
+    want = [int(g["bitstring_1"].replace(" ", ""), 2), int(g["bitstring_2"].replace(" ", ""), 2)]
+    for A in (np.array([vals]), np.array([vals]).T):
+        p = o.compress_cm(A)
+        assert [int(w) for w in p.payload] == want and p.bits == 10
+        assert o.decompress_cm(p).tolist() == A.tolist()
+    h = o.header_cm(o.compress_cm(np.array([vals]).T))
+    assert h[7] == 2 and int.from_bytes(h[8:16], "little") == 8
+    assert int.from_bytes(h[16:24], "little") == 1
+
+
+def pin_cm_layout(o):
+    """Column-major streams read back field by field: element (i, j) at stream
+    index j*rows + i, same widths and word count as row-major."""
+    rng = np.random.default_rng(31)
+    for t in range(40):
+        r, c = int(rng.integers(1, 20)), int(rng.integers(1, 20))
+        b = int(rng.integers(1, 65))
+        signed = b == 64 or t % 2 == 1
+        A = _random_matrix(rng, r, c, b, signed)
+        p = o.compress_cm(A)
+        q = o.compress(A)
+        assert (p.bits, p.is_signed, p.words) == (q.bits, q.is_signed, q.words)
+        stream = sum(int(w) << (64 * k) for k, w in enumerate(p.payload))
+        for i in range(r):
+            for j in range(c):
+                u = (stream >> ((j * r + i) * p.bits)) & ((1 << p.bits) - 1)
+                assert u == int(A[i, j]) & ((1 << p.bits) - 1), (i, j)
+        assert stream >> (r * c * p.bits) == 0
+        assert o.decompress_cm(p).tolist() == A.tolist()
+        i, j = int(rng.integers(0, r)), int(rng.integers(0, c))
+        assert o.get_cm(p, i, j) == int(A[i, j])
+
+
+def pin_transposed_products_bruteforce(o):
+    """y = A x (column-major A) and y = A^T x (both layouts) against Python
+    integers modulo 2^64, and the identity matvec_t(A, e_i) = row i of A."""
+    rng = np.random.default_rng(37)
+    for t in range(40):
+        r, c = int(rng.integers(1, 30)), int(rng.integers(1, 30))
+        b = [1, 5, 17, 33, 62][t % 5]
+        A = _random_matrix(rng, r, c, b, t % 2 == 1)
+        xr = rng.integers(-2**62, 2**62, size=r, dtype=np.int64)
+        xc = rng.integers(-2**62, 2**62, size=c, dtype=np.int64)
+        L = A.tolist()
+        want_t = [_to_signed64(sum(L[i][j] * int(xr[i]) for i in range(r))) for j in range(c)]
+        want = [_to_signed64(sum(L[i][j] * int(xc[j]) for j in range(c))) for i in range(r)]
+        pr, pc = o.compress(A), o.compress_cm(A)
+        assert o.matvec_t(pr, xr).tolist() == want_t
+        assert o.matvec_t_cm(pc, xr).tolist() == want_t
+        assert o.matvec_cm(pc, xc).tolist() == want
+        i = int(rng.integers(0, r))
+        e = np.zeros(r, dtype=np.int64)
+        e[i] = 1
+        assert o.matvec_t(pr, e).tolist() == L[i]
+
+
+# ---------------------------------------------------------------------------
 # Method 2 (Variable Length Blocks)
 # ---------------------------------------------------------------------------
 
@@ -554,4 +619,5 @@ ALL_PINS = [pin_table1, pin_eq1_special_case, pin_bitlen_bruteforce, pin_width_b
             pin_worked_example, pin_word_count, pin_round_trip, pin_signed_small_bruteforce,
             pin_locality, pin_get, pin_ops_bruteforce, pin_ops_exhaustive_2x2, pin_identities,
             pin_overflow_rules, pin_vlb_worked_example, pin_vlb_layout, pin_vlb_extremes,
-            pin_vlb_ops_bruteforce, pin_vlb_exhaustive_small]
+            pin_vlb_ops_bruteforce, pin_vlb_exhaustive_small, pin_cm_worked_example,
+            pin_cm_layout, pin_transposed_products_bruteforce]

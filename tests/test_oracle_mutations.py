@@ -48,6 +48,11 @@ MUTANTS = {
                       "if (p * (unsigned __int128)(uint64_t)a->cols > lim)")],
     # signed flag ignored when decoding
     "decode_unsigned": [("if (is_signed && ((u >> (bits - 1)) & 1u)) {", "if (0) {")],
+    # column-major stream index taken row-major
+    "cm_index_rowmajor": [("return (uint64_t)(j * m->rows + i);", "return (uint64_t)(i * m->cols + j);")],
+    # y = A^T x reads A transposed (a[j][i])
+    "matvec_t_transposed": [("(uint64_t)(i * a->cols + j), a->bits, a->is_signed);\n      acc",
+                             "(uint64_t)(j * a->rows + i), a->bits, a->is_signed);\n      acc")],
     # Method 2: the element written before its length chunk
     "vlb_value_first": [("put_bits(m->payload, p, m->k, (uint64_t)b); /* the fixed-size length chunk */\n"
                          "    p += (uint64_t)m->k;\n"
