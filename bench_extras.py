@@ -206,8 +206,50 @@ def vlb(torch, ccm, reps=20):
     return out
 
 
+def transposed(torch, ccm, reps=10):
+    """y = A^T x (the column-major matrix's y = A x) on the 16384 x 16384
+    unsigned sweep matrices, beside y = A x on the same payload; enough copies
+    that each call streams from HBM (their total > 512 MB)."""
+    import numpy as np
+    out = {}
+    for k in W.SWEEP_WIDTHS:
+        a_s, _, x_s, _ = W.sweep(k, False)
+        one = 8 * ccm.words(a_s.rows, a_s.cols, k)
+        ncopy = max(2, -(-(512 << 20) // one))
+        mats = [ccm.generate(a_s.rows, a_s.cols, a_s.lo, a_s.hi, a_s.seed, a_s.stream)
+                for _ in range(ncopy)]
+        x = torch.empty(a_s.rows, dtype=torch.int32, device="cuda")
+        ccm.fill_uniform(x, x_s.lo, x_s.hi, x_s.seed, x_s.stream)
+        y = torch.empty(a_s.cols, dtype=torch.int64, device="cuda")
+        res = {}
+        for name, fn in (("matvec_t", ccm.matvec_t), ("matvec", ccm.matvec)):
+            for i in range(2 * ncopy):
+                fn(mats[i % ncopy], x, y)
+            torch.cuda.synchronize()
+            ts = []
+            for i in range(reps):
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                e[0].record()
+                fn(mats[i % ncopy], x, y)
+                e[1].record()
+                torch.cuda.synchronize()
+                ts.append(e[0].elapsed_time(e[1]) * 1e-3)
+            t = float(np.median(ts))
+            res[name] = {"us": round(t * 1e6, 1), "gb_s": round(one / t / 1e9, 1)}
+        res["packed_mb"] = round(one / 1e6, 1)
+        out[f"k{k}"] = res
+        del mats
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_extras(torch, ccm, log=None):
     out = {}
+    t0 = time.perf_counter()
+    out["transposed"] = transposed(torch, ccm)
+    out["transposed"]["wall_s"] = round(time.perf_counter() - t0, 2)
+    if log:
+        log("transposed done")
     t0 = time.perf_counter()
     out["vlb"] = vlb(torch, ccm)
     out["vlb"]["wall_s"] = round(time.perf_counter() - t0, 2)

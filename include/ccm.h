@@ -245,6 +245,34 @@ int ccm_generate_plan(int64_t rows, int64_t cols, int64_t lo, int64_t hi, uint64
 int ccm_generate(const ccm_desc *out, int64_t lo, int64_t hi, uint64_t seed,
                  uint64_t stream_id, void *stream);
 
+/* ---- column-major unravel (Methods, "Matrix compression") and y = A^T x ---
+ *
+ * The paper lets a matrix be unravelled by column (Fortran order) or by row.
+ * A matrix A (R x C) unravelled by column holds element (i, j) at stream
+ * element j*R + i: exactly the row-major stream of A^T (C x R), with the same
+ * width rule, fields and word count.  The library therefore describes a
+ * column-major A by the row-major descriptor of A^T (rows = C, cols = R); its
+ * serialized header states A's own shape with flags bit 1 set.  Every
+ * row-major call applies to that descriptor: y = A^T x of the column-major A
+ * is ccm_matvec on it, and y = A x is ccm_matvec_t. */
+
+/* y = A^T x (y[j] = sum_i a_ij x_i modulo 2^64) for the row-major matrix a:
+ * x device, a->rows values of xdtype; y device, a->cols int64.  Async. */
+int ccm_matvec_t(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, void *stream);
+
+/* Packs A, given dense row-major (out->cols x out->rows values of dtype),
+ * unravelled by column into out->payload; out describes A^T and comes from
+ * ccm_compress_plan(dense, dtype, out->rows, out->cols, ...) (the range pass
+ * does not depend on the shape).  Writes the whole capacity.  Async. */
+int ccm_compress_cm(const void *dense, int32_t dtype, const ccm_desc *out, void *stream);
+
+/* Header of the column-major matrix whose stream `at` describes (A^T,
+ * row-major): A's rows and cols, flags bit 1 set.  Decode: a header with
+ * flags bit 1 set back to the descriptor of A^T (payload NULL); CCM_E_INVAL
+ * when bit 1 is clear (ccm_header_decode reads only row-major headers). */
+int ccm_header_encode_cm(const ccm_desc *at, uint8_t out[64]);
+int ccm_header_decode_cm(const uint8_t in[64], ccm_desc *at);
+
 /* ---- Method 2: Variable Length Blocks (Methods, "Method 2"; Eq. 16) ------
  *
  * Encoding: every element e has its own width b_e -- Eq. 1 applied to the

@@ -16,7 +16,7 @@ from ._lib import (E_INVAL, E_NOMEM, E_OVERFLOW, E_RANGE, E_SHAPE, E_UNSUPPORTED
 
 __all__ = ["CMatrix", "CcmError", "compress", "decompress", "get", "gather", "add", "scale",
            "matvec_launcher",
-           "matvec", "matmul", "matmul_plan", "matmul_pack", "fill_uniform", "generate", "from_serialized", "words",
+           "matvec", "matvec_t", "matmul", "matmul_plan", "matmul_pack", "fill_uniform", "generate", "from_serialized", "words",
            "packed_bytes", "payload_capacity", "width", "Batch", "DynBatch",
            "VlbMatrix", "vlb_compress", "vlb_decompress", "vlb_get", "vlb_matvec",
            "vlb_matvec_launcher"]
@@ -64,18 +64,27 @@ def width(vmin: int, vmax: int) -> tuple[int, bool]:
 
 
 class CMatrix:
-    """A compressed matrix: its descriptor plus the device payload it owns."""
+    """A compressed matrix: its descriptor plus the device payload it owns.
 
-    def __init__(self, desc: Desc, payload: torch.Tensor | None = None, device=None):
+    order "C": unravelled by row, `desc` describes the matrix itself.
+    order "F": unravelled by column; the stream is the row-major stream of the
+    transpose, which `desc` describes (rows and cols swapped).  `T` flips the
+    order and swaps the shape without touching the payload."""
+
+    def __init__(self, desc: Desc, payload: torch.Tensor | None = None, device=None,
+                 order: str = "C"):
+        if order not in ("C", "F"):
+            raise ValueError("order must be 'C' or 'F'")
         self.desc = desc
+        self.order = order
         if payload is None:
             cap = int(lib.ccm_payload_capacity(desc.rows, desc.cols, desc.bits))
             payload = torch.empty(cap, dtype=torch.uint8, device=device or "cuda")
         self.payload = payload
         self.desc.payload = payload.data_ptr()
 
-    rows = property(lambda self: int(self.desc.rows))
-    cols = property(lambda self: int(self.desc.cols))
+    rows = property(lambda self: int(self.desc.rows if self.order == "C" else self.desc.cols))
+    cols = property(lambda self: int(self.desc.cols if self.order == "C" else self.desc.rows))
     vmin = property(lambda self: int(self.desc.vmin))
     vmax = property(lambda self: int(self.desc.vmax))
     bits = property(lambda self: int(self.desc.bits))
@@ -91,9 +100,19 @@ class CMatrix:
         """Serialized size: 64-byte header plus 8*W payload bytes."""
         return 64 + 8 * self.words
 
+    @property
+    def T(self) -> "CMatrix":
+        """The transpose: the same payload read in the other order."""
+        d = Desc()
+        ctypes.pointer(d)[0] = self.desc
+        return CMatrix(d, self.payload, order="F" if self.order == "C" else "C")
+
     def header(self) -> bytes:
         buf = (ctypes.c_uint8 * 64)()
-        check(lib.ccm_header_encode(ctypes.byref(self.desc), buf), "ccm_header_encode")
+        if self.order == "C":
+            check(lib.ccm_header_encode(ctypes.byref(self.desc), buf), "ccm_header_encode")
+        else:
+            check(lib.ccm_header_encode_cm(ctypes.byref(self.desc), buf), "ccm_header_encode_cm")
         return bytes(buf)
 
     def payload_bytes(self) -> bytes:
@@ -105,8 +124,13 @@ class CMatrix:
         return self.header() + self.payload_bytes()
 
     def __repr__(self):
-        return (f"CMatrix({self.rows}x{self.cols}, bits={self.bits}, signed={self.is_signed}, "
-                f"range=[{self.vmin}, {self.vmax}])")
+        return (f"CMatrix({self.rows}x{self.cols}, order={self.order}, bits={self.bits}, "
+                f"signed={self.is_signed}, range=[{self.vmin}, {self.vmax}])")
+
+
+def _row_major(m: CMatrix, what: str) -> None:
+    if m.order != "C":
+        raise CcmError(E_UNSUPPORTED, f"{what}: column-major operand (use .T or re-compress)")
 
 
 def from_serialized(blob: bytes, device="cuda") -> CMatrix:
@@ -115,43 +139,58 @@ def from_serialized(blob: bytes, device="cuda") -> CMatrix:
         raise CcmError(E_INVAL, "from_serialized")
     d = Desc()
     hdr = (ctypes.c_uint8 * 64).from_buffer_copy(blob[:64])
-    check(lib.ccm_header_decode(hdr, ctypes.byref(d)), "ccm_header_decode")
+    order = "F" if blob[7] & 2 else "C"
+    if order == "C":
+        check(lib.ccm_header_decode(hdr, ctypes.byref(d)), "ccm_header_decode")
+    else:
+        check(lib.ccm_header_decode_cm(hdr, ctypes.byref(d)), "ccm_header_decode_cm")
     nbytes = 8 * int(d.words)
     if len(blob) != 64 + nbytes:
         raise CcmError(E_INVAL, "from_serialized: payload length")
-    m = CMatrix(d, device=device)
+    m = CMatrix(d, device=device, order=order)
     m.payload.zero_()
     host = torch.frombuffer(bytearray(blob[64:]), dtype=torch.uint8)
     m.payload[:nbytes].copy_(host)
     return m
 
 
-def compress(dense: torch.Tensor, stream=None) -> CMatrix:
-    """SM-compress a 2-D int32/int64 device tensor (range pass, then packing)."""
+def compress(dense: torch.Tensor, stream=None, order: str = "C") -> CMatrix:
+    """SM-compress a 2-D int32/int64 device tensor (range pass, then packing),
+    unravelled by row (order "C") or by column (order "F")."""
     t = _device_tensor(dense, "dense")
     if t.dim() != 2:
         raise ValueError("2-D tensor expected")
+    if order not in ("C", "F"):
+        raise ValueError("order must be 'C' or 'F'")
     code = _dtype_code(t)
     s = _stream(stream)
     d = Desc()
-    check(lib.ccm_compress_plan(_ptr(t), code, t.shape[0], t.shape[1], ctypes.byref(d), s),
-          "ccm_compress_plan")
-    m = CMatrix(d, device=t.device)
-    check(lib.ccm_compress(_ptr(t), code, ctypes.byref(m.desc), s), "ccm_compress")
+    r, c = (t.shape[0], t.shape[1]) if order == "C" else (t.shape[1], t.shape[0])
+    check(lib.ccm_compress_plan(_ptr(t), code, r, c, ctypes.byref(d), s), "ccm_compress_plan")
+    m = CMatrix(d, device=t.device, order=order)
+    if order == "C":
+        check(lib.ccm_compress(_ptr(t), code, ctypes.byref(m.desc), s), "ccm_compress")
+    else:
+        check(lib.ccm_compress_cm(_ptr(t), code, ctypes.byref(m.desc), s), "ccm_compress_cm")
     return m
 
 
 def decompress(m: CMatrix, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """The dense int64 matrix.  For order "F" the kernel writes the transpose
+    row by row and the result is its transposed view (out, if given, receives
+    the transpose: shape cols x rows)."""
     if out is None:
-        out = torch.empty((m.rows, m.cols), dtype=torch.int64, device=m.payload.device)
+        out = torch.empty((m.desc.rows, m.desc.cols), dtype=torch.int64, device=m.payload.device)
     elif out.dtype != torch.int64 or out.numel() != m.rows * m.cols or not out.is_contiguous():
         raise CcmError(E_INVAL, "decompress: out")
     check(lib.ccm_decompress(ctypes.byref(m.desc), _ptr(out), _stream(stream)), "ccm_decompress")
-    return out
+    return out if m.order == "C" else out.view(m.desc.rows, m.desc.cols).t()
 
 
 def get(m: CMatrix, i: int, j: int, stream=None) -> int:
     v = ctypes.c_int64()
+    if m.order == "F":
+        i, j = j, i
     check(lib.ccm_get(ctypes.byref(m.desc), i, j, ctypes.byref(v), _stream(stream)), "ccm_get")
     return int(v.value)
 
@@ -161,6 +200,8 @@ def gather(m: CMatrix, ii: torch.Tensor, jj: torch.Tensor, stream=None, sync: bo
     sync=False the second item is the device flag tensor (no host wait)."""
     ii = _device_tensor(ii.to(torch.int64), "ii")
     jj = _device_tensor(jj.to(torch.int64), "jj")
+    if m.order == "F":
+        ii, jj = jj, ii
     out = torch.empty(ii.numel(), dtype=torch.int64, device=ii.device)
     bad = torch.zeros(1, dtype=torch.int32, device=ii.device)
     check(lib.ccm_gather(ctypes.byref(m.desc), _ptr(ii), _ptr(jj), ii.numel(), _ptr(out),
@@ -169,11 +210,14 @@ def gather(m: CMatrix, ii: torch.Tensor, jj: torch.Tensor, stream=None, sync: bo
 
 
 def add(a: CMatrix, b: CMatrix, stream=None) -> CMatrix:
+    """C = A + B; both operands in the same order (the result keeps it)."""
+    if a.order != b.order:
+        raise CcmError(E_UNSUPPORTED, "add: operands unravelled in different orders")
     s = _stream(stream)
     d = Desc()
     check(lib.ccm_add_plan(ctypes.byref(a.desc), ctypes.byref(b.desc), ctypes.byref(d), s),
           "ccm_add_plan")
-    c = CMatrix(d, device=a.payload.device)
+    c = CMatrix(d, device=a.payload.device, order=a.order)
     check(lib.ccm_add(ctypes.byref(a.desc), ctypes.byref(b.desc), ctypes.byref(c.desc), s),
           "ccm_add")
     return c
@@ -182,24 +226,42 @@ def add(a: CMatrix, b: CMatrix, stream=None) -> CMatrix:
 def scale(a: CMatrix, s_: int, stream=None) -> CMatrix:
     d = Desc()
     check(lib.ccm_scale_plan(ctypes.byref(a.desc), s_, ctypes.byref(d)), "ccm_scale_plan")
-    c = CMatrix(d, device=a.payload.device)
+    c = CMatrix(d, device=a.payload.device, order=a.order)
     check(lib.ccm_scale(ctypes.byref(a.desc), s_, ctypes.byref(c.desc), _stream(stream)),
           "ccm_scale")
     return c
 
 
-def matvec(a: CMatrix, x: torch.Tensor, y: torch.Tensor | None = None, stream=None):
-    """y = A x (int64, modulo 2^64); x is an int32 or int64 device vector."""
+def _mv_call(a: CMatrix, transposed: bool):
+    """The C entry point computing y = A x (transposed False) or y = A^T x on
+    a's stream: a row-major stream runs them directly, a column-major one (the
+    row-major stream of A^T) swaps them."""
+    row_major_op = transposed == (a.order == "C")
+    return (lib.ccm_matvec_t, "ccm_matvec_t") if row_major_op else (lib.ccm_matvec, "ccm_matvec")
+
+
+def _mv(a: CMatrix, x, y, stream, transposed: bool):
+    nin, nout = (a.rows, a.cols) if transposed else (a.cols, a.rows)
     x = _device_tensor(x, "x")
-    if x.numel() != a.cols:
+    if x.numel() != nin:
         raise CcmError(E_SHAPE, "matvec")
     if y is None:
-        y = torch.empty(a.rows, dtype=torch.int64, device=x.device)
-    elif y.dtype != torch.int64 or y.numel() != a.rows or not y.is_contiguous():
+        y = torch.empty(nout, dtype=torch.int64, device=x.device)
+    elif y.dtype != torch.int64 or y.numel() != nout or not y.is_contiguous():
         raise CcmError(E_INVAL, "matvec: y")
-    check(lib.ccm_matvec(ctypes.byref(a.desc), _ptr(x), _dtype_code(x), _ptr(y),
-                         _stream(stream)), "ccm_matvec")
+    fn, name = _mv_call(a, transposed)
+    check(fn(ctypes.byref(a.desc), _ptr(x), _dtype_code(x), _ptr(y), _stream(stream)), name)
     return y
+
+
+def matvec(a: CMatrix, x: torch.Tensor, y: torch.Tensor | None = None, stream=None):
+    """y = A x (int64, modulo 2^64); x is an int32 or int64 device vector."""
+    return _mv(a, x, y, stream, transposed=False)
+
+
+def matvec_t(a: CMatrix, x: torch.Tensor, y: torch.Tensor | None = None, stream=None):
+    """y = A^T x (int64, modulo 2^64); x has one value per row of A."""
+    return _mv(a, x, y, stream, transposed=True)
 
 
 def matvec_launcher(a: CMatrix, x: torch.Tensor, y: torch.Tensor, stream=None):
@@ -212,23 +274,27 @@ def matvec_launcher(a: CMatrix, x: torch.Tensor, y: torch.Tensor, stream=None):
         raise CcmError(E_SHAPE, "matvec")
     if y.dtype != torch.int64 or y.numel() != a.rows or not y.is_contiguous():
         raise CcmError(E_INVAL, "matvec: y")
-    fn = lib.ccm_matvec
+    fn, name = _mv_call(a, False)
     args = (ctypes.byref(a.desc), _ptr(x), _dtype_code(x), _ptr(y), _stream(stream))
 
     def launch():
         rc = fn(*args)
         if rc != 0:
-            raise CcmError(rc, "ccm_matvec")
+            raise CcmError(rc, name)
     return launch
 
 
 def matmul_scratch_bytes(a: CMatrix, b: CMatrix) -> int:
+    _row_major(a, "matmul")
+    _row_major(b, "matmul")
     return int(lib.ccm_matmul_scratch_bytes(ctypes.byref(a.desc), ctypes.byref(b.desc)))
 
 
 def matmul_plan(a: CMatrix, b: CMatrix, scratch: torch.Tensor | None = None, stream=None):
     """Range pass of C = A B: computes C into scratch and returns (C, scratch), C
     allocated at its final width but not yet packed."""
+    _row_major(a, "matmul")
+    _row_major(b, "matmul")
     if a.cols != b.rows:
         raise CcmError(E_SHAPE, "matmul")
     need = matmul_scratch_bytes(a, b)

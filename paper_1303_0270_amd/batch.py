@@ -7,7 +7,12 @@ import os
 
 import torch
 
-from ._lib import I32, I64, Desc, check, lib
+from ._lib import E_UNSUPPORTED, I32, I64, CcmError, Desc, check, lib
+
+
+def _row_major(m, what: str) -> None:
+    if getattr(m, "order", "C") != "C":
+        raise CcmError(E_UNSUPPORTED, f"{what}: column-major matrix")
 
 # Widest matrix (columns) a batched launch accepts: its x is staged whole in LDS.
 BATCH_MAX_COLS = 8192
@@ -26,6 +31,7 @@ class Batch:
         n = len(self.mats)
         arr = (Desc * n)()
         for t, m in enumerate(self.mats):
+            _row_major(m, "Batch")
             arr[t] = m.desc
         self._descs = arr
         self.xcode = I32 if xdtype == torch.int32 else I64
@@ -86,6 +92,7 @@ class DynBatch:
         n = len(mats)
         arr = (Desc * n)()
         for t, m in enumerate(mats):
+            _row_major(m, "DynBatch")
             arr[t] = m.desc
         xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
         yp = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])

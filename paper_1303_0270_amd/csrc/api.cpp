@@ -540,6 +540,55 @@ int ccm_generate(const ccm_desc *out, int64_t lo, int64_t hi, uint64_t seed,
   return CCM_OK;
 }
 
+// ---- column-major unravel and y = A^T x ----------------------------------
+
+int ccm_matvec_t(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, void *stream) {
+  int rc = check_desc(a, true);
+  if (rc != CCM_OK) return rc;
+  if (!x || !y || (xdtype != CCM_I32 && xdtype != CCM_I64)) return CCM_E_INVAL;
+  CCM_HIP(ccm::launch_matvec_t((const uint32_t *)a->payload, a->rows, a->cols, a->bits,
+                               a->is_signed, x, xdtype, y, (hipStream_t)stream));
+  return CCM_OK;
+}
+
+int ccm_compress_cm(const void *dense, int32_t dtype, const ccm_desc *out, void *stream) {
+  if (!dense || (dtype != CCM_I32 && dtype != CCM_I64)) return CCM_E_INVAL;
+  int rc = check_desc(out, true);
+  if (rc != CCM_OK) return rc;
+  // dense is A (out->cols x out->rows, row-major); out describes A^T
+  CCM_HIP(ccm::launch_compress_cm(dense, dtype, out->cols, out->rows, out->bits,
+                                  (uint32_t *)out->payload,
+                                  ccm::cap_words32(nelem(out), out->bits), (hipStream_t)stream));
+  return CCM_OK;
+}
+
+int ccm_header_encode_cm(const ccm_desc *at, uint8_t out[64]) {
+  if (!at) return CCM_E_INVAL;
+  ccm_desc a = *at;
+  a.rows = at->cols;
+  a.cols = at->rows;
+  int rc = ccm_header_encode(&a, out);
+  if (rc != CCM_OK) return rc;
+  out[7] = (uint8_t)(out[7] | 2u);
+  return CCM_OK;
+}
+
+int ccm_header_decode_cm(const uint8_t in[64], ccm_desc *at) {
+  if (!in || !at) return CCM_E_INVAL;
+  if (!(in[7] & 2u)) return CCM_E_INVAL;
+  uint8_t h[64];
+  std::memcpy(h, in, 64);
+  h[7] = (uint8_t)(h[7] & ~2u);
+  ccm_desc a;
+  int rc = ccm_header_decode(h, &a);
+  if (rc != CCM_OK) return rc;
+  ccm_desc t = a;
+  t.rows = a.cols;
+  t.cols = a.rows;
+  *at = t;
+  return CCM_OK;
+}
+
 // ---- Method 2: variable length blocks -----------------------------------
 
 }  // extern "C"

@@ -271,6 +271,15 @@ hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t s);
 hipError_t launch_matvec(const uint32_t *w, int64_t rows, int64_t cols, int bits, int sgn,
                          const void *x, int xdtype, int64_t *y, hipStream_t s);
 
+// y = A^T x over a row-major stream (x: rows values, y: cols).
+hipError_t launch_matvec_t(const uint32_t *w, int64_t rows, int64_t cols, int bits, int sgn,
+                           const void *x, int xdtype, int64_t *y, hipStream_t s);
+
+// Packs a dense row-major rows x cols matrix unravelled by column (the
+// row-major stream of its transpose) into out[0, cap32).
+hipError_t launch_compress_cm(const void *dense, int dtype, int64_t rows, int64_t cols,
+                              int bits, uint32_t *out, uint64_t cap32, hipStream_t s);
+
 // matmul into dense scratch (int32 if out32 else int64) with its range.
 hipError_t launch_matmul(const uint32_t *aw, int abits, int asgn, const uint32_t *bw,
                          int bbits, int bsgn, int64_t M, int64_t K, int64_t N, int use_i8,

@@ -1,0 +1,165 @@
+"""Column-major unravel and y = A^T x on the GPU against the CPU oracle.
+
+A column-major matrix's payload and header are compared byte for byte with
+the oracle's column-major encoding; decompress, get, gather, add and scale
+keep the order; y = A x and y = A^T x are compared element by element for
+both orders, through both packing kernels (rows a multiple of 32 or not) and
+with rows split over several blocks.  The full-size case checks the identity
+z . (A^T x) = x . (A z) modulo 2^64 between the two matvec kernels.
+"""
+import numpy as np
+import pytest
+
+import ccm_workloads as W
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "gpu tests need a GPU"
+    import paper_1303_0270_amd  # noqa: F401  (fails loudly without libccm.so)
+
+
+def ccm():
+    import paper_1303_0270_amd as c
+    return c
+
+
+def dev(a, dtype=torch.int64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def rand_matrix(rng, rows, cols, b, signed):
+    lo, hi = ((-(1 << (b - 1)), (1 << (b - 1)) - 1) if signed else (0, (1 << b) - 1))
+    m = rng.integers(lo, hi, size=(rows, cols), endpoint=True, dtype=np.int64)
+    flat = m.reshape(-1)
+    flat[int(rng.integers(0, flat.size))] = hi
+    if signed:
+        flat[int(rng.integers(0, flat.size))] = lo
+    return m
+
+
+def payload_words(g):
+    torch.cuda.synchronize()
+    return g.payload[: 8 * g.words].cpu().numpy().view(np.uint64)
+
+
+def check_cm(g, ref, A, rng):
+    c = ccm()
+    assert g.order == "F" and g.shape == A.shape
+    assert g.header() == oracle.header_cm(ref)
+    assert np.array_equal(payload_words(g), ref.payload)
+    assert not g.payload[8 * g.words:].cpu().numpy().any()
+    assert np.array_equal(c.decompress(g).cpu().numpy(), A)
+    rows, cols = A.shape
+    for i, j in [(0, 0), (rows - 1, cols - 1), (int(rng.integers(0, rows)), int(rng.integers(0, cols)))]:
+        assert c.get(g, i, j) == int(A[i, j]) == oracle.get_cm(ref, i, j)
+
+
+def check_products(g, A, rng):
+    """matvec and matvec_t of g (either order) against the oracle."""
+    c = ccm()
+    rows, cols = A.shape
+    pr = oracle.compress(A)
+    for xdt, lo, hi in [(torch.int32, -(1 << 31), (1 << 31) - 1), (torch.int64, -2**62, 2**62)]:
+        xc = rng.integers(lo, hi, size=cols, endpoint=True, dtype=np.int64)
+        xr = rng.integers(lo, hi, size=rows, endpoint=True, dtype=np.int64)
+        assert np.array_equal(c.matvec(g, dev(xc, xdt)).cpu().numpy(), oracle.matvec(pr, xc))
+        assert np.array_equal(c.matvec_t(g, dev(xr, xdt)).cpu().numpy(), oracle.matvec_t(pr, xr))
+
+
+SHAPES = [(1, 1), (1, 40), (40, 1), (32, 7), (64, 100), (37, 33), (96, 2100), (130, 257),
+          (2049, 3), (300, 4200)]
+
+
+@pytest.mark.parametrize("b", list(range(1, 65)))
+def test_column_major_all_widths(b):
+    c = ccm()
+    rng = np.random.default_rng(500 + b)
+    for signed in ((False, True) if b < 64 else (True,)):
+        for rows, cols in SHAPES[: 4 + b % 7]:
+            if signed and b == 1 and rows * cols < 2:
+                continue
+            A = rand_matrix(rng, rows, cols, b, signed)
+            ref = oracle.compress_cm(A)
+            g = c.compress(dev(A), order="F")
+            check_cm(g, ref, A, rng)
+            if b <= 31:
+                check_cm(c.compress(dev(A, torch.int32), order="F"), ref, A, rng)
+            check_products(g, A, rng)
+            # the row-major matrix: y = A^T x through the transposed kernel
+            check_products(c.compress(dev(A)), A, rng)
+
+
+@pytest.mark.parametrize("shape", [(5000, 70), (4096, 4096), (777, 5000)], ids=str)
+@pytest.mark.parametrize("b", [1, 3, 12, 31, 40])
+def test_transposed_split_rows(shape, b):
+    """Rows split over several blocks (atomic column sums), several panels."""
+    c = ccm()
+    rng = np.random.default_rng(b * 7 + shape[0])
+    A = rand_matrix(rng, *shape, b, b % 2 == 1)
+    check_products(c.compress(dev(A)), A, rng)
+
+
+def test_transpose_view_and_ops():
+    c = ccm()
+    rng = np.random.default_rng(9)
+    A = rand_matrix(rng, 70, 45, 9, True)
+    B = rand_matrix(rng, 70, 45, 5, False)
+    gA = c.compress(dev(A))
+    t = gA.T  # the transpose, same payload, column-major
+    assert t.order == "F" and t.shape == (45, 70)
+    assert np.array_equal(c.decompress(t).cpu().numpy(), A.T)
+    assert c.get(t, 3, 60) == int(A[60, 3])
+    assert t.T.order == "C" and np.array_equal(c.decompress(t.T).cpu().numpy(), A)
+    check_products(t, A.T, rng)
+    fA, fB = c.compress(dev(A), order="F"), c.compress(dev(B), order="F")
+    s = c.add(fA, fB)
+    assert s.order == "F" and np.array_equal(c.decompress(s).cpu().numpy(), A + B)
+    k = c.scale(fA, -3)
+    assert k.order == "F" and np.array_equal(c.decompress(k).cpu().numpy(), -3 * A)
+    ii = torch.tensor([0, 69, 5], device="cuda")
+    jj = torch.tensor([0, 44, 40], device="cuda")
+    vals, bad = c.gather(fA, ii, jj)
+    assert vals.cpu().tolist() == [int(A[0, 0]), int(A[69, 44]), int(A[5, 40])] and not bad
+    blob = fA.serialize()
+    assert blob[7] & 2 and blob[:64] == oracle.header_cm(oracle.compress_cm(A))
+    back = c.from_serialized(blob)
+    assert back.order == "F" and np.array_equal(c.decompress(back).cpu().numpy(), A)
+    with pytest.raises(c.CcmError):
+        c.add(gA, fB)
+    with pytest.raises(c.CcmError):
+        c.matmul(fA, c.compress(dev(B.T)))
+    with pytest.raises(c.CcmError):
+        c.matvec_t(gA, torch.zeros(45, dtype=torch.int32, device="cuda"))
+
+
+def test_worked_example_column():
+    """The paper's example row as a column: the same two bitstrings."""
+    c = ccm()
+    vals = np.array([[900, 1023, 721, 256, 1, 10, 700, 20]])
+    g = c.compress(dev(vals.T), order="F")
+    assert np.array_equal(payload_words(g), oracle.compress(vals).payload)
+    assert c.decompress(g).cpu().numpy().tolist() == vals.T.tolist()
+
+
+@pytest.mark.parametrize("k", [3, 12, 31])
+def test_full_size_identity(k):
+    """16384 x 16384 sweep matrix: z . (A^T x) == x . (A z) modulo 2^64, the
+    two sides from the two matvec kernels."""
+    c = ccm()
+    a_s, _, _, _ = W.sweep(k, False)
+    A = c.generate(a_s.rows, a_s.cols, a_s.lo, a_s.hi, a_s.seed, a_s.stream)
+    rng = np.random.default_rng(k)
+    x = rng.integers(-(1 << 15), 1 << 15, size=a_s.rows, dtype=np.int64)
+    z = rng.integers(-(1 << 15), 1 << 15, size=a_s.cols, dtype=np.int64)
+    aty = c.matvec_t(A, dev(x, torch.int32)).cpu().numpy()
+    az = c.matvec(A, dev(z, torch.int32)).cpu().numpy()
+    m = (1 << 64) - 1
+    lhs = sum(int(u) * int(v) for u, v in zip(z, aty)) & m
+    rhs = sum(int(u) * int(v) for u, v in zip(x, az)) & m
+    assert lhs == rhs
