@@ -81,6 +81,9 @@ _SIGNATURES = {
     "ccmref_matvec_t": (ctypes.c_int, [_MP, _I64P, _I64P]),
     "ccmref_matvec_t_cm": (ctypes.c_int, [_MP, _I64P, _I64P]),
     "ccmref_header_cm": (None, [_MP, ctypes.POINTER(ctypes.c_uint8)]),
+    "ccmref_method_info_of": (ctypes.c_int, [_I64P, ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.c_void_p]),
+    "ccmref_eta2_model": (ctypes.c_double, [ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
     "ccmref_vlb_width": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32]),
     "ccmref_vlb_plan": (ctypes.c_int, [_I64P, ctypes.c_int64, ctypes.c_int64, _VP]),
     "ccmref_vlb_compress": (ctypes.c_int, [_I64P, _VP]),
@@ -126,6 +129,14 @@ class Packed:
 
     def payload_bytes(self) -> bytes:
         return self.payload.astype("<u8").tobytes()
+
+
+class _MethodInfo(ctypes.Structure):
+    _fields_ = [("vmin", ctypes.c_int64), ("vmax", ctypes.c_int64),
+                ("sm_bits", ctypes.c_int32), ("vlb_k", ctypes.c_int32),
+                ("sm_nbits", ctypes.c_uint64), ("vlb_nbits", ctypes.c_uint64),
+                ("eta1", ctypes.c_double), ("eta2", ctypes.c_double),
+                ("method", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 @dataclass
@@ -341,6 +352,26 @@ class Oracle:
         self._lib.ccmref_header_cm(ctypes.byref(m), buf)
         return bytes(buf)
 
+    # -- choosing the method -----------------------------------------------------
+    def method_info(self, dense) -> dict:
+        """Both methods' bit counts and efficiencies (Eq. 15, 17) and the one
+        using fewer bits (1 on a tie)."""
+        d = np.ascontiguousarray(np.asarray(dense, dtype=np.int64))
+        if d.ndim != 2:
+            raise OracleError(E_INVAL)
+        info = _MethodInfo()
+        _check(self._lib.ccmref_method_info_of(_i64(d), d.shape[0], d.shape[1],
+                                               ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in _MethodInfo._fields_ if f != "pad"}
+
+    def eta2_model(self, pmf, k: int) -> float:
+        """Eq. 29 for pmf[b-1] = P(bit-length b), b = 1..64, fixed k."""
+        p = np.zeros(64, dtype=np.float64)
+        q = np.asarray(pmf, dtype=np.float64).ravel()
+        p[: q.size] = q
+        return float(self._lib.ccmref_eta2_model(p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 k))
+
     # -- Method 2 (VLB) -------------------------------------------------------
     def vlb_width(self, v: int, is_signed: bool) -> int:
         return int(self._lib.ccmref_vlb_width(v, 1 if is_signed else 0))
@@ -425,6 +456,8 @@ matvec_cm = _ORACLE.matvec_cm
 matvec_t = _ORACLE.matvec_t
 matvec_t_cm = _ORACLE.matvec_t_cm
 header_cm = _ORACLE.header_cm
+method_info = _ORACLE.method_info
+eta2_model = _ORACLE.eta2_model
 vlb_width = _ORACLE.vlb_width
 vlb_compress = _ORACLE.vlb_compress
 vlb_decompress = _ORACLE.vlb_decompress

@@ -445,3 +445,34 @@ int ccmref_vlb_matvec(const ccmref_vlb *m, const int64_t *x, int64_t *y) {
   }
   return CCMREF_OK;
 }
+
+/* ---- choosing the method ---------------------------------------------------- */
+
+int ccmref_method_info_of(const int64_t *dense, int64_t rows, int64_t cols,
+                          ccmref_method_info *out) {
+  if (!dense || !out || rows < 1 || cols < 1) return CCMREF_E_INVAL;
+  ccmref_matrix m1;
+  int rc = ccmref_plan(dense, rows, cols, &m1);
+  if (rc != CCMREF_OK) return rc;
+  ccmref_vlb m2;
+  rc = ccmref_vlb_plan(dense, rows, cols, &m2);
+  if (rc != CCMREF_OK) return rc;
+  const uint64_t n = (uint64_t)rows * (uint64_t)cols;
+  out->vmin = m1.vmin;
+  out->vmax = m1.vmax;
+  out->sm_bits = m1.bits;
+  out->vlb_k = m2.k;
+  out->sm_nbits = n * (uint64_t)m1.bits;
+  out->vlb_nbits = m2.nbits;
+  out->eta1 = 1.0 - (double)out->sm_nbits / (64.0 * (double)n);
+  out->eta2 = 1.0 - (double)out->vlb_nbits / (64.0 * (double)n);
+  out->method = out->vlb_nbits < out->sm_nbits ? 2 : 1;
+  out->pad = 0;
+  return CCMREF_OK;
+}
+
+double ccmref_eta2_model(const double *p, int32_t k) {
+  double mean = 0.0;
+  for (int b = 1; b <= 64; b++) mean += (double)b * p[b - 1];
+  return 1.0 - mean / 64.0 - (double)k / 64.0;
+}

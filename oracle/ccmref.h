@@ -199,6 +199,35 @@ int ccmref_vlb_offsets(const ccmref_vlb *m, int64_t group, uint64_t *out);
 /* y[i] = sum_j a[i][j] * x[j] modulo 2^64 for every row. */
 int ccmref_vlb_matvec(const ccmref_vlb *m, const int64_t *x, int64_t *y);
 
+/* ---- Choosing the method (Eq. 14-17; Discussion, "Calculating
+ * Efficiencies") ----------------------------------------------------------
+ *
+ * Efficiency is eta = (bits allocated - bits used) / bits allocated against
+ * 64-bit storage (Eq. 14).  Method 1 uses n*b bits (eta_1 = (64 - b)/64,
+ * Eq. 15); Method 2 uses sum over elements of (k + b_e) (Eq. 16, 17).  The
+ * method chosen is the one using fewer bits; on a tie Method 1 (its fields
+ * need no index to reach).  The bit counts are exact integers; the eta values
+ * are doubles computed from them as 1 - used / (64 n).
+ */
+typedef struct {
+  int64_t vmin, vmax;
+  int32_t sm_bits;      /* Method 1 width b */
+  int32_t vlb_k;        /* Method 2 length-field width */
+  uint64_t sm_nbits;    /* n * b */
+  uint64_t vlb_nbits;   /* sum of k + b_e */
+  double eta1, eta2;
+  int32_t method;       /* 1 or 2 */
+  int32_t pad;
+} ccmref_method_info;
+
+int ccmref_method_info_of(const int64_t *dense, int64_t rows, int64_t cols,
+                          ccmref_method_info *out);
+
+/* Eq. 29: expected eta_2 for a bit-length distribution, p[b-1] = P(bit-length
+ * = b) for b = 1..64, with a fixed k: 1 - sum_b b p_b / 64 - k / 64.  The
+ * paper's analytic tables fix k = 7. */
+double ccmref_eta2_model(const double *p, int32_t k);
+
 #ifdef __cplusplus
 }
 #endif

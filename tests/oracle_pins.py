@@ -19,7 +19,9 @@ build to fail at least one of them.
 from __future__ import annotations
 
 import itertools
+import math
 import os
+from fractions import Fraction
 
 import numpy as np
 
@@ -615,9 +617,120 @@ def pin_vlb_exhaustive_small(o):
         assert got == list(vals) and got_w == widths and stream >> used == 0
 
 
+# ---------------------------------------------------------------------------
+# Choosing the method (Eq. 14-17, 29; Discussion)
+# ---------------------------------------------------------------------------
+
+def _efficiency_table():
+    rows = []
+    with open(os.path.join(GOLDEN, "efficiency_tables.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def _of_length(L: int) -> int:
+    """A value whose two's complement width is exactly L (a signed matrix:
+    bit-lengths up to 64 need the sign reading)."""
+    return -(1 << (L - 1))
+
+
+def pin_method_worked_example(o):
+    """The worked example: 80 bits with Method 1, 91 with Method 2 (as the
+    printed bitstrings lay out), so Method 1; eta_1 = (64 - 10)/64 (Eq. 15)."""
+    info = o.method_info(np.array([[900, 1023, 721, 256, 1, 10, 700, 20]]))
+    assert (info["sm_bits"], info["sm_nbits"], info["vlb_k"], info["vlb_nbits"]) == (10, 80, 4, 91)
+    assert info["method"] == 1 and info["eta1"] == 54 / 64 and info["eta2"] == 1 - 91 / 512
+
+
+def pin_method_paper_values(o):
+    """Eq. 17 on matrices built to the Discussion's bit-length mixes: Table 2,
+    the equal-group examples and the half-1/half-64 example, to the printed
+    digits; every one of them picks Method 2 (eta_1 = 0 at width 64)."""
+    for row in _efficiency_table():
+        kind = row[0]
+        # Table 2 and the group list print eta_2 truncated (not rounded) to 3
+        # and 4 decimals; the half-and-half example rounds intermediate terms.
+        if kind == "two_groups":
+            p1, want, digits = float(row[1]), float(row[2]), 3
+            n1 = round(10 * p1)
+            vals = [0] * n1 + [_of_length(64)] * (10 - n1)
+        elif kind == "groups":
+            vals = [_of_length(int(L)) if int(L) > 1 else 0 for L in row[1].split(",")]
+            want, digits = float(row[2]), 4
+        elif kind == "half_1_64":
+            vals = [0, _of_length(64)] * 4
+            want, digits = float(row[1]), None
+        else:
+            continue
+        info = o.method_info(np.array([vals], dtype=np.int64))
+        assert info["vlb_k"] == 7 and info["sm_bits"] == 64 and info["eta1"] == 0.0
+        n = len(vals)
+        exact = Fraction(64 * n - info["vlb_nbits"], 64 * n)  # Eq. 14 with Eq. 16's bits
+        assert abs(info["eta2"] - float(exact)) < 1e-15
+        if digits is None:
+            assert abs(exact - Fraction(row[1])) <= Fraction(1, 10 ** 4), (row, exact)
+        else:
+            assert math.trunc(exact * 10 ** digits) == round(want * 10 ** digits), (row, exact)
+        assert info["method"] == (2 if info["vlb_nbits"] < info["sm_nbits"] else 1)
+
+
+def pin_eta2_model_tables(o):
+    """Eq. 29 with k = 7 against Tables 3-5 (uniform, binomial, truncated
+    Poisson bit-lengths) and Eq. 45 (38.28 %)."""
+    from math import comb, exp, lgamma, log
+    for row in _efficiency_table():
+        kind, par, want = row[0], int(row[1]) if row[0] in ("uniform", "binomial", "poisson") \
+            else None, float(row[-1])
+        if kind == "uniform":
+            pmf = [1.0 / par if b <= par else 0.0 for b in range(1, 65)]
+        elif kind == "binomial":
+            # the first column is n (Table 4's caption; its header says n p):
+            # the printed values fit E(B) = n / 2
+            n = par
+            pmf = [comb(n, b) / 2.0 ** n if b <= n else 0.0 for b in range(1, 65)]
+        elif kind == "poisson":
+            pmf = [exp(b * log(par) - par - lgamma(b + 1)) for b in range(1, 65)]
+        else:
+            continue
+        assert abs(o.eta2_model(pmf, 7) - want) <= 1e-4, (row, o.eta2_model(pmf, 7))
+    assert round(100 * o.eta2_model([1 / 64] * 64, 7), 2) == 38.28
+    # the model equals the exact eta_2 of a matrix with that bit-length mix
+    vals = [_of_length(L) if L > 1 else 0 for L in range(1, 65)]
+    info = o.method_info(np.array([vals], dtype=np.int64))
+    assert abs(info["eta2"] - o.eta2_model([1 / 64] * 64, 7)) < 1e-12
+
+
+def pin_method_bruteforce(o):
+    """Bit counts against brute force; Method 2 iff it uses strictly fewer
+    bits; a tie (here 32 bits each) goes to Method 1."""
+    rng = np.random.default_rng(41)
+    for t in range(60):
+        r, c = int(rng.integers(1, 12)), int(rng.integers(1, 12))
+        top = int(rng.integers(1, 63))
+        A = rng.integers(0, 1 << top, size=(r, c), dtype=np.int64) >> rng.integers(0, top + 1,
+                                                                                   size=(r, c))
+        if t % 3 == 0:
+            A = -A - 1 + (A % 2)
+        flat = [int(v) for v in A.ravel()]
+        signed = min(flat) < 0
+        b = _min_width(min(flat), max(flat))[0]
+        widths = [_vlb_elem_width(v, signed) for v in flat]
+        k = max(widths).bit_length()
+        info = o.method_info(A)
+        assert info["sm_bits"] == b and info["sm_nbits"] == r * c * b
+        assert info["vlb_k"] == k and info["vlb_nbits"] == sum(k + w for w in widths)
+        assert info["method"] == (2 if sum(k + w for w in widths) < r * c * b else 1)
+    tie = o.method_info(np.array([[1 << 15, 1 << 5]]))
+    assert tie["sm_nbits"] == tie["vlb_nbits"] == 32 and tie["method"] == 1
+
+
 ALL_PINS = [pin_table1, pin_eq1_special_case, pin_bitlen_bruteforce, pin_width_bruteforce,
             pin_worked_example, pin_word_count, pin_round_trip, pin_signed_small_bruteforce,
             pin_locality, pin_get, pin_ops_bruteforce, pin_ops_exhaustive_2x2, pin_identities,
             pin_overflow_rules, pin_vlb_worked_example, pin_vlb_layout, pin_vlb_extremes,
             pin_vlb_ops_bruteforce, pin_vlb_exhaustive_small, pin_cm_worked_example,
-            pin_cm_layout, pin_transposed_products_bruteforce]
+            pin_cm_layout, pin_transposed_products_bruteforce, pin_method_worked_example,
+            pin_method_paper_values, pin_eta2_model_tables, pin_method_bruteforce]

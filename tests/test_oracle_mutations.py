@@ -53,6 +53,11 @@ MUTANTS = {
     # y = A^T x reads A transposed (a[j][i])
     "matvec_t_transposed": [("(uint64_t)(i * a->cols + j), a->bits, a->is_signed);\n      acc",
                              "(uint64_t)(j * a->rows + i), a->bits, a->is_signed);\n      acc")],
+    # the method choice breaks ties towards Method 2
+    "method_tie": [("out->method = out->vlb_nbits < out->sm_nbits ? 2 : 1;",
+                    "out->method = out->vlb_nbits <= out->sm_nbits ? 2 : 1;")],
+    # Eq. 29 without the length field's k / 64
+    "eta2_model_no_k": [("return 1.0 - mean / 64.0 - (double)k / 64.0;", "return 1.0 - mean / 64.0;")],
     # Method 2: the element written before its length chunk
     "vlb_value_first": [("put_bits(m->payload, p, m->k, (uint64_t)b); /* the fixed-size length chunk */\n"
                          "    p += (uint64_t)m->k;\n"
