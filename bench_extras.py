@@ -161,6 +161,11 @@ def vlb(torch, ccm, reps=20):
         spec, xs = W.vlb_sweep(name)
         A = spec.dense_device(ccm.fill_uniform, torch)
         n = spec.rows * spec.cols
+        ccm.method_info(A)  # warm-up
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        info = ccm.method_info(A)  # blocking: one pass plus the readback
+        t_sel = time.perf_counter() - c0
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         torch.cuda.synchronize()
         ev[0].record()
@@ -192,6 +197,9 @@ def vlb(torch, ccm, reps=20):
             "workload": f"{spec.rows}x{spec.cols}, bit-lengths Beta({spec.a1:g}, {spec.b1:g}) on [1, 64]",
             "k": g0.k, "avg_bits_per_elem": round(g0.nbits / n, 3), "gmax_bits": g0.gmax,
             "eta2_vlb": round(1 - g0.nbits / (64 * n), 4), "eta1_sm": round(1 - sm_bits / 64, 4),
+            "method_chosen": info["method"],
+            "select_ms": round(t_sel * 1e3, 3),
+            "select_gb_s_dense": round(8 * n / t_sel / 1e9, 1),
             "index_bytes": g0.index_bytes, "stream_bytes": stream,
             "compress_ms": round(t_comp * 1e3, 2),
             "matvec_us": round(t * 1e6, 1),

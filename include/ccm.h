@@ -273,6 +273,31 @@ int ccm_compress_cm(const void *dense, int32_t dtype, const ccm_desc *out, void 
 int ccm_header_encode_cm(const ccm_desc *at, uint8_t out[64]);
 int ccm_header_decode_cm(const uint8_t in[64], ccm_desc *at);
 
+/* ---- choosing the method (Eq. 14-17; Discussion, "Calculating
+ * Efficiencies") ------------------------------------------------------------
+ *
+ * The paper picks Method 1 for small or nearly constant bit-lengths and
+ * Method 2 otherwise, from the efficiency eta = (bits allocated - bits used) /
+ * bits allocated against 64-bit storage (Eq. 14).  Here both bit counts are
+ * computed exactly: Method 1 uses n*b bits (eta_1 = (64 - b)/64, Eq. 15),
+ * Method 2 sum of (k + b_e) bits (Eq. 16, 17).  The choice is Method 2 iff it
+ * uses strictly fewer bits (Method 1 on a tie: its fields need no index). */
+typedef struct ccm_method_info {
+  int64_t vmin, vmax;  /* exact extremes */
+  int32_t sm_bits;     /* Method 1 width b */
+  int32_t vlb_k;       /* Method 2 length-field width */
+  uint64_t sm_nbits;   /* n * b */
+  uint64_t vlb_nbits;  /* sum of k + b_e */
+  double eta1, eta2;   /* 1 - bits / (64 n) */
+  int32_t method;      /* 1 or 2 */
+  int32_t reserved;
+} ccm_method_info;
+
+/* One pass over dense (device, rows*cols values of dtype): extremes and both
+ * sums of element widths; fills out.  Blocking. */
+int ccm_method_plan(const void *dense, int32_t dtype, int64_t rows, int64_t cols,
+                    ccm_method_info *out, void *stream);
+
 /* ---- Method 2: Variable Length Blocks (Methods, "Method 2"; Eq. 16) ------
  *
  * Encoding: every element e has its own width b_e -- Eq. 1 applied to the

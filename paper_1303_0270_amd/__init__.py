@@ -12,12 +12,13 @@ import ctypes
 import torch
 
 from ._lib import (E_INVAL, E_NOMEM, E_OVERFLOW, E_RANGE, E_SHAPE, E_UNSUPPORTED, I32, I64,
-                   OK, CcmError, Desc, VlbDesc, check, lib)
+                   OK, CcmError, Desc, MethodInfo, VlbDesc, check, lib)
 
 __all__ = ["CMatrix", "CcmError", "compress", "decompress", "get", "gather", "add", "scale",
            "matvec_launcher",
            "matvec", "matvec_t", "matmul", "matmul_plan", "matmul_pack", "fill_uniform", "generate", "from_serialized", "words",
            "packed_bytes", "payload_capacity", "width", "Batch", "DynBatch",
+           "method_info", "compress_auto",
            "VlbMatrix", "vlb_compress", "vlb_decompress", "vlb_get", "vlb_matvec",
            "vlb_matvec_launcher"]
 
@@ -440,6 +441,25 @@ def vlb_matvec_launcher(m: VlbMatrix, x: torch.Tensor, y: torch.Tensor, stream=N
         check(fn(*args), "ccm_vlb_matvec")
 
     return launch
+
+
+def method_info(dense: torch.Tensor, stream=None) -> dict:
+    """Both methods' exact bit counts and efficiencies (Eq. 15, Eq. 17) and the
+    method using fewer bits (1 on a tie), from one pass over dense."""
+    t = _device_tensor(dense, "dense")
+    if t.dim() != 2:
+        raise ValueError("2-D tensor expected")
+    info = MethodInfo()
+    check(lib.ccm_method_plan(_ptr(t), _dtype_code(t), t.shape[0], t.shape[1],
+                              ctypes.byref(info), _stream(stream)), "ccm_method_plan")
+    return {f: getattr(info, f) for f, _ in MethodInfo._fields_ if f != "reserved"}
+
+
+def compress_auto(dense: torch.Tensor, stream=None):
+    """Compress with the method that uses fewer bits: a CMatrix (Method 1) or a
+    VlbMatrix (Method 2)."""
+    info = method_info(dense, stream)
+    return compress(dense, stream) if info["method"] == 1 else vlb_compress(dense, stream)
 
 
 def fill_uniform(t: torch.Tensor, lo: int, hi: int, seed: int, stream_id: int = 0,

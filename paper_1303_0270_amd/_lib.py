@@ -42,6 +42,15 @@ class VlbDesc(ctypes.Structure):
                 ("payload", ctypes.c_void_p), ("index", ctypes.c_void_p)]
 
 
+class MethodInfo(ctypes.Structure):
+    """Mirror of ccm_method_info."""
+    _fields_ = [("vmin", ctypes.c_int64), ("vmax", ctypes.c_int64),
+                ("sm_bits", ctypes.c_int32), ("vlb_k", ctypes.c_int32),
+                ("sm_nbits", ctypes.c_uint64), ("vlb_nbits", ctypes.c_uint64),
+                ("eta1", ctypes.c_double), ("eta2", ctypes.c_double),
+                ("method", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 _i64 = ctypes.c_int64
 _u64 = ctypes.c_uint64
 _i32 = ctypes.c_int32
@@ -88,6 +97,7 @@ SIGNATURES = {
     "ccm_fill_uniform": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i64, _u64, _u64, _u64, _vp]),
     "ccm_generate_plan": (ctypes.c_int, [_i64, _i64, _i64, _i64, _u64, _u64, _dp, _vp]),
     "ccm_generate": (ctypes.c_int, [_dp, _i64, _i64, _u64, _u64, _vp]),
+    "ccm_method_plan": (ctypes.c_int, [_vp, _i32, _i64, _i64, ctypes.POINTER(MethodInfo), _vp]),
     "ccm_matvec_t": (ctypes.c_int, [_dp, _vp, _i32, _vp, _vp]),
     "ccm_compress_cm": (ctypes.c_int, [_vp, _i32, _dp, _vp]),
     "ccm_header_encode_cm": (ctypes.c_int, [_dp, ctypes.POINTER(ctypes.c_uint8)]),

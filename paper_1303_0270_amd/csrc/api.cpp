@@ -36,7 +36,8 @@ int dev_err(hipError_t e, const char *where) {
 struct DeviceCtx {
   ccm::RangeSlot *slot = nullptr;
   ccm::RangeSlot *host = nullptr;
-  int64_t *one = nullptr;  // single-element get
+  int64_t *one = nullptr;    // single-element get
+  uint64_t *sums = nullptr;  // spread sum pairs (method choice)
 };
 std::mutex g_mu;
 std::vector<DeviceCtx> g_ctx;
@@ -48,11 +49,12 @@ int device_ctx(DeviceCtx **out) {
   DeviceCtx &c = g_ctx[(size_t)dev];
   if (!c.slot) {
     void *p = nullptr;
-    CCM_HIP(hipMalloc(&p, ccm::kRangeBytes + 256));
+    CCM_HIP(hipMalloc(&p, ccm::kRangeBytes + 256 + ccm::kSumBytes));
     c.slot = (ccm::RangeSlot *)p;
     c.one = (int64_t *)((char *)p + ccm::kRangeBytes);
+    c.sums = (uint64_t *)((char *)p + ccm::kRangeBytes + 256);
     void *h = nullptr;
-    CCM_HIP(hipHostMalloc(&h, ccm::kRangeBytes + 64, hipHostMallocDefault));
+    CCM_HIP(hipHostMalloc(&h, ccm::kRangeBytes + 64 + ccm::kSumBytes, hipHostMallocDefault));
     c.host = (ccm::RangeSlot *)h;
   }
   *out = &c;
@@ -537,6 +539,55 @@ int ccm_generate(const ccm_desc *out, int64_t lo, int64_t hi, uint64_t seed,
   CCM_HIP(ccm::launch_gen_pack(n, lo, span, seed, stream_id, out->bits,
                                (uint32_t *)out->payload, ccm::cap_words32(n, out->bits),
                                (hipStream_t)stream));
+  return CCM_OK;
+}
+
+// ---- choosing the method -------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+void vlb_widths(int64_t vmin, int64_t vmax, int32_t *bmax, int32_t *k);
+}  // namespace
+
+extern "C" {
+
+int ccm_method_plan(const void *dense, int32_t dtype, int64_t rows, int64_t cols,
+                    ccm_method_info *out, void *stream) {
+  if (!dense || !out || !shape_ok(rows, cols) || (dtype != CCM_I32 && dtype != CCM_I64))
+    return CCM_E_INVAL;
+  const uint64_t n = (uint64_t)rows * (uint64_t)cols;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx *c = nullptr;
+  int rc = device_ctx(&c);
+  if (rc != CCM_OK) return rc;
+  CCM_HIP(ccm::launch_range_init(c->slot, s));
+  CCM_HIP(ccm::launch_method_stats(dense, dtype, n, c->slot, c->sums, s));
+  uint64_t *hs = (uint64_t *)((char *)c->host + ccm::kRangeBytes + 64);
+  CCM_HIP(hipMemcpyAsync(hs, c->sums, ccm::kSumBytes, hipMemcpyDeviceToHost, s));
+  ccm::RangeSlot r;
+  rc = read_slot(c, s, &r);  // synchronizes the stream
+  if (rc != CCM_OK) return rc;
+  uint64_t su = 0, ss = 0;
+  for (int i = 0; i < ccm::kRangeSpread; ++i) {
+    su += hs[2 * ccm::kSumStride * i];
+    ss += hs[2 * ccm::kSumStride * i + 1];
+  }
+  int32_t b = 0, sgn = 0, bmax = 0, k = 0;
+  rc = width_rule(r.vmin, r.vmax, &b, &sgn);
+  if (rc != CCM_OK) return rc;
+  vlb_widths(r.vmin, r.vmax, &bmax, &k);
+  out->vmin = r.vmin;
+  out->vmax = r.vmax;
+  out->sm_bits = b;
+  out->vlb_k = k;
+  out->sm_nbits = n * (uint64_t)b;
+  out->vlb_nbits = n * (uint64_t)k + (sgn ? ss : su);
+  out->eta1 = 1.0 - (double)out->sm_nbits / (64.0 * (double)n);
+  out->eta2 = 1.0 - (double)out->vlb_nbits / (64.0 * (double)n);
+  out->method = out->vlb_nbits < out->sm_nbits ? 2 : 1;
+  out->reserved = 0;
   return CCM_OK;
 }
 

@@ -200,6 +200,11 @@ constexpr int kRangeSpread = 64;
 constexpr int kRangeStride = 4;  // RangeSlot units per slot (128 bytes)
 constexpr size_t kRangeBytes = sizeof(RangeSlot) * kRangeStride * kRangeSpread;
 
+// Spread 64-bit sums (pairs), laid out like the range slots: pair i at
+// uint64 offset 2 * kSumStride * i (128 bytes apart).
+constexpr int kSumStride = 8;
+constexpr size_t kSumBytes = sizeof(uint64_t) * 2 * kSumStride * kRangeSpread;
+
 // Block-wide (min, max, flag) folded into the block's slot of a spread range
 // result with one atomic each per block.  Every thread of the block must call
 // it.
@@ -319,6 +324,12 @@ hipError_t launch_vlb_decode(const VlbView &a, int64_t *out, hipStream_t s);
 hipError_t launch_vlb_get(const VlbView &a, int64_t i, int64_t j, int64_t *out, hipStream_t s);
 hipError_t launch_vlb_matvec(const VlbView &a, const void *x, int xdtype, int64_t *y,
                              hipStream_t s);
+
+// One pass for the method choice: (min, max) into slot (initialised by
+// launch_range_init) and, into the spread pairs `sums`, the sums of the
+// unsigned and of the two's complement element widths (zeroed here).
+hipError_t launch_method_stats(const void *dense, int dtype, uint64_t n, RangeSlot *slot,
+                               uint64_t *sums, hipStream_t s);
 
 // synthetic data
 hipError_t launch_fill_uniform(void *dense, int dtype, uint64_t n, int64_t lo, uint64_t span,
