@@ -18,7 +18,7 @@ gigabytes before a matrix is read again, so the 256 MB last-level cache does
 not hold A between its compression and its matvec.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-extras] [--profile]
+                       [--no-extras] [--profile] [--extras-only NAMES]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -67,6 +67,12 @@ def parse():
                     help="the JSON line the profiled run printed (matvec event times, compared)")
     ap.add_argument("--trace-cmd", default="", help="the profiled command, recorded in the summary")
     ap.add_argument("--trace-out", default=os.path.join("profiles", "sweep_step_kernels.md"))
+    ap.add_argument("--trace-title", default="", help="summary title (default: the step's)")
+    ap.add_argument("--trace-note", default="", help="summary description (default: the step's)")
+    ap.add_argument("--extras-only", metavar="NAMES",
+                    help="run only these measurements of bench_extras (comma list of "
+                         "transposed, vlb, gemm, batched, serving) and print their JSON; for "
+                         "profiling the kernels they launch")
     return ap.parse_args()
 
 
@@ -169,7 +175,7 @@ def summarize_counters(src_dir, out_path):
     print(out_path)
 
 
-def summarize_trace(stats_csv, out_path, bench_json=None, cmd=""):
+def summarize_trace(stats_csv, out_path, bench_json=None, cmd="", title="", note=""):
     """Kernel-time table of a rocprofv3 --kernel-trace --stats run of this
     benchmark; with the run's JSON line, the matvec kernels' trace averages
     next to the HIP-event times bench.py measured in the same run."""
@@ -182,12 +188,14 @@ def summarize_trace(stats_csv, out_path, bench_json=None, cmd=""):
         return name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
 
     rows = list(csv.DictReader(open(stats_csv)))
-    lines = ["# Kernel times: one benchmark step over the 16384 x 16384 bandwidth sweep", "",
+    title = title or "Kernel times: one benchmark step over the 16384 x 16384 bandwidth sweep"
+    note = note or ("A step runs width + compress, matvec, add (range + pack), scale by 7, "
+                    "decompress and 1000 gets over the twelve sweep matrices (k in "
+                    "{1,3,7,12,17,31}, unsigned and signed); the dense int32 comparison, the read "
+                    "probe and a 1 GiB copy follow.")
+    lines = ["# " + title, "",
              "Command (repo root on the MI355X box; rocprofv3 run from /tmp with TMPDIR=/tmp):", "",
-             "    " + cmd, "",
-             "A step runs width + compress, matvec, add (range + pack), scale by 7, decompress and "
-             "1000 gets over the twelve sweep matrices (k in {1,3,7,12,17,31}, unsigned and "
-             "signed); the dense int32 comparison, the read probe and a 1 GiB copy follow.", "",
+             "    " + cmd, "", note, "",
              "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
     for r in rows:
         lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
@@ -277,7 +285,8 @@ def main():
         summarize_counters(args.summarize_counters, args.counters_out)
         return
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, args.trace_out, args.trace_json, args.trace_cmd)
+        summarize_trace(args.summarize_trace, args.trace_out, args.trace_json, args.trace_cmd,
+                        args.trace_title, args.trace_note)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -293,6 +302,17 @@ def main():
     torch.cuda.set_device(0)
     if args.matvec_only:
         matvec_only(args, torch, W, ccm)
+        return
+    if args.extras_only:
+        import bench_extras as X
+        fns = {"transposed": X.transposed, "vlb": X.vlb, "gemm": X.gemm, "batched": X.batched,
+               "serving": X.serving}
+        res = {}
+        for name in args.extras_only.split(","):
+            res[name] = fns[name](torch, ccm)
+            torch.cuda.empty_cache()
+            log(f"{name} done")
+        print(json.dumps({"extras_only": res}), flush=True)
         return
     bench_lib = ctypes.CDLL(os.path.join(ROOT, "paper_1303_0270_amd", "libccm_bench.so"))
     bench_lib.ccmb_dense_matvec_i32.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
