@@ -766,7 +766,7 @@ int ccm_vlb_compress(const void *dense, int32_t dtype, const ccm_vlb_desc *out, 
   int rc = check_vlb(out);
   if (rc != CCM_OK) return rc;
   CCM_HIP(ccm::launch_vlb_pack(dense, dtype, vlb_view(out), (uint32_t *)out->payload,
-                               vlb_cap32(out->nbits), (hipStream_t)stream));
+                               vlb_cap32(out->nbits), out->nbits, (hipStream_t)stream));
   return CCM_OK;
 }
 

@@ -319,7 +319,7 @@ hipError_t launch_vlb_scan(int64_t rows, int64_t cols, uint32_t *grp, uint64_t *
                            hipStream_t s);
 // pass 3: the stream (zeroes cap32 words first)
 hipError_t launch_vlb_pack(const void *dense, int dtype, const VlbView &a, uint32_t *out,
-                           uint64_t cap32, hipStream_t s);
+                           uint64_t cap32, uint64_t nbits, hipStream_t s);
 hipError_t launch_vlb_decode(const VlbView &a, int64_t *out, hipStream_t s);
 hipError_t launch_vlb_get(const VlbView &a, int64_t i, int64_t j, int64_t *out, hipStream_t s);
 hipError_t launch_vlb_matvec(const VlbView &a, const void *x, int xdtype, int64_t *y,

@@ -18,9 +18,11 @@
 //
 // Encoding runs in three passes: group bit counts (sum of k + b_e), scans
 // (within rows, then over rows) that turn the counts into the index, and the
-// packing pass, where each lane writes its group's bits: the words its group
-// covers entirely with plain stores, the at most two it shares with a
-// neighbour with atomic ORs into the zeroed payload.
+// packing pass, where a block assembles the bits of 64 consecutive groups in
+// LDS (a half-wave per group places its pairs with a prefix sum of their
+// lengths) and writes them out: the words its stretch covers entirely with
+// plain stores, the two it shares with its neighbours with atomic ORs into
+// the zeroed payload.
 #include <hip/hip_runtime.h>
 
 #include "ccm_internal.hpp"
@@ -168,78 +170,89 @@ __global__ void k_zero_u32(uint32_t *p, uint64_t n) {
   for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) p[e] = 0;
 }
 
-// Bit writer for one group's span [s, e) of the stream.  Words entirely inside
-// the span belong to this group alone and are stored; a word shared with a
-// neighbouring group is ORed into the zeroed payload.
-struct SpanWriter {
-  uint32_t *w;
-  uint64_t s, e;
-  uint64_t q;    // word being filled
-  uint64_t buf;  // its pending bits, starting at bit 0 of word q
-  int used;      // bits of word q accounted for (including those before s)
+// ORs the low nb (1..64) bits of val into an LDS bit span at bit pos (at
+// most three words; LDS atomics, since neighbouring lanes share words).
+__device__ __forceinline__ void lds_or_bits(uint32_t *span, uint32_t pos, uint64_t val, int nb) {
+  val &= mask64(nb);
+  const uint32_t q = pos >> 5, sh = pos & 31u;
+  const uint64_t lo = val << sh;
+  const uint32_t hi = sh ? (uint32_t)(val >> (64u - sh)) : 0u;
+  const int nw = (int)((sh + (uint32_t)nb + 31u) >> 5);
+  if ((uint32_t)lo) atomicOr(&span[q], (uint32_t)lo);
+  if (nw > 1 && (uint32_t)(lo >> 32)) atomicOr(&span[q + 1], (uint32_t)(lo >> 32));
+  if (nw > 2 && hi) atomicOr(&span[q + 2], hi);
+}
 
-  __device__ SpanWriter(uint32_t *words, uint64_t start, uint64_t end)
-      : w(words), s(start), e(end), q(start >> 5), buf(0), used((int)(start & 31u)) {}
-
-  __device__ __forceinline__ void flush_word() {
-    const uint32_t v = (uint32_t)buf;
-    const uint64_t lo = q * 32u;
-    if (lo >= s && lo + 32u <= e)
-      w[q] = v;
-    else if (v != 0)
-      atomicOr(&w[q], v);
-  }
-
-  // nb (1..32) bits
-  __device__ __forceinline__ void put32(uint32_t v, int nb) {
-    buf |= (uint64_t)(v & mask32(nb)) << used;
-    used += nb;
-    if (used >= 32) {
-      flush_word();
-      ++q;
-      buf >>= 32;
-      used -= 32;
-    }
-  }
-
-  __device__ __forceinline__ void put(uint64_t v, int nb) {
-    if (nb <= 32) {
-      put32((uint32_t)v, nb);
-    } else {
-      put32((uint32_t)v, 32);
-      put32((uint32_t)(v >> 32), nb - 32);
-    }
-  }
-
-  __device__ __forceinline__ void finish() {
-    if (used > 0) flush_word();
-  }
-};
+// A block assembles the stream of kPackGroups consecutive groups (a
+// contiguous stretch of bits [S, E)) in LDS, then writes it out.
+//   * A half-wave per group: lane l reads element 32g + l (coalesced), takes
+//     its width b_e, and a 32-lane prefix sum of k + b_e places its pair
+//     (length field, then value) inside the group, which starts at the bit
+//     the index gives.  The pair is ORed into the LDS stretch.
+//   * Write-out: the words the stretch covers entirely are plain coalesced
+//     stores; its first and last words, shared with the neighbouring blocks,
+//     are atomic ORs into the zeroed payload.
+constexpr int kPackGroups = 64;
 
 template <typename T>
 __global__ __launch_bounds__(kVThreads) void k_vlb_pack(const T *__restrict__ dense, int64_t rows,
                                                         int64_t cols, int64_t ngr, int k, int sgn,
                                                         const uint64_t *__restrict__ row_bit,
                                                         const uint32_t *__restrict__ grp,
+                                                        uint64_t nbits, int span_words,
                                                         uint32_t *__restrict__ out) {
+  extern __shared__ uint32_t span[];
   const uint64_t total = (uint64_t)rows * (uint64_t)ngr;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t gi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += stride) {
-    const int64_t i = (int64_t)(gi / (uint64_t)ngr);
-    const int64_t g = (int64_t)(gi - (uint64_t)i * (uint64_t)ngr);
-    uint64_t s, e;
-    group_span(row_bit, grp, i, g, ngr, &s, &e);
-    SpanWriter wr(out, s, e);
-    const int64_t j0 = g * kVG;
-    const int n = cols - j0 < kVG ? (int)(cols - j0) : kVG;
-    const T *src = dense + (uint64_t)i * (uint64_t)cols + (uint64_t)j0;
-    for (int l = 0; l < n; ++l) {
-      const int64_t v = load_dense(src, (uint64_t)l);
-      const int b = elem_width(v, sgn);
-      wr.put32((uint32_t)b, k);       // the length field
-      wr.put((uint64_t)v, b);         // then the value's low b bits
+  const int half = threadIdx.x >> 5, l = threadIdx.x & 31;
+  for (uint64_t gb = (uint64_t)blockIdx.x * kPackGroups; gb < total;
+       gb += (uint64_t)gridDim.x * kPackGroups) {
+    const uint64_t ge = gb + kPackGroups < total ? gb + kPackGroups : total;
+    // stretch [S, E) of groups gb .. ge - 1
+    const uint64_t ib = gb / (uint64_t)ngr;
+    const uint64_t S = row_bit[ib] + grp[gb];
+    uint64_t E;
+    if (ge < total) {
+      const uint64_t ie = ge / (uint64_t)ngr;
+      E = row_bit[ie] + grp[ge];
+    } else {
+      E = nbits;
     }
-    wr.finish();
+    const uint64_t q0 = S >> 5;
+    const int nwords = (int)(((E + 31u) >> 5) - q0);
+    for (int w = threadIdx.x; w < span_words; w += blockDim.x) span[w] = 0;
+    __syncthreads();
+    for (uint64_t gi = gb + (uint64_t)half; gi < ge; gi += kVThreads / 32) {
+      const uint64_t i = gi / (uint64_t)ngr;
+      const uint64_t g = gi - i * (uint64_t)ngr;
+      const uint64_t j = g * kVG + (uint64_t)l;
+      const bool live = j < (uint64_t)cols;
+      const int64_t v = live ? load_dense(dense, i * (uint64_t)cols + j) : 0;
+      const int b = live ? elem_width(v, sgn) : 0;
+      uint32_t len = live ? (uint32_t)(k + b) : 0u;
+      // exclusive prefix sum over the 32 lanes of the group
+      uint32_t inc = len;
+#pragma unroll
+      for (int d = 1; d < 32; d <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_up((int)inc, d, 32);
+        if (l >= d) inc += o;
+      }
+      const uint64_t gstart = row_bit[i] + grp[gi];
+      const uint32_t pos = (uint32_t)(gstart - q0 * 32u) + (inc - len);
+      if (live) {
+        lds_or_bits(span, pos, (uint64_t)b, k);          // the length field
+        lds_or_bits(span, pos + (uint32_t)k, (uint64_t)v, b);  // then the value
+      }
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x) {
+      const uint64_t q = q0 + (uint64_t)w;
+      const uint32_t val = span[w];
+      if (q * 32u >= S && q * 32u + 32u <= E)
+        out[q] = val;
+      else if (val)
+        atomicOr(&out[q], val);
+    }
+    __syncthreads();  // the span is cleared for the next stretch
   }
 }
 
@@ -667,17 +680,25 @@ hipError_t launch_vlb_scan(int64_t rows, int64_t cols, uint32_t *grp, uint64_t *
 }
 
 hipError_t launch_vlb_pack(const void *dense, int dtype, const VlbView &a, uint32_t *out,
-                           uint64_t cap32, hipStream_t s) {
+                           uint64_t cap32, uint64_t nbits, hipStream_t s) {
   k_zero_u32<<<vgrid(cap32, kVThreads * 8, 8192), kVThreads, 0, s>>>(out, cap32);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const unsigned grid = vgrid((uint64_t)a.rows * (uint64_t)a.ngr, kVThreads, 65536);
+  // a stretch of kPackGroups groups spans at most kPackGroups * gmax bits
+  // and one word more
+  const int span_words = (int)(((uint64_t)kPackGroups * a.gmax + 31u) / 32u + 2u);
+  const size_t lds = (size_t)span_words * 4u;
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  const uint64_t total = (uint64_t)a.rows * (uint64_t)a.ngr;
+  const unsigned grid = vgrid(total, kPackGroups, 65536);
   if (dtype == CCM_I64)
-    k_vlb_pack<int64_t><<<grid, kVThreads, 0, s>>>((const int64_t *)dense, a.rows, a.cols, a.ngr,
-                                                   a.k, a.sgn, a.row_bit, a.grp, out);
+    k_vlb_pack<int64_t><<<grid, kVThreads, lds, s>>>((const int64_t *)dense, a.rows, a.cols,
+                                                     a.ngr, a.k, a.sgn, a.row_bit, a.grp, nbits,
+                                                     span_words, out);
   else
-    k_vlb_pack<int32_t><<<grid, kVThreads, 0, s>>>((const int32_t *)dense, a.rows, a.cols, a.ngr,
-                                                   a.k, a.sgn, a.row_bit, a.grp, out);
+    k_vlb_pack<int32_t><<<grid, kVThreads, lds, s>>>((const int32_t *)dense, a.rows, a.cols,
+                                                     a.ngr, a.k, a.sgn, a.row_bit, a.grp, nbits,
+                                                     span_words, out);
   return hipGetLastError();
 }
 
