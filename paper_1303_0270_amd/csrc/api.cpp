@@ -706,6 +706,7 @@ ccm::VlbView vlb_view(const ccm_vlb_desc *d) {
   v.bmax = bmax;
   v.sgn = d->is_signed;
   v.gmax = d->gmax;
+  v.nbits = d->nbits;
   return v;
 }
 

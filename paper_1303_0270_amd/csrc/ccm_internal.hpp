@@ -308,6 +308,7 @@ struct VlbView {
   int bmax;                 // largest element width
   int sgn;
   uint64_t gmax;            // bits of the longest group
+  uint64_t nbits;           // stream bits
 };
 uint64_t vlb_ngr(int64_t cols);
 // pass 1: grp[i][g] = bits of group g of row i (sum of k + b_e); the largest

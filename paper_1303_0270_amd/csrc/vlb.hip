@@ -388,7 +388,7 @@ __device__ __forceinline__ uint64_t lds_bits64(const uint32_t *seg, uint32_t pv)
 //     (ragged row end, partial panel); its walk then continues through bits
 //     of the next group or past the stretch, with x = 0 for those elements,
 //     and its reads are clamped inside the staged buffer.
-template <bool SGN, int GPT, bool CLAMP>
+template <bool SGN, int GPT, bool CLAMP, bool WIDE>
 __global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
     const uint32_t *__restrict__ w, const uint64_t *__restrict__ row_bit,
     const uint32_t *__restrict__ grp, int64_t rows, int64_t cols, int64_t ngr, int k,
@@ -404,6 +404,7 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
   const uint32_t narrow = 32u - (uint32_t)k;  // largest b read from one 32-bit window
   const uint32_t qmax = (uint32_t)seg_words - 4u;
   const uint32_t pmax = qmax * 32u;
+  const uint32_t pmaxw = ((uint32_t)seg_words - 5u) * 32u;  // four-word reads
 
   int32_t xr[GPT][kVG];
 #pragma unroll
@@ -495,13 +496,31 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
     for (int u = 0; u < GPT; ++u) {
       acc[u] = 0;
       q[u] = p[u] >> 5;
-      w0[u] = seg[q[u]];
-      w1[u] = seg[q[u] + 1];
+      w0[u] = WIDE ? 0u : seg[q[u]];
+      w1[u] = WIDE ? 0u : seg[q[u] + 1];
     }
 #pragma unroll
     for (int j = 0; j < kVG; ++j) {
 #pragma unroll
       for (int u = 0; u < GPT; ++u) {
+        if constexpr (WIDE) {
+          // four words at the pair's start give 96 bits: the length and a
+          // value of up to 64 bits, with no branch
+          if (CLAMP) p[u] = p[u] < pmaxw ? p[u] : pmaxw;
+          const uint32_t qq = p[u] >> 5, sh = p[u] & 31u;
+          const uint32_t a0 = __builtin_amdgcn_alignbit(seg[qq + 1], seg[qq], sh);
+          const uint32_t a1 = __builtin_amdgcn_alignbit(seg[qq + 2], seg[qq + 1], sh);
+          const uint32_t a2 = __builtin_amdgcn_alignbit(seg[qq + 3], seg[qq + 2], sh);
+          const uint32_t b = a0 & kmask;
+          const int nb = b < 64u ? (int)b : 64;
+          const uint64_t lo = ((uint64_t)a1 << 32) | a0;
+          uint64_t v = ((lo >> k) | ((uint64_t)a2 << (64 - k))) & mask64(nb);
+          if (SGN) v = (uint64_t)sext64(v, nb > 0 ? nb : 1);
+          acc[u] += (int64_t)(v * (uint64_t)(int64_t)xr[u][j]);
+          asm volatile("" : "+v"(acc[u]));
+          p[u] += (uint32_t)k + b;
+          continue;
+        }
         const uint32_t wv = __builtin_amdgcn_alignbit(w1[u], w0[u], p[u] & 31u);
         const uint32_t b = wv & kmask;
         int32_t a;
@@ -584,17 +603,17 @@ size_t stage_lds(uint64_t gmax, int gpt) {
   return (size_t)stage_words(gmax, gpt) * 4u + 2u * (kVThreads / 64) * 8u;
 }
 
-template <bool SGN, int GPT, bool CLAMP>
+template <bool SGN, int GPT, bool CLAMP, bool WIDE>
 int resident_lds(size_t lds) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_vlb_mv_lds<SGN, GPT, CLAMP>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_vlb_mv_lds<SGN, GPT, CLAMP, WIDE>,
                                                    kVThreads, lds) != hipSuccess ||
       occ < 1)
     occ = 1;
   return occ * compute_units();
 }
 
-template <bool SGN, int GPT, bool CLAMP>
+template <bool SGN, int GPT, bool CLAMP, bool WIDE>
 hipError_t launch_mv_lds(const VlbView &a, const int32_t *x, int64_t *y, hipStream_t s) {
   const int64_t per_panel = (int64_t)kVThreads * GPT;
   const int64_t npanels = (a.ngr + per_panel - 1) / per_panel;
@@ -604,7 +623,7 @@ hipError_t launch_mv_lds(const VlbView &a, const int32_t *x, int64_t *y, hipStre
   if (lds > kMaxLds) return hipErrorInvalidValue;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_vlb_mv_lds<SGN, GPT, CLAMP>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_vlb_mv_lds<SGN, GPT, CLAMP, WIDE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
     if (e != hipSuccess) return e;
     attr = true;
@@ -613,35 +632,44 @@ hipError_t launch_mv_lds(const VlbView &a, const int32_t *x, int64_t *y, hipStre
     hipError_t e = launch_fill_i64(y, (uint64_t)a.rows, 0, s);
     if (e != hipSuccess) return e;
   }
-  int64_t gy = resident_lds<SGN, GPT, CLAMP>(lds) / npanels;
+  int64_t gy = resident_lds<SGN, GPT, CLAMP, WIDE>(lds) / npanels;
   gy = gy < 1 ? 1 : (gy > a.rows ? a.rows : gy);
   if (gy > 65535) gy = 65535;
   dim3 grid((unsigned)npanels, (unsigned)gy);
-  k_vlb_mv_lds<SGN, GPT, CLAMP><<<grid, kVThreads, lds, s>>>(
+  k_vlb_mv_lds<SGN, GPT, CLAMP, WIDE><<<grid, kVThreads, lds, s>>>(
       a.w, a.row_bit, a.grp, a.rows, a.cols, a.ngr, a.k, seg_words, x, y, npanels > 1 ? 1 : 0);
   return hipGetLastError();
 }
 
-template <bool SGN, int GPT>
+template <bool SGN, int GPT, bool WIDE>
 hipError_t launch_mv_lds_c(const VlbView &a, const int32_t *x, int64_t *y, hipStream_t s) {
   const bool clamp = (a.cols % ((int64_t)kVThreads * GPT * kVG)) != 0;
-  return clamp ? launch_mv_lds<SGN, GPT, true>(a, x, y, s)
-               : launch_mv_lds<SGN, GPT, false>(a, x, y, s);
+  return clamp ? launch_mv_lds<SGN, GPT, true, WIDE>(a, x, y, s)
+               : launch_mv_lds<SGN, GPT, false, WIDE>(a, x, y, s);
 }
 
 // Staged matvec: one group per lane (256 groups of at most 32 * 71 bits
 // always fit in LDS), or two when that keeps strictly more chains resident
 // per CU (blocks per CU from registers and LDS, times 256 GPT).  At equal
 // chain counts one group per lane measured faster: twice the waves to hide
-// the LDS latency of the walks.
-template <bool SGN>
-hipError_t launch_mv_staged(const VlbView &a, const int32_t *x, int64_t *y, hipStream_t s) {
-  const int64_t chains1 = (int64_t)resident_lds<SGN, 1, true>(stage_lds(a.gmax, 1));
+// the LDS latency of the walks.  Matrices whose pairs average more than 24
+// bits (so that most pairs pass 32 bits, as with uniform bit-lengths) take
+// the branch-free four-word walk.
+template <bool SGN, bool WIDE>
+hipError_t launch_mv_staged_w(const VlbView &a, const int32_t *x, int64_t *y, hipStream_t s) {
+  const int64_t chains1 = (int64_t)resident_lds<SGN, 1, true, WIDE>(stage_lds(a.gmax, 1));
   int64_t chains2 = 0;
   if (stage_lds(a.gmax, 2) <= kMaxLds)
-    chains2 = 2 * (int64_t)resident_lds<SGN, 2, true>(stage_lds(a.gmax, 2));
-  return chains2 > chains1 ? launch_mv_lds_c<SGN, 2>(a, x, y, s)
-                           : launch_mv_lds_c<SGN, 1>(a, x, y, s);
+    chains2 = 2 * (int64_t)resident_lds<SGN, 2, true, WIDE>(stage_lds(a.gmax, 2));
+  return chains2 > chains1 ? launch_mv_lds_c<SGN, 2, WIDE>(a, x, y, s)
+                           : launch_mv_lds_c<SGN, 1, WIDE>(a, x, y, s);
+}
+
+template <bool SGN>
+hipError_t launch_mv_staged(const VlbView &a, const int32_t *x, int64_t *y, hipStream_t s) {
+  const uint64_t n = (uint64_t)a.rows * (uint64_t)a.cols;
+  return a.nbits > 24u * n ? launch_mv_staged_w<SGN, true>(a, x, y, s)
+                           : launch_mv_staged_w<SGN, false>(a, x, y, s);
 }
 
 unsigned vgrid(uint64_t work, uint64_t per_block, unsigned cap) {

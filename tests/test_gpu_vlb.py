@@ -182,3 +182,23 @@ def test_workload_full_size_sampled():
         assert rb[r + 1] - rb[r] == ref.nbits - spec.cols * ref.k + spec.cols * g.k, r
         for j in (0, 31, 32, spec.cols - 1):
             assert c.vlb_get(g, r, j) == int(row[0, j])
+
+
+@pytest.mark.parametrize("shape", [(7, 1000), (2, 16384), (3, 16416), (40, 2000)], ids=str)
+def test_rare_wide_pairs(shape):
+    """Mostly short pairs with a few past 32 bits: the staged kernel's
+    short-pair walk with its long-pair branch (the four-word walk is for
+    matrices whose pairs average more than 24 bits)."""
+    c = ccm()
+    rng = np.random.default_rng(shape[1])
+    A = rng.integers(0, 8, size=shape, dtype=np.int64)
+    flat = A.reshape(-1)
+    wide = rng.choice(flat.size, size=max(3, flat.size // 100), replace=False)
+    flat[wide] = rng.integers(1 << 30, 1 << 62, size=wide.size, dtype=np.int64)
+    for signed in (False, True):
+        M = A if not signed else np.where(rng.random(A.shape) < 0.5, -A - 1, A)
+        ref = oracle.vlb_compress(M)
+        assert ref.nbits < 24 * M.size
+        g = c.vlb_compress(dev(M))
+        check_encoding(g, ref)
+        check_ops(g, ref, M, rng)
