@@ -2,21 +2,22 @@
 // column).  The same kernel serves y = A x for a matrix unravelled by column,
 // whose stream is that of A^T unravelled by row.
 //
-//   * Block = 8 waves; a block owns a panel of 64 groups (2048 columns) and a
-//     range of rows; lane l owns group 64 p + l, i.e. columns
-//     2048 p + 32 l .. + 31, and keeps their 32 sums in registers (int64).
-//   * Wave w walks rows r0 + w, r0 + w + 8, ...  For each row it copies the
+//   * Block = 16 waves (b <= 8) or 8; a block owns a panel of 64 groups
+//     (2048 columns) and a range of rows; lane l owns group 64 p + l, i.e.
+//     columns 2048 p + 32 l .. + 31, and keeps their 32 sums in registers.
+//   * Wave w walks rows r0 + w, r0 + w + W, ...  For each row it copies the
 //     panel's stretch of the row (64 groups = 64 b words, contiguous) into its
-//     own LDS ring of up to 4 row buffers with 16-byte memory-to-LDS loads
-//     (global_load_lds_dwordx4, a fixed count per lane so the wait counts are
-//     constants): up to 3 rows are in flight while it decodes one.  No block
+//     own LDS ring of up to 8 (b <= 8) or 4 row buffers with 16-byte
+//     memory-to-LDS loads (global_load_lds_dwordx4, a fixed count per lane so
+//     the wait counts are constants): up to 7 or 3 rows are in flight while
+//     it decodes one.  No block
 //     barrier until the end: each wave reads only what it copied.
 //   * A lane reads its group's b words (plus one) from LDS; a row whose start
 //     is not word-aligned (cols not a multiple of 32) shifts every group of
 //     the row by the same bit offset, undone with one funnel shift per word.
 //     The 32 fields decode at fixed offsets (width b is a template
 //     parameter) and each adds field * x[r] to its column's sum.
-//   * End: the 8 waves' sums are added through LDS and each column's total
+//   * End: the waves' sums are added through LDS and each column's total
 //     goes to y, atomically when the rows are split over several blocks (y
 //     zeroed first; at most 32 splits, since same-address atomics are slow).
 //     Columns past the last (a ragged last group) are decoded but never
@@ -31,10 +32,15 @@
 namespace ccm {
 namespace mvt {
 
-constexpr int kWaves = 8;
-constexpr int kThreads = 64 * kWaves;
 constexpr int kPanelGroups = 64;
 constexpr size_t kMaxLds = 160 * 1024 - 64;
+
+// Waves per block: 16 for narrow fields (short rows, so more waves share a
+// panel's atomics), 8 otherwise (the wide decode needs more registers).
+template <int B>
+constexpr int waves() {
+  return B <= 8 ? 16 : 8;
+}
 
 // 16-byte vectors a lane copies per row: a stretch holds at most 64 b + 6
 // words (64 groups, the alignment of its first word down to 16 bytes and a
@@ -45,18 +51,18 @@ constexpr int vec_per_lane() {
 }
 
 // Row buffers per wave (a ring: NB - 1 rows in flight while one is decoded),
-// as many as fit, at most 4.
+// as many as fit, at most 8 (short rows) or 4.
 template <int B>
 constexpr int nbuf() {
-  int n = 4;
-  while (n > 1 && (size_t)kWaves * n * vec_per_lane<B>() * 64 * 16 > kMaxLds) --n;
+  int n = B <= 8 ? 8 : 4;
+  while (n > 1 && (size_t)waves<B>() * n * vec_per_lane<B>() * 64 * 16 > kMaxLds) --n;
   return n;
 }
 
 template <int B>
 constexpr size_t lds_bytes() {
-  const size_t stage = (size_t)kWaves * nbuf<B>() * vec_per_lane<B>() * 64 * 16;
-  const size_t red = (size_t)kWaves * 64 * 4 * 8;  // 4 columns per round
+  const size_t stage = (size_t)waves<B>() * nbuf<B>() * vec_per_lane<B>() * 64 * 16;
+  const size_t red = (size_t)waves<B>() * 64 * 4 * 8;  // 4 columns per round
   return stage > red ? stage : red;
 }
 
@@ -65,28 +71,30 @@ __device__ __forceinline__ void wait_vm() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-// Waits until at most m * NL copies are outstanding (m < NB, wave-uniform).
-template <int NL, int NB>
+// Waits until at most m * NL copies are outstanding (m < NB, wave-uniform;
+// the count is an immediate, so one case per m).
+template <int NL, int NB, int M = NB - 1>
 __device__ __forceinline__ void wait_rows(int m) {
-  if (NB > 3 && m >= 3) {
-    wait_vm<3 * NL>();
-  } else if (NB > 2 && m == 2) {
-    wait_vm<2 * NL>();
-  } else if (NB > 1 && m == 1) {
-    wait_vm<NL>();
-  } else {
+  if constexpr (M == 0) {
     wait_vm<0>();
+  } else {
+    static_assert(M * NL <= 63, "vmcnt holds at most 63");
+    if (m >= M)
+      wait_vm<M * NL>();
+    else
+      wait_rows<NL, NB, M - 1>(m);
   }
 }
 
 template <int B, bool SGN, typename XT>
-__global__ __launch_bounds__(kThreads) void k_matvec_t(const uint32_t *__restrict__ w,
+__global__ __launch_bounds__(64 * waves<B>()) void k_matvec_t(const uint32_t *__restrict__ w,
                                                        int64_t rows, int64_t cols,
                                                        int64_t rows_per_block,
                                                        const XT *__restrict__ x,
                                                        int64_t *__restrict__ y, int atomic_out) {
   constexpr int NL = vec_per_lane<B>();
   constexpr int NB = nbuf<B>();
+  constexpr int kWaves = waves<B>();
   extern __shared__ uint4 lds4[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -188,7 +196,7 @@ __global__ __launch_bounds__(kThreads) void k_matvec_t(const uint32_t *__restric
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) red[((wave * 4) + jj) * 64 + lane] = acc[j0 + jj];
     __syncthreads();
-    if (t < 256) {
+    if (t < 256) {  // 64 lanes x 4 columns
       uint64_t sum = 0;
 #pragma unroll
       for (int v = 0; v < kWaves; ++v) sum += (uint64_t)red[((v * 4) + tj) * 64 + tl];
@@ -221,7 +229,8 @@ hipError_t launch_t(const uint32_t *w, int64_t rows, int64_t cols, const XT *x, 
       if (e != hipSuccess) return e;
     }
     int o = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_matvec_t<B, SGN, XT>, kThreads, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_matvec_t<B, SGN, XT>, 64 * waves<B>(),
+                                                     lds) !=
             hipSuccess ||
         o < 1)
       o = 1;
@@ -230,7 +239,7 @@ hipError_t launch_t(const uint32_t *w, int64_t rows, int64_t cols, const XT *x, 
   // Rows split so the resident blocks cover the grid once; at most 32 splits
   // (each split adds one atomic per column), at least 8 rows per wave.
   int64_t splits = ((int64_t)occ * compute_units_t() + npanels - 1) / npanels;
-  const int64_t max_splits = (rows + 8 * kWaves - 1) / (8 * kWaves);
+  const int64_t max_splits = (rows + 8 * waves<B>() - 1) / (8 * waves<B>());
   splits = splits > 32 ? 32 : splits;
   splits = splits < 1 ? 1 : (splits > max_splits ? max_splits : splits);
   if (splits < 1) splits = 1;
@@ -242,7 +251,8 @@ hipError_t launch_t(const uint32_t *w, int64_t rows, int64_t cols, const XT *x, 
     if (e != hipSuccess) return e;
   }
   dim3 grid((unsigned)npanels, (unsigned)splits);
-  k_matvec_t<B, SGN, XT><<<grid, kThreads, lds, s>>>(w, rows, cols, rpb, x, y, splits > 1 ? 1 : 0);
+  k_matvec_t<B, SGN, XT><<<grid, 64 * waves<B>(), lds, s>>>(w, rows, cols, rpb, x, y,
+                                                             splits > 1 ? 1 : 0);
   return hipGetLastError();
 }
 
