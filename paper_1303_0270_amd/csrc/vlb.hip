@@ -62,15 +62,6 @@ __device__ __forceinline__ uint64_t bits_at(const uint32_t *w, uint64_t p, int n
   return v & mask64(nb);
 }
 
-// Start bit (absolute) and end bit of group g of row i.
-__device__ __forceinline__ void group_span(const uint64_t *row_bit, const uint32_t *grp,
-                                           int64_t i, int64_t g, int64_t ngr, uint64_t *s,
-                                           uint64_t *e) {
-  const uint64_t base = row_bit[i];
-  *s = base + grp[(uint64_t)i * (uint64_t)ngr + (uint64_t)g];
-  *e = g + 1 < ngr ? base + grp[(uint64_t)i * (uint64_t)ngr + (uint64_t)g + 1] : row_bit[i + 1];
-}
-
 // ---- pass 1: bits per group --------------------------------------------
 
 // Half-wave h of a wave owns one group: lane l reads element 32g + l, and the
