@@ -111,13 +111,16 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
-constexpr int kBM = 256, kBN = 256, kBK = 128, kPitch8 = kBK + 16;  // LDS row pitch, bytes
-constexpr int kWM = 64, kWN = 64;  // output rows and columns per wave
+constexpr int kBM = 256, kBN = 256, kBK = 128;  // block tile; K bytes per step (= LDS row)
+constexpr int kKPad = kBK;                      // K padding of the int8 operands
+constexpr int kWM = 128, kWN = 64;  // output rows and columns per wave
 constexpr int kFM = kWM / 32, kFN = kWN / 32;  // 32x32 accumulator blocks per wave
 constexpr int kGemmThreads = 64 * (kBM / kWM) * (kBN / kWN);
-constexpr size_t kGemmLds = 2u * (kBM + kBN) * kPitch8;  // two buffers of A and B tiles
+constexpr size_t kTileBytes = (size_t)(kBM + kBN) * kBK;  // A and B tiles of one K step
+constexpr size_t kGemmLds = 2u * kTileBytes;              // two buffers
+constexpr int kGroupM = 4;  // tile rows per group of the block order
 
-__host__ __device__ inline int64_t padded_k(int64_t K) { return (K + kBK - 1) / kBK * kBK; }
+__host__ __device__ inline int64_t padded_k(int64_t K) { return (K + kKPad - 1) / kKPad * kKPad; }
 
 // Four int8 fields (values fit int8) into one word, byte i = field i.
 __device__ __forceinline__ uint32_t bytes4(int32_t a, int32_t b, int32_t c, int32_t d) {
@@ -163,79 +166,132 @@ __global__ __launch_bounds__(256) void k_decode_rows_i8(const uint32_t *__restri
   }
 }
 
-// out[n][k] = B[k][n] as int8 (zero at or past K): lane l of a wave takes
-// column n0 + l, so each step reads 64 neighbouring fields of one row of B;
-// the wave's 32 consecutive k are packed into 32 bytes.
+// out[n][k] = B[k][n] as int8 (zero at or past K), through an LDS tile of
+// 128 k x 64 n per block: each lane first decodes one group (32 consecutive n
+// of one row k of B, read as the group's words), then 4 lanes per n gather
+// their 32 k each from the tile and write the 128 bytes of out's row n as
+// 16-byte stores.
+constexpr int kCtK = 128, kCtN = 64, kCtPitch = kCtN + 4;  // tile pitch in bytes
+
 template <int B>
 __global__ __launch_bounds__(256) void k_decode_cols_i8(const uint32_t *__restrict__ w,
                                                         uint64_t cap, int sgn, int64_t K,
                                                         int64_t N, int64_t ldk,
                                                         int8_t *__restrict__ out) {
-  const int64_t n = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-  const int64_t k0 = (int64_t)blockIdx.y * 128 + 32 * (threadIdx.x >> 6);
-  if (n >= N || k0 >= ldk) return;
-  int32_t v[32];
-#pragma unroll
-  for (int i = 0; i < 32; ++i) {
-    const int64_t k = k0 + i;
-    v[i] = 0;
-    if (k < K) {
-      const uint64_t bit = ((uint64_t)k * (uint64_t)N + (uint64_t)n) * B;
+  __shared__ __align__(16) uint8_t tile[kCtK * kCtPitch];
+  const int64_t nb = (int64_t)blockIdx.x * kCtN, kb = (int64_t)blockIdx.y * kCtK;
+  const int t = threadIdx.x;
+  {
+    const int kl = t >> 1, half = t & 1;
+    const int64_t k = kb + kl, n0 = nb + 32 * half;
+    int32_t v[32];
+    if (k < K && n0 < N) {
+      const uint64_t bit = ((uint64_t)k * (uint64_t)N + (uint64_t)n0) * B;
       const uint64_t w0 = bit >> 5;
-      uint32_t u;
-      if constexpr (32 % B == 0) {  // fields never straddle a word
-        u = (w[w0] >> (bit & 31u)) & ((1u << B) - 1u);
-      } else {
-        const uint32_t lo = w[w0], hi = w[w0 + 1 < cap ? w0 + 1 : cap - 1];
-        u = __builtin_amdgcn_alignbit(hi, lo, (int)(bit & 31u)) & ((1u << B) - 1u);
-      }
-      v[i] = sgn ? ((int32_t)(u << (32 - B)) >> (32 - B)) : (int32_t)u;
-    }
-  }
-  uint4 *d = reinterpret_cast<uint4 *>(out + n * ldk + k0);
+      const int sh = (int)(bit & 31u);
+      uint32_t ww[B + 1];
 #pragma unroll
-  for (int q = 0; q < 2; ++q)
-    d[q] = make_uint4(bytes4(v[16 * q], v[16 * q + 1], v[16 * q + 2], v[16 * q + 3]),
-                      bytes4(v[16 * q + 4], v[16 * q + 5], v[16 * q + 6], v[16 * q + 7]),
-                      bytes4(v[16 * q + 8], v[16 * q + 9], v[16 * q + 10], v[16 * q + 11]),
-                      bytes4(v[16 * q + 12], v[16 * q + 13], v[16 * q + 14], v[16 * q + 15]));
+      for (int q = 0; q <= B; ++q) ww[q] = w[w0 + q < cap ? w0 + q : cap - 1];
+#pragma unroll
+      for (int q = 0; q < B; ++q) ww[q] = __builtin_amdgcn_alignbit(ww[q + 1], ww[q], sh);
+      const int lim = N - n0 < 32 ? (int)(N - n0) : 32;
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        const uint64_t u = codec::field<B>(ww, i);
+        v[i] = i < lim ? (sgn ? (int32_t)sext64(u, B) : (int32_t)u) : 0;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 32; ++i) v[i] = 0;
+    }
+    uint32_t *row = reinterpret_cast<uint32_t *>(tile + kl * kCtPitch + 32 * half);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) row[q] = bytes4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  }
+  __syncthreads();
+  const int nl = t >> 2, kq = t & 3;
+  const int64_t n = nb + nl;
+  if (n >= N || kb >= ldk) return;
+  uint32_t o[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int k0 = 32 * kq + 4 * q;
+    o[q] = (uint32_t)tile[k0 * kCtPitch + nl] | ((uint32_t)tile[(k0 + 1) * kCtPitch + nl] << 8) |
+           ((uint32_t)tile[(k0 + 2) * kCtPitch + nl] << 16) |
+           ((uint32_t)tile[(k0 + 3) * kCtPitch + nl] << 24);
+  }
+  uint4 *d = reinterpret_cast<uint4 *>(out + n * ldk + kb + 32 * kq);
+  d[0] = make_uint4(o[0], o[1], o[2], o[3]);
+  d[1] = make_uint4(o[4], o[5], o[6], o[7]);
 }
 
+// 16-byte chunk c of tile row r sits at chunk position c ^ swz(r) of its
+// 128-byte LDS row, so the MFMA operand reads (lanes 0-31 rows r..r+31 at one
+// chunk, lanes 32-63 at the next) are conflict-free whether the LDS serves 8
+// lanes of 16 bytes per cycle from 32 banks (8 consecutive rows take
+// distinct positions) or 16 lanes from 64 banks (rows of equal parity among
+// 16 take distinct positions); the bank-conflict counter reads 0.
+__device__ __forceinline__ int swz(int r) { return (r ^ (r >> 3)) & 7; }
+
+// C = A B^T-layout int8 GEMM with exact int32 accumulation (MFMA
+// v_mfma_i32_32x32x32_i8), C stored as OT, and C's exact range.
+//   * Block = 8 waves, 256 x 256 outputs; each wave owns 128 x 64 (4 x 2
+//     MFMA blocks, 128 accumulator registers): 6 LDS reads of 16 bytes feed 8
+//     MFMAs.
+//   * K steps of 128: the A and B tiles (2 x 256 rows x 128 bytes) are copied
+//     into LDS with memory-to-LDS loads (global_load_lds_dwordx4: each wave
+//     instruction fills 8 rows, a lane's source chunk chosen so the row lands
+//     swizzled), into the other of two buffers while the MFMAs consume this
+//     one.  (Steps of 64 with a ring of four buffers, three in flight,
+//     measured slower: twice the barriers.)  Rows past M or N copy the last
+//     row (their outputs are not stored).
 template <typename OT>
 __global__ __launch_bounds__(kGemmThreads) void k_gemm_i8(const int8_t *__restrict__ A,
                                                           const int8_t *__restrict__ Bt, int64_t M,
                                                           int64_t N, int64_t ldk,
                                                           OT *__restrict__ C, RangeSlot *slot) {
   extern __shared__ __align__(16) int8_t gemm_lds[];
-  // buffer b: A tile at b * (kBM + kBN) * kPitch8, then the B tile
-  auto tile = [&](int b, int opnd) {
-    return gemm_lds + b * (kBM + kBN) * kPitch8 + opnd * kBM * kPitch8;
-  };
-  const int64_t m0 = (int64_t)blockIdx.y * kBM, n0 = (int64_t)blockIdx.x * kBN;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // Tile of this block.  Tiles are taken in groups of kGroupM tile rows
+  // (consecutive tiles walk down the group, then across), and when the tile
+  // count is a multiple of 8 each XCD (blocks are dealt to the 8 XCDs in
+  // turn) gets one contiguous run of that order: the 32 blocks an XCD runs at
+  // once then share 4 A panels and 8 B panels, whose K slices its L2 holds.
+  const int64_t gx = (N + kBN - 1) / kBN, gy = (M + kBM - 1) / kBM, ntile = gx * gy;
+  int64_t tix = blockIdx.x;
+  if (ntile % 8 == 0) tix = (tix % 8) * (ntile / 8) + tix / 8;
+  const int64_t gsz_full = (int64_t)kGroupM * gx;
+  const int64_t first_m = tix / gsz_full * kGroupM;
+  const int64_t gsz = gy - first_m < kGroupM ? gy - first_m : kGroupM;
+  const int64_t tm = first_m + (tix % gsz_full) % gsz, tn = (tix % gsz_full) / gsz;
+  const int64_t m0 = tm * kBM, n0 = tn * kBN;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / (kBN / kWN), wn = wave % (kBN / kWN);  // the wave's kWM x kWN block
 
-  // tile loads: 2 operands x 256 rows x kBK/16 pieces of 16 bytes, NP per
-  // lane: lane t takes piece t % kPR of rows t / kPR + kRP * j; rows past the
-  // end read the last row (their products land only in outputs not stored)
-  constexpr int kPR = kBK / 16, kRP = kGemmThreads / kPR, kNP = 2 * kBM / kRP;
-  const int prow = tid / kPR, pq = tid % kPR;
-  const int lds0 = prow * kPitch8 + 16 * pq;
-  v4u pre[kNP];  // native vectors: an array of uint4 structs is not kept in registers
-#define CCM_GEMM_LOAD(k0)                                                               \
-  _Pragma("unroll") for (int j = 0; j < kNP; ++j) {                                     \
-    const int opnd = j / (kBM / kRP);                                                   \
-    const int64_t r = (opnd ? n0 : m0) + prow + kRP * (j % (kBM / kRP));                \
-    const int64_t lim = opnd ? N : M;                                                   \
-    pre[j] = *reinterpret_cast<const v4u *>((opnd ? Bt : A) + (r < lim ? r : lim - 1) * ldk + \
-                                              16 * pq + (k0));                          \
-  }
-#define CCM_GEMM_STORE(b)                                                               \
-  _Pragma("unroll") for (int j = 0; j < kNP; ++j) {                                     \
-    const int opnd = j / (kBM / kRP);                                                   \
-    *reinterpret_cast<v4u *>(gemm_lds + (b) * (kBM + kBN) * kPitch8 + opnd * kBM * kPitch8 + \
-                               lds0 + kRP * (j % (kBM / kRP)) * kPitch8) = pre[j];      \
-  }
+  // the copy of one K step: 2 x 256 rows of 128 bytes = 64 wave instructions
+  // of 8 rows, kInstPerWave per wave; instruction I: operand I / 32, rows
+  // 8 (I % 32) .. + 7
+  constexpr int kRowsPerInst = 64 * 16 / kBK;
+  constexpr int kInstPerWave = (2 * kBM / kRowsPerInst) / (kGemmThreads / 64);
+  constexpr int kChunks = kBK / 16;
+  const int lrow = lane / kChunks, lpos = lane % kChunks;
+  auto stage = [&](int64_t k0, int buf) {
+#pragma unroll
+    for (int q = 0; q < kInstPerWave; ++q) {
+      const int I = wave * kInstPerWave + q;
+      const int opnd = I / (kBM / kRowsPerInst);
+      const int rb = kRowsPerInst * (I % (kBM / kRowsPerInst));
+      const int r = rb + lrow;
+      const int64_t lim = opnd ? N : M;
+      int64_t gr = (opnd ? n0 : m0) + r;
+      gr = gr < lim ? gr : lim - 1;
+      const int c = lpos ^ swz(r);
+      const int8_t *src = (opnd ? Bt : A) + gr * ldk + k0 + 16 * c;
+      int8_t *dst = gemm_lds + (size_t)buf * kTileBytes + (size_t)opnd * kBM * kBK + (size_t)rb * kBK;
+      __builtin_amdgcn_global_load_lds((const void *)src,
+                                       (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+    }
+  };
 
   v16i acc[kFM][kFN];
 #pragma unroll
@@ -246,34 +302,37 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_i8(const int8_t *__restri
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
 
   const int64_t nk = ldk / kBK;
-  CCM_GEMM_LOAD(0);
-  CCM_GEMM_STORE(0);
+  stage(0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   for (int64_t kc = 0; kc < nk; ++kc) {
     const int cur = (int)(kc & 1);
-    if (kc + 1 < nk) CCM_GEMM_LOAD((kc + 1) * kBK);  // in flight during the MFMAs
-    const int8_t *as = tile(cur, 0), *bs = tile(cur, 1);
+    if (kc + 1 < nk) stage((kc + 1) * kBK, cur ^ 1);  // in flight during the MFMAs
+    const int8_t *as = gemm_lds + (size_t)cur * kTileBytes;
+    const int8_t *bs = as + (size_t)kBM * kBK;
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 32) {
-      const int koff = kk + 16 * (lane >> 5);
+      const int c = kk / 16 + (lane >> 5);
       v4i a[kFM], b[kFN];
 #pragma unroll
-      for (int t = 0; t < kFM; ++t)
-        a[t] = *reinterpret_cast<const v4i *>(as + (wm * kWM + t * 32 + (lane & 31)) * kPitch8 + koff);
+      for (int t = 0; t < kFM; ++t) {
+        const int r = wm * kWM + t * 32 + (lane & 31);
+        a[t] = *reinterpret_cast<const v4i *>(as + r * kBK + 16 * (c ^ swz(r)));
+      }
 #pragma unroll
-      for (int t = 0; t < kFN; ++t)
-        b[t] = *reinterpret_cast<const v4i *>(bs + (wn * kWN + t * 32 + (lane & 31)) * kPitch8 + koff);
+      for (int t = 0; t < kFN; ++t) {
+        const int r = wn * kWN + t * 32 + (lane & 31);
+        b[t] = *reinterpret_cast<const v4i *>(bs + r * kBK + 16 * (c ^ swz(r)));
+      }
 #pragma unroll
       for (int ta = 0; ta < kFM; ++ta)
 #pragma unroll
         for (int tb = 0; tb < kFN; ++tb)
           acc[ta][tb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
     }
-    if (kc + 1 < nk) CCM_GEMM_STORE(cur ^ 1);
-    __syncthreads();  // the next buffer is written and this one is read
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this lane's copies of the next step
+    __syncthreads();  // everyone's copies have landed and this buffer is read
   }
-#undef CCM_GEMM_LOAD
-#undef CCM_GEMM_STORE
 
   // 32x32 accumulator layout: lane l, register r -> column l%32,
   // row 8*(r/4) + 4*(l/32) + r%4
@@ -312,7 +371,7 @@ hipError_t launch_matmul_i8(const uint32_t *aw, int abits, int asgn, const uint3
   int8_t *ai8 = scratch_i8, *bti8 = scratch_i8 + M * ldk;
   const uint64_t acap = cap_words32((uint64_t)M * (uint64_t)K, abits);
   const uint64_t bcap = cap_words32((uint64_t)K * (uint64_t)N, bbits);
-  const dim3 cgrid((unsigned)((N + 63) / 64), (unsigned)((ldk + 127) / 128));
+  const dim3 cgrid((unsigned)((N + kCtN - 1) / kCtN), (unsigned)(ldk / kCtK));
   switch (abits) {
 #define CCM_DEC_A(b)                                                                              \
   case b:                                                                                         \
@@ -335,7 +394,9 @@ hipError_t launch_matmul_i8(const uint32_t *aw, int abits, int asgn, const uint3
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  dim3 grid((unsigned)((N + kBN - 1) / kBN), (unsigned)((M + kBM - 1) / kBM));
+  const int64_t ntile = ((N + kBN - 1) / kBN) * ((M + kBM - 1) / kBM);
+  if (ntile > 0x7fffffffll) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)ntile);
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_gemm_i8<int32_t>),
