@@ -215,3 +215,44 @@ def test_vlb_invalid_descriptors_rejected_before_gpu_work(L):
     assert L.lib.ccm_vlb_get(ctypes.byref(d), 0, 8, ctypes.byref(y), None) == L.E_RANGE
     assert L.lib.ccm_vlb_matvec(ctypes.byref(d), None, L.I32, 0x4000, None) == L.E_INVAL
     assert L.lib.ccm_vlb_matvec(ctypes.byref(d), 0x3000, 7, 0x4000, None) == L.E_INVAL
+
+
+def test_column_major_headers_match_oracle(L):
+    """ccm_header_encode_cm (host only) writes the oracle's column-major header
+    from the transpose's descriptor; decode_cm inverts it and rejects a
+    row-major header, which ccm_header_decode keeps rejecting the other way."""
+    rng = np.random.default_rng(13)
+    for _ in range(50):
+        r, c = (int(v) for v in rng.integers(1, 9, size=2))
+        b = int(rng.integers(1, 40))
+        A = rng.integers(0, 1 << b, size=(r, c), dtype=np.int64)
+        pc = oracle.compress_cm(A)
+        at = _desc_from(oracle.compress(A.T))  # the stream's own descriptor
+        buf = (ctypes.c_uint8 * 64)()
+        assert L.lib.ccm_header_encode_cm(ctypes.byref(at), buf) == L.OK
+        assert bytes(buf) == oracle.header_cm(pc)
+        back = L.Desc()
+        assert L.lib.ccm_header_decode_cm(buf, ctypes.byref(back)) == L.OK
+        assert (back.rows, back.cols, back.bits, back.words) == (at.rows, at.cols, at.bits, at.words)
+        assert L.lib.ccm_header_decode(buf, ctypes.byref(back)) == L.E_INVAL
+        row = (ctypes.c_uint8 * 64).from_buffer_copy(oracle.header(oracle.compress(A)))
+        assert L.lib.ccm_header_decode_cm(row, ctypes.byref(back)) == L.E_INVAL
+
+
+def test_new_entry_points_reject_bad_arguments_before_gpu_work(L):
+    p = oracle.compress(np.array([[1, 2], [3, 4]]))
+    d = _desc_from(p)  # payload NULL
+    assert L.lib.ccm_matvec_t(ctypes.byref(d), 0x1000, L.I32, 0x2000, None) == L.E_INVAL
+    assert L.lib.ccm_compress_cm(0x1000, L.I64, ctypes.byref(d), None) == L.E_INVAL
+    d.payload = 0x3000
+    d.bits = 7  # not the width of [1, 4]
+    assert L.lib.ccm_matvec_t(ctypes.byref(d), 0x1000, L.I32, 0x2000, None) == L.E_INVAL
+    d = _desc_from(p)
+    d.payload = 0x3000
+    assert L.lib.ccm_matvec_t(ctypes.byref(d), None, L.I32, 0x2000, None) == L.E_INVAL
+    assert L.lib.ccm_matvec_t(ctypes.byref(d), 0x1000, 5, 0x2000, None) == L.E_INVAL
+    info = L.MethodInfo()
+    assert L.lib.ccm_method_plan(None, L.I64, 2, 2, ctypes.byref(info), None) == L.E_INVAL
+    assert L.lib.ccm_method_plan(0x1000, L.I64, 0, 2, ctypes.byref(info), None) == L.E_INVAL
+    assert L.lib.ccm_method_plan(0x1000, 9, 2, 2, ctypes.byref(info), None) == L.E_INVAL
+    assert L.lib.ccm_method_plan(0x1000, L.I64, 2, 2, None, None) == L.E_INVAL
