@@ -148,11 +148,11 @@ def summarize_counters(src_dir, out_path):
         "",
         "Commands (repo root on the MI355X box; rocprofv3 run from /tmp with TMPDIR=/tmp):",
         "",
-        "    timeout -s KILL 60 rocprofv3 --pmc FETCH_SIZE -d gpurun_out/ctr/fetch -o fetch \\",
+        f"    timeout -s KILL 60 rocprofv3 --pmc FETCH_SIZE -d {src_dir}/fetch -o fetch \\",
         "        --output-format csv -- python3 bench.py --matvec-only --steps 1 --warmup 0",
-        "    timeout -s KILL 60 rocprofv3 --pmc WRITE_SIZE -d gpurun_out/ctr/write -o write \\",
+        f"    timeout -s KILL 60 rocprofv3 --pmc WRITE_SIZE -d {src_dir}/write -o write \\",
         "        --output-format csv -- python3 bench.py --matvec-only --steps 1 --warmup 0",
-        "    python3 bench.py --summarize-counters gpurun_out/ctr",
+        f"    python3 bench.py --summarize-counters {src_dir}",
         "",
         "`--matvec-only` generates the twelve packed sweep matrices (k in {1,3,7,12,17,31}, "
         "unsigned and signed) on the device, runs one matvec per matrix, then a plain 1 GiB "
@@ -289,7 +289,7 @@ def main():
                         args.trace_title, args.trace_note)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
@@ -418,7 +418,7 @@ def main():
     tot_t = float(np.sum(phases))
     value = sweep_bytes * len(phases) / tot_t / 1e9
 
-    # ---- the other operations (algorithmic bytes, SURVEY per-op units) ---
+    # ---- the other operations (algorithmic bytes per op) ---
     def op_stats(prefix, bytes_fn):
         tt = bb = 0.0
         for c, a in zip(cases, packed):

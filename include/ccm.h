@@ -67,7 +67,7 @@ typedef enum {
   CCM_E_OVERFLOW = -4,    /* an exact result does not fit in int64 (rules below) */
   CCM_E_NOMEM = -5,       /* a caller buffer is too small, or an allocation failed */
   CCM_E_DEVICE = -6,      /* HIP runtime error */
-  CCM_E_UNSUPPORTED = -7  /* valid request this build does not implement */
+  CCM_E_UNSUPPORTED = -7  /* valid request the library does not implement */
 } ccm_status;
 
 typedef enum { CCM_I32 = 0, CCM_I64 = 1 } ccm_dtype;
