@@ -257,8 +257,17 @@ int ccm_generate(const ccm_desc *out, int64_t lo, int64_t hi, uint64_t seed,
  * is ccm_matvec on it, and y = A x is ccm_matvec_t. */
 
 /* y = A^T x (y[j] = sum_i a_ij x_i modulo 2^64) for the row-major matrix a:
- * x device, a->rows values of xdtype; y device, a->cols int64.  Async. */
-int ccm_matvec_t(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, void *stream);
+ * x device, a->rows values of xdtype; y device, a->cols int64.
+ *   The rows are split over up to 32 blocks per 2048-column panel.  With
+ *   scratch (device, 8-byte aligned, at least ccm_matvec_t_scratch_bytes(a)
+ *   bytes: 32 int64 partial sums per column) each split stores its column
+ *   sums there and a second kernel adds them into y; with scratch NULL the
+ *   splits add into y with atomics after zeroing it (slower).  A non-NULL
+ *   scratch that is too small is CCM_E_NOMEM, a misaligned one CCM_E_INVAL.
+ *   Calls that share one scratch buffer must be ordered (one stream).  Async. */
+uint64_t ccm_matvec_t_scratch_bytes(const ccm_desc *a);
+int ccm_matvec_t(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, void *scratch,
+                 uint64_t scratch_bytes, void *stream);
 
 /* Packs A, given dense row-major (out->cols x out->rows values of dtype),
  * unravelled by column into out->payload; out describes A^T and comes from

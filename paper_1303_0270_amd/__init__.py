@@ -241,6 +241,29 @@ def _mv_call(a: CMatrix, transposed: bool):
     return (lib.ccm_matvec_t, "ccm_matvec_t") if row_major_op else (lib.ccm_matvec, "ccm_matvec")
 
 
+# Largest scratch allocated for the split partial sums of y = A^T x; past it
+# the splits add with atomics instead.
+_MVT_SCRATCH_MAX = 256 << 20
+
+
+def _mv_args(a: CMatrix, x, y, stream, transposed: bool):
+    """The C entry point and its arguments for y = A x (transposed False) or
+    y = A^T x; ccm_matvec_t gets scratch for its split partial sums (returned
+    too: it must live until the launch completes)."""
+    fn, name = _mv_call(a, transposed)
+    args = [ctypes.byref(a.desc), _ptr(x), _dtype_code(x), _ptr(y)]
+    scratch = None
+    if name == "ccm_matvec_t":
+        nb = int(lib.ccm_matvec_t_scratch_bytes(ctypes.byref(a.desc)))
+        if 0 < nb <= _MVT_SCRATCH_MAX:
+            scratch = torch.empty(nb // 8, dtype=torch.int64, device=x.device)
+            args += [_ptr(scratch), nb]
+        else:
+            args += [None, 0]
+    args.append(_stream(stream))
+    return fn, name, tuple(args), scratch
+
+
 def _mv(a: CMatrix, x, y, stream, transposed: bool):
     nin, nout = (a.rows, a.cols) if transposed else (a.cols, a.rows)
     x = _device_tensor(x, "x")
@@ -250,8 +273,10 @@ def _mv(a: CMatrix, x, y, stream, transposed: bool):
         y = torch.empty(nout, dtype=torch.int64, device=x.device)
     elif y.dtype != torch.int64 or y.numel() != nout or not y.is_contiguous():
         raise CcmError(E_INVAL, "matvec: y")
-    fn, name = _mv_call(a, transposed)
-    check(fn(ctypes.byref(a.desc), _ptr(x), _dtype_code(x), _ptr(y), _stream(stream)), name)
+    fn, name, args, scratch = _mv_args(a, x, y, stream, transposed)
+    check(fn(*args), name)
+    if scratch is not None and stream is not None:
+        scratch.record_stream(stream)  # freed for reuse only after that stream's work
     return y
 
 
@@ -265,20 +290,22 @@ def matvec_t(a: CMatrix, x: torch.Tensor, y: torch.Tensor | None = None, stream=
     return _mv(a, x, y, stream, transposed=True)
 
 
-def matvec_launcher(a: CMatrix, x: torch.Tensor, y: torch.Tensor, stream=None):
-    """Marshals the arguments of y = A x once and returns a callable that
-    launches it with no further Python work (for back-to-back launches whose
-    kernels are shorter than the per-call marshalling).  a, x and y must stay
-    alive while the callable is used."""
+def matvec_launcher(a: CMatrix, x: torch.Tensor, y: torch.Tensor, stream=None,
+                    transposed: bool = False):
+    """Marshals the arguments of y = A x (y = A^T x when transposed) once and
+    returns a callable that launches it with no further Python work (for
+    back-to-back launches whose kernels are shorter than the per-call
+    marshalling).  a, x and y must stay alive while the callable is used."""
+    nin, nout = (a.rows, a.cols) if transposed else (a.cols, a.rows)
     x = _device_tensor(x, "x")
-    if x.numel() != a.cols:
+    if x.numel() != nin:
         raise CcmError(E_SHAPE, "matvec")
-    if y.dtype != torch.int64 or y.numel() != a.rows or not y.is_contiguous():
+    if y.dtype != torch.int64 or y.numel() != nout or not y.is_contiguous():
         raise CcmError(E_INVAL, "matvec: y")
-    fn, name = _mv_call(a, False)
-    args = (ctypes.byref(a.desc), _ptr(x), _dtype_code(x), _ptr(y), _stream(stream))
+    fn, name, args, scratch = _mv_args(a, x, y, stream, transposed)
 
     def launch():
+        _ = scratch  # the scratch lives as long as the callable
         rc = fn(*args)
         if rc != 0:
             raise CcmError(rc, name)

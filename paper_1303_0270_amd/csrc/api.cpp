@@ -593,12 +593,21 @@ int ccm_method_plan(const void *dense, int32_t dtype, int64_t rows, int64_t cols
 
 // ---- column-major unravel and y = A^T x ----------------------------------
 
-int ccm_matvec_t(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, void *stream) {
+uint64_t ccm_matvec_t_scratch_bytes(const ccm_desc *a) {
+  if (check_desc(a, false) != CCM_OK) return 0;
+  return 8ull * (uint64_t)ccm::kMaxSplitsT * (uint64_t)a->cols;
+}
+
+int ccm_matvec_t(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, void *scratch,
+                 uint64_t scratch_bytes, void *stream) {
   int rc = check_desc(a, true);
   if (rc != CCM_OK) return rc;
   if (!x || !y || (xdtype != CCM_I32 && xdtype != CCM_I64)) return CCM_E_INVAL;
+  if (scratch && (uintptr_t)scratch % 8 != 0) return CCM_E_INVAL;
+  if (scratch && scratch_bytes < ccm_matvec_t_scratch_bytes(a)) return CCM_E_NOMEM;
   CCM_HIP(ccm::launch_matvec_t((const uint32_t *)a->payload, a->rows, a->cols, a->bits,
-                               a->is_signed, x, xdtype, y, (hipStream_t)stream));
+                               a->is_signed, x, xdtype, y, (int64_t *)scratch,
+                               scratch ? scratch_bytes / 8 : 0, (hipStream_t)stream));
   return CCM_OK;
 }
 

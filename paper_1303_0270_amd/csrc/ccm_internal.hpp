@@ -276,9 +276,18 @@ hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t s);
 hipError_t launch_matvec(const uint32_t *w, int64_t rows, int64_t cols, int bits, int sgn,
                          const void *x, int xdtype, int64_t *y, hipStream_t s);
 
-// y = A^T x over a row-major stream (x: rows values, y: cols).
+// y = A^T x over a row-major stream (x: rows values, y: cols).  Rows are
+// split over at most kMaxSplitsT blocks per column panel; with part (device,
+// part_words >= kMaxSplitsT * cols int64) the splits store partial column
+// sums there and a second kernel adds them into y, otherwise they add into a
+// zeroed y with atomics.
+constexpr int kMaxSplitsT = 32;
 hipError_t launch_matvec_t(const uint32_t *w, int64_t rows, int64_t cols, int bits, int sgn,
-                           const void *x, int xdtype, int64_t *y, hipStream_t s);
+                           const void *x, int xdtype, int64_t *y, int64_t *part,
+                           uint64_t part_words, hipStream_t s);
+// y[c] = sum over s < splits of part[s * cols + c] (mod 2^64).
+hipError_t launch_sum_splits(const int64_t *part, int64_t splits, int64_t cols, int64_t *y,
+                             hipStream_t s);
 
 // Packs a dense row-major rows x cols matrix unravelled by column (the
 // row-major stream of its transpose) into out[0, cap32).

@@ -28,13 +28,13 @@ int compute_units_t() {
 }
 
 hipError_t launch_t_widths_1(const uint32_t *, int64_t, int64_t, int, int, const void *, int,
-                             int64_t *, hipStream_t);
+                             int64_t *, int64_t *, uint64_t, hipStream_t);
 hipError_t launch_t_widths_2(const uint32_t *, int64_t, int64_t, int, int, const void *, int,
-                             int64_t *, hipStream_t);
+                             int64_t *, int64_t *, uint64_t, hipStream_t);
 hipError_t launch_t_widths_3(const uint32_t *, int64_t, int64_t, int, int, const void *, int,
-                             int64_t *, hipStream_t);
+                             int64_t *, int64_t *, uint64_t, hipStream_t);
 hipError_t launch_t_widths_4(const uint32_t *, int64_t, int64_t, int, int, const void *, int,
-                             int64_t *, hipStream_t);
+                             int64_t *, int64_t *, uint64_t, hipStream_t);
 
 }  // namespace mvt
 
@@ -100,6 +100,20 @@ __global__ __launch_bounds__(kCmThreads) void k_compress_cm_gen(const T *__restr
   }
 }
 
+// Column c's total of the row splits' partial sums (coalesced across c).
+__global__ __launch_bounds__(256) void k_sum_splits(const int64_t *__restrict__ part,
+                                                    int64_t splits, int64_t cols,
+                                                    int64_t *__restrict__ y) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < (uint64_t)cols;
+       c += stride) {
+    uint64_t t = 0;
+#pragma unroll 8
+    for (int64_t k = 0; k < splits; ++k) t += (uint64_t)part[(uint64_t)k * (uint64_t)cols + c];
+    y[c] = (int64_t)t;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_compress_cm(const void *dense, int dtype, int64_t rows, int64_t cols,
@@ -136,11 +150,23 @@ hipError_t launch_compress_cm(const void *dense, int dtype, int64_t rows, int64_
 }
 
 hipError_t launch_matvec_t(const uint32_t *w, int64_t rows, int64_t cols, int bits, int sgn,
-                           const void *x, int xdtype, int64_t *y, hipStream_t s) {
-  if (bits <= 16) return mvt::launch_t_widths_1(w, rows, cols, bits, sgn, x, xdtype, y, s);
-  if (bits <= 32) return mvt::launch_t_widths_2(w, rows, cols, bits, sgn, x, xdtype, y, s);
-  if (bits <= 48) return mvt::launch_t_widths_3(w, rows, cols, bits, sgn, x, xdtype, y, s);
-  return mvt::launch_t_widths_4(w, rows, cols, bits, sgn, x, xdtype, y, s);
+                           const void *x, int xdtype, int64_t *y, int64_t *part,
+                           uint64_t part_words, hipStream_t s) {
+  if (bits <= 16)
+    return mvt::launch_t_widths_1(w, rows, cols, bits, sgn, x, xdtype, y, part, part_words, s);
+  if (bits <= 32)
+    return mvt::launch_t_widths_2(w, rows, cols, bits, sgn, x, xdtype, y, part, part_words, s);
+  if (bits <= 48)
+    return mvt::launch_t_widths_3(w, rows, cols, bits, sgn, x, xdtype, y, part, part_words, s);
+  return mvt::launch_t_widths_4(w, rows, cols, bits, sgn, x, xdtype, y, part, part_words, s);
+}
+
+hipError_t launch_sum_splits(const int64_t *part, int64_t splits, int64_t cols, int64_t *y,
+                             hipStream_t s) {
+  uint64_t g = ((uint64_t)cols + 255) / 256;
+  g = g < 1 ? 1 : (g > 65536 ? 65536 : g);
+  k_sum_splits<<<(unsigned)g, 256, 0, s>>>(part, splits, cols, y);
+  return hipGetLastError();
 }
 
 }  // namespace ccm

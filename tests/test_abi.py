@@ -242,15 +242,25 @@ def test_column_major_headers_match_oracle(L):
 def test_new_entry_points_reject_bad_arguments_before_gpu_work(L):
     p = oracle.compress(np.array([[1, 2], [3, 4]]))
     d = _desc_from(p)  # payload NULL
-    assert L.lib.ccm_matvec_t(ctypes.byref(d), 0x1000, L.I32, 0x2000, None) == L.E_INVAL
+    assert L.lib.ccm_matvec_t(ctypes.byref(d), 0x1000, L.I32, 0x2000, None, 0, None) == L.E_INVAL
     assert L.lib.ccm_compress_cm(0x1000, L.I64, ctypes.byref(d), None) == L.E_INVAL
     d.payload = 0x3000
     d.bits = 7  # not the width of [1, 4]
-    assert L.lib.ccm_matvec_t(ctypes.byref(d), 0x1000, L.I32, 0x2000, None) == L.E_INVAL
+    assert L.lib.ccm_matvec_t(ctypes.byref(d), 0x1000, L.I32, 0x2000, None, 0, None) == L.E_INVAL
     d = _desc_from(p)
     d.payload = 0x3000
-    assert L.lib.ccm_matvec_t(ctypes.byref(d), None, L.I32, 0x2000, None) == L.E_INVAL
-    assert L.lib.ccm_matvec_t(ctypes.byref(d), 0x1000, 5, 0x2000, None) == L.E_INVAL
+    assert L.lib.ccm_matvec_t(ctypes.byref(d), None, L.I32, 0x2000, None, 0, None) == L.E_INVAL
+    assert L.lib.ccm_matvec_t(ctypes.byref(d), 0x1000, 5, 0x2000, None, 0, None) == L.E_INVAL
+    # scratch: 32 int64 partial sums per column; too small or misaligned is refused
+    need = L.lib.ccm_matvec_t_scratch_bytes(ctypes.byref(d))
+    assert need == 8 * 32 * 2
+    assert L.lib.ccm_matvec_t(ctypes.byref(d), 0x1000, L.I32, 0x2000, 0x4000, need - 8,
+                              None) == L.E_NOMEM
+    assert L.lib.ccm_matvec_t(ctypes.byref(d), 0x1000, L.I32, 0x2000, 0x4004, need,
+                              None) == L.E_INVAL
+    bad = _desc_from(p)
+    bad.rows = 0
+    assert L.lib.ccm_matvec_t_scratch_bytes(ctypes.byref(bad)) == 0
     info = L.MethodInfo()
     assert L.lib.ccm_method_plan(None, L.I64, 2, 2, ctypes.byref(info), None) == L.E_INVAL
     assert L.lib.ccm_method_plan(0x1000, L.I64, 0, 2, ctypes.byref(info), None) == L.E_INVAL

@@ -60,8 +60,20 @@ def check_cm(g, ref, A, rng):
         assert c.get(g, i, j) == int(A[i, j]) == oracle.get_cm(ref, i, j)
 
 
+def narrow_x(rng, n, wide_at=None):
+    """x in [-2^15, 2^15) with both ends present; optionally one value past it."""
+    x = rng.integers(-(1 << 15), (1 << 15) - 1, size=n, endpoint=True, dtype=np.int64)
+    x[int(rng.integers(0, n))] = -(1 << 15)
+    x[int(rng.integers(0, n))] = (1 << 15) - 1
+    if wide_at is not None:
+        x[wide_at] = 1 << 15
+    return x
+
+
 def check_products(g, A, rng):
-    """matvec and matvec_t of g (either order) against the oracle."""
+    """matvec and matvec_t of g (either order) against the oracle: x over the
+    whole int32 and int64 ranges, x in [-2^15, 2^15) (the 32-bit partial sums
+    of y = A^T x), and such x with one value just past that range."""
     c = ccm()
     rows, cols = A.shape
     pr = oracle.compress(A)
@@ -70,6 +82,11 @@ def check_products(g, A, rng):
         xr = rng.integers(lo, hi, size=rows, endpoint=True, dtype=np.int64)
         assert np.array_equal(c.matvec(g, dev(xc, xdt)).cpu().numpy(), oracle.matvec(pr, xc))
         assert np.array_equal(c.matvec_t(g, dev(xr, xdt)).cpu().numpy(), oracle.matvec_t(pr, xr))
+    for xdt in (torch.int32, torch.int64):
+        for wide_at in (None, int(rng.integers(0, rows))):
+            xr = narrow_x(rng, rows, wide_at)
+            assert np.array_equal(c.matvec_t(g, dev(xr, xdt)).cpu().numpy(),
+                                  oracle.matvec_t(pr, xr))
 
 
 SHAPES = [(1, 1), (1, 40), (40, 1), (32, 7), (64, 100), (37, 33), (96, 2100), (130, 257),
@@ -103,6 +120,69 @@ def test_transposed_split_rows(shape, b):
     rng = np.random.default_rng(b * 7 + shape[0])
     A = rand_matrix(rng, *shape, b, b % 2 == 1)
     check_products(c.compress(dev(A)), A, rng)
+
+
+@pytest.mark.parametrize("b", [1, 3, 7, 8, 9, 12, 13, 14, 15])
+def test_transposed_narrow_extremes(b):
+    """The 32-bit partial sums at their bound: every field at its largest
+    magnitude and every x at -2^15 (then 2^15 - 1), with enough rows per wave
+    that the wider fields fold their partial sums several times."""
+    c = ccm()
+    rows, cols = 40000, 64
+    for signed in (False, True):
+        a = -(1 << (b - 1)) if signed else (1 << b) - 1
+        A = np.full((rows, cols), a, dtype=np.int64)
+        A[0, 0] = 0 if not signed else (1 << (b - 1)) - 1  # keep the width at b
+        g = c.compress(dev(A))
+        assert g.bits == b and g.is_signed == signed
+        pr = oracle.compress(A)
+        for xv in (-(1 << 15), (1 << 15) - 1):
+            x = np.full(rows, xv, dtype=np.int64)
+            assert np.array_equal(c.matvec_t(g, dev(x, torch.int32)).cpu().numpy(),
+                                  oracle.matvec_t(pr, x)), (signed, xv)
+
+
+@pytest.mark.parametrize("b", [7, 8])
+def test_transposed_long_waves(b):
+    """Rows per wave past the 32-bit run length (b <= 8 takes 64-bit products
+    then, whatever x)."""
+    c = ccm()
+    rng = np.random.default_rng(40 + b)
+    A = rand_matrix(rng, 300000, 40, b, False)
+    g = c.compress(dev(A))
+    pr = oracle.compress(A)
+    x = narrow_x(rng, A.shape[0])
+    assert np.array_equal(c.matvec_t(g, dev(x, torch.int32)).cpu().numpy(), oracle.matvec_t(pr, x))
+
+
+@pytest.mark.parametrize("shape", [(5000, 70), (4096, 4096), (777, 5000)], ids=str)
+def test_transposed_without_scratch(shape):
+    """ccm_matvec_t with scratch NULL (row splits added with atomics) and with
+    one scratch buffer reused by consecutive calls, against the oracle."""
+    import ctypes
+    c = ccm()
+    rng = np.random.default_rng(shape[1])
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    nb = None
+    scratch = None
+    for b in (1, 12, 40):
+        A = rand_matrix(rng, *shape, b, True)
+        g = c.compress(dev(A))
+        pr = oracle.compress(A)
+        if scratch is None:
+            nb = int(c.lib.ccm_matvec_t_scratch_bytes(ctypes.byref(g.desc)))
+            assert nb == 8 * 32 * shape[1]
+            scratch = torch.empty(nb // 8, dtype=torch.int64, device="cuda")
+        for xr in (narrow_x(rng, shape[0]),
+                   rng.integers(-(1 << 31), (1 << 31) - 1, size=shape[0], dtype=np.int64)):
+            x = dev(xr, torch.int32)
+            want = oracle.matvec_t(pr, xr)
+            for sp, sb in ((None, 0), (ctypes.c_void_p(scratch.data_ptr()), nb)):
+                y = torch.full((shape[1],), 7, dtype=torch.int64, device="cuda")
+                rc = c.lib.ccm_matvec_t(ctypes.byref(g.desc), ctypes.c_void_p(x.data_ptr()),
+                                        c.I32, ctypes.c_void_p(y.data_ptr()), sp, sb, s)
+                assert rc == 0
+                assert np.array_equal(y.cpu().numpy(), want), (b, sp is None)
 
 
 def test_transpose_view_and_ops():
