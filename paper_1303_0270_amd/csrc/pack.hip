@@ -233,60 +233,79 @@ __global__ __launch_bounds__(256) void k_ewise_pack(int op, PackedOperand a, Pac
 // (from the headers) all fit the value type VT (int32_t or uint32_t): the sum
 // or product is then exact in VT and cannot overflow, so every element costs
 // a few 32-bit instructions instead of 64-bit arithmetic with overflow tests.
-template <typename VT>
-__device__ __forceinline__ VT ewise_value32(int op, VT a, VT b, VT scalar) {
-  return op == EW_ADD ? (VT)(a + b) : (VT)(a * scalar);
+template <int OP, typename VT>
+__device__ __forceinline__ VT ewise_value32(VT a, VT b, VT scalar) {
+  return OP == EW_ADD ? (VT)(a + b) : (VT)(a * scalar);
 }
 
-template <typename VT>
-__global__ __launch_bounds__(256) void k_ewise_range32(int op, PackedOperand a, PackedOperand b,
+// The 32 results of group g (every element below n, or zero past it when
+// CHECK: only the last group of a ragged matrix needs the test).
+template <int OP, typename VT, bool CHECK>
+__device__ __forceinline__ void ewise_group32(const PackedOperand &a, const PackedOperand &b,
+                                              VT sc, uint64_t g, uint64_t n, uint32_t *vc) {
+  codec::decode32_rt(a.w + g * (uint64_t)a.bits, a.bits, a.sgn, vc);
+  if constexpr (OP == EW_ADD) {
+    uint32_t vb[kGroup];
+    codec::decode32_rt(b.w + g * (uint64_t)b.bits, b.bits, b.sgn, vb);
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i)
+      vc[i] = (uint32_t)ewise_value32<OP, VT>((VT)vc[i], (VT)vb[i], sc);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) vc[i] = (uint32_t)ewise_value32<OP, VT>((VT)vc[i], (VT)0, sc);
+  }
+  if constexpr (CHECK) {
+    const uint64_t left = n - g * kGroup;  // < 32 here
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) vc[i] = (uint64_t)i < left ? vc[i] : 0u;
+  }
+}
+
+template <int OP, typename VT>
+__global__ __launch_bounds__(256) void k_ewise_range32(PackedOperand a, PackedOperand b,
                                                        int64_t scalar, uint64_t n,
                                                        RangeSlot *slot) {
   VT lo = std::numeric_limits<VT>::max(), hi = std::numeric_limits<VT>::min();
   const VT sc = (VT)scalar;
-  const uint64_t ngroups = (n + kGroup - 1) / kGroup;
-  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups;
-       g += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t va[kGroup], vb[kGroup];
-    codec::decode32_rt(a.w + g * (uint64_t)a.bits, a.bits, a.sgn, va);
-    if (op == EW_ADD) codec::decode32_rt(b.w + g * (uint64_t)b.bits, b.bits, b.sgn, vb);
-    const uint64_t e0 = g * kGroup;
+  const uint64_t nfull = n / kGroup;
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint64_t g = tid; g < nfull; g += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t vc[kGroup];
+    ewise_group32<OP, VT, false>(a, b, sc, g, n, vc);
 #pragma unroll
     for (int i = 0; i < kGroup; ++i) {
-      if (e0 + i < n) {
-        const VT c = ewise_value32<VT>(op, (VT)va[i], op == EW_ADD ? (VT)vb[i] : (VT)0, sc);
-        lo = c < lo ? c : lo;
-        hi = c > hi ? c : hi;
-      }
+      lo = (VT)vc[i] < lo ? (VT)vc[i] : lo;
+      hi = (VT)vc[i] > hi ? (VT)vc[i] : hi;
+    }
+  }
+  if (tid == 0 && nfull * kGroup < n) {  // the ragged last group
+    uint32_t vc[kGroup];
+    ewise_group32<OP, VT, true>(a, b, sc, nfull, n, vc);
+    for (uint64_t i = 0; i < n - nfull * kGroup; ++i) {
+      lo = (VT)vc[i] < lo ? (VT)vc[i] : lo;
+      hi = (VT)vc[i] > hi ? (VT)vc[i] : hi;
     }
   }
   block_range_commit((int64_t)lo, (int64_t)hi, 0, slot);
 }
 
-template <typename VT>
-__global__ __launch_bounds__(256) void k_ewise_pack32(int op, PackedOperand a, PackedOperand b,
+template <int OP, typename VT>
+__global__ __launch_bounds__(256) void k_ewise_pack32(PackedOperand a, PackedOperand b,
                                                       int64_t scalar, uint64_t n, int out_bits,
                                                       uint32_t *__restrict__ out, uint64_t cap32,
                                                       uint64_t ngroups_out) {
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ngroups_out) return;
   const uint64_t w0 = g * (uint64_t)out_bits;
-  const uint64_t ngroups_in = (n + kGroup - 1) / kGroup;
+  const uint64_t nfull = n / kGroup;
   uint32_t vc[kGroup];
-  if (g >= ngroups_in) {
+  if (g < nfull) {
+    ewise_group32<OP, VT, false>(a, b, (VT)scalar, g, n, vc);
+  } else if (g * kGroup < n) {
+    ewise_group32<OP, VT, true>(a, b, (VT)scalar, g, n, vc);
+  } else {
 #pragma unroll
     for (int i = 0; i < kGroup; ++i) vc[i] = 0;
-  } else {
-    uint32_t vb[kGroup];
-    codec::decode32_rt(a.w + g * (uint64_t)a.bits, a.bits, a.sgn, vc);
-    if (op == EW_ADD) codec::decode32_rt(b.w + g * (uint64_t)b.bits, b.bits, b.sgn, vb);
-    const uint64_t e0 = g * kGroup;
-    const VT sc = (VT)scalar;
-#pragma unroll
-    for (int i = 0; i < kGroup; ++i)
-      vc[i] = e0 + i < n ? (uint32_t)ewise_value32<VT>(op, (VT)vc[i],
-                                                        op == EW_ADD ? (VT)vb[i] : (VT)0, sc)
-                         : 0u;
   }
   codec::encode32_rt(vc, out_bits, out + w0, cap32 - w0);
 }
@@ -403,10 +422,14 @@ hipError_t launch_ewise_range(int op, PackedOperand a, PackedOperand b, int64_t 
                               uint64_t n, int vclass, RangeSlot *slot, hipStream_t s) {
   const uint64_t ngroups = (n + kGroup - 1) / kGroup;
   const unsigned grid = grid_for(ngroups, 256, 2048);
-  if (vclass == EW_I32)
-    k_ewise_range32<int32_t><<<grid, 256, 0, s>>>(op, a, b, scalar, n, slot);
+  if (vclass == EW_I32 && op == EW_ADD)
+    k_ewise_range32<EW_ADD, int32_t><<<grid, 256, 0, s>>>(a, b, scalar, n, slot);
+  else if (vclass == EW_I32)
+    k_ewise_range32<EW_SCALE, int32_t><<<grid, 256, 0, s>>>(a, b, scalar, n, slot);
+  else if (vclass == EW_U32 && op == EW_ADD)
+    k_ewise_range32<EW_ADD, uint32_t><<<grid, 256, 0, s>>>(a, b, scalar, n, slot);
   else if (vclass == EW_U32)
-    k_ewise_range32<uint32_t><<<grid, 256, 0, s>>>(op, a, b, scalar, n, slot);
+    k_ewise_range32<EW_SCALE, uint32_t><<<grid, 256, 0, s>>>(a, b, scalar, n, slot);
   else
     k_ewise_range<<<grid, 256, 0, s>>>(op, a, b, scalar, n, slot);
   return hipGetLastError();
@@ -417,12 +440,18 @@ hipError_t launch_ewise_pack(int op, PackedOperand a, PackedOperand b, int64_t s
                              hipStream_t s) {
   const uint64_t ngroups_out = (cap32 + out_bits - 1) / out_bits;
   const unsigned grid = grid_for(ngroups_out, 256, 0x7fffffffu);
-  if (vclass == EW_I32 && out_bits <= 32)
-    k_ewise_pack32<int32_t><<<grid, 256, 0, s>>>(op, a, b, scalar, n, out_bits, out, cap32,
-                                                  ngroups_out);
+  if (vclass == EW_I32 && out_bits <= 32 && op == EW_ADD)
+    k_ewise_pack32<EW_ADD, int32_t><<<grid, 256, 0, s>>>(a, b, scalar, n, out_bits, out, cap32,
+                                                          ngroups_out);
+  else if (vclass == EW_I32 && out_bits <= 32)
+    k_ewise_pack32<EW_SCALE, int32_t><<<grid, 256, 0, s>>>(a, b, scalar, n, out_bits, out, cap32,
+                                                            ngroups_out);
+  else if (vclass == EW_U32 && out_bits <= 32 && op == EW_ADD)
+    k_ewise_pack32<EW_ADD, uint32_t><<<grid, 256, 0, s>>>(a, b, scalar, n, out_bits, out, cap32,
+                                                           ngroups_out);
   else if (vclass == EW_U32 && out_bits <= 32)
-    k_ewise_pack32<uint32_t><<<grid, 256, 0, s>>>(op, a, b, scalar, n, out_bits, out, cap32,
-                                                   ngroups_out);
+    k_ewise_pack32<EW_SCALE, uint32_t><<<grid, 256, 0, s>>>(a, b, scalar, n, out_bits, out,
+                                                             cap32, ngroups_out);
   else
     k_ewise_pack<<<grid, 256, 0, s>>>(op, a, b, scalar, n, out_bits, out, cap32, ngroups_out);
   return hipGetLastError();

@@ -165,6 +165,22 @@ def test_scale_class_edges(r, s):
     assert_same_packed(c.scale(c.compress(dev(A)), s), ref)
 
 
+@pytest.mark.parametrize("shape", [(1, 5), (5, 77), (70, 130), (3, 96)], ids=str)
+def test_elementwise_extremes_in_last_group(shape):
+    """The result's minimum and maximum only in the last (ragged, when n % 32
+    != 0) group: the range pass must see them there."""
+    c = ccm()
+    rng = np.random.default_rng(shape[1])
+    A = rng.integers(0, 100, size=shape, dtype=np.int64)
+    B = rng.integers(0, 100, size=shape, dtype=np.int64)
+    A.flat[-1] = 1 << 20
+    B.flat[-2 if A.size > 1 else -1] = -5
+    ref = oracle.add(oracle.compress(A), oracle.compress(B))
+    assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B))), ref)
+    for s in (3, -3):
+        assert_same_packed(c.scale(c.compress(dev(A)), s), oracle.scale(oracle.compress(A), s))
+
+
 def test_add_overflow_and_shape():
     c = ccm()
     a = c.compress(dev(np.array([[2**63 - 1, 0]])))
