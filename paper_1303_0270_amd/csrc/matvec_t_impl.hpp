@@ -148,18 +148,18 @@ __global__ __launch_bounds__(64 * waves<B>()) void k_matvec_t(const uint32_t *__
   uint32_t *xl = reinterpret_cast<uint32_t *>(lds4) + (size_t)wave * 256;  // [chunk slot][lo, hi][64]
   uint4 *mybuf = lds4 + xlds_bytes<B>() / 16 + (size_t)wave * NB * NL * 64;
 
-  // Copies row r's stretch (from first_word(r), a 16-byte boundary) into
-  // buffer `buf`.  The wave's earlier LDS reads complete first (and the compiler may not move
-  // them past this point): the copy overwrites the words read NB - 1 rows
-  // ago.
-  auto first_word = [&](int64_t r) -> uint64_t {
-    return ((((uint64_t)r * (uint64_t)cols + (uint64_t)g0 * kGroup) * B) >> 5) & ~3ull;
-  };
-  auto stage = [&](int64_t r, int buf) {
+  // Row r's stretch starts at stream bit (r cols + 32 g0) b and spans `span`
+  // bits; the rows of a wave are kWaves apart, `dbit` bits.
+  const uint64_t span = ((uint64_t)cend - (uint64_t)g0 * kGroup) * B;
+  const uint64_t dbit = (uint64_t)kWaves * (uint64_t)cols * B;
+  // Copies the stretch starting at stream bit `bit` (from the 16-byte
+  // boundary at or below it) into buffer `buf`.  The wave's earlier LDS reads
+  // complete first (and the compiler may not move them past this point): the
+  // copy overwrites the words read NB - 1 rows ago.
+  auto stage = [&](uint64_t bit, int buf) {
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    const uint64_t e = ((uint64_t)r * (uint64_t)cols + (uint64_t)cend) * B;
-    const uint64_t ws = first_word(r);
-    const uint64_t we = (e >> 5) + 2u;
+    const uint64_t ws = (bit >> 5) & ~3ull;
+    const uint64_t we = ((bit + span) >> 5) + 2u;
     const int nvec = (int)((we - ws + 3u) >> 2);
     const uint4 *src = (const uint4 *)(w + ws);
     uint4 *dst = mybuf + (size_t)buf * NL * 64;
@@ -182,7 +182,6 @@ __global__ __launch_bounds__(64 * waves<B>()) void k_matvec_t(const uint32_t *__
 #pragma unroll
   for (int j = 0; j < kGroup; ++j) acc[j] = 0;
 
-  const int64_t g = g0 + lane;
   const int64_t r0 = rb + wave;
   // this wave's rows: r0, r0 + kWaves, ... < re
   const int64_t nrows = r0 < re ? (re - r0 + kWaves - 1) / kWaves : 0;
@@ -240,15 +239,16 @@ __global__ __launch_bounds__(64 * waves<B>()) void k_matvec_t(const uint32_t *__
     // would make the compiler wait for the whole queue at every row.)
     if (nrows > 0) stage_x(0);
     if (nrows > 64) stage_x(1);
+    uint64_t bit = ((uint64_t)r0 * (uint64_t)cols + (uint64_t)g0 * kGroup) * B;  // row i
 #pragma unroll
     for (int q = 0; q < NB - 1; ++q)
-      if (q < nrows) stage(r0 + (int64_t)q * kWaves, q);
-    for (int64_t i = 0; i < nrows; ++i) {
-      const int64_t r = r0 + i * kWaves;
+      if (q < nrows) stage(bit + (uint64_t)q * dbit, q);
+    uint64_t abit = bit + (uint64_t)(NB - 1) * dbit;  // row i + NB - 1
+    for (int64_t i = 0; i < nrows; ++i, bit += dbit, abit += dbit) {
       const int cur = (int)(i % NB);
       if (i > 0 && (i & 63) == 0 && i + 64 < nrows) stage_x((i >> 6) + 1);
       const int64_t ia = i + NB - 1;  // the row copied ahead now
-      if (ia < nrows) stage(r0 + ia * kWaves, (int)(ia % NB));
+      if (ia < nrows) stage(abit, (int)(ia % NB));
       // copies issued after row r's: rows i+1 .. min(ia, nrows-1)
       const int64_t later = (ia < nrows ? ia : nrows - 1) - i;
       wait_rows<NL, NB>((int)later);
@@ -258,11 +258,11 @@ __global__ __launch_bounds__(64 * waves<B>()) void k_matvec_t(const uint32_t *__
         xr = (XT)(((uint64_t)xw[64] << 32) | xw[0]);
       else
         xr = (XT)xw[0];
-      const uint64_t ws = first_word(r);
+      // group g0 + lane starts 32 b lane bits after the row's first: word
+      // (bit / 32) % 4 + b lane of the copy, at the row's bit offset
       const uint32_t *buf = (const uint32_t *)(mybuf + (size_t)cur * NL * 64);
-      const uint64_t gs = ((uint64_t)r * (uint64_t)cols + (uint64_t)g * kGroup) * B;
-      const uint32_t off = (uint32_t)(gs & 31u);  // the same for every group of the row
-      const uint32_t *gw = buf + ((gs >> 5) - ws);
+      const uint32_t off = (uint32_t)bit & 31u;
+      const uint32_t *gw = buf + (((uint32_t)(bit >> 5)) & 3u) + lane * B;
       uint32_t wd[B + 1];
 #pragma unroll
       for (int k = 0; k <= B; ++k) wd[k] = gw[k];
