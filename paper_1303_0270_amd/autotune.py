@@ -1,5 +1,5 @@
 """Autotuner for the batched matvec: per field width, picks the rows per work
-item ("tile_rows") and the rows each lane keeps in flight (1 or 2) that give
+item ("tile_rows") and the rows each lane keeps in flight (1, 2 or 4) that give
 the fastest graph launch on a synthetic batch of that width, and writes the
 table read by ccm_batch_create.
 
@@ -76,7 +76,7 @@ def main(argv=None):
         nbytes = sum(8 * m.words for m in mats)
         best = None
         for tile in TILE_ROWS:
-            for rif in ((1, 2) if b <= 8 else (1,)):
+            for rif in ((1, 2, 4) if b <= 8 else (1, 2) if b <= 16 else (1,)):
                 path = os.path.join(tmpdir, f"t{b}_{tile}_{rif}.json")
                 with open(path, "w") as f:
                     json.dump({"widths": {str(b): {"tile_rows": tile, "rows_in_flight": rif}}}, f)

@@ -60,15 +60,12 @@ __device__ __forceinline__ int64_t seg_sum(int64_t v, int L) {
   return (int64_t)u;
 }
 
+// Dot product of one group held in w[0..B] (B + 1 words from the group's
+// first word), funnel-shifted by the row's bit offset s (0 leaves the words).
 template <int B, bool SGN, bool FAST>
-__device__ __forceinline__ uint64_t row_group_dot(const uint32_t *gp, int s, const int32_t *xg) {
-  uint32_t w[B + 1];
+__device__ __forceinline__ uint64_t group_words_dot(uint32_t *w, int s, const int32_t *xg) {
 #pragma unroll
-  for (int k = 0; k <= B; ++k) w[k] = gp[k];
-  if (s != 0) {
-#pragma unroll
-    for (int k = 0; k < B; ++k) w[k] = __builtin_amdgcn_alignbit(w[k + 1], w[k], s);
-  }
+  for (int k = 0; k < B; ++k) w[k] = __builtin_amdgcn_alignbit(w[k + 1], w[k], s);
   if constexpr (FAST && B <= 16)
     return mv::group_dot_small<B, SGN>(w, xg);
   else
@@ -77,6 +74,10 @@ __device__ __forceinline__ uint64_t row_group_dot(const uint32_t *gp, int s, con
 
 // Rows [row0, row0+nrows) of matrix m; x staged in xs.  FAST: every x of the
 // matrix is in int16 range (exact int32 runs, see the single-matrix kernel).
+// Each lane has RIF rows in flight: the words of all of them are requested
+// before any is decoded, with rows past the item clamped to its last row
+// (decoded and dropped), so the loads are unconditional and the compiler
+// waits for them together instead of one row at a time.
 template <int B, bool SGN, int RIF, bool FAST>
 __device__ __forceinline__ void item_rows(const Mat &m, int row0, int nrows, const int32_t *xs) {
   const int ng = (int)((m.cols + kGroup - 1) / kGroup);
@@ -88,21 +89,28 @@ __device__ __forceinline__ void item_rows(const Mat &m, int row0, int nrows, con
   const int rows_per_pass = (kThreads / 64) * sub_per_wave * RIF;
   for (int base = 0; base < nrows; base += rows_per_pass) {
     uint64_t acc[RIF];
-    int64_t rr[RIF];
+    int rr[RIF];
 #pragma unroll
     for (int q = 0; q < RIF; ++q) {
       acc[q] = 0;
       rr[q] = base + ((wave * RIF + q) * sub_per_wave + sub);
     }
     for (int j = j0; j < ng; j += L) {
+      uint32_t w[RIF][B + 1];
+      int sh[RIF];
 #pragma unroll
       for (int q = 0; q < RIF; ++q) {
-        if (rr[q] < nrows) {
-          const int64_t r = row0 + rr[q];
-          const uint64_t bit = ((uint64_t)r * (uint64_t)m.cols + (uint64_t)j * kGroup) * B;
-          acc[q] += row_group_dot<B, SGN, FAST>(m.w + (bit >> 5), (int)(bit & 31u),
-                                                xs + j * kPitch);
-        }
+        const int64_t r = row0 + (rr[q] < nrows ? rr[q] : nrows - 1);
+        const uint64_t bit = ((uint64_t)r * (uint64_t)m.cols + (uint64_t)j * kGroup) * B;
+        const uint32_t *gp = m.w + (bit >> 5);
+        sh[q] = (int)(bit & 31u);
+#pragma unroll
+        for (int k = 0; k <= B; ++k) w[q][k] = gp[k];
+      }
+#pragma unroll
+      for (int q = 0; q < RIF; ++q) {
+        const uint64_t d = group_words_dot<B, SGN, FAST>(w[q], sh[q], xs + j * kPitch);
+        acc[q] += rr[q] < nrows ? d : 0u;
       }
     }
 #pragma unroll
@@ -128,12 +136,24 @@ __device__ void item_rows_rt(const Mat &m, int row0, int nrows, const int32_t *x
   }
 }
 
-// Two rows in flight per lane only pay off (and fit in registers) for the
-// small widths.
+// Rows in flight per lane: up to 4 for widths to 8, 2 to 16, 1 above (the
+// words of every row in flight are held in registers, and one kernel holds
+// every width's code, so the widest case sets the register count).
+template <int B>
+constexpr int max_rif() {
+  return B <= 8 ? 4 : B <= 16 ? 2 : 1;
+}
+
 template <int B, bool SGN, bool FAST>
 __device__ __forceinline__ void item_width(const Mat &m, const Item &it, const int32_t *xs) {
-  if constexpr (B <= 8) {
-    if (it.rif == 2) {
+  if constexpr (max_rif<B>() >= 4) {
+    if (it.rif >= 4) {
+      item_rows<B, SGN, 4, FAST>(m, it.row0, it.nrows, xs);
+      return;
+    }
+  }
+  if constexpr (max_rif<B>() >= 2) {
+    if (it.rif >= 2) {
       item_rows<B, SGN, 2, FAST>(m, it.row0, it.nrows, xs);
       return;
     }
@@ -249,7 +269,7 @@ struct TuneEntry {
 TuneEntry default_tune(int bits) {
   TuneEntry t;
   t.tile_rows = bits <= 4 ? 512 : bits <= 12 ? 256 : 128;
-  t.rif = bits <= 8 ? 2 : 1;
+  t.rif = bits <= 8 ? 4 : bits <= 16 ? 2 : 1;
   return t;
 }
 
@@ -278,7 +298,7 @@ void load_tune(const char *path, TuneEntry table[65]) {
     };
     field("\"tile_rows\"", &table[b].tile_rows);
     field("\"rows_in_flight\"", &table[b].rif);
-    if (table[b].rif != 2) table[b].rif = 1;
+    if (table[b].rif != 2 && table[b].rif != 4) table[b].rif = 1;
     if (table[b].tile_rows < 1) table[b].tile_rows = 1;
   }
 }
