@@ -182,17 +182,22 @@ __device__ __forceinline__ void dispatch(const Mat &m, const Item &it, const int
 __global__ void k_counter_reset(int *counter) { *counter = 0; }
 
 // Every block loops until the shared counter passes the item count; the exit
-// test is block-uniform (item index broadcast through LDS).
+// test is block-uniform (item index broadcast through LDS).  A block stops
+// at its first index past the end, so every block exits.
 __global__ __launch_bounds__(kThreads) void k_batch(const Mat *__restrict__ mats,
                                                     const Item *__restrict__ items, int nitems,
                                                     int *counter) {
   __shared__ __align__(16) int32_t xs[(kMaxCols / kGroup) * kPitch];
   __shared__ int s_item;
+  // The next item's index is requested when an item starts and read when it
+  // ends, so the atomic's round trip overlaps the item's work.
+  int next = 0;
+  if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
     const int it = s_item;
     if (it >= nitems) break;
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
     const Item item = items[it];
     const Mat m = mats[item.mat];
     const int ng = (int)((m.cols + kGroup - 1) / kGroup);
@@ -228,6 +233,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const Mat *__restrict__ mats
         dispatch<false, false>(m, item, xs);
     }
     __syncthreads();  // xs and s_item are rewritten by the next item
+    if (threadIdx.x == 0) s_item = next;
   }
 }
 
