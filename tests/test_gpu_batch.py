@@ -105,6 +105,30 @@ def test_tuning_table_is_used(tmp_path):
         assert np.array_equal(y.cpu().numpy(), oracle.matvec(oracle.compress(A), x))
 
 
+@pytest.mark.parametrize("rif", [1, 2, 4])
+@pytest.mark.parametrize("tile", [5, 100])
+def test_rows_in_flight_and_ragged_items(tmp_path, rif, tile):
+    """Every rows-in-flight setting (capped per width inside the kernel) with
+    items shorter than a pass (rows past an item are read clamped and
+    dropped) and longer ones."""
+    c = ccm()
+    rng = np.random.default_rng(50 + rif + tile)
+    widths = [1, 2, 3, 4, 7, 8, 9, 12, 16, 17, 24, 31, 40]
+    mats, packed, xs, xh = make_batch(rng, len(widths) * 2, 260, widths)
+    table = tmp_path / "tune.json"
+    table.write_text(json.dumps({"widths": {str(b): {"tile_rows": tile, "rows_in_flight": rif}
+                                            for b in widths}}))
+    batch = c.Batch(packed, tune_json=str(table))
+    ys = [torch.full((m.rows,), 3, dtype=torch.int64, device="cuda") for m in packed]
+    batch.set_io(xs, ys)
+    batch.run(use_graph=True)
+    torch.cuda.synchronize()
+    for A, m, x, y in zip(mats, packed, xh, ys):
+        want = oracle.matvec(oracle.compress(A), x)
+        assert np.array_equal(y.cpu().numpy(), want), (m.rows, m.cols, m.bits, rif, tile)
+    batch.close()
+
+
 def test_batched_workload_matches_per_call_and_oracle():
     """The batched workload at full size (4096 matrices, 32..2048 x 32..2048,
     widths 1..24): every y equals the per-call path; 12 small sampled
