@@ -100,17 +100,29 @@ __global__ __launch_bounds__(kCmThreads) void k_compress_cm_gen(const T *__restr
   }
 }
 
-// Column c's total of the row splits' partial sums (coalesced across c).
+// Column totals of the row splits' partial sums.  Block = 64 columns x 4
+// waves: wave q adds splits q, q + 4, ... of its lane's column (loads
+// coalesced across the columns, all of a lane's in flight together), and the
+// four partials meet in LDS.
 __global__ __launch_bounds__(256) void k_sum_splits(const int64_t *__restrict__ part,
                                                     int64_t splits, int64_t cols,
                                                     int64_t *__restrict__ y) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < (uint64_t)cols;
-       c += stride) {
+  __shared__ uint64_t red[4][64];
+  const int q = threadIdx.x >> 6, cl = threadIdx.x & 63;
+  for (uint64_t c0 = (uint64_t)blockIdx.x * 64; c0 < (uint64_t)cols;
+       c0 += (uint64_t)gridDim.x * 64) {
+    const uint64_t c = c0 + cl;
     uint64_t t = 0;
+    if (c < (uint64_t)cols) {
 #pragma unroll 8
-    for (int64_t k = 0; k < splits; ++k) t += (uint64_t)part[(uint64_t)k * (uint64_t)cols + c];
-    y[c] = (int64_t)t;
+      for (int64_t k = q; k < splits; k += 4)
+        t += (uint64_t)part[(uint64_t)k * (uint64_t)cols + c];
+    }
+    red[q][cl] = t;
+    __syncthreads();
+    if (q == 0 && c < (uint64_t)cols)
+      y[c] = (int64_t)(red[0][cl] + red[1][cl] + red[2][cl] + red[3][cl]);
+    __syncthreads();
   }
 }
 
@@ -163,7 +175,7 @@ hipError_t launch_matvec_t(const uint32_t *w, int64_t rows, int64_t cols, int bi
 
 hipError_t launch_sum_splits(const int64_t *part, int64_t splits, int64_t cols, int64_t *y,
                              hipStream_t s) {
-  uint64_t g = ((uint64_t)cols + 255) / 256;
+  uint64_t g = ((uint64_t)cols + 63) / 64;
   g = g < 1 ? 1 : (g > 65536 ? 65536 : g);
   k_sum_splits<<<(unsigned)g, 256, 0, s>>>(part, splits, cols, y);
   return hipGetLastError();
