@@ -48,7 +48,8 @@ constexpr int kPanelGroups = 64;
 constexpr size_t kMaxLds = 160 * 1024 - 64;
 
 // Waves per block: 16 for narrow fields (short rows, so more waves share a
-// panel's atomics), 8 otherwise (the wide decode needs more registers).
+// panel's end-of-block reduction), 8 otherwise (the wide decode needs more
+// registers).
 template <int B>
 constexpr int waves() {
   return B <= 8 ? 16 : 8;
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(64 * waves<B>()) void k_matvec_t(const uint32_t *__
       int bad = 0;
       for (int64_t i = lane; i < nrows; i += 64) {
         const int64_t xv = (int64_t)x[r0 + i * kWaves];
-        bad |= (uint64_t)(xv + 32768) >= 65536u;
+        bad |= ((uint64_t)xv + 32768u) >= 65536u;
       }
       narrow = !__any(bad);
     }
@@ -219,16 +220,16 @@ __global__ __launch_bounds__(64 * waves<B>()) void k_matvec_t(const uint32_t *__
   // The row walk; NARROW: products into 32-bit partial sums.
   auto walk = [&](auto narrow_tag) {
     constexpr bool NARROW = decltype(narrow_tag)::value;
-    int32_t part[NARROW ? kGroup : 1];
+    int32_t psum[NARROW ? kGroup : 1];
 #pragma unroll
-    for (int j = 0; j < (NARROW ? kGroup : 1); ++j) part[j] = 0;
-    int nrun = 0;  // rows in part (wave-uniform)
+    for (int j = 0; j < (NARROW ? kGroup : 1); ++j) psum[j] = 0;
+    int nrun = 0;  // rows in psum (wave-uniform)
     auto fold = [&]() {
       if constexpr (NARROW) {
 #pragma unroll
         for (int j = 0; j < kGroup; ++j) {
-          acc[j] += (int64_t)part[j];
-          part[j] = 0;
+          acc[j] += (int64_t)psum[j];
+          psum[j] = 0;
         }
       }
       nrun = 0;
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(64 * waves<B>()) void k_matvec_t(const uint32_t *__
           const int sh = o + B <= 32 ? o : 0;
           const int32_t f = SGN ? __builtin_amdgcn_sbfe((int32_t)src, sh, B)
                                 : (int32_t)__builtin_amdgcn_ubfe(src, sh, B);
-          part[j] = mad24_t(f, xs, part[j]);
+          psum[j] = mad24_t(f, xs, psum[j]);
         }
         if constexpr (kFoldInLoop)
           if (++nrun == RUN) fold();
