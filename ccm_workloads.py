@@ -65,6 +65,19 @@ def uniform(seed: int, stream: int, start: int, count: int, lo: int, hi: int) ->
     return (off.astype(np.int64) + np.int64(lo)).astype(np.int64)
 
 
+def uniform_at(seed: int, stream: int, idx: np.ndarray, lo: int, hi: int) -> np.ndarray:
+    """Draws number ``idx`` (any int64 array) of stream ``stream``, uniform in
+    [lo, hi): the same values ``uniform`` gives at those positions."""
+    span = hi - lo
+    if not (1 <= span <= 2**32):
+        raise ValueError("span must be in [1, 2^32]")
+    ctr = (np.uint64(stream) << np.uint64(STREAM_SHIFT)) + np.asarray(idx, dtype=np.uint64)
+    h = splitmix64(seed, ctr)
+    with np.errstate(over="ignore"):
+        off = ((h >> np.uint64(32)) * np.uint64(span)) >> np.uint64(32)
+    return (off.astype(np.int64) + np.int64(lo)).astype(np.int64)
+
+
 def uniform_matrix(seed: int, stream: int, rows: int, cols: int, lo: int, hi: int) -> np.ndarray:
     return uniform(seed, stream, 0, rows * cols, lo, hi).reshape(rows, cols)
 
@@ -93,6 +106,11 @@ class MatrixSpec:
 
     def rows_slice(self, r0: int, r1: int) -> np.ndarray:
         return matrix_rows(self.seed, self.stream, self.cols, r0, r1, self.lo, self.hi)
+
+    def column(self, j: int) -> np.ndarray:
+        """Column j (rows values)."""
+        idx = np.arange(self.rows, dtype=np.int64) * self.cols + j
+        return uniform_at(self.seed, self.stream, idx, self.lo, self.hi)
 
 
 @dataclass(frozen=True)

@@ -36,3 +36,13 @@ def test_workload_shapes():
     assert all(1 <= p.bits <= 20 and p.rows * p.cols >= 1 for p in pool)
     total = sum(64 + 8 * ((p.rows * p.cols * p.bits) // 64 + 1) for p in pool)
     assert total >= 5e7
+
+
+def test_column_and_uniform_at_match_the_dense_matrix():
+    spec = W.MatrixSpec(37, 53, -9, 40, W.seed_for(2, 0), 5)
+    A = spec.dense()
+    for j in (0, 1, 52, 17):
+        assert np.array_equal(spec.column(j), A[:, j])
+    idx = np.array([0, 5, 1960, 37 * 53 - 1])
+    assert np.array_equal(W.uniform_at(spec.seed, spec.stream, idx, spec.lo, spec.hi),
+                          A.reshape(-1)[idx])
