@@ -243,3 +243,31 @@ def test_full_size_identity(k):
     lhs = sum(int(u) * int(v) for u, v in zip(z, aty)) & m
     rhs = sum(int(u) * int(v) for u, v in zip(x, az)) & m
     assert lhs == rhs
+
+
+@pytest.mark.parametrize("k,signed", [(1, False), (12, True), (31, False)])
+def test_full_size_sampled_columns(k, signed):
+    """y = A^T x on the 16384 x 16384 sweep matrix with the sweep's x, launched
+    as the benchmark launches it (pre-marshalled, scratch for the row splits):
+    sampled columns against the oracle's A^T x of that column alone, the
+    column regenerated on the host."""
+    c = ccm()
+    a_s, _, x_s, _ = W.sweep(k, signed)
+    A = c.generate(a_s.rows, a_s.cols, a_s.lo, a_s.hi, a_s.seed, a_s.stream)
+    x = torch.empty(a_s.rows, dtype=torch.int32, device="cuda")
+    c.fill_uniform(x, x_s.lo, x_s.hi, x_s.seed, x_s.stream)
+    y = torch.full((a_s.cols,), 5, dtype=torch.int64, device="cuda")
+    go = c.matvec_launcher(A, x, y, transposed=True)
+    go()
+    go()  # a second call reuses the scratch
+    got = y.cpu().numpy()
+    xh = x_s.dense()
+    assert np.array_equal(x.cpu().numpy(), xh)
+    rng = np.random.default_rng(k)
+    cols = sorted({0, 1, 31, 32, 2047, 2048, a_s.cols - 1} |
+                  {int(j) for j in rng.integers(0, a_s.cols, 5)})
+    for j in cols:
+        col = a_s.column(j).reshape(-1, 1)
+        want = oracle.matvec_t(oracle.compress(col), xh)
+        assert got[j] == want[0], j
+
