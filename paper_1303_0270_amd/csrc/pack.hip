@@ -289,14 +289,19 @@ __global__ __launch_bounds__(256) void k_ewise_range32(PackedOperand a, PackedOp
   block_range_commit((int64_t)lo, (int64_t)hi, 0, slot);
 }
 
+// Packing pass, 32-bit results: thread t of block x packs group 256 x + t.
+// The block's groups are consecutive, so its output is one contiguous run
+// of 256 out_bits words: each thread encodes into LDS and the block writes
+// the run with coalesced 16-byte stores (a thread storing its own group
+// directly issues out_bits stores of 64 lanes each at a stride of out_bits
+// words).  Words at or past cap32 are dropped; groups past n are zeros.
 template <int OP, typename VT>
 __global__ __launch_bounds__(256) void k_ewise_pack32(PackedOperand a, PackedOperand b,
                                                       int64_t scalar, uint64_t n, int out_bits,
                                                       uint32_t *__restrict__ out, uint64_t cap32,
                                                       uint64_t ngroups_out) {
+  extern __shared__ __align__(16) uint32_t s_out[];  // 256 out_bits words
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ngroups_out) return;
-  const uint64_t w0 = g * (uint64_t)out_bits;
   const uint64_t nfull = n / kGroup;
   uint32_t vc[kGroup];
   if (g < nfull) {
@@ -307,7 +312,17 @@ __global__ __launch_bounds__(256) void k_ewise_pack32(PackedOperand a, PackedOpe
 #pragma unroll
     for (int i = 0; i < kGroup; ++i) vc[i] = 0;
   }
-  codec::encode32_rt(vc, out_bits, out + w0, cap32 - w0);
+  codec::encode32_rt(vc, out_bits, s_out + threadIdx.x * out_bits, (uint64_t)out_bits);
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * (uint64_t)out_bits;  // a word index
+  if (base >= cap32) return;
+  const uint64_t left = cap32 - base;
+  const uint32_t nw = (uint32_t)(left < 256ull * out_bits ? left : 256ull * out_bits);
+  uint4 *o4 = reinterpret_cast<uint4 *>(out + base);  // 1024 out_bits bytes per block: aligned
+  const uint4 *l4 = reinterpret_cast<const uint4 *>(s_out);
+  for (uint32_t q = threadIdx.x; q < nw / 4; q += blockDim.x) o4[q] = l4[q];
+  for (uint32_t q = (nw & ~3u) + threadIdx.x; q < nw; q += blockDim.x) out[base + q] = s_out[q];
+  (void)ngroups_out;
 }
 
 __global__ void k_fill_i64(int64_t *p, uint64_t n, int64_t v) {
@@ -440,18 +455,19 @@ hipError_t launch_ewise_pack(int op, PackedOperand a, PackedOperand b, int64_t s
                              hipStream_t s) {
   const uint64_t ngroups_out = (cap32 + out_bits - 1) / out_bits;
   const unsigned grid = grid_for(ngroups_out, 256, 0x7fffffffu);
+  const size_t lds32 = (size_t)256 * (size_t)(out_bits <= 32 ? out_bits : 32) * 4u;
   if (vclass == EW_I32 && out_bits <= 32 && op == EW_ADD)
-    k_ewise_pack32<EW_ADD, int32_t><<<grid, 256, 0, s>>>(a, b, scalar, n, out_bits, out, cap32,
-                                                          ngroups_out);
+    k_ewise_pack32<EW_ADD, int32_t>
+        <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, ngroups_out);
   else if (vclass == EW_I32 && out_bits <= 32)
-    k_ewise_pack32<EW_SCALE, int32_t><<<grid, 256, 0, s>>>(a, b, scalar, n, out_bits, out, cap32,
-                                                            ngroups_out);
+    k_ewise_pack32<EW_SCALE, int32_t>
+        <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, ngroups_out);
   else if (vclass == EW_U32 && out_bits <= 32 && op == EW_ADD)
-    k_ewise_pack32<EW_ADD, uint32_t><<<grid, 256, 0, s>>>(a, b, scalar, n, out_bits, out, cap32,
-                                                           ngroups_out);
+    k_ewise_pack32<EW_ADD, uint32_t>
+        <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, ngroups_out);
   else if (vclass == EW_U32 && out_bits <= 32)
-    k_ewise_pack32<EW_SCALE, uint32_t><<<grid, 256, 0, s>>>(a, b, scalar, n, out_bits, out,
-                                                             cap32, ngroups_out);
+    k_ewise_pack32<EW_SCALE, uint32_t>
+        <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, ngroups_out);
   else
     k_ewise_pack<<<grid, 256, 0, s>>>(op, a, b, scalar, n, out_bits, out, cap32, ngroups_out);
   return hipGetLastError();
