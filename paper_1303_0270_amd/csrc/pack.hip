@@ -202,15 +202,32 @@ __global__ __launch_bounds__(256) void k_ewise_range(int op, PackedOperand a, Pa
   block_range_commit(lo, hi, ovf, slot);
 }
 
-// Packing pass of an elementwise result: lane g writes output words
-// [g*out_bits, (g+1)*out_bits) for the 32 results of group g (zeros past n).
+// Writes a block's output run: thread t of block x encoded group 256 x + t
+// into s_out[t out_bits ..), and the block's groups are consecutive, so its
+// words are out[256 x out_bits ..) contiguous: 16-byte stores, words at or
+// past cap32 dropped.  (A thread storing its own group directly issues
+// out_bits stores of 64 lanes each at a stride of out_bits words.)
+__device__ __forceinline__ void store_block_run(const uint32_t *s_out, int out_bits,
+                                                uint32_t *__restrict__ out, uint64_t cap32) {
+  const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * (uint64_t)out_bits;  // a word index
+  if (base >= cap32) return;
+  const uint64_t left = cap32 - base;
+  const uint64_t run = (uint64_t)blockDim.x * (uint64_t)out_bits;
+  const uint32_t nw = (uint32_t)(left < run ? left : run);
+  uint4 *o4 = reinterpret_cast<uint4 *>(out + base);  // 1024 out_bits bytes per block: aligned
+  const uint4 *l4 = reinterpret_cast<const uint4 *>(s_out);
+  for (uint32_t q = threadIdx.x; q < nw / 4; q += blockDim.x) o4[q] = l4[q];
+  for (uint32_t q = (nw & ~3u) + threadIdx.x; q < nw; q += blockDim.x) out[base + q] = s_out[q];
+}
+
+// Packing pass of an elementwise result: thread t of block x packs the 32
+// results of group 256 x + t (zeros past n) at out_bits, through LDS.
 __global__ __launch_bounds__(256) void k_ewise_pack(int op, PackedOperand a, PackedOperand b,
                                                     int64_t scalar, uint64_t n, int out_bits,
                                                     uint32_t *__restrict__ out, uint64_t cap32,
                                                     uint64_t ngroups_out) {
+  extern __shared__ __align__(16) uint32_t s_out[];  // 256 out_bits words
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ngroups_out) return;
-  const uint64_t w0 = g * (uint64_t)out_bits;
   const uint64_t ngroups_in = (n + kGroup - 1) / kGroup;
   int64_t vc[kGroup];
   if (g >= ngroups_in) {
@@ -226,7 +243,10 @@ __global__ __launch_bounds__(256) void k_ewise_pack(int op, PackedOperand a, Pac
     for (int i = 0; i < kGroup; ++i)
       vc[i] = e0 + i < n ? ewise_value(op, va[i], op == EW_ADD ? vb[i] : 0, scalar, &ovf) : 0;
   }
-  codec::encode_rt(vc, out_bits, out + w0, cap32 - w0);
+  codec::encode_rt(vc, out_bits, s_out + threadIdx.x * out_bits, (uint64_t)out_bits);
+  __syncthreads();
+  store_block_run(s_out, out_bits, out, cap32);
+  (void)ngroups_out;
 }
 
 // 32-bit variants, taken when the operands' and the result's exact ranges
@@ -289,12 +309,8 @@ __global__ __launch_bounds__(256) void k_ewise_range32(PackedOperand a, PackedOp
   block_range_commit((int64_t)lo, (int64_t)hi, 0, slot);
 }
 
-// Packing pass, 32-bit results: thread t of block x packs group 256 x + t.
-// The block's groups are consecutive, so its output is one contiguous run
-// of 256 out_bits words: each thread encodes into LDS and the block writes
-// the run with coalesced 16-byte stores (a thread storing its own group
-// directly issues out_bits stores of 64 lanes each at a stride of out_bits
-// words).  Words at or past cap32 are dropped; groups past n are zeros.
+// Packing pass, 32-bit results: thread t of block x packs group 256 x + t
+// (zeros past n) at out_bits, through LDS (store_block_run).
 template <int OP, typename VT>
 __global__ __launch_bounds__(256) void k_ewise_pack32(PackedOperand a, PackedOperand b,
                                                       int64_t scalar, uint64_t n, int out_bits,
@@ -314,14 +330,7 @@ __global__ __launch_bounds__(256) void k_ewise_pack32(PackedOperand a, PackedOpe
   }
   codec::encode32_rt(vc, out_bits, s_out + threadIdx.x * out_bits, (uint64_t)out_bits);
   __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * (uint64_t)out_bits;  // a word index
-  if (base >= cap32) return;
-  const uint64_t left = cap32 - base;
-  const uint32_t nw = (uint32_t)(left < 256ull * out_bits ? left : 256ull * out_bits);
-  uint4 *o4 = reinterpret_cast<uint4 *>(out + base);  // 1024 out_bits bytes per block: aligned
-  const uint4 *l4 = reinterpret_cast<const uint4 *>(s_out);
-  for (uint32_t q = threadIdx.x; q < nw / 4; q += blockDim.x) o4[q] = l4[q];
-  for (uint32_t q = (nw & ~3u) + threadIdx.x; q < nw; q += blockDim.x) out[base + q] = s_out[q];
+  store_block_run(s_out, out_bits, out, cap32);
   (void)ngroups_out;
 }
 
@@ -469,7 +478,8 @@ hipError_t launch_ewise_pack(int op, PackedOperand a, PackedOperand b, int64_t s
     k_ewise_pack32<EW_SCALE, uint32_t>
         <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, ngroups_out);
   else
-    k_ewise_pack<<<grid, 256, 0, s>>>(op, a, b, scalar, n, out_bits, out, cap32, ngroups_out);
+    k_ewise_pack<<<grid, 256, (size_t)256 * (size_t)out_bits * 4u, s>>>(
+        op, a, b, scalar, n, out_bits, out, cap32, ngroups_out);
   return hipGetLastError();
 }
 
