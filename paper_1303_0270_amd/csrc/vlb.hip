@@ -74,19 +74,45 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_sizes(const T *__restrict__ d
                                                          RangeSlot *slot) {
   const uint64_t total = (uint64_t)rows * (uint64_t)ngr * kVG;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  // group gi = (row i, group g of the row), advanced by the grid step with
+  // one division up front (a 64-bit division per element would cost more
+  // than the element's own work)
+  const uint64_t gstep = stride >> 5;
+  const uint64_t di = gstep / (uint64_t)ngr, dg = gstep - di * (uint64_t)ngr;
+  uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t i = (t >> 5) / (uint64_t)ngr, g = (t >> 5) - i * (uint64_t)ngr;
+  const int l = (int)(t & 31u);
   uint32_t gmax = 0;
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-    const uint64_t gi = t >> 5;
-    const int l = (int)(t & 31u);
-    const uint64_t i = gi / (uint64_t)ngr;
-    const uint64_t g = gi - i * (uint64_t)ngr;
-    const uint64_t j = g * kVG + (uint64_t)l;
-    uint32_t nb = 0;
-    if (j < (uint64_t)cols) nb = (uint32_t)(k + elem_width(load_dense(dense, i * cols + j), sgn));
+  // kSizeSteps grid steps per iteration: their loads (unconditional, with
+  // clamped row and column) are all issued before any is used.  A step's
+  // validity is the same for the 32 lanes of a group (total and the step are
+  // multiples of 32), so the group's shuffles always run together.
+  constexpr int kSizeSteps = 4;
+  for (; t < total; t += kSizeSteps * stride) {
+    int64_t v[kSizeSteps];
+    bool live[kSizeSteps], valid[kSizeSteps];
 #pragma unroll
-    for (int m = 16; m >= 1; m >>= 1) nb += (uint32_t)__shfl_xor((int)nb, m, 32);
-    if (l == 0) grp[gi] = nb;
-    gmax = nb > gmax ? nb : gmax;
+    for (int u = 0; u < kSizeSteps; ++u) {
+      valid[u] = t + u * stride < total;
+      const uint64_t j = g * kVG + (uint64_t)l;
+      live[u] = valid[u] && j < (uint64_t)cols;
+      const uint64_t ic = valid[u] ? i : (uint64_t)rows - 1;
+      v[u] = load_dense(dense, ic * (uint64_t)cols + (live[u] ? j : (uint64_t)cols - 1));
+      g += dg;
+      i += di;
+      if (g >= (uint64_t)ngr) {
+        g -= (uint64_t)ngr;
+        ++i;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSizeSteps; ++u) {
+      uint32_t nb = live[u] ? (uint32_t)(k + elem_width(v[u], sgn)) : 0u;
+#pragma unroll
+      for (int m = 16; m >= 1; m >>= 1) nb += (uint32_t)__shfl_xor((int)nb, m, 32);
+      if (l == 0 && valid[u]) grp[(t + u * stride) >> 5] = nb;
+      gmax = nb > gmax ? nb : gmax;
+    }
   }
   // the longest group (sizes the staging buffers of the matvec kernel)
   block_range_commit(0, (int64_t)gmax, 0, slot);
@@ -212,14 +238,37 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_pack(const T *__restrict__ de
     const int nwords = (int)(((E + 31u) >> 5) - q0);
     for (int w = threadIdx.x; w < span_words; w += blockDim.x) span[w] = 0;
     __syncthreads();
-    for (uint64_t gi = gb + (uint64_t)half; gi < ge; gi += kVThreads / 32) {
-      const uint64_t i = gi / (uint64_t)ngr;
-      const uint64_t g = gi - i * (uint64_t)ngr;
+    // This half-wave's groups of the stretch (at most kPackPer): their
+    // elements and start bits are requested first, with clamped addresses,
+    // then placed one group at a time.  (row, group) advance from one
+    // division per stretch.
+    constexpr int kPackPer = kPackGroups / (kVThreads / 32);
+    const uint64_t gi0 = gb + (uint64_t)half;
+    uint64_t i = gi0 / (uint64_t)ngr, g = gi0 - i * (uint64_t)ngr;
+    int64_t v[kPackPer];
+    uint64_t gstart[kPackPer];
+    bool live[kPackPer];
+#pragma unroll
+    for (int u = 0; u < kPackPer; ++u) {
+      const uint64_t gi = gi0 + (uint64_t)u * (kVThreads / 32);
+      const bool valid = gi < ge;
       const uint64_t j = g * kVG + (uint64_t)l;
-      const bool live = j < (uint64_t)cols;
-      const int64_t v = live ? load_dense(dense, i * (uint64_t)cols + j) : 0;
-      const int b = live ? elem_width(v, sgn) : 0;
-      uint32_t len = live ? (uint32_t)(k + b) : 0u;
+      live[u] = valid && j < (uint64_t)cols;
+      const uint64_t ic = valid ? i : (uint64_t)rows - 1;
+      v[u] = load_dense(dense, ic * (uint64_t)cols + (live[u] ? j : (uint64_t)cols - 1));
+      gstart[u] = row_bit[ic] + grp[valid ? gi : total - 1];
+      g += kVThreads / 32;
+      while (g >= (uint64_t)ngr) {
+        g -= (uint64_t)ngr;
+        ++i;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kPackPer; ++u) {
+      // the same for the 32 lanes of a group, so its shuffles run together
+      if (gi0 + (uint64_t)u * (kVThreads / 32) >= ge) break;
+      const int b = live[u] ? elem_width(v[u], sgn) : 0;
+      const uint32_t len = live[u] ? (uint32_t)(k + b) : 0u;
       // exclusive prefix sum over the 32 lanes of the group
       uint32_t inc = len;
 #pragma unroll
@@ -227,11 +276,10 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_pack(const T *__restrict__ de
         const uint32_t o = (uint32_t)__shfl_up((int)inc, d, 32);
         if (l >= d) inc += o;
       }
-      const uint64_t gstart = row_bit[i] + grp[gi];
-      const uint32_t pos = (uint32_t)(gstart - q0 * 32u) + (inc - len);
-      if (live) {
-        lds_or_bits(span, pos, (uint64_t)b, k);          // the length field
-        lds_or_bits(span, pos + (uint32_t)k, (uint64_t)v, b);  // then the value
+      const uint32_t pos = (uint32_t)(gstart[u] - q0 * 32u) + (inc - len);
+      if (live[u]) {
+        lds_or_bits(span, pos, (uint64_t)b, k);                   // the length field
+        lds_or_bits(span, pos + (uint32_t)k, (uint64_t)v[u], b);  // then the value
       }
     }
     __syncthreads();
