@@ -189,8 +189,10 @@ int ccm_matmul(const ccm_desc *a, const ccm_desc *b, const ccm_desc *out,
  * payloads must stay valid) and an int32 or int64 x dtype.  Creating it
  * builds a work list of (matrix, row block) items ordered by width and size,
  * with per-width tile choices from a tuning table (JSON written by the
- * project's autotuner; NULL or an unreadable path uses built-in defaults),
- * and copies it to device memory the batch owns. */
+ * project's autotuner, {"widths": {"<b>": {"tile_rows": r,
+ * "rows_in_flight": f}}}, f in {1, 2, 4}, capped at 4 for b <= 8, 2 for
+ * b <= 16 and 1 above; NULL, an unreadable path or a missing width uses
+ * built-in defaults), and copies it to device memory the batch owns. */
 typedef struct ccm_batch ccm_batch;
 
 int ccm_batch_create(const ccm_desc *as, int32_t n, int32_t xdtype, const char *tune_json,
