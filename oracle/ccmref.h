@@ -34,11 +34,11 @@
  *   encode / decode / size: the worked example's two bitstrings (Eq. 3 and the
  *     straddle step), round trips, closed-form size, zero padding, width
  *     minimality;
- *   signed encoding: parity unpinned by the paper (it treats positive integers
- *     only); pinned by round trips, minimality and brute force;
- *   add / scale / matvec / matmul: parity unpinned by the paper (it gives no
- *     arithmetic example); pinned by brute force against uncompressed Python
- *     integer arithmetic and by algebraic identities.
+ *   signed encoding: the paper treats positive integers only, so no printed
+ *     value covers it; pinned by round trips, minimality and brute force;
+ *   add / scale / matvec / matmul: the paper prints no arithmetic example;
+ *     pinned by brute force against uncompressed Python integer arithmetic
+ *     and by algebraic identities.
  */
 #ifndef CCMREF_H
 #define CCMREF_H
