@@ -160,12 +160,14 @@ def test_errors():
         c.vlb_matvec(g, torch.zeros(5, dtype=torch.int32, device="cuda"))
 
 
-def test_workload_full_size_sampled():
-    """The Beta(5, 33) 16384 x 16384 matrix as the benchmark builds it (on the
-    GPU): sampled rows' values, start bits and matvec outputs against the
-    oracle run on those rows alone."""
+@pytest.mark.parametrize("name", ["beta_5_33", "beta_1_1"])
+def test_workload_full_size_sampled(name):
+    """A 16384 x 16384 Beta matrix as the benchmark builds it (on the GPU):
+    sampled rows' values, start bits and matvec outputs against the oracle
+    run on those rows alone.  Beta(1, 1)'s stream is 10.3 G bits, so row
+    starts and staged stretches lie past 2^32 bits."""
     c = ccm()
-    spec, xs = W.vlb_sweep("beta_5_33")
+    spec, xs = W.vlb_sweep(name)
     A = spec.dense_device(c.fill_uniform, torch)
     g = c.vlb_compress(A)
     del A
