@@ -378,16 +378,19 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_mv_gen(
   }
 }
 
-// a == b ? x : y on registers.  Written as one compare and one v_cndmask:
-// as plain C the compiler turns the select of two values just read from LDS
-// into a select of their addresses and demotes the chain state to scratch.
-__device__ __forceinline__ uint32_t select_eq(uint32_t a, uint32_t b, uint32_t x, uint32_t y) {
-  uint32_t r;
-  asm("v_cmp_eq_u32 vcc, %1, %2\n\tv_cndmask_b32 %0, %4, %3, vcc"
-      : "=v"(r)
-      : "v"(a), "v"(b), "v"(x), "v"(y)
+// Both of (a == b ? x0 : y0) and (a == b ? x1 : y1) from one compare and
+// two v_cndmask.  As plain C the compiler turns the select of two values just
+// read from LDS into a select of their addresses and demotes the chain state
+// to scratch.
+__device__ __forceinline__ void select_eq2(uint32_t a, uint32_t b, uint32_t x0, uint32_t y0,
+                                           uint32_t x1, uint32_t y1, uint32_t &r0,
+                                           uint32_t &r1) {
+  asm("v_cmp_eq_u32 vcc, %2, %3\n\t"
+      "v_cndmask_b32 %0, %5, %4, vcc\n\t"
+      "v_cndmask_b32 %1, %7, %6, vcc"
+      : "=&v"(r0), "=v"(r1)
+      : "v"(a), "v"(b), "v"(x0), "v"(y0), "v"(x1), "v"(y1)
       : "vcc");
-  return r;
 }
 
 // 64 stream bits from bit pv of a staged stretch (reads three words).
@@ -530,13 +533,18 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
 
     const uint32_t *seg = (const uint32_t *)seg4;
     int64_t acc[GPT];
-    uint32_t q[GPT], w0[GPT], w1[GPT];
+    // the window: words q, q + 1 around the position and q + 2 requested
+    // ahead (a pair of at most 32 bits moves the position by at most a
+    // word, so the next window is (w0, w1) or (w1, w2), never a word still
+    // in flight)
+    uint32_t q[GPT], w0[GPT], w1[GPT], w2[GPT];
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
       acc[u] = 0;
       q[u] = p[u] >> 5;
       w0[u] = WIDE ? 0u : seg[q[u]];
       w1[u] = WIDE ? 0u : seg[q[u] + 1];
+      w2[u] = WIDE ? 0u : seg[q[u] + 2];
     }
 #pragma unroll
     for (int j = 0; j < kVG; ++j) {
@@ -571,7 +579,13 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
         const uint32_t pn = p[u] + (uint32_t)k + b;
         uint32_t qn = pn >> 5;
         if (CLAMP) qn = qn < qmax ? qn : qmax;
-        uint32_t w0n = select_eq(qn, q[u], w0[u], w1[u]);
+        // the word after the next window, requested as early as its address
+        // is known (kept here: left to itself the scheduler sinks the
+        // request to its use in the next element, which then waits for it)
+        const uint32_t w2n = seg[qn + 2];
+        __builtin_amdgcn_sched_barrier(0);
+        uint32_t w0n, w1n;
+        select_eq2(qn, q[u], w0[u], w1[u], w1[u], w2[u], w0n, w1n);
         if (__builtin_expect(b > narrow, 0)) {
           // the value runs past the 32 bits read: replace a by the full
           // value, and reload the window where the next pair starts
@@ -584,9 +598,14 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
           asm volatile("" : "+v"(xw));  // sign-extend here, not hoisted
           acc[u] += (int64_t)((v - (uint64_t)(int64_t)a) * (uint64_t)(int64_t)xw);
           w0n = seg[qn];
+          w1n = seg[qn + 1];
+          // wait for these two here, on the rare path: a wait at the merge
+          // would also wait for the prefetch on the common one
+          __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
         }
         asm volatile("" : "+v"(acc[u]));  // accumulate in place, element by element
-        w1[u] = seg[qn + 1];
+        w2[u] = w2n;
+        w1[u] = w1n;
         w0[u] = w0n;
         q[u] = qn;
         p[u] = pn;
