@@ -537,14 +537,27 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
     // ahead (a pair of at most 32 bits moves the position by at most a
     // word, so the next window is (w0, w1) or (w1, w2), never a word still
     // in flight)
-    uint32_t q[GPT], w0[GPT], w1[GPT], w2[GPT];
+    // The four-word walk keeps the four words at its (clamped) read
+    // position q in w0..w3, and requests the next element's as soon as the
+    // length is known, before the value and the product.
+    uint32_t q[GPT], w0[GPT], w1[GPT], w2[GPT], w3[GPT];
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
       acc[u] = 0;
-      q[u] = p[u] >> 5;
-      w0[u] = WIDE ? 0u : seg[q[u]];
-      w1[u] = WIDE ? 0u : seg[q[u] + 1];
-      w2[u] = WIDE ? 0u : seg[q[u] + 2];
+      if constexpr (WIDE) {
+        q[u] = CLAMP && p[u] > pmaxw ? pmaxw : p[u];
+        const uint32_t qc = q[u] >> 5;
+        w0[u] = seg[qc];
+        w1[u] = seg[qc + 1];
+        w2[u] = seg[qc + 2];
+        w3[u] = seg[qc + 3];
+      } else {
+        q[u] = p[u] >> 5;
+        w0[u] = seg[q[u]];
+        w1[u] = seg[q[u] + 1];
+        w2[u] = seg[q[u] + 2];
+        w3[u] = 0u;
+      }
     }
 #pragma unroll
     for (int j = 0; j < kVG; ++j) {
@@ -553,19 +566,27 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
         if constexpr (WIDE) {
           // four words at the pair's start give 96 bits: the length and a
           // value of up to 64 bits, with no branch
-          if (CLAMP) p[u] = p[u] < pmaxw ? p[u] : pmaxw;
-          const uint32_t qq = p[u] >> 5, sh = p[u] & 31u;
-          const uint32_t a0 = __builtin_amdgcn_alignbit(seg[qq + 1], seg[qq], sh);
-          const uint32_t a1 = __builtin_amdgcn_alignbit(seg[qq + 2], seg[qq + 1], sh);
-          const uint32_t a2 = __builtin_amdgcn_alignbit(seg[qq + 3], seg[qq + 2], sh);
+          const uint32_t sh = q[u] & 31u;
+          const uint32_t a0 = __builtin_amdgcn_alignbit(w1[u], w0[u], sh);
+          const uint32_t a1 = __builtin_amdgcn_alignbit(w2[u], w1[u], sh);
+          const uint32_t a2 = __builtin_amdgcn_alignbit(w3[u], w2[u], sh);
           const uint32_t b = a0 & kmask;
+          p[u] += (uint32_t)k + b;
+          // the next pair's words, requested before this one's value and
+          // product (kept here: the scheduler would sink them to their use)
+          q[u] = CLAMP && p[u] > pmaxw ? pmaxw : p[u];
+          const uint32_t qc = q[u] >> 5;
+          w0[u] = seg[qc];
+          w1[u] = seg[qc + 1];
+          w2[u] = seg[qc + 2];
+          w3[u] = seg[qc + 3];
+          __builtin_amdgcn_sched_barrier(0);
           const int nb = b < 64u ? (int)b : 64;
           const uint64_t lo = ((uint64_t)a1 << 32) | a0;
           uint64_t v = ((lo >> k) | ((uint64_t)a2 << (64 - k))) & mask64(nb);
           if (SGN) v = (uint64_t)sext64(v, nb > 0 ? nb : 1);
           acc[u] += (int64_t)(v * (uint64_t)(int64_t)xr[u][j]);
           asm volatile("" : "+v"(acc[u]));
-          p[u] += (uint32_t)k + b;
           continue;
         }
         const uint32_t wv = __builtin_amdgcn_alignbit(w1[u], w0[u], p[u] & 31u);
