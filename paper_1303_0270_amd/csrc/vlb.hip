@@ -597,7 +597,10 @@ __global__ __launch_bounds__(kVThreads) void k_vlb_mv_lds(
         else
           a = (int32_t)__builtin_amdgcn_ubfe(wv, k, b);
         acc[u] += (int64_t)a * (int64_t)xr[u][j];
-        const uint32_t pn = p[u] + (uint32_t)k + b;
+        // one v_add3 (the compiler otherwise keeps p + k apart for the rare
+        // branch and spends two adds on every element)
+        uint32_t pn;
+        asm("v_add3_u32 %0, %1, %2, %3" : "=v"(pn) : "v"(p[u]), "s"((uint32_t)k), "v"(b));
         uint32_t qn = pn >> 5;
         if (CLAMP) qn = qn < qmax ? qn : qmax;
         // the word after the next window, requested as early as its address
