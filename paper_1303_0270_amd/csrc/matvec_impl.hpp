@@ -895,8 +895,26 @@ k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   int64_t rb = blockIdx.x;
 
   // stage the x panel, zero-padded to whole groups
-  {
-    const int nchunk = ng * kGroup / 4;
+  const int nchunk = ng * kGroup / 4;
+  if (x_aligned16 && pc == ng * kGroup) {
+    // whole groups, aligned x: every chunk requested at once (a fixed count,
+    // clamped), then the first unit, then the chunks stored -- the wait for
+    // the chunks leaves the unit's loads in flight (the counter is in order)
+    constexpr int kXPer = kPanelW / 4 / kThreadsW;
+    const int4 *x4 = reinterpret_cast<const int4 *>(x + c0);
+    int4 xv[kXPer];
+#pragma unroll
+    for (int u = 0; u < kXPer; ++u) {
+      const int q = (int)threadIdx.x + kThreadsW * u;
+      xv[u] = x4[q < nchunk ? q : nchunk - 1];
+    }
+    if constexpr (PF) load_unit(w0, rb, 0, s0);  // in flight across the barrier
+#pragma unroll
+    for (int u = 0; u < kXPer; ++u) {
+      const int e = 4 * ((int)threadIdx.x + kThreadsW * u);
+      if (e < 4 * nchunk) *reinterpret_cast<int4 *>(xs + (e >> 5) * kPitchW + (e & 31)) = xv[u];
+    }
+  } else {
     for (int q = threadIdx.x; q < nchunk; q += kThreadsW) {
       const int e = 4 * q;
       int4 v;
@@ -907,8 +925,8 @@ k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
                       e + 2 < pc ? x[c0 + e + 2] : 0, e + 3 < pc ? x[c0 + e + 3] : 0);
       *reinterpret_cast<int4 *>(xs + (e >> 5) * kPitchW + (e & 31)) = v;
     }
+    if constexpr (PF) load_unit(w0, rb, 0, s0);  // in flight across the barrier
   }
-  if constexpr (PF) load_unit(w0, rb, 0, s0);  // in flight across the barrier
   __syncthreads();
 
   uint64_t acc = 0;
