@@ -152,6 +152,22 @@ int ccm_gather(const ccm_desc *a, const int64_t *ii, const int64_t *jj, int64_t 
 int ccm_add_plan(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *stream);
 int ccm_add(const ccm_desc *a, const ccm_desc *b, const ccm_desc *out, void *stream);
 
+/* C = A + B in one call, usually one pass over A and B: the same result as
+ * ccm_add_plan followed by ccm_add.  The headers bound the sums to
+ * [a.vmin + b.vmin, a.vmax + b.vmax]; when that bound has a width of at most
+ * 32 bits and every operand and sum fits int32 (or uint32), the sums are
+ * packed at the bound's width while their exact extremes are reduced, and
+ * only if the exact range needs a narrower width are they packed again at
+ * that width.  Otherwise the range pass runs first, as in ccm_add_plan.
+ * out->payload: device, caller-owned, at least ccm_add_capacity(a, b) bytes
+ * (never less than the final width needs); the other fields of *out are
+ * outputs, set on success.  The first ccm_payload_capacity(rows, cols,
+ * out->bits) bytes then hold what ccm_add writes there (zeros past 8*W); the
+ * bytes after them are unspecified.  CCM_E_OVERFLOW iff some sum leaves
+ * int64.  Blocking (one device-to-host read of the range). */
+uint64_t ccm_add_capacity(const ccm_desc *a, const ccm_desc *b); /* 0 if invalid */
+int ccm_add_onepass(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *stream);
+
 /* C = s * A.  The result range [s*min, s*max] (ordered) comes from A's
  * header, so the plan is host-only; CCM_E_OVERFLOW iff it leaves int64.
  * s = 0 gives an all-zero matrix with b = 1.  Op: async. */

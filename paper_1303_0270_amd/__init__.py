@@ -210,12 +210,27 @@ def gather(m: CMatrix, ii: torch.Tensor, jj: torch.Tensor, stream=None, sync: bo
     return out, (bool(bad.item()) if sync else bad)
 
 
-def add(a: CMatrix, b: CMatrix, stream=None) -> CMatrix:
-    """C = A + B; both operands in the same order (the result keeps it)."""
+def add(a: CMatrix, b: CMatrix, stream=None, onepass: bool = True) -> CMatrix:
+    """C = A + B; both operands in the same order (the result keeps it).
+    onepass: ccm_add_onepass (packs at the width the headers bound while the
+    exact range is reduced); otherwise ccm_add_plan then ccm_add."""
     if a.order != b.order:
         raise CcmError(E_UNSUPPORTED, "add: operands unravelled in different orders")
     s = _stream(stream)
     d = Desc()
+    if onepass:
+        if a.shape != b.shape:
+            raise CcmError(E_SHAPE, "add: operand shapes differ")
+        cap = int(lib.ccm_add_capacity(ctypes.byref(a.desc), ctypes.byref(b.desc)))
+        if cap == 0:
+            raise CcmError(E_INVAL, "ccm_add_capacity: invalid operands")
+        payload = torch.empty(cap, dtype=torch.uint8, device=a.payload.device)
+        d.payload = payload.data_ptr()
+        check(lib.ccm_add_onepass(ctypes.byref(a.desc), ctypes.byref(b.desc), ctypes.byref(d),
+                                  s), "ccm_add_onepass")
+        # past the final width's capacity the buffer may hold the first pack's words
+        keep = int(lib.ccm_payload_capacity(d.rows, d.cols, d.bits))
+        return CMatrix(d, payload[:keep], order=a.order)
     check(lib.ccm_add_plan(ctypes.byref(a.desc), ctypes.byref(b.desc), ctypes.byref(d), s),
           "ccm_add_plan")
     c = CMatrix(d, device=a.payload.device, order=a.order)

@@ -76,6 +76,8 @@ SIGNATURES = {
     "ccm_gather": (ctypes.c_int, [_dp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "ccm_add_plan": (ctypes.c_int, [_dp, _dp, _dp, _vp]),
     "ccm_add": (ctypes.c_int, [_dp, _dp, _dp, _vp]),
+    "ccm_add_capacity": (_u64, [_dp, _dp]),
+    "ccm_add_onepass": (ctypes.c_int, [_dp, _dp, _dp, _vp]),
     "ccm_scale_plan": (ctypes.c_int, [_dp, _i64, _dp]),
     "ccm_scale": (ctypes.c_int, [_dp, _i64, _dp, _vp]),
     "ccm_matvec": (ctypes.c_int, [_dp, _vp, _i32, _vp, _vp]),

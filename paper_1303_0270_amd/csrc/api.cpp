@@ -383,6 +383,80 @@ int ccm_add(const ccm_desc *a, const ccm_desc *b, const ccm_desc *out, void *str
   return CCM_OK;
 }
 
+// The result range the headers bound: [a.min + b.min, a.max + b.max], or
+// false when it leaves int64 (some sum may overflow).
+static bool add_bound(const ccm_desc *a, const ccm_desc *b, int64_t *lo, int64_t *hi) {
+  const __int128 l = (__int128)a->vmin + b->vmin, h = (__int128)a->vmax + b->vmax;
+  if (l < (__int128)INT64_MIN || h > (__int128)INT64_MAX) return false;
+  *lo = (int64_t)l;
+  *hi = (int64_t)h;
+  return true;
+}
+
+uint64_t ccm_add_capacity(const ccm_desc *a, const ccm_desc *b) {
+  if (check_desc(a, false) != CCM_OK || check_desc(b, false) != CCM_OK) return 0;
+  if (a->rows != b->rows || a->cols != b->cols) return 0;
+  int64_t lo, hi;
+  int32_t bits = 64, sgn = 0;
+  if (add_bound(a, b, &lo, &hi) && width_rule(lo, hi, &bits, &sgn) != CCM_OK) return 0;
+  return ccm_payload_capacity(a->rows, a->cols, bits);
+}
+
+int ccm_add_onepass(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *stream) {
+  int rc = check_desc(a, true);
+  if (rc == CCM_OK) rc = check_desc(b, true);
+  if (rc != CCM_OK) return rc;
+  if (!out || !out->payload) return CCM_E_INVAL;
+  if (a->rows != b->rows || a->cols != b->cols) return CCM_E_SHAPE;
+  void *payload = out->payload;
+  const uint64_t n = nelem(a);
+  const int vclass = add_class(a, b);
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx *c = nullptr;
+  rc = device_ctx(&c);
+  if (rc != CCM_OK) return rc;
+  ccm_desc bound, exact;
+  int64_t lo, hi;
+  ccm::RangeSlot r;
+  if (n > 0 && vclass != ccm::EW_I64 && add_bound(a, b, &lo, &hi) &&
+      fill_desc(a->rows, a->cols, lo, hi, &bound) == CCM_OK && bound.bits <= 32) {
+    // one pass: pack at the bounded width, learn the exact range meanwhile
+    CCM_HIP(ccm::launch_range_init(c->slot, s));
+    CCM_HIP(ccm::launch_add_pack_range(operand(a), operand(b), n, vclass, bound.bits,
+                                       (uint32_t *)payload, ccm::cap_words32(n, bound.bits),
+                                       c->slot, s));
+    rc = read_slot(c, s, &r);
+    if (rc != CCM_OK) return rc;
+    rc = fill_desc(a->rows, a->cols, r.vmin, r.vmax, &exact);
+    if (rc != CCM_OK) return rc;
+    exact.payload = payload;
+    if (exact.bits > bound.bits) return CCM_E_DEVICE;  // sums outside the bound: a failed pass
+    if (exact.bits != bound.bits || exact.is_signed != bound.is_signed) {
+      // the bound was loose: pack again at the exact width (it is narrower,
+      // so the payload holds it)
+      CCM_HIP(ccm::launch_ewise_pack(ccm::EW_ADD, operand(a), operand(b), 0, n, vclass,
+                                     exact.bits, (uint32_t *)payload,
+                                     ccm::cap_words32(n, exact.bits), s));
+    }
+    *out = exact;
+    return CCM_OK;
+  }
+  // the range pass first (it detects overflow), then the pack
+  CCM_HIP(ccm::launch_range_init(c->slot, s));
+  CCM_HIP(ccm::launch_ewise_range(ccm::EW_ADD, operand(a), operand(b), 0, n, vclass, c->slot, s));
+  rc = read_slot(c, s, &r);
+  if (rc != CCM_OK) return rc;
+  if (r.flag) return CCM_E_OVERFLOW;
+  rc = fill_desc(a->rows, a->cols, r.vmin, r.vmax, &exact);
+  if (rc != CCM_OK) return rc;
+  exact.payload = payload;
+  CCM_HIP(ccm::launch_ewise_pack(ccm::EW_ADD, operand(a), operand(b), 0, n, vclass, exact.bits,
+                                 (uint32_t *)payload, ccm::cap_words32(n, exact.bits), s));
+  *out = exact;
+  return CCM_OK;
+}
+
 int ccm_scale_plan(const ccm_desc *a, int64_t s, ccm_desc *out) {
   int rc = check_desc(a, false);
   if (rc != CCM_OK) return rc;

@@ -310,12 +310,15 @@ __global__ __launch_bounds__(256) void k_ewise_range32(PackedOperand a, PackedOp
 }
 
 // Packing pass, 32-bit results: thread t of block x packs group 256 x + t
-// (zeros past n) at out_bits, through LDS (store_block_run).
-template <int OP, typename VT>
+// (zeros past n) at out_bits, through LDS (store_block_run).  With RANGE it
+// also folds the exact extremes of the results below n into slot, so a
+// result packed at a width bounded from the operands' headers learns its
+// exact range in the same pass over the operands.
+template <int OP, typename VT, bool RANGE>
 __global__ __launch_bounds__(256) void k_ewise_pack32(PackedOperand a, PackedOperand b,
                                                       int64_t scalar, uint64_t n, int out_bits,
                                                       uint32_t *__restrict__ out, uint64_t cap32,
-                                                      uint64_t ngroups_out) {
+                                                      RangeSlot *slot) {
   extern __shared__ __align__(16) uint32_t s_out[];  // 256 out_bits words
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t nfull = n / kGroup;
@@ -328,10 +331,22 @@ __global__ __launch_bounds__(256) void k_ewise_pack32(PackedOperand a, PackedOpe
 #pragma unroll
     for (int i = 0; i < kGroup; ++i) vc[i] = 0;
   }
+  if constexpr (RANGE) {
+    // every thread of the block reaches the commit's barriers (no early exit)
+    const uint64_t left = g < nfull ? (uint64_t)kGroup : g * kGroup < n ? n - g * kGroup : 0;
+    VT lo = std::numeric_limits<VT>::max(), hi = std::numeric_limits<VT>::min();
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) {
+      if ((uint64_t)i < left) {
+        lo = (VT)vc[i] < lo ? (VT)vc[i] : lo;
+        hi = (VT)vc[i] > hi ? (VT)vc[i] : hi;
+      }
+    }
+    block_range_commit((int64_t)lo, (int64_t)hi, 0, slot);
+  }
   codec::encode32_rt(vc, out_bits, s_out + threadIdx.x * out_bits, (uint64_t)out_bits);
   __syncthreads();
   store_block_run(s_out, out_bits, out, cap32);
-  (void)ngroups_out;
 }
 
 __global__ void k_fill_i64(int64_t *p, uint64_t n, int64_t v) {
@@ -466,20 +481,37 @@ hipError_t launch_ewise_pack(int op, PackedOperand a, PackedOperand b, int64_t s
   const unsigned grid = grid_for(ngroups_out, 256, 0x7fffffffu);
   const size_t lds32 = (size_t)256 * (size_t)(out_bits <= 32 ? out_bits : 32) * 4u;
   if (vclass == EW_I32 && out_bits <= 32 && op == EW_ADD)
-    k_ewise_pack32<EW_ADD, int32_t>
-        <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, ngroups_out);
+    k_ewise_pack32<EW_ADD, int32_t, false>
+        <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, nullptr);
   else if (vclass == EW_I32 && out_bits <= 32)
-    k_ewise_pack32<EW_SCALE, int32_t>
-        <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, ngroups_out);
+    k_ewise_pack32<EW_SCALE, int32_t, false>
+        <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, nullptr);
   else if (vclass == EW_U32 && out_bits <= 32 && op == EW_ADD)
-    k_ewise_pack32<EW_ADD, uint32_t>
-        <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, ngroups_out);
+    k_ewise_pack32<EW_ADD, uint32_t, false>
+        <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, nullptr);
   else if (vclass == EW_U32 && out_bits <= 32)
-    k_ewise_pack32<EW_SCALE, uint32_t>
-        <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, ngroups_out);
+    k_ewise_pack32<EW_SCALE, uint32_t, false>
+        <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, nullptr);
   else
     k_ewise_pack<<<grid, 256, (size_t)256 * (size_t)out_bits * 4u, s>>>(
         op, a, b, scalar, n, out_bits, out, cap32, ngroups_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_pack_range(PackedOperand a, PackedOperand b, uint64_t n, int vclass,
+                                 int out_bits, uint32_t *out, uint64_t cap32, RangeSlot *slot,
+                                 hipStream_t s) {
+  if (out_bits < 1 || out_bits > 32 || (vclass != EW_I32 && vclass != EW_U32))
+    return hipErrorInvalidValue;
+  const uint64_t ngroups_out = (cap32 + out_bits - 1) / out_bits;
+  const unsigned grid = grid_for(ngroups_out, 256, 0x7fffffffu);
+  const size_t lds32 = (size_t)256 * (size_t)out_bits * 4u;
+  if (vclass == EW_I32)
+    k_ewise_pack32<EW_ADD, int32_t, true>
+        <<<grid, 256, lds32, s>>>(a, b, 0, n, out_bits, out, cap32, slot);
+  else
+    k_ewise_pack32<EW_ADD, uint32_t, true>
+        <<<grid, 256, lds32, s>>>(a, b, 0, n, out_bits, out, cap32, slot);
   return hipGetLastError();
 }
 

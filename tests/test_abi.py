@@ -138,6 +138,37 @@ def test_scale_plan_matches_oracle(L):
         L.E_OVERFLOW
 
 
+def test_add_capacity_covers_the_exact_sum(L):
+    """ccm_add_capacity is the payload capacity at the width of the range the
+    headers bound, [a.min + b.min, a.max + b.max]: never less than the exact
+    sum's width needs (the one-pass add packs into it at either width)."""
+    rng = np.random.default_rng(6)
+    for _ in range(200):
+        shape = (int(rng.integers(1, 5)), int(rng.integers(1, 70)))
+        lim = int(rng.choice([3, 300, 3 * 10**5, 2**40]))
+        a = np.array(rng.integers(-lim, lim, size=shape), dtype=np.int64)
+        b = np.array(rng.integers(-lim, lim, size=shape), dtype=np.int64)
+        if rng.integers(0, 2):
+            a, b = np.abs(a), np.abs(b)
+        pa, pb = oracle.compress(a), oracle.compress(b)
+        want = oracle.add(pa, pb)
+        cap = L.lib.ccm_add_capacity(ctypes.byref(_desc_from(pa)), ctypes.byref(_desc_from(pb)))
+        bits, sgn = ctypes.c_int32(), ctypes.c_int32()
+        assert L.lib.ccm_width(pa.vmin + pb.vmin, pa.vmax + pb.vmax, ctypes.byref(bits),
+                               ctypes.byref(sgn)) == L.OK
+        assert bits.value >= want.bits
+        assert cap == L.lib.ccm_payload_capacity(shape[0], shape[1], bits.value)
+        assert cap >= L.lib.ccm_payload_capacity(shape[0], shape[1], want.bits)
+    # a bound past int64 (the sums themselves may still fit): 64-bit capacity
+    pa = oracle.compress(np.array([[2**63 - 1, 0]], dtype=np.int64))
+    pb = oracle.compress(np.array([[0, 2**63 - 1]], dtype=np.int64))
+    assert L.lib.ccm_add_capacity(ctypes.byref(_desc_from(pa)), ctypes.byref(_desc_from(pb))) \
+        == L.lib.ccm_payload_capacity(1, 2, 64)
+    # shapes that differ: 0
+    pc = oracle.compress(np.array([[1], [2]], dtype=np.int64))
+    assert L.lib.ccm_add_capacity(ctypes.byref(_desc_from(pa)), ctypes.byref(_desc_from(pc))) == 0
+
+
 def test_matmul_overflow_rule_matches_oracle(L):
     cases = [([[2**31, 2**31]], [[2**31], [-2**31]]), ([[2**31]], [[-2**31]]),
              ([[3, 4]], [[5], [6]]), ([[2**62]], [[1]]), ([[2**62, 1]], [[2], [1]])]

@@ -108,8 +108,9 @@ ADD_CASES = [(1, False, 1, False), (3, True, 5, False), (10, False, 10, False),
              (40, True, 63, False), (64, True, 7, True), (62, False, 62, False)]
 
 
+@pytest.mark.parametrize("onepass", [True, False], ids=["onepass", "plan"])
 @pytest.mark.parametrize("ba,sa,bb,sb", ADD_CASES)
-def test_add_matches_oracle(ba, sa, bb, sb):
+def test_add_matches_oracle(ba, sa, bb, sb, onepass):
     c = ccm()
     rng = np.random.default_rng(ba * 100 + bb)
     for rows, cols in ((1, 1), (5, 77), (70, 130)):
@@ -120,10 +121,10 @@ def test_add_matches_oracle(ba, sa, bb, sb):
         except oracle.OracleError as e:
             assert e.code == oracle.E_OVERFLOW
             with pytest.raises(c.CcmError) as ei:
-                c.add(c.compress(dev(A)), c.compress(dev(B)))
+                c.add(c.compress(dev(A)), c.compress(dev(B)), onepass=onepass)
             assert ei.value.status == c._lib.E_OVERFLOW
             continue
-        assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B))), ref)
+        assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B)), onepass=onepass), ref)
 
 
 # Operand ranges at the edges of the 32-bit elementwise classes (every operand
@@ -139,8 +140,9 @@ EDGE_PAIRS = [
 ]
 
 
+@pytest.mark.parametrize("onepass", [True, False], ids=["onepass", "plan"])
 @pytest.mark.parametrize("ra,rb", EDGE_PAIRS)
-def test_add_class_edges(ra, rb):
+def test_add_class_edges(ra, rb, onepass):
     c = ccm()
     rng = np.random.default_rng(abs(ra[0]) % 97 + rb[1] % 89)
     for rows, cols in ((3, 40), (65, 97)):
@@ -150,7 +152,7 @@ def test_add_class_edges(ra, rb):
         A.flat[0], B.flat[0] = ra[0], rb[0]
         A.flat[1], B.flat[1] = ra[1], rb[1]
         ref = oracle.add(oracle.compress(A), oracle.compress(B))
-        assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B))), ref)
+        assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B)), onepass=onepass), ref)
 
 
 @pytest.mark.parametrize("r,s", [((-2**31, 2**31 - 1), 1), ((-2**31, 2**31 - 1), -1),
@@ -176,21 +178,60 @@ def test_elementwise_extremes_in_last_group(shape):
     A.flat[-1] = 1 << 20
     B.flat[-2 if A.size > 1 else -1] = -5
     ref = oracle.add(oracle.compress(A), oracle.compress(B))
-    assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B))), ref)
+    for onepass in (True, False):
+        assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B)), onepass=onepass), ref)
     for s in (3, -3):
         assert_same_packed(c.scale(c.compress(dev(A)), s), oracle.scale(oracle.compress(A), s))
 
 
-def test_add_overflow_and_shape():
+@pytest.mark.parametrize("onepass", [True, False], ids=["onepass", "plan"])
+def test_add_overflow_and_shape(onepass):
     c = ccm()
     a = c.compress(dev(np.array([[2**63 - 1, 0]])))
     one = c.compress(dev(np.array([[1, 0]])))
     with pytest.raises(c.CcmError) as ei:
-        c.add(a, one)
+        c.add(a, one, onepass=onepass)
     assert ei.value.status == c._lib.E_OVERFLOW
     with pytest.raises(c.CcmError) as ei:
-        c.add(a, c.compress(dev(np.array([[1], [0]]))))
+        c.add(a, c.compress(dev(np.array([[1], [0]]))), onepass=onepass)
     assert ei.value.status == c._lib.E_SHAPE
+
+
+# One-pass add: the width the headers bound against the exact one.
+ONEPASS_CASES = {
+    # extremes of A and B at different positions: bound [0, 2000] (11 bits),
+    # exact [0, 1000] (10 bits), so the sums are packed a second time
+    "loose_bound_repack": lambda r, n: (np.where(np.arange(n) == 0, 1000, r.integers(0, 500, n)),
+                                        np.where(np.arange(n) == n - 1, 1000,
+                                                 r.integers(0, 500, n))),
+    # bound [-5, 110] (signed, 8 bits), exact [0, 100] (unsigned, 7 bits)
+    "sign_changes": lambda r, n: (np.where(np.arange(n) == 0, -5, r.integers(0, 91, n)),
+                                  np.where(np.arange(n) == 0, 5, r.integers(0, 11, n))),
+    # bound equals the exact range: one pass
+    "tight_bound": lambda r, n: (r.integers(-2**14, 2**14, n), r.integers(-2**14, 2**14, n)),
+    # unsigned 32-bit class at its top: sums up to 2^32 - 1
+    "u32_top": lambda r, n: (r.integers(0, 2**31 + 1, n), r.integers(0, 2**31, n)),
+    # a bound past int64 whose sums fit: the range pass runs first
+    "bound_past_int64": lambda r, n: (np.where(np.arange(n) % 2 == 0, 2**62 + 7, -(2**62)),
+                                      np.where(np.arange(n) % 2 == 0, -(2**62), 2**62 + 5)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(ONEPASS_CASES))
+@pytest.mark.parametrize("shape", [(1, 1), (3, 37), (300, 1001)], ids=str)
+def test_add_onepass_bound_cases(case, shape):
+    """Several blocks (300 x 1001 is 9385 groups, the last ragged) fold the
+    exact range; each case's result must equal the oracle's bit for bit."""
+    c = ccm()
+    n = shape[0] * shape[1]
+    rng = np.random.default_rng(len(case) * 7 + n)
+    a, b = ONEPASS_CASES[case](rng, n)
+    A = np.asarray(a, dtype=np.int64).reshape(shape)
+    B = np.asarray(b, dtype=np.int64).reshape(shape)
+    ref = oracle.add(oracle.compress(A), oracle.compress(B))
+    got = c.add(c.compress(dev(A)), c.compress(dev(B)), onepass=True)
+    assert_same_packed(got, ref)
+    assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B)), onepass=False), ref)
 
 
 @pytest.mark.parametrize("b,signed", [(1, False), (4, True), (13, False), (31, True),
