@@ -154,11 +154,11 @@ int ccm_add(const ccm_desc *a, const ccm_desc *b, const ccm_desc *out, void *str
 
 /* C = A + B in one call, usually one pass over A and B: the same result as
  * ccm_add_plan followed by ccm_add.  The headers bound the sums to
- * [a.vmin + b.vmin, a.vmax + b.vmax]; when that bound has a width of at most
- * 32 bits and every operand and sum fits int32 (or uint32), the sums are
- * packed at the bound's width while their exact extremes are reduced, and
- * only if the exact range needs a narrower width are they packed again at
- * that width.  Otherwise the range pass runs first, as in ccm_add_plan.
+ * [a.vmin + b.vmin, a.vmax + b.vmax]; when that bound lies inside int64 (no
+ * sum can overflow), the sums are packed at the bound's width while their
+ * exact extremes are reduced, and only if the exact range needs a narrower
+ * width are they packed again at that width.  Otherwise the range pass runs
+ * first, as in ccm_add_plan.
  * out->payload: device, caller-owned, at least ccm_add_capacity(a, b) bytes
  * (never less than the final width needs); the other fields of *out are
  * outputs, set on success.  The first ccm_payload_capacity(rows, cols,

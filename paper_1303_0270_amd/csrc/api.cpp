@@ -419,8 +419,8 @@ int ccm_add_onepass(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *s
   ccm_desc bound, exact;
   int64_t lo, hi;
   ccm::RangeSlot r;
-  if (n > 0 && vclass != ccm::EW_I64 && add_bound(a, b, &lo, &hi) &&
-      fill_desc(a->rows, a->cols, lo, hi, &bound) == CCM_OK && bound.bits <= 32) {
+  if (n > 0 && add_bound(a, b, &lo, &hi) &&
+      fill_desc(a->rows, a->cols, lo, hi, &bound) == CCM_OK) {
     // one pass: pack at the bounded width, learn the exact range meanwhile
     CCM_HIP(ccm::launch_range_init(c->slot, s));
     CCM_HIP(ccm::launch_add_pack_range(operand(a), operand(b), n, vclass, bound.bits,
@@ -442,7 +442,7 @@ int ccm_add_onepass(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *s
     *out = exact;
     return CCM_OK;
   }
-  // the range pass first (it detects overflow), then the pack
+  // a bound past int64: the range pass first (it detects overflow), then the pack
   CCM_HIP(ccm::launch_range_init(c->slot, s));
   CCM_HIP(ccm::launch_ewise_range(ccm::EW_ADD, operand(a), operand(b), 0, n, vclass, c->slot, s));
   rc = read_slot(c, s, &r);

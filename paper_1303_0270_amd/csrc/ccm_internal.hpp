@@ -269,9 +269,9 @@ hipError_t launch_ewise_range(int op, PackedOperand a, PackedOperand b, int64_t 
 hipError_t launch_ewise_pack(int op, PackedOperand a, PackedOperand b, int64_t scalar,
                              uint64_t n, int vclass, int out_bits, uint32_t *out, uint64_t cap32,
                              hipStream_t s);
-// A + B packed at out_bits (<= 32; vclass EW_I32 or EW_U32, so no sum
-// overflows) while the exact extremes of the sums fold into slot, which the
-// caller initialised.
+// A + B packed at out_bits (at most 32 for the 32-bit classes) while the
+// exact extremes of the sums fold into slot, which the caller initialised.
+// The caller guarantees that no sum leaves int64 (the headers bound them).
 hipError_t launch_add_pack_range(PackedOperand a, PackedOperand b, uint64_t n, int vclass,
                                  int out_bits, uint32_t *out, uint64_t cap32, RangeSlot *slot,
                                  hipStream_t s);

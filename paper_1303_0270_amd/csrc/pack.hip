@@ -221,15 +221,19 @@ __device__ __forceinline__ void store_block_run(const uint32_t *s_out, int out_b
 }
 
 // Packing pass of an elementwise result: thread t of block x packs the 32
-// results of group 256 x + t (zeros past n) at out_bits, through LDS.
+// results of group 256 x + t (zeros past n) at out_bits, through LDS.  With
+// RANGE (only for results known to fit int64) it also folds the exact
+// extremes of the results below n into slot.
+template <bool RANGE>
 __global__ __launch_bounds__(256) void k_ewise_pack(int op, PackedOperand a, PackedOperand b,
                                                     int64_t scalar, uint64_t n, int out_bits,
                                                     uint32_t *__restrict__ out, uint64_t cap32,
-                                                    uint64_t ngroups_out) {
+                                                    RangeSlot *slot) {
   extern __shared__ __align__(16) uint32_t s_out[];  // 256 out_bits words
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t ngroups_in = (n + kGroup - 1) / kGroup;
   int64_t vc[kGroup];
+  int64_t lo = INT64_MAX, hi = INT64_MIN;
   if (g >= ngroups_in) {
 #pragma unroll
     for (int i = 0; i < kGroup; ++i) vc[i] = 0;
@@ -240,13 +244,19 @@ __global__ __launch_bounds__(256) void k_ewise_pack(int op, PackedOperand a, Pac
     const uint64_t e0 = g * kGroup;
     int ovf = 0;
 #pragma unroll
-    for (int i = 0; i < kGroup; ++i)
+    for (int i = 0; i < kGroup; ++i) {
       vc[i] = e0 + i < n ? ewise_value(op, va[i], op == EW_ADD ? vb[i] : 0, scalar, &ovf) : 0;
+      if (RANGE && e0 + i < n) {
+        lo = vc[i] < lo ? vc[i] : lo;
+        hi = vc[i] > hi ? vc[i] : hi;
+      }
+    }
   }
+  // every thread of the block reaches the commit's barriers (no early exit)
+  if constexpr (RANGE) block_range_commit(lo, hi, 0, slot);
   codec::encode_rt(vc, out_bits, s_out + threadIdx.x * out_bits, (uint64_t)out_bits);
   __syncthreads();
   store_block_run(s_out, out_bits, out, cap32);
-  (void)ngroups_out;
 }
 
 // 32-bit variants, taken when the operands' and the result's exact ranges
@@ -493,25 +503,34 @@ hipError_t launch_ewise_pack(int op, PackedOperand a, PackedOperand b, int64_t s
     k_ewise_pack32<EW_SCALE, uint32_t, false>
         <<<grid, 256, lds32, s>>>(a, b, scalar, n, out_bits, out, cap32, nullptr);
   else
-    k_ewise_pack<<<grid, 256, (size_t)256 * (size_t)out_bits * 4u, s>>>(
-        op, a, b, scalar, n, out_bits, out, cap32, ngroups_out);
+    k_ewise_pack<false><<<grid, 256, (size_t)256 * (size_t)out_bits * 4u, s>>>(
+        op, a, b, scalar, n, out_bits, out, cap32, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_add_pack_range(PackedOperand a, PackedOperand b, uint64_t n, int vclass,
                                  int out_bits, uint32_t *out, uint64_t cap32, RangeSlot *slot,
                                  hipStream_t s) {
-  if (out_bits < 1 || out_bits > 32 || (vclass != EW_I32 && vclass != EW_U32))
+  if (out_bits < 1 || out_bits > 64 || (vclass != EW_I64 && out_bits > 32))
     return hipErrorInvalidValue;
   const uint64_t ngroups_out = (cap32 + out_bits - 1) / out_bits;
   const unsigned grid = grid_for(ngroups_out, 256, 0x7fffffffu);
-  const size_t lds32 = (size_t)256 * (size_t)out_bits * 4u;
+  const size_t lds = (size_t)256 * (size_t)out_bits * 4u;
   if (vclass == EW_I32)
     k_ewise_pack32<EW_ADD, int32_t, true>
-        <<<grid, 256, lds32, s>>>(a, b, 0, n, out_bits, out, cap32, slot);
-  else
+        <<<grid, 256, lds, s>>>(a, b, 0, n, out_bits, out, cap32, slot);
+  else if (vclass == EW_U32)
     k_ewise_pack32<EW_ADD, uint32_t, true>
-        <<<grid, 256, lds32, s>>>(a, b, 0, n, out_bits, out, cap32, slot);
+        <<<grid, 256, lds, s>>>(a, b, 0, n, out_bits, out, cap32, slot);
+  else {
+    // 64 KB of output staging at 64 bits, next to the range commit's static LDS
+    static const bool lds_set =
+        hipFuncSetAttribute(reinterpret_cast<const void *>(k_ewise_pack<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 256 * 64 * 4) ==
+        hipSuccess;
+    (void)lds_set;
+    k_ewise_pack<true><<<grid, 256, lds, s>>>(EW_ADD, a, b, 0, n, out_bits, out, cap32, slot);
+  }
   return hipGetLastError();
 }
 

@@ -211,6 +211,14 @@ ONEPASS_CASES = {
     "tight_bound": lambda r, n: (r.integers(-2**14, 2**14, n), r.integers(-2**14, 2**14, n)),
     # unsigned 32-bit class at its top: sums up to 2^32 - 1
     "u32_top": lambda r, n: (r.integers(0, 2**31 + 1, n), r.integers(0, 2**31, n)),
+    # int64 class, extremes apart: bound [0, 2^41] (42 bits), exact 41 bits
+    "i64_loose_bound": lambda r, n: (np.where(np.arange(n) == 0, 2**40, r.integers(0, 2**39, n)),
+                                     np.where(np.arange(n) == n - 1, 2**40,
+                                              r.integers(0, 2**39, n))),
+    # int64 class, signed, the bound's width reached
+    "i64_tight_bound": lambda r, n: (r.integers(-2**45, 2**45, n), r.integers(-2**45, 2**45, n)),
+    # a 64-bit result: bound [-2^62 - 2^61, 2^62 + 2^61 - 2] inside int64
+    "i64_full_width": lambda r, n: (r.integers(-2**62, 2**62, n), r.integers(-2**61, 2**61, n)),
     # a bound past int64 whose sums fit: the range pass runs first
     "bound_past_int64": lambda r, n: (np.where(np.arange(n) % 2 == 0, 2**62 + 7, -(2**62)),
                                       np.where(np.arange(n) % 2 == 0, -(2**62), 2**62 + 5)),
