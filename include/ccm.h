@@ -145,6 +145,9 @@ int ccm_gather(const ccm_desc *a, const int64_t *ii, const int64_t *jj, int64_t 
                int64_t *out, int32_t *bad, void *stream);
 
 /* ---- elementwise add and scalar multiply -------------------------------- */
+/* The Introduction asks that compressed matrices take the arithmetic of the
+ * uncompressed ones; every result here is exact and re-encoded at the width
+ * the width rule (Eq. 1) gives for its own extremes. */
 
 /* C = A + B.  Plan: range pass over the exact sums, fills out (payload
  * NULL); CCM_E_OVERFLOW iff some sum leaves int64.  Blocking.
