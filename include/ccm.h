@@ -202,6 +202,59 @@ int ccm_matmul_plan(const ccm_desc *a, const ccm_desc *b, ccm_desc *out, void *s
 int ccm_matmul(const ccm_desc *a, const ccm_desc *b, const ccm_desc *out,
                const void *scratch, uint64_t scratch_bytes, void *stream);
 
+/* ---- results whose width stays on the device (no host wait) -------------
+ *
+ * The same results as ccm_add_onepass and ccm_matmul_plan + ccm_matmul, with
+ * every step enqueued on `stream` and no host synchronization: the exact
+ * range is reduced on the device, the width rule (Eq. 1, or two's complement
+ * for a negative minimum) is applied there, and the packing kernels read the
+ * width from device memory.  For callers that keep work in flight (a serving
+ * loop): the result's header fields are read back only once the stream's
+ * work is known to be complete.
+ *
+ * ws: device, caller-owned, at least ccm_async_ws_bytes() bytes, 256-byte
+ *   aligned.  Bytes [0, 64) receive a ccm_result when the enqueued work
+ *   completes; the rest holds the range reduction's slots.  Calls whose work
+ *   may overlap on the device need distinct ws buffers.
+ * payload: device, caller-owned, at least the capacity stated for each call
+ *   (the capacity at the width the operand headers bound, which is never
+ *   less than the exact width needs).  On completion its first
+ *   ccm_payload_capacity(rows, cols, result.bits) bytes hold exactly what the
+ *   blocking calls write (zeros past 8*W); the bytes after them are
+ *   unspecified.
+ * Argument errors are returned at once; an overflow found on the device
+ * (add only) is reported in result.status. */
+typedef struct ccm_result {
+  int64_t rows, cols;
+  int64_t vmin, vmax;  /* exact extremes of the result */
+  int32_t bits;        /* its width */
+  int32_t is_signed;
+  uint64_t words;      /* W = floor(rows*cols*bits/64) + 1 */
+  int32_t status;      /* CCM_OK, or CCM_E_OVERFLOW (then no payload was written) */
+  int32_t reserved0;
+  uint64_t reserved1;
+} ccm_result;          /* 64 bytes */
+
+uint64_t ccm_async_ws_bytes(void);
+
+/* C = A + B (Introduction: the arithmetic of the uncompressed matrices).
+ * payload: at least ccm_add_capacity(a, b) bytes.  Async. */
+int ccm_add_async(const ccm_desc *a, const ccm_desc *b, void *payload, uint64_t payload_bytes,
+                  void *ws, void *stream);
+
+/* C = A B, as ccm_matmul_plan + ccm_matmul (same overflow rule, same
+ * scratch).  payload: at least ccm_matmul_capacity(a, b) bytes (0 if the
+ * operands are invalid or the overflow bound is exceeded).  Async. */
+uint64_t ccm_matmul_capacity(const ccm_desc *a, const ccm_desc *b);
+int ccm_matmul_async(const ccm_desc *a, const ccm_desc *b, void *payload,
+                     uint64_t payload_bytes, void *scratch, uint64_t scratch_bytes, void *ws,
+                     void *stream);
+
+/* Descriptor of a completed asynchronous result from a host copy of its
+ * ccm_result (the first 64 bytes of ws) and its payload pointer: checks the
+ * fields (status, width rule, word count) and fills *out.  Host only. */
+int ccm_result_desc(const ccm_result *r, void *payload, ccm_desc *out);
+
 /* ---- batched matvec (many matrices, one persistent launch) ------------- */
 
 /* A batch binds n compressed matrices (their descriptors are copied; the

@@ -224,6 +224,17 @@ class Oracle:
         self._lib.ccmref_header(ctypes.byref(m), buf)
         return bytes(buf)
 
+    def header_of(self, rows: int, cols: int, vmin: int, vmax: int) -> bytes:
+        """Header of the rows x cols matrix whose exact extremes are vmin and
+        vmax (its width from the width rule, its bitstring count from the
+        closed form); no payload is needed to form it."""
+        bits, signed = self.width(vmin, vmax)
+        m = _Matrix(rows, cols, vmin, vmax, bits, 1 if signed else 0,
+                    self.words(rows, cols, bits), None)
+        buf = (ctypes.c_uint8 * 64)()
+        self._lib.ccmref_header(ctypes.byref(m), buf)
+        return bytes(buf)
+
     def encode_run(self, vals, bits: int, nwords: int | None = None) -> np.ndarray:
         v = np.ascontiguousarray(np.asarray(vals, dtype=np.int64).ravel())
         n = v.size
@@ -438,6 +449,7 @@ compress = _ORACLE.compress
 decompress = _ORACLE.decompress
 get = _ORACLE.get
 header = _ORACLE.header
+header_of = _ORACLE.header_of
 encode_run = _ORACLE.encode_run
 decode_run = _ORACLE.decode_run
 add_dense = _ORACLE.add_dense

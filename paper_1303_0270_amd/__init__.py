@@ -12,11 +12,12 @@ import ctypes
 import torch
 
 from ._lib import (E_INVAL, E_NOMEM, E_OVERFLOW, E_RANGE, E_SHAPE, E_UNSUPPORTED, I32, I64,
-                   OK, CcmError, Desc, MethodInfo, VlbDesc, check, lib)
+                   OK, CcmError, Desc, MethodInfo, Result, VlbDesc, check, lib)
 
 __all__ = ["CMatrix", "CcmError", "compress", "decompress", "get", "gather", "add", "scale",
            "matvec_launcher",
            "matvec", "matvec_t", "matmul", "matmul_plan", "matmul_pack", "fill_uniform", "generate", "from_serialized", "words",
+           "Pending", "async_ws", "add_async", "matmul_async", "matmul_capacity",
            "packed_bytes", "payload_capacity", "width", "Batch", "DynBatch",
            "method_info", "compress_auto",
            "VlbMatrix", "vlb_compress", "vlb_decompress", "vlb_get", "vlb_matvec",
@@ -362,6 +363,100 @@ def matmul_pack(a: CMatrix, b: CMatrix, c: CMatrix, scratch: torch.Tensor, strea
 def matmul(a: CMatrix, b: CMatrix, scratch: torch.Tensor | None = None, stream=None) -> CMatrix:
     c, scratch = matmul_plan(a, b, scratch, stream)
     return matmul_pack(a, b, c, scratch, stream)
+
+
+# ---- results whose width stays on the device ------------------------------
+
+def async_ws(device="cuda") -> torch.Tensor:
+    """A workspace for one asynchronous result in flight (the device writes
+    the result's header fields into its first 64 bytes)."""
+    return torch.empty(int(lib.ccm_async_ws_bytes()), dtype=torch.uint8, device=device)
+
+
+class Pending:
+    """A matrix-valued result enqueued with ccm_add_async / ccm_matmul_async.
+    Its header fields stay on the device until the work completes; `done()`
+    polls without blocking, `get()` waits and returns the CMatrix."""
+
+    def __init__(self, payload: torch.Tensor, ws: torch.Tensor, host: torch.Tensor, stream,
+                 order: str = "C", keep=()):
+        self.payload, self.ws, self.host, self.order = payload, ws, host, order
+        self._keep = keep  # inputs that must live until the work completes
+        self.event = torch.cuda.Event()
+        self.event.record(stream)
+        self._mat = None
+
+    def done(self) -> bool:
+        return self.event.query()
+
+    def get(self) -> CMatrix:
+        if self._mat is None:
+            self.event.synchronize()
+            r = Result.from_buffer_copy(bytes(self.host.numpy().tobytes()))
+            d = Desc()
+            check(lib.ccm_result_desc(ctypes.byref(r), ctypes.c_void_p(self.payload.data_ptr()),
+                                      ctypes.byref(d)), "ccm_result_desc")
+            keep = int(lib.ccm_payload_capacity(d.rows, d.cols, d.bits))
+            self._mat = CMatrix(d, self.payload[:keep], order=self.order)
+            self._keep = ()
+        return self._mat
+
+
+def _pending(payload, ws, host, stream, order, keep):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    if host is None:
+        host = torch.empty(64, dtype=torch.uint8, pin_memory=True)
+    with torch.cuda.stream(s):
+        host.copy_(ws[:64], non_blocking=True)
+    return Pending(payload, ws, host, s, order, keep)
+
+
+def add_async(a: CMatrix, b: CMatrix, ws: torch.Tensor | None = None,
+              host: torch.Tensor | None = None, stream=None) -> Pending:
+    """C = A + B with no host wait (ccm_add_async); host: optional pinned
+    64-byte buffer that receives the result's header fields."""
+    if a.order != b.order:
+        raise CcmError(E_UNSUPPORTED, "add: operands unravelled in different orders")
+    if a.shape != b.shape:
+        raise CcmError(E_SHAPE, "add: operand shapes differ")
+    cap = int(lib.ccm_add_capacity(ctypes.byref(a.desc), ctypes.byref(b.desc)))
+    if cap == 0:
+        raise CcmError(E_INVAL, "ccm_add_capacity: invalid operands")
+    payload = torch.empty(cap, dtype=torch.uint8, device=a.payload.device)
+    ws = async_ws(a.payload.device) if ws is None else ws
+    check(lib.ccm_add_async(ctypes.byref(a.desc), ctypes.byref(b.desc), _ptr(payload), cap,
+                            _ptr(ws), _stream(stream)), "ccm_add_async")
+    return _pending(payload, ws, host, stream, a.order, (a, b))
+
+
+def matmul_capacity(a: CMatrix, b: CMatrix) -> int:
+    _row_major(a, "matmul")
+    _row_major(b, "matmul")
+    return int(lib.ccm_matmul_capacity(ctypes.byref(a.desc), ctypes.byref(b.desc)))
+
+
+def matmul_async(a: CMatrix, b: CMatrix, scratch: torch.Tensor | None = None,
+                 ws: torch.Tensor | None = None, payload: torch.Tensor | None = None,
+                 host: torch.Tensor | None = None, stream=None) -> Pending:
+    """C = A B with no host wait (ccm_matmul_async)."""
+    _row_major(a, "matmul")
+    _row_major(b, "matmul")
+    if a.cols != b.rows:
+        raise CcmError(E_SHAPE, "matmul")
+    cap = matmul_capacity(a, b)
+    need = matmul_scratch_bytes(a, b)
+    if cap == 0 or need == 0:
+        raise CcmError(E_OVERFLOW, "matmul: operands past the overflow bound")
+    dev = a.payload.device
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+    if payload is None or payload.numel() < cap:
+        payload = torch.empty(cap, dtype=torch.uint8, device=dev)
+    ws = async_ws(dev) if ws is None else ws
+    check(lib.ccm_matmul_async(ctypes.byref(a.desc), ctypes.byref(b.desc), _ptr(payload),
+                               payload.numel(), _ptr(scratch), scratch.numel(), _ptr(ws),
+                               _stream(stream)), "ccm_matmul_async")
+    return _pending(payload, ws, host, stream, "C", (a, b, scratch))
 
 
 class VlbMatrix:

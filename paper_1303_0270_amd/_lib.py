@@ -32,6 +32,15 @@ class Desc(ctypes.Structure):
                 ("words", ctypes.c_uint64), ("payload", ctypes.c_void_p)]
 
 
+class Result(ctypes.Structure):
+    """Mirror of ccm_result (64 bytes)."""
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("vmin", ctypes.c_int64), ("vmax", ctypes.c_int64),
+                ("bits", ctypes.c_int32), ("is_signed", ctypes.c_int32),
+                ("words", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_uint64)]
+
+
 class VlbDesc(ctypes.Structure):
     """Mirror of ccm_vlb_desc."""
     _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
@@ -84,6 +93,11 @@ SIGNATURES = {
     "ccm_matmul_scratch_bytes": (_u64, [_dp, _dp]),
     "ccm_matmul_plan": (ctypes.c_int, [_dp, _dp, _dp, _vp, _u64, _vp]),
     "ccm_matmul": (ctypes.c_int, [_dp, _dp, _dp, _vp, _u64, _vp]),
+    "ccm_async_ws_bytes": (_u64, []),
+    "ccm_add_async": (ctypes.c_int, [_dp, _dp, _vp, _u64, _vp, _vp]),
+    "ccm_matmul_capacity": (_u64, [_dp, _dp]),
+    "ccm_matmul_async": (ctypes.c_int, [_dp, _dp, _vp, _u64, _vp, _u64, _vp, _vp]),
+    "ccm_result_desc": (ctypes.c_int, [ctypes.POINTER(Result), _vp, _dp]),
     "ccm_batch_create": (ctypes.c_int, [_dp, _i32, _i32, ctypes.c_char_p,
                                         ctypes.POINTER(_vp)]),
     "ccm_batch_set_io": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),

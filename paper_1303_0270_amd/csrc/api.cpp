@@ -571,6 +571,112 @@ int ccm_matmul(const ccm_desc *a, const ccm_desc *b, const ccm_desc *out, const 
   return CCM_OK;
 }
 
+// ---- results whose width stays on the device ----------------------------
+// ws layout: the ccm_result at byte 0, the spread range slots from byte 256.
+constexpr uint64_t kWsSlots = 256;
+
+uint64_t ccm_async_ws_bytes(void) { return kWsSlots + ccm::kRangeBytes; }
+
+static int async_ws(void *ws, ccm::RangeSlot **slots, ccm_result **res) {
+  if (!ws || ((uintptr_t)ws % 256) != 0) return CCM_E_INVAL;
+  *res = (ccm_result *)ws;
+  *slots = (ccm::RangeSlot *)((char *)ws + kWsSlots);
+  return CCM_OK;
+}
+
+int ccm_add_async(const ccm_desc *a, const ccm_desc *b, void *payload, uint64_t payload_bytes,
+                  void *ws, void *stream) {
+  int rc = check_desc(a, true);
+  if (rc == CCM_OK) rc = check_desc(b, true);
+  if (rc != CCM_OK) return rc;
+  if (a->rows != b->rows || a->cols != b->cols) return CCM_E_SHAPE;
+  if (!payload) return CCM_E_INVAL;
+  ccm::RangeSlot *slots = nullptr;
+  ccm_result *res = nullptr;
+  rc = async_ws(ws, &slots, &res);
+  if (rc != CCM_OK) return rc;
+  if (payload_bytes < ccm_add_capacity(a, b)) return CCM_E_NOMEM;
+  const uint64_t n = nelem(a);
+  const int vclass = add_class(a, b);
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t *out = (uint32_t *)payload;
+  ccm_desc bound;
+  int64_t lo, hi;
+  CCM_HIP(ccm::launch_range_init(slots, s));
+  if (add_bound(a, b, &lo, &hi) && fill_desc(a->rows, a->cols, lo, hi, &bound) == CCM_OK) {
+    // pack at the bounded width while the exact range folds into the slots;
+    // the device then repacks only if the exact width is narrower
+    CCM_HIP(ccm::launch_add_pack_range(operand(a), operand(b), n, vclass, bound.bits, out,
+                                       ccm::cap_words32(n, bound.bits), slots, s));
+    CCM_HIP(ccm::launch_result_finalize(slots, a->rows, a->cols, 0, res, s));
+    CCM_HIP(ccm::launch_ewise_pack_dev(ccm::EW_ADD, operand(a), operand(b), 0, n, vclass,
+                                       bound.bits, bound.bits, out, res, s));
+    return CCM_OK;
+  }
+  // a bound past int64: the range pass (which flags overflow), then the pack
+  CCM_HIP(ccm::launch_ewise_range(ccm::EW_ADD, operand(a), operand(b), 0, n, vclass, slots, s));
+  CCM_HIP(ccm::launch_result_finalize(slots, a->rows, a->cols, 1, res, s));
+  CCM_HIP(ccm::launch_ewise_pack_dev(ccm::EW_ADD, operand(a), operand(b), 0, n, vclass, 64, 0,
+                                     out, res, s));
+  return CCM_OK;
+}
+
+// Widest width a product can take under the overflow rule's bound.
+static bool matmul_max_bits(const ccm_desc *a, const ccm_desc *b, int32_t *bits) {
+  unsigned __int128 bound = 0;
+  if (!matmul_bound(a, b, &bound)) return false;
+  int32_t sg = 0;
+  return width_rule(-(int64_t)bound, (int64_t)bound, bits, &sg) == CCM_OK;
+}
+
+uint64_t ccm_matmul_capacity(const ccm_desc *a, const ccm_desc *b) {
+  if (check_desc(a, false) != CCM_OK || check_desc(b, false) != CCM_OK) return 0;
+  if (a->cols != b->rows || !shape_ok(a->rows, b->cols)) return 0;
+  int32_t bits = 0;
+  if (!matmul_max_bits(a, b, &bits)) return 0;
+  return ccm_payload_capacity(a->rows, b->cols, bits);
+}
+
+int ccm_matmul_async(const ccm_desc *a, const ccm_desc *b, void *payload,
+                     uint64_t payload_bytes, void *scratch, uint64_t scratch_bytes, void *ws,
+                     void *stream) {
+  MatmulPlan mp;
+  int rc = matmul_common(a, b, scratch_bytes, scratch, &mp);
+  if (rc != CCM_OK) return rc;
+  if (!payload) return CCM_E_INVAL;
+  ccm::RangeSlot *slots = nullptr;
+  ccm_result *res = nullptr;
+  rc = async_ws(ws, &slots, &res);
+  if (rc != CCM_OK) return rc;
+  int32_t max_bits = 0;
+  if (!matmul_max_bits(a, b, &max_bits)) return CCM_E_OVERFLOW;
+  if (payload_bytes < ccm_payload_capacity(a->rows, b->cols, max_bits)) return CCM_E_NOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  CCM_HIP(ccm::launch_range_init(slots, s));
+  CCM_HIP(ccm::launch_matmul((const uint32_t *)a->payload, a->bits, a->is_signed,
+                             (const uint32_t *)b->payload, b->bits, b->is_signed, a->rows,
+                             a->cols, b->cols, mp.use_i8, mp.out32, scratch, slots, s));
+  CCM_HIP(ccm::launch_result_finalize(slots, a->rows, b->cols, 0, res, s));
+  CCM_HIP(ccm::launch_compress_dev(scratch, mp.out32 ? CCM_I32 : CCM_I64,
+                                   (uint64_t)a->rows * (uint64_t)b->cols, max_bits,
+                                   (uint32_t *)payload, res, s));
+  return CCM_OK;
+}
+
+int ccm_result_desc(const ccm_result *r, void *payload, ccm_desc *out) {
+  if (!r || !out) return CCM_E_INVAL;
+  if (r->status != CCM_OK) return r->status;
+  ccm_desc d;
+  int rc = fill_desc(r->rows, r->cols, r->vmin, r->vmax, &d);
+  if (rc != CCM_OK) return CCM_E_INVAL;
+  if (!shape_ok(r->rows, r->cols) || d.bits != r->bits || d.is_signed != r->is_signed ||
+      d.words != r->words)
+    return CCM_E_INVAL;
+  d.payload = payload;
+  *out = d;
+  return CCM_OK;
+}
+
 int ccm_fill_uniform(void *dense, int32_t dtype, int64_t n, int64_t lo, int64_t hi,
                      uint64_t seed, uint64_t stream_id, uint64_t start, void *stream) {
   if (!dense || n < 0 || (dtype != CCM_I32 && dtype != CCM_I64)) return CCM_E_INVAL;

@@ -47,6 +47,26 @@ __device__ __forceinline__ int32_t opaque_i32(int32_t v) {
   return v;
 }
 
+// The width rule (Eq. 1 for a non-negative range; otherwise the smallest
+// two's complement width holding [vmin, vmax]), for device code that decides
+// a result's width from a range it has just reduced.  vmin <= vmax.
+__host__ __device__ inline int bitlen_u64(uint64_t u) {
+  int L = 0;
+  while (L < 64 && (u >> L) != 0) ++L;
+  return L;
+}
+__host__ __device__ inline void width_of(int64_t vmin, int64_t vmax, int *bits, int *sgn) {
+  if (vmin >= 0) {
+    *sgn = 0;
+    *bits = vmax <= 1 ? 1 : bitlen_u64((uint64_t)vmax);
+  } else {
+    const int lo = bitlen_u64(~(uint64_t)vmin);
+    const int hi = vmax > 0 ? bitlen_u64((uint64_t)vmax) : 0;
+    *sgn = 1;
+    *bits = 1 + (lo > hi ? lo : hi);
+  }
+}
+
 // Two's-complement sign extension of the low `bits` bits.
 __host__ __device__ inline int64_t sext64(uint64_t u, int bits) {
   const int s = 64 - bits;
@@ -277,6 +297,27 @@ hipError_t launch_add_pack_range(PackedOperand a, PackedOperand b, uint64_t n, i
                                  hipStream_t s);
 
 hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Results whose width stays on the device.  A reduced range (the spread
+// slots) is folded on the device into a ccm_result (exact extremes, width,
+// word count, status); the packing launchers below read the width from it.
+// ---------------------------------------------------------------------------
+
+// res <- the folded range of slot as a rows x cols result; with check_flag a
+// set overflow flag gives status CCM_E_OVERFLOW (and bits 0).
+hipError_t launch_result_finalize(const RangeSlot *slot, int64_t rows, int64_t cols,
+                                  int check_flag, ccm_result *res, hipStream_t s);
+// Packs dense at res->bits (skipped when res->status != CCM_OK); the grid is
+// sized for any width up to max_bits.
+hipError_t launch_compress_dev(const void *dense, int dtype, uint64_t n, int max_bits,
+                               uint32_t *out, const ccm_result *res, hipStream_t s);
+// Elementwise packing at res->bits, skipped when res->status != CCM_OK or
+// res->bits == skip_bits (the payload already holds that width); max_bits
+// bounds res->bits.
+hipError_t launch_ewise_pack_dev(int op, PackedOperand a, PackedOperand b, int64_t scalar,
+                                 uint64_t n, int vclass, int max_bits, int skip_bits,
+                                 uint32_t *out, const ccm_result *res, hipStream_t s);
 
 // matvec: y = A x.  x dtype CCM_I32 / CCM_I64.
 hipError_t launch_matvec(const uint32_t *w, int64_t rows, int64_t cols, int bits, int sgn,

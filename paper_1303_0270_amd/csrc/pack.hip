@@ -81,11 +81,22 @@ __global__ __launch_bounds__(256) void k_range_dense(const T *__restrict__ d, ui
 // dense (n values) -> packed words [0, cap32): lane g writes words [g*b, g*b+b).
 // The block's 32*128 elements are first staged through LDS with 16-byte
 // loads, all issued before any is consumed.
-template <typename T>
+// With DEVW the width comes from res (a result whose range was reduced on the
+// device): the block exits when res reports an error, and the capacity and
+// group count follow that width; the grid covers any width up to the launch's
+// maximum.
+template <typename T, bool DEVW = false>
 __global__ __launch_bounds__(kTileThreads) void k_compress(const T *__restrict__ d, uint64_t n,
                                                            int bits, uint32_t *__restrict__ out,
                                                            uint64_t cap32, uint64_t ngroups,
-                                                           int aligned16) {
+                                                           int aligned16,
+                                                           const ccm_result *res = nullptr) {
+  if constexpr (DEVW) {
+    if (res->status != CCM_OK) return;
+    bits = res->bits;
+    cap32 = cap_words32(n, bits);
+    ngroups = (cap32 + bits - 1) / bits;
+  }
   constexpr int PER = 16 / sizeof(T);
   constexpr int NLOAD = kTileElems / (kTileThreads * PER);
   __shared__ T tile[kTileThreads * kPad];
@@ -255,11 +266,21 @@ __device__ __forceinline__ void store_block_run(const uint32_t *s_out, int out_b
 // results of group 256 x + t (zeros past n) at out_bits, through LDS.  With
 // RANGE (only for results known to fit int64) it also folds the exact
 // extremes of the results below n into slot.
-template <bool RANGE>
+// With DEVW the width comes from res: the block exits when res reports an
+// error or when res->bits == skip_bits (the payload already holds the result
+// at that width), otherwise it packs at res->bits (at most the launch's width).
+template <bool RANGE, bool DEVW = false>
 __global__ __launch_bounds__(256) void k_ewise_pack(int op, PackedOperand a, PackedOperand b,
                                                     int64_t scalar, uint64_t n, int out_bits,
                                                     uint32_t *__restrict__ out, uint64_t cap32,
-                                                    RangeSlot *slot) {
+                                                    RangeSlot *slot,
+                                                    const ccm_result *res = nullptr,
+                                                    int skip_bits = 0) {
+  if constexpr (DEVW) {
+    if (res->status != CCM_OK || res->bits == skip_bits) return;
+    out_bits = res->bits;
+    cap32 = cap_words32(n, out_bits);
+  }
   extern __shared__ __align__(16) uint32_t s_out[];  // 256 out_bits words
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t ngroups_in = (n + kGroup - 1) / kGroup;
@@ -355,11 +376,18 @@ __global__ __launch_bounds__(256) void k_ewise_range32(PackedOperand a, PackedOp
 // also folds the exact extremes of the results below n into slot, so a
 // result packed at a width bounded from the operands' headers learns its
 // exact range in the same pass over the operands.
-template <int OP, typename VT, bool RANGE>
+template <int OP, typename VT, bool RANGE, bool DEVW = false>
 __global__ __launch_bounds__(256) void k_ewise_pack32(PackedOperand a, PackedOperand b,
                                                       int64_t scalar, uint64_t n, int out_bits,
                                                       uint32_t *__restrict__ out, uint64_t cap32,
-                                                      RangeSlot *slot) {
+                                                      RangeSlot *slot,
+                                                      const ccm_result *res = nullptr,
+                                                      int skip_bits = 0) {
+  if constexpr (DEVW) {  // as in k_ewise_pack
+    if (res->status != CCM_OK || res->bits == skip_bits) return;
+    out_bits = res->bits;
+    cap32 = cap_words32(n, out_bits);
+  }
   extern __shared__ __align__(16) uint32_t s_out[];  // 256 out_bits words
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t nfull = n / kGroup;
@@ -388,6 +416,33 @@ __global__ __launch_bounds__(256) void k_ewise_pack32(PackedOperand a, PackedOpe
   codec::encode32_rt(vc, out_bits, s_out + threadIdx.x * out_bits, (uint64_t)out_bits);
   __syncthreads();
   store_block_run(s_out, out_bits, out, cap32);
+}
+
+// One wave folds the spread range slots into a ccm_result.
+__global__ __launch_bounds__(64) void k_result_finalize(const RangeSlot *slot, int64_t rows,
+                                                        int64_t cols, int check_flag,
+                                                        ccm_result *res) {
+  const RangeSlot r = slot[kRangeStride * threadIdx.x];  // 64 lanes, 64 slots
+  const int64_t lo = wave_min(r.vmin), hi = wave_max(r.vmax);
+  const int flag = __any(r.flag) ? 1 : 0;
+  if (threadIdx.x == 0) {
+    ccm_result o = {};
+    o.rows = rows;
+    o.cols = cols;
+    o.vmin = lo;
+    o.vmax = hi;
+    if (check_flag && flag) {
+      o.status = CCM_E_OVERFLOW;
+    } else {
+      int b = 0, sg = 0;
+      width_of(lo, hi, &b, &sg);
+      o.bits = b;
+      o.is_signed = sg;
+      o.words = (uint64_t)rows * (uint64_t)cols * (uint64_t)b / 64u + 1u;
+      o.status = CCM_OK;
+    }
+    *res = o;
+  }
 }
 
 __global__ void k_fill_i64(int64_t *p, uint64_t n, int64_t v) {
@@ -561,6 +616,69 @@ hipError_t launch_add_pack_range(PackedOperand a, PackedOperand b, uint64_t n, i
         hipSuccess;
     (void)lds_set;
     k_ewise_pack<true><<<grid, 256, lds, s>>>(EW_ADD, a, b, 0, n, out_bits, out, cap32, slot);
+  }
+  return hipGetLastError();
+}
+
+// Groups a packing grid must cover for every width up to max_bits (the
+// capacity's guard words make narrow widths need the most groups).
+static uint64_t groups_upto(uint64_t n, int max_bits) {
+  uint64_t g = 0;
+  for (int b = 1; b <= max_bits; ++b) {
+    const uint64_t c = (cap_words32(n, b) + b - 1) / b;
+    g = c > g ? c : g;
+  }
+  return g;
+}
+
+hipError_t launch_result_finalize(const RangeSlot *slot, int64_t rows, int64_t cols,
+                                  int check_flag, ccm_result *res, hipStream_t s) {
+  k_result_finalize<<<1, kRangeSpread, 0, s>>>(slot, rows, cols, check_flag, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_compress_dev(const void *dense, int dtype, uint64_t n, int max_bits,
+                               uint32_t *out, const ccm_result *res, hipStream_t s) {
+  if (max_bits < 1 || max_bits > 64) return hipErrorInvalidValue;
+  const uint64_t ngroups = groups_upto(n, max_bits);
+  const unsigned grid = grid_for(ngroups, kTileThreads, 0x7fffffffu);
+  const int al = ((uintptr_t)dense % 16) == 0;
+  if (dtype == CCM_I64)
+    k_compress<int64_t, true><<<grid, kTileThreads, 0, s>>>((const int64_t *)dense, n, 0, out, 0,
+                                                             0, al, res);
+  else
+    k_compress<int32_t, true><<<grid, kTileThreads, 0, s>>>((const int32_t *)dense, n, 0, out, 0,
+                                                             0, al, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_ewise_pack_dev(int op, PackedOperand a, PackedOperand b, int64_t scalar,
+                                 uint64_t n, int vclass, int max_bits, int skip_bits,
+                                 uint32_t *out, const ccm_result *res, hipStream_t s) {
+  if (max_bits < 1 || max_bits > 64 || (vclass != EW_I64 && max_bits > 32))
+    return hipErrorInvalidValue;
+  const unsigned grid = grid_for(groups_upto(n, max_bits), 256, 0x7fffffffu);
+  const size_t lds = (size_t)256 * (size_t)max_bits * 4u;
+  if (vclass == EW_I32 && op == EW_ADD)
+    k_ewise_pack32<EW_ADD, int32_t, false, true>
+        <<<grid, 256, lds, s>>>(a, b, scalar, n, 0, out, 0, nullptr, res, skip_bits);
+  else if (vclass == EW_I32)
+    k_ewise_pack32<EW_SCALE, int32_t, false, true>
+        <<<grid, 256, lds, s>>>(a, b, scalar, n, 0, out, 0, nullptr, res, skip_bits);
+  else if (vclass == EW_U32 && op == EW_ADD)
+    k_ewise_pack32<EW_ADD, uint32_t, false, true>
+        <<<grid, 256, lds, s>>>(a, b, scalar, n, 0, out, 0, nullptr, res, skip_bits);
+  else if (vclass == EW_U32)
+    k_ewise_pack32<EW_SCALE, uint32_t, false, true>
+        <<<grid, 256, lds, s>>>(a, b, scalar, n, 0, out, 0, nullptr, res, skip_bits);
+  else {
+    static const bool lds_set =
+        hipFuncSetAttribute(reinterpret_cast<const void *>(k_ewise_pack<false, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 256 * 64 * 4) ==
+        hipSuccess;
+    (void)lds_set;
+    k_ewise_pack<false, true><<<grid, 256, lds, s>>>(op, a, b, scalar, n, 0, out, 0, nullptr, res,
+                                                     skip_bits);
   }
   return hipGetLastError();
 }

@@ -11,7 +11,10 @@ over time.  The loop runs continuous batching on a few HIP streams:
   (one persistent kernel over all of them, ccm_batch_matvec_dyn) on the next
   free stream -- matrices wider than the batched kernel's x staging take the
   single-matrix kernel in the same launch; a matmul runs on a free stream of
-  its own;
+  its own (ccm_matmul_async: its result width is decided on the device, and
+  its header fields are read back only once the launch has completed);
+* nothing in the loop waits for the device: launches are enqueued, and
+  completion is polled;
 * launches on different streams overlap on the device; requests that arrive
   while others run are admitted as slots and memory free up and join the next
   launch;
@@ -29,9 +32,8 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from . import (CMatrix, generate, matmul_pack, matmul_plan, matmul_scratch_bytes, matvec,
-               payload_capacity)
-from . import width as width_rule
+from . import (CMatrix, Pending, generate, lib, matmul_async, matmul_capacity,
+               matmul_scratch_bytes, matvec)
 from .batch import BATCH_MAX_COLS, DynBatch
 
 
@@ -46,6 +48,7 @@ class Request:
     footprint: int = 0
     y: torch.Tensor | None = None  # matvec result
     c: CMatrix | None = None  # matmul result
+    pending: Pending | None = None  # matmul result while in flight
     done: float = math.nan  # completion, seconds after the start of the run
     launch: int = -1  # id of the launch that served it
 
@@ -54,21 +57,22 @@ class Request:
 class _Launch:
     lid: int
     stream_idx: int
+    start: torch.cuda.Event
     event: torch.cuda.Event
     requests: list
-    scratch: list = field(default_factory=list)
+    hosts: list = field(default_factory=list)  # pinned result buffers to hand back
 
 
 def request_footprint(req: Request, pool) -> int:
-    """Device bytes a request holds while in flight."""
+    """Device bytes a request holds while in flight: x and y, or B, the
+    result at the width the operand headers bound, the matmul scratch and
+    the result's workspace."""
     a = pool[req.mat]
     if req.kind == "mv":
         return 4 * a.cols + 8 * a.rows
     b = req.b
-    bound = a.cols * max(abs(a.vmin), abs(a.vmax)) * max(abs(b.vmin), abs(b.vmax))
-    cb, _ = width_rule(-bound, bound) if bound < (1 << 63) else (64, True)
-    return (payload_capacity(b.rows, b.cols, b.bits) + payload_capacity(a.rows, b.cols, cb) +
-            matmul_scratch_bytes(a, b))
+    return (b.payload.numel() + matmul_capacity(a, b) + matmul_scratch_bytes(a, b) +
+            int(lib.ccm_async_ws_bytes()))
 
 
 class Server:
@@ -81,6 +85,9 @@ class Server:
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
         self.dyn = [DynBatch(max_mats=max_batch, max_items=1 << 17, slots=4)
                     for _ in range(streams)]
+        # pinned 64-byte buffers receiving matmul results' header fields
+        self._hosts_mem = torch.empty((max_inflight, 64), dtype=torch.uint8, pin_memory=True)
+        self._hosts = [self._hosts_mem[i] for i in range(max_inflight)]
 
     def close(self):
         for d in self.dyn:
@@ -105,6 +112,8 @@ class Server:
         n = len(reqs)
         finished = 0
         launches = []
+        done_launches = []
+        max_inflight_seen = 0
         torch.cuda.synchronize()
         start_evt = torch.cuda.Event(enable_timing=True)
         start_evt.record()
@@ -114,18 +123,23 @@ class Server:
             while nxt < n and reqs[nxt].arrival <= now:
                 waiting.append(reqs[nxt])
                 nxt += 1
-            # completions
+            # completions (polled; the header fields of a matmul result are
+            # on the host once its launch's event has completed)
             still = []
             for L in inflight:
                 if L.event.query():
                     t_done = start_evt.elapsed_time(L.event) * 1e-3
                     for r in L.requests:
+                        if r.pending is not None:
+                            r.c = r.pending.get()
+                            r.pending = None
                         r.done = t_done
                         used_bytes -= r.footprint
                         admitted -= 1
                         finished += 1
                     free_streams.append(L.stream_idx)
-                    L.scratch.clear()
+                    self._hosts.extend(L.hosts)
+                    done_launches.append(L)
                 else:
                     still.append(L)
             inflight = still
@@ -140,17 +154,16 @@ class Server:
             while free_streams and (pending_mv or pending_mm):
                 si = free_streams.pop(0)
                 stream = self.streams[si]
-                evt = torch.cuda.Event(enable_timing=True)
-                L = _Launch(lid, si, evt, [])
+                L = _Launch(lid, si, torch.cuda.Event(enable_timing=True),
+                            torch.cuda.Event(enable_timing=True), [])
                 with torch.cuda.stream(stream):
+                    L.start.record(stream)
                     if pending_mm and (not pending_mv or len(pending_mm) * 8 >= len(pending_mv)):
                         r = pending_mm.pop(0)
-                        a = self.pool[r.mat]
-                        c, scratch = matmul_plan(a, r.b, stream=stream)
-                        matmul_pack(a, r.b, c, scratch, stream=stream)
-                        r.c = c
+                        host = self._hosts.pop()
+                        r.pending = matmul_async(self.pool[r.mat], r.b, host=host, stream=stream)
                         L.requests.append(r)
-                        L.scratch.append(scratch)
+                        L.hosts.append(host)
                     else:
                         group = pending_mv[: self.max_batch]
                         del pending_mv[: len(group)]
@@ -167,16 +180,28 @@ class Server:
                                                 [r.x for r in narrow], [r.y for r in narrow],
                                                 stream=stream)
                         L.requests.extend(group)
-                    evt.record(stream)
+                    L.event.record(stream)
                 for r in L.requests:
                     r.launch = lid
                 inflight.append(L)
+                max_inflight_seen = max(max_inflight_seen, len(inflight))
                 launches.append(len(L.requests))
                 lid += 1
             if poll_sleep:
                 time.sleep(poll_sleep)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        # launches whose device execution overlapped an earlier launch's, and
+        # matmul launches that overlapped a matvec launch
+        spans = sorted((start_evt.elapsed_time(L.start), start_evt.elapsed_time(L.event),
+                        L.requests[0].kind) for L in done_launches)
+        overlapped, end_max = 0, -math.inf
+        for s0, s1, _ in spans:
+            overlapped += s0 < end_max
+            end_max = max(end_max, s1)
+        mv_spans = [(s0, s1) for s0, s1, k in spans if k == "mv"]
+        mm_with_mv = sum(any(a0 < s1 and s0 < a1 for a0, a1 in mv_spans)
+                         for s0, s1, k in spans if k == "mm")
         lat = np.array([r.done - r.arrival for r in reqs])
         span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
         touched = sum(8 * self.pool[r.mat].words for r in reqs)
@@ -187,6 +212,9 @@ class Server:
                 "mean_ms": round(float(lat.mean()) * 1e3, 3),
                 "throughput_rps": round(n / span, 1),
                 "throughput_gbs": round(touched / span / 1e9, 1),
+                "max_launches_in_flight": max_inflight_seen,
+                "overlapped_launches": int(overlapped),
+                "mm_overlapping_mv": int(mm_with_mv),
                 "wall_s": round(wall, 4)}
 
 

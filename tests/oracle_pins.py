@@ -146,6 +146,24 @@ def pin_worked_example(o):
     assert h[48:] == bytes(16)
 
 
+def pin_signed_headers(o):
+    """The header and bitstring of a small signed matrix, row-major and
+    column-major, against bytes derived by hand: flags 1 and 3, the negative
+    min in little-endian two's complement, 4-bit two's complement fields."""
+    g = _golden_kv("signed_headers.txt")
+    A = np.array([[int(v) for v in r.split()] for r in g["matrix"].split(";")], dtype=np.int64)
+    hx = lambda key: bytes(int(t, 16) for t in g[key].split())
+    p = o.compress(A)
+    assert (p.bits, p.is_signed) == (int(g["bits"]), True)
+    assert o.header(p) == hx("header_row_major")
+    assert [int(w) for w in p.payload] == [int(g["payload_row_major"], 16)]
+    q = o.compress_cm(A)
+    assert (q.bits, q.is_signed) == (int(g["bits"]), True)
+    assert o.header_cm(q) == hx("header_col_major")
+    assert [int(w) for w in q.payload] == [int(g["payload_col_major"], 16)]
+    assert o.decompress(p).tolist() == A.tolist() == o.decompress_cm(q).tolist()
+
+
 def pin_word_count(o):
     """floor(n*b/64) + 1 bitstrings; the payload uses exactly n*b bits (Eq. 15)."""
     rng = np.random.default_rng(11)
@@ -728,7 +746,7 @@ def pin_method_bruteforce(o):
 
 
 ALL_PINS = [pin_table1, pin_eq1_special_case, pin_bitlen_bruteforce, pin_width_bruteforce,
-            pin_worked_example, pin_word_count, pin_round_trip, pin_signed_small_bruteforce,
+            pin_worked_example, pin_signed_headers, pin_word_count, pin_round_trip, pin_signed_small_bruteforce,
             pin_locality, pin_get, pin_ops_bruteforce, pin_ops_exhaustive_2x2, pin_identities,
             pin_overflow_rules, pin_vlb_worked_example, pin_vlb_layout, pin_vlb_extremes,
             pin_vlb_ops_bruteforce, pin_vlb_exhaustive_small, pin_cm_worked_example,

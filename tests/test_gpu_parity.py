@@ -242,6 +242,60 @@ def test_add_onepass_bound_cases(case, shape):
     assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B)), onepass=False), ref)
 
 
+# The one-pass add folds each packing block's extremes (8192 elements per
+# block) into one of 64 range slots (block i into slot i mod 64), and a block
+# issues its atomic only when its extreme beats the value it reads in its
+# slot.  2048 x 4096 is 1024 blocks, 16 per slot: these patterns put the
+# extremes where that skip decides the result.
+_NB = 8192
+
+
+def _blk(n):
+    return np.arange(n, dtype=np.int64) // _NB
+
+
+def _peak(n):
+    e = np.arange(n, dtype=np.int64)
+    return (e % _NB == 5) & ((_blk(n) % 7 == 0) | (_blk(n) == n // _NB - 1))
+
+
+LATE_EXTREME_CASES = {
+    # every block's maximum beats all earlier blocks' (no skip for the max),
+    # every block's minimum is above block 0's (skips for the min)
+    "increasing": lambda r, n: (_blk(n) * 3 + r.integers(0, 3, n), r.integers(0, 3, n)),
+    # the reverse: the exact minimum only in the last block
+    "decreasing": lambda r, n: ((1023 - _blk(n)) * 3 + r.integers(0, 3, n), r.integers(0, 3, n)),
+    # random values with a spike in block 1000 (slot 40, written by 15 earlier
+    # blocks) and a dip in block 900 (slot 4)
+    "late_spikes": lambda r, n: (np.where(np.arange(n) == 1000 * _NB + 17, 5000,
+                                          r.integers(0, 1000, n)),
+                                 np.where(np.arange(n) == 900 * _NB + 3, -3000,
+                                          r.integers(0, 1000, n))),
+    # the same maximum reached in every seventh block and in the last one
+    "repeated_extremes": lambda r, n: (np.where(_peak(n), 700, 350),
+                                       np.where(_peak(n), 300, r.integers(0, 300, n))),
+}
+
+
+@pytest.mark.parametrize("scale", [1, 2**35], ids=["i32_class", "i64_class"])
+@pytest.mark.parametrize("case", sorted(LATE_EXTREME_CASES))
+def test_add_onepass_skip_fold(case, scale):
+    """Thousands of packing blocks per add: the exact extremes folded with
+    skipped atomics must still be the true ones (header and payload equal the
+    oracle's byte for byte), for both value classes."""
+    c = ccm()
+    shape = (2048, 4096)
+    n = shape[0] * shape[1]
+    rng = np.random.default_rng(len(case) * 11 + (scale > 1))
+    a, b = LATE_EXTREME_CASES[case](rng, n)
+    A = (np.asarray(a, dtype=np.int64) * scale).reshape(shape)
+    B = (np.asarray(b, dtype=np.int64) * scale).reshape(shape)
+    ref = oracle.add(oracle.compress(A), oracle.compress(B))
+    got = c.add(c.compress(dev(A)), c.compress(dev(B)), onepass=True)
+    assert (got.vmin, got.vmax) == (int((A + B).min()), int((A + B).max()))
+    assert_same_packed(got, ref)
+
+
 @pytest.mark.parametrize("b,signed", [(1, False), (4, True), (13, False), (31, True),
                                       (40, False), (64, True)])
 def test_scale_matches_oracle(b, signed):

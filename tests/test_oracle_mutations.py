@@ -25,6 +25,13 @@ MUTANTS = {
     # fields written most significant bit first (consistently on both sides)
     "msb_first_fields": [("put_bit(words, p0 + (uint64_t)t,", "put_bit(words, p0 + (uint64_t)(bits - 1 - t),"),
                          ("get_bit(words, p0 + (uint64_t)t) << t", "get_bit(words, p0 + (uint64_t)(bits - 1 - t)) << t")],
+    # the header's signed flag never set
+    "header_flag_unsigned": [("out[7] = (uint8_t)(m->is_signed ? 1u : 0u);", "out[7] = 0;")],
+    # the header's min written as its magnitude
+    "header_min_magnitude": [("put_le(out + 24, (uint64_t)m->vmin, 8);",
+                              "put_le(out + 24, (uint64_t)(m->vmin < 0 ? -m->vmin : m->vmin), 8);")],
+    # the column-major flag replaces the signed flag instead of joining it
+    "header_cm_flag_only": [("out[7] = (uint8_t)(out[7] | 2u);", "out[7] = 2u;")],
     # the "+1" of the bitstring count dropped
     "word_count": [("/ 64u + 1u", "/ 64u")],
     # bit-length off by one
