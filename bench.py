@@ -321,7 +321,9 @@ def main():
                                                 ctypes.c_void_p, ctypes.c_void_p,
                                                 ctypes.c_void_p]
     bench_lib.ccmb_read_bytes.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
-                                          ctypes.c_void_p]
+                                          ctypes.c_int, ctypes.c_void_p]
+    bench_lib.ccmb_mfma_i8_peak.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                            ctypes.c_void_p]
     stream = torch.cuda.current_stream()
     sp = ctypes.c_void_p(stream.cuda_stream)
     n = args.n
@@ -471,19 +473,35 @@ def main():
     del copies32, dense32
     torch.cuda.empty_cache()
 
+    # practical HBM read peak: a grid-stride 16-byte read of 1 GiB slices of a
+    # 4 GiB buffer (each read leaves the 256 MB cache), over several grid
+    # sizes; the best is reported
     big = torch.empty(4 << 30, dtype=torch.uint8, device="cuda")
     big.fill_(1)
     sink = torch.zeros(1, dtype=torch.int32, device="cuda")
-    for _ in range(2):
-        bench_lib.ccmb_read_bytes(ctypes.c_void_p(big.data_ptr()), big.numel(),
-                                  ctypes.c_void_p(sink.data_ptr()), sp)
+    gib = 1 << 30
+    read_by_grid = {}
+    for grid in (1024, 2048, 4096, 8192):
+        def rd(i, grid=grid):
+            bench_lib.ccmb_read_bytes(ctypes.c_void_p(big.data_ptr() + (i % 4) * gib), gib,
+                                      ctypes.c_void_p(sink.data_ptr()), grid, sp)
+        for i in range(2):
+            rd(i)
+        e0.record()
+        for i in range(8):
+            rd(i)
+        e1.record()
+        torch.cuda.synchronize()
+        read_by_grid[grid] = round(gib / (e0.elapsed_time(e1) * 1e-3 / 8) / 1e9, 1)
+    read_peak = max(read_by_grid.values())
+    # int8 matrix-unit peak: 4 waves per SIMD of back-to-back MFMA chains
+    waves, iters = 4 * 4 * 256, 2048
+    bench_lib.ccmb_mfma_i8_peak(waves, 64, ctypes.c_void_p(sink.data_ptr()), sp)
     e0.record()
-    for _ in range(5):
-        bench_lib.ccmb_read_bytes(ctypes.c_void_p(big.data_ptr()), big.numel(),
-                                  ctypes.c_void_p(sink.data_ptr()), sp)
+    bench_lib.ccmb_mfma_i8_peak(waves, iters, ctypes.c_void_p(sink.data_ptr()), sp)
     e1.record()
     torch.cuda.synchronize()
-    read_peak = big.numel() / (e0.elapsed_time(e1) * 1e-3 / 5) / 1e9
+    i8_peak = 4.0 * 65536 * iters * waves / (e0.elapsed_time(e1) * 1e-3) / 1e12
     # plain copy of known size (calibrates the FETCH_SIZE / WRITE_SIZE counters)
     half = big[: 1 << 30]
     big[2 << 30: 3 << 30].copy_(half)
@@ -521,12 +539,17 @@ def main():
         "gelem_s_packed": round(len(per_width) * n * n / sweep_t / 1e9, 1),
         "dense_i32": dense_i32,
         "hbm_read_probe_gbs": round(read_peak, 1),
+        "hbm_read_probe_by_grid": read_by_grid,
+        "roofline_practical": {"hbm_read_gbs": round(read_peak, 1),
+                               "frac": round(value / read_peak, 4),
+                               "i8_mfma_tops": round(i8_peak, 1),
+                               "i8_mfma_spec_tops": 5000.0},
     }
 
     log("dense int32 and read probe done")
     if not args.no_extras and not args.profile:
         from bench_extras import run_extras
-        result["extras"] = run_extras(torch, ccm, log)
+        result["extras"] = run_extras(torch, ccm, log, i8_peak_measured=i8_peak)
 
     if not args.no_cpu_baseline and not args.profile:
         log("extras done; timing the oracle")
@@ -560,49 +583,103 @@ def matvec_only(args, torch, W, ccm):
 
 def cpu_baseline(W, rows=192, vlb_rows=32):
     """The oracle on the host cores, on the first `rows` rows of each of the
-    twelve sweep matrices: the same step as the GPU (compress A and B, matvec,
-    add, scale by 7, decompress).  value = the oracle's packed-matvec GB/s."""
+    twelve sweep matrices: the step's operations (compress A and B, matvec,
+    add, scale by 7, decompress), each timed on one thread and on all cores.
+    All cores: the sample's rows are split into one chunk per core and the
+    oracle runs on the chunks from a thread pool (its calls release the
+    interpreter lock); its own OpenMP loops are held to one thread throughout.
+    value = the oracle's packed-matvec GB/s on all cores."""
+    import ctypes.util
+    from concurrent.futures import ThreadPoolExecutor
+
+
     import oracle
-    t_mv = t_step = 0.0
-    mv_bytes = 0.0
+    cores = oracle.threads()
+    gomp = ctypes.CDLL(ctypes.util.find_library("gomp") or "libgomp.so.1")
+    gomp.omp_set_num_threads(1)
+    samples = []
     for k in W.SWEEP_WIDTHS:
         for signed in (False, True):
             a_s, b_s, x_s, s = W.sweep(k, signed)
-            A, B, xv = a_s.rows_slice(0, rows), b_s.rows_slice(0, rows), x_s.dense()
+            samples.append((a_s.rows_slice(0, rows), b_s.rows_slice(0, rows), x_s.dense(), s))
+
+    def run_ops(part):
+        """part: list of (A rows, B rows, x, s); returns seconds per op."""
+        t = dict.fromkeys(("compress", "matvec", "add", "scale", "decompress"), 0.0)
+        for A, B, xv, s in part:
             t0 = time.perf_counter()
             pa, pb = oracle.compress(A), oracle.compress(B)
             t1 = time.perf_counter()
             oracle.matvec(pa, xv)
             t2 = time.perf_counter()
             oracle.add(pa, pb)
-            oracle.scale(pa, s)
-            oracle.decompress(pa)
             t3 = time.perf_counter()
-            t_mv += t2 - t1
-            t_step += t3 - t0
-            mv_bytes += rows * a_s.cols * pa.bits / 8
+            oracle.scale(pa, s)
+            t4 = time.perf_counter()
+            oracle.decompress(pa)
+            t5 = time.perf_counter()
+            for key, dt in (("compress", t1 - t0), ("matvec", t2 - t1), ("add", t3 - t2),
+                            ("scale", t4 - t3), ("decompress", t5 - t4)):
+                t[key] += dt
+        return t
+
+    w0 = time.perf_counter()
+    one = run_ops(samples)
+    t_one = time.perf_counter() - w0
+    chunk = -(-rows // cores)
+    parts = [[(A[r:r + chunk], B[r:r + chunk], xv, s) for A, B, xv, s in samples]
+             for r in range(0, rows, chunk)]
+    packed = [[(oracle.compress(A), oracle.compress(B), xv, s) for A, B, xv, s in p]
+              for p in parts]
+
+    def all_cores(fn):
+        """Wall time of fn(i) for every chunk i, one pool thread per chunk."""
+        w = time.perf_counter()
+        with ThreadPoolExecutor(len(parts)) as ex:
+            list(ex.map(fn, range(len(parts))))
+        return time.perf_counter() - w
+
+    alls = {
+        "compress": all_cores(lambda i: [(oracle.compress(A), oracle.compress(B))
+                                         for A, B, _, _ in parts[i]]),
+        "matvec": all_cores(lambda i: [oracle.matvec(pa, xv) for pa, _, xv, _ in packed[i]]),
+        "add": all_cores(lambda i: [oracle.add(pa, pb) for pa, pb, _, _ in packed[i]]),
+        "scale": all_cores(lambda i: [oracle.scale(pa, s) for pa, _, _, s in packed[i]]),
+        "decompress": all_cores(lambda i: [oracle.decompress(pa) for pa, _, _, _ in packed[i]]),
+    }
+    t_all = sum(alls.values())
+    n = rows * samples[0][0].shape[1]
+    a_bytes = sum(n * oracle.width(int(A.min()), int(A.max()))[0] / 8 for A, _, _, _ in samples)
+    per_op = {}
+    for key in ("compress", "matvec", "add", "scale", "decompress"):
+        per_op[key] = {"one_thread_s": round(one[key], 4), "all_cores_s": round(alls[key], 4),
+                       "one_thread_melem_s": round(12 * n / one[key] / 1e6, 2),
+                       "all_cores_melem_s": round(12 * n / alls[key] / 1e6, 2)}
     # Method 2: the oracle's matvec on the first rows of each Beta workload
-    # (each row compressed on its own; its y entry is the same)
+    # (each row compressed on its own; its y entry is the same), one thread
     vlb = {}
     for name in W.VLB_BETAS:
         spec, x_s = W.vlb_sweep(name)
         xv = x_s.dense()
-        packed = [oracle.vlb_compress(spec.rows_slice(r, r + 1)) for r in range(vlb_rows)]
+        pk = [oracle.vlb_compress(spec.rows_slice(r, r + 1)) for r in range(vlb_rows)]
         t0 = time.perf_counter()
-        for p in packed:
+        for p in pk:
             oracle.vlb_matvec(p, xv)
         dt = time.perf_counter() - t0
         vlb[name] = {"gelem_s": round(vlb_rows * spec.cols / dt / 1e9, 5),
-                     "gb_s": round(sum(p.nbits for p in packed) / 8 / dt / 1e9, 5)}
-    return {"value": round(mv_bytes / t_mv / 1e9, 4), "unit": "GB/s",
-            "cores": oracle.threads(), "kind": "oracle",
+                     "gb_s": round(sum(p.nbits for p in pk) / 8 / dt / 1e9, 5)}
+    gomp.omp_set_num_threads(cores)
+    return {"value": round(a_bytes / alls["matvec"] / 1e9, 4), "unit": "GB/s",
+            "cores": cores, "kind": "oracle",
+            "value_one_thread": round(a_bytes / one["matvec"] / 1e9, 4),
+            "per_op": per_op,
+            "step_one_thread_s": round(t_one, 2), "step_all_cores_s": round(t_all, 2),
             "vlb_matvec": vlb, "vlb_sample": f"rows 0..{vlb_rows - 1} of each 16384 x 16384 "
                                              "Beta workload, one thread",
             "sample": f"rows 0..{rows - 1} of each of the 12 sweep matrices ({12 * rows} x 16384 "
-                      "elements): compress A and B, matvec, add, scale, decompress; value = "
-                      "packed bytes of A over the oracle's matvec time",
-            "matvec_seconds": round(t_mv, 3), "step_seconds": round(t_step, 2),
-            "step_ms_per_row": round(t_step / (12 * rows) * 1e3, 3)}
+                      "elements): compress A and B, matvec, add, scale, decompress, each on one "
+                      "thread and on all cores (rows split over a thread pool); value = packed "
+                      "bytes of A over the oracle's all-cores matvec time"}
 
 
 if __name__ == "__main__":

@@ -1,7 +1,6 @@
 // Comparison kernels for the benchmark, outside the compressed-matrix
-// library: a dense int32 matvec (the "Gelem/s vs dense int32" reference, laid
-// out like the packed kernel: x panel in LDS, 4 rows per wave, 16-byte loads)
-// and an HBM read-bandwidth probe.
+// library: a dense int32 matvec (the "Gelem/s vs dense int32" reference), an
+// HBM read-bandwidth probe and an int8 matrix-unit peak probe.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -59,6 +58,79 @@ __global__ __launch_bounds__(kThreads) void k_dense_mv(const int32_t *__restrict
   }
 }
 
+// Dense int32 matvec for cols <= 16384 (cols % 4 == 0, 16-byte aligned rows):
+// 512-lane blocks, x staged once per block in LDS (64 KB), one row per wave
+// at a time (grid-stride), each lane keeping eight 16-byte loads of the row in
+// flight (addresses clamped, so every load is issued unconditionally), 64-bit
+// products.  y[r] is written once: no zero fill, no atomics.
+constexpr int kDenseThreads = 512, kDenseUnroll = 8;
+
+__global__ __launch_bounds__(kDenseThreads) void k_dense_mv_wide(const int32_t *__restrict__ A,
+                                                                 int64_t rows, int64_t cols,
+                                                                 const int32_t *__restrict__ x,
+                                                                 int64_t *__restrict__ y) {
+  extern __shared__ int4 xs4[];
+  const int nq = (int)(cols / 4);
+  const int4 *x4 = reinterpret_cast<const int4 *>(x);
+  for (int q = threadIdx.x; q < nq; q += kDenseThreads) xs4[q] = x4[q];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = kDenseThreads / 64;
+  for (int64_t r = (int64_t)blockIdx.x * nw + wave; r < rows; r += (int64_t)gridDim.x * nw) {
+    const int4 *a4 = reinterpret_cast<const int4 *>(A + r * cols);
+    int64_t acc0 = 0, acc1 = 0;
+    for (int q0 = lane; q0 < nq; q0 += 64 * kDenseUnroll) {
+      int4 v[kDenseUnroll];
+#pragma unroll
+      for (int u = 0; u < kDenseUnroll; ++u) {
+        const int q = q0 + 64 * u;
+        v[u] = a4[q < nq ? q : nq - 1];
+      }
+#pragma unroll
+      for (int u = 0; u < kDenseUnroll; ++u) {
+        const int q = q0 + 64 * u;
+        const int4 xv = xs4[q < nq ? q : nq - 1];
+        const int64_t t0 = (int64_t)v[u].x * xv.x + (int64_t)v[u].y * xv.y;
+        const int64_t t1 = (int64_t)v[u].z * xv.z + (int64_t)v[u].w * xv.w;
+        if (q < nq) {
+          acc0 += t0;
+          acc1 += t1;
+        }
+      }
+    }
+    int64_t t = acc0 + acc1;
+    for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, 64);
+    if (lane == 0) y[r] = t;
+  }
+}
+
+// Peak rate of the int8 matrix units: each wave runs four independent chains
+// of v_mfma_i32_32x32x32_i8 (2 * 32 * 32 * 32 operations each) with no memory
+// traffic; operands come from the lane index so nothing folds.
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef int v16i_t __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(256) void k_mfma_i8_peak(int iters, int *sink) {
+  const int lane = threadIdx.x & 63;
+  v4i_t a = {lane, lane * 3 + 1, lane ^ 0x55, 7 - lane};
+  v4i_t b = {lane * 5, lane + 9, lane ^ 0x33, lane * 7 + 3};
+  v16i_t acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[t], 0, 0, 0);
+  }
+  int s = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s ^= acc[t][r];
+  if (s == 0x12345678) sink[0] = s;
+}
+
 __global__ void k_zero(int64_t *y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = 0;
@@ -80,6 +152,20 @@ __global__ __launch_bounds__(256) void k_read(const uint4 *__restrict__ p, uint6
 extern "C" int ccmb_dense_matvec_i32(const int32_t *A, int64_t rows, int64_t cols,
                                      const int32_t *x, int64_t *y, void *stream) {
   hipStream_t s = (hipStream_t)stream;
+  if (cols <= 16384 && cols % 4 == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)x % 16) == 0) {
+    const size_t lds = (size_t)cols * 4;
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_dense_mv_wide),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+      attr = true;
+    }
+    const int64_t per = kDenseThreads / 64;
+    int64_t g = (rows + per - 1) / per;
+    g = g > 512 ? 512 : (g < 1 ? 1 : g);  // two 64 KB blocks per compute unit
+    k_dense_mv_wide<<<(unsigned)g, kDenseThreads, lds, s>>>(A, rows, cols, x, y);
+    return hipGetLastError() == hipSuccess ? 0 : -6;
+  }
   const int64_t npanels = (cols + kPanel - 1) / kPanel;
   const int64_t nrb = (rows + 4 * kRows - 1) / (4 * kRows);
   int64_t gx = nrb < 1024 ? nrb : 1024;
@@ -92,8 +178,19 @@ extern "C" int ccmb_dense_matvec_i32(const int32_t *A, int64_t rows, int64_t col
   return hipGetLastError() == hipSuccess ? 0 : -6;
 }
 
-extern "C" int ccmb_read_bytes(const void *buf, uint64_t nbytes, uint32_t *sink, void *stream) {
+// Streaming read of nbytes with `grid` blocks of 256 lanes (one 16-byte load
+// per lane per grid-wide sweep).
+extern "C" int ccmb_read_bytes(const void *buf, uint64_t nbytes, uint32_t *sink, int grid,
+                               void *stream) {
   hipStream_t s = (hipStream_t)stream;
-  k_read<<<4096, 256, 0, s>>>((const uint4 *)buf, nbytes / 16, sink);
+  k_read<<<grid > 0 ? grid : 4096, 256, 0, s>>>((const uint4 *)buf, nbytes / 16, sink);
+  return hipGetLastError() == hipSuccess ? 0 : -6;
+}
+
+// `waves` waves each running `iters` steps of four int8 MFMAs (32x32x32):
+// 4 * 65536 * iters * waves integer operations.
+extern "C" int ccmb_mfma_i8_peak(int waves, int iters, int *sink, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  k_mfma_i8_peak<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(iters, sink);
   return hipGetLastError() == hipSuccess ? 0 : -6;
 }

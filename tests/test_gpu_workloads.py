@@ -100,7 +100,7 @@ def test_sweep_full_size_sampled(k, signed):
         assert np.array_equal(words_of_rows(A, r, r + 1), pa.payload[: pa.words - 1])
         # decompress: the row's values, as the oracle decodes them
         got = dec[r].cpu().numpy()
-        assert np.array_equal(got, oracle.decompress(pa)[0]) and np.array_equal(got, va)
+        assert np.array_equal(got, oracle.decompress(pa)[0]) and np.array_equal(got, va[0])
         # matvec
         assert y[r] == oracle.matvec(pa, xv)[0]
         # add and scale, encoded at the oracle's width of the exact result range
