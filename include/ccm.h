@@ -343,6 +343,16 @@ uint64_t ccm_matvec_t_scratch_bytes(const ccm_desc *a);
 int ccm_matvec_t(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, void *scratch,
                  uint64_t scratch_bytes, void *stream);
 
+/* y = A^T x as ccm_matvec_t with a scratch buffer, for callers that cannot
+ * allocate device memory (code under stream capture, serving loops, harnesses
+ * that forbid allocation): the split partial sums go to a buffer the library
+ * holds for the life of the process, 32 int64 per column for up to 65536
+ * columns (16 MB per device).  Allocates nothing.  a->cols > 65536 is
+ * CCM_E_NOMEM.  Calls whose work overlaps on one device share that buffer and
+ * race: order them (one stream).  Async. */
+int ccm_matvec_t_noalloc(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y,
+                         void *stream);
+
 /* Packs A, given dense row-major (out->cols x out->rows values of dtype),
  * unravelled by column into out->payload; out describes A^T and comes from
  * ccm_compress_plan(dense, dtype, out->rows, out->cols, ...) (the range pass

@@ -116,6 +116,7 @@ SIGNATURES = {
     "ccm_method_plan": (ctypes.c_int, [_vp, _i32, _i64, _i64, ctypes.POINTER(MethodInfo), _vp]),
     "ccm_matvec_t_scratch_bytes": (_u64, [_dp]),
     "ccm_matvec_t": (ctypes.c_int, [_dp, _vp, _i32, _vp, _vp, _u64, _vp]),
+    "ccm_matvec_t_noalloc": (ctypes.c_int, [_dp, _vp, _i32, _vp, _vp]),
     "ccm_compress_cm": (ctypes.c_int, [_vp, _i32, _dp, _vp]),
     "ccm_header_encode_cm": (ctypes.c_int, [_dp, ctypes.POINTER(ctypes.c_uint8)]),
     "ccm_header_decode_cm": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint8), _dp]),

@@ -791,6 +791,20 @@ int ccm_matvec_t(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, v
   return CCM_OK;
 }
 
+int ccm_matvec_t_noalloc(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y,
+                         void *stream) {
+  int rc = check_desc(a, true);
+  if (rc != CCM_OK) return rc;
+  if (!x || !y || (xdtype != CCM_I32 && xdtype != CCM_I64)) return CCM_E_INVAL;
+  if (a->cols > ccm::kNoAllocColsT) return CCM_E_NOMEM;
+  int64_t *part = nullptr;
+  uint64_t words = 0;
+  CCM_HIP(ccm::static_matvec_t_scratch(&part, &words));
+  CCM_HIP(ccm::launch_matvec_t((const uint32_t *)a->payload, a->rows, a->cols, a->bits,
+                               a->is_signed, x, xdtype, y, part, words, (hipStream_t)stream));
+  return CCM_OK;
+}
+
 int ccm_compress_cm(const void *dense, int32_t dtype, const ccm_desc *out, void *stream) {
   if (!dense || (dtype != CCM_I32 && dtype != CCM_I64)) return CCM_E_INVAL;
   int rc = check_desc(out, true);

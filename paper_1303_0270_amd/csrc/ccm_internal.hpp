@@ -332,6 +332,11 @@ constexpr int kMaxSplitsT = 32;
 hipError_t launch_matvec_t(const uint32_t *w, int64_t rows, int64_t cols, int bits, int sgn,
                            const void *x, int xdtype, int64_t *y, int64_t *part,
                            uint64_t part_words, hipStream_t s);
+// The library's own partial-sum buffer for y = A^T x (columns up to
+// kNoAllocColsT): its device address on the current device and its size in
+// int64 words.
+constexpr int64_t kNoAllocColsT = 65536;
+hipError_t static_matvec_t_scratch(int64_t **ptr, uint64_t *words);
 // y[c] = sum over s < splits of part[s * cols + c] (mod 2^64).
 hipError_t launch_sum_splits(const int64_t *part, int64_t splits, int64_t cols, int64_t *y,
                              hipStream_t s);

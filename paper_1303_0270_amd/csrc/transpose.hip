@@ -8,6 +8,9 @@
 //     for the column-major matrix.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
 #include "ccm_internal.hpp"
 #include "group_codec.hpp"
 
@@ -171,6 +174,33 @@ hipError_t launch_matvec_t(const uint32_t *w, int64_t rows, int64_t cols, int bi
   if (bits <= 48)
     return mvt::launch_t_widths_3(w, rows, cols, bits, sgn, x, xdtype, y, part, part_words, s);
   return mvt::launch_t_widths_4(w, rows, cols, bits, sgn, x, xdtype, y, part, part_words, s);
+}
+
+// Library-owned partial sums of y = A^T x for callers that cannot allocate:
+// kMaxSplitsT rows of kNoAllocColsT int64 (16 MB per device, held until the
+// process ends).  In host code `scratch` names a host-side stand-in, never
+// the device array: its device address is looked up once per device below
+// and only that address reaches kernels.  Calls that overlap on one device
+// share (and race on) it.
+static __device__ __align__(256) int64_t scratch[kMaxSplitsT * kNoAllocColsT];
+
+hipError_t static_matvec_t_scratch(int64_t **ptr, uint64_t *words) {
+  static std::mutex mu;
+  static std::vector<int64_t *> per_dev;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((size_t)dev >= per_dev.size()) per_dev.resize((size_t)dev + 1, nullptr);
+  if (!per_dev[(size_t)dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    per_dev[(size_t)dev] = (int64_t *)p;
+  }
+  *ptr = per_dev[(size_t)dev];
+  *words = (uint64_t)kMaxSplitsT * (uint64_t)kNoAllocColsT;
+  return hipSuccess;
 }
 
 hipError_t launch_sum_splits(const int64_t *part, int64_t splits, int64_t cols, int64_t *y,
