@@ -40,6 +40,7 @@ def gemm(torch, ccm, n=8192, reps=3, i8_peak_measured=None):
         e[0].record()
         p = ccm.matmul_async(A, B, scratch=scratch, ws=ws, payload=payload)
         e[1].record()
+        torch.cuda.synchronize()
         Ca = p.get()
         t_async.append(e[0].elapsed_time(e[1]) * 1e-3)
     assert Ca.header() == C.header()
