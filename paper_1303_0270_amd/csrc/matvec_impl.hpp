@@ -434,9 +434,10 @@ hipError_t launch_one(const uint32_t *w, int64_t rows, int64_t cols, const XT *x
 // words) and every panel holds whole quads of groups.  Quad q of a row panel
 // is the four groups 4q..4q+3, i.e. 4b contiguous words fetched with b
 // 16-byte loads.
-//   * 512-lane blocks, 16384-column panels (67.6 KB of LDS: two blocks per
-//     CU), so a matrix up to 16384 columns wide is one panel: each row sum is
-//     stored once, with no zero-fill pass and no atomics.
+//   * 512- or 1024-lane blocks (AlCfg), 16384-column panels (67.6 KB of LDS:
+//     two or one blocks per CU, 16 waves), so a matrix up to 16384 columns
+//     wide is one panel: each row sum is stored once, with no zero-fill pass
+//     and no atomics.
 //   * A wave owns R rows of a row block; lane l owns quads l and l+64 of the
 //     panel.  One "unit" is (row block, quad slot): R*b 16-byte loads per lane.
 //   * With PF the next unit's words are requested before the current one is
@@ -452,8 +453,6 @@ hipError_t launch_one(const uint32_t *w, int64_t rows, int64_t cols, const XT *x
 //     lanes fall in distinct banks.
 //   * b = 1: lane g builds the digit words of group g straight from its 32 x
 //     values (byte permutes and nibble masks), with no int32 copy of x.
-constexpr int kThreadsAl = 512;
-constexpr int kWavesAl = kThreadsAl / 64;
 constexpr int kPanelAl = 16384;
 constexpr int kQuadX = 4 * kGroup + 4;  // int32 per quad of groups
 constexpr int kQuadD = 4 * 16 + 4;      // digit words per quad of groups
@@ -462,20 +461,25 @@ constexpr int kQuadD = 4 * 16 + 4;      // digit words per quad of groups
 // one is decoded.  Measured on the 16384^2 sweep, it pays for b <= 4 only;
 // wider fields issue enough bytes per unit for the other waves to hide the
 // latency.
+// NT: lanes per block.  1024 (one block per CU) stages x once per CU instead of
+// twice; measured on the sweep it pays for b <= 4 (about 0.5 us of 15-28 us)
+// and loses 1-2 us at b = 7 and 12.
 template <int B>
 struct AlCfg {
   static constexpr int R = B == 1 ? 4 : B <= 4 ? 2 : 1;  // rows per wave and unit
   static constexpr bool PF = B <= 4;
+  static constexpr int NT = B <= 4 ? 1024 : 512;
 };
 
 // Stages x[c0, c0+pc) (pc a multiple of 128) into xs (quad-skewed), general
 // loop for the slow path; returns whether this thread saw only int16-range
 // values.
+template <int NT>
 __device__ __forceinline__ int stage_x_al(const int32_t *__restrict__ x, int64_t c0, int pc,
                                           int32_t *xs) {
   uint32_t m = 0;
   const int nchunk = pc / 4;
-  for (int q = threadIdx.x; q < nchunk; q += kThreadsAl) {
+  for (int q = threadIdx.x; q < nchunk; q += NT) {
     const int4 v = *reinterpret_cast<const int4 *>(x + c0 + 4 * q);
     const int e = 4 * q;
     *reinterpret_cast<int4 *>(xs + e + 4 * (e >> 7)) = v;
@@ -516,10 +520,11 @@ __device__ __forceinline__ void store_digits_al(const uint32_t *v, int g, uint32
     *reinterpret_cast<uint4 *>(dst + 4 * d) = make_uint4(D[d][0], D[d][1], D[d][2], D[d][3]);
 }
 
-template <int B, bool SGN>
-__global__ __launch_bounds__(kThreadsAl) __attribute__((amdgpu_waves_per_eu(4))) void
+template <int B, bool SGN, int NT = AlCfg<B>::NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void
 k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
             const int32_t *__restrict__ x, int64_t *__restrict__ y, int atomic_out) {
+  static_assert(NT >= 512 && NT % 64 == 0, "a lane per b = 1 group of a 16384-column panel");
   constexpr int R = AlCfg<B>::R;
   constexpr bool PF = AlCfg<B>::PF;
   constexpr int NWD = 4 * B;  // words per (row, quad)
@@ -533,19 +538,19 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   const int nslot = (nq + 63) / 64;  // quad slots per lane: 1 or 2 (wave-uniform)
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t nrb = (rows + kWavesAl * R - 1) / (kWavesAl * R);  // > blockIdx.x
+  const int64_t nrb = (rows + (NT / 64) * R - 1) / ((NT / 64) * R);  // > blockIdx.x
   const uint64_t row_words = (uint64_t)cols * B / 32;  // a multiple of 4
   const uint64_t panel_word = (uint64_t)c0 * B / 32;
 
   // rows r0 .. r0+nv-1 of row block rb belong to this wave
   auto rows_of = [&](int64_t rb, int64_t &r0) -> int {
-    r0 = rb * (kWavesAl * R) + (int64_t)wave * R;
+    r0 = rb * ((NT / 64) * R) + (int64_t)wave * R;
     const int64_t left = rows - r0;
     return left >= R ? R : (left > 0 ? (int)left : 0);
   };
   // the unit's words; rows and quads past the end are clamped to the last one
   auto load_unit = [&](uint32_t (&w)[R][NWD], int64_t rb, int h) {
-    const int64_t r0 = rb * (kWavesAl * R) + (int64_t)wave * R;
+    const int64_t r0 = rb * ((NT / 64) * R) + (int64_t)wave * R;
     const int qq = lane + 64 * h;
     const int q = qq < nq ? qq : nq - 1;
 #pragma unroll
@@ -573,11 +578,11 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
 #pragma unroll
     for (int i = 0; i < 8; ++i) xv[i] = x4[8 * g + i];
   } else {
-    // lane t: 16-byte chunks t, t+512, ... (pc/4 <= 4096 chunks: one round)
+    // lane t: 16-byte chunks t, t+NT, ... (pc/4 <= 4096 chunks: one round)
     const int nchunk = pc / 4;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int q = (int)threadIdx.x + kThreadsAl * u;
+    for (int u = 0; u < kPanelAl / 4 / NT; ++u) {
+      const int q = (int)threadIdx.x + NT * u;
       xv[u] = x4[q < nchunk ? q : nchunk - 1];
     }
   }
@@ -604,8 +609,8 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   } else {
     const int nchunk = pc / 4;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int q = (int)threadIdx.x + kThreadsAl * u;
+    for (int u = 0; u < kPanelAl / 4 / NT; ++u) {
+      const int q = (int)threadIdx.x + NT * u;
       if (q < nchunk) {
         const int e = 4 * q;
         *reinterpret_cast<int4 *>(xs + e + 4 * (e >> 7)) = xv[u];
@@ -620,7 +625,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   if (!fast) {
     // general x: 64-bit products, one row and one group at a time
     if constexpr (B == 1) {
-      (void)stage_x_al(x, c0, pc, xs);
+      (void)stage_x_al<NT>(x, c0, pc, xs);
       __syncthreads();
     }
     for (; rb < nrb; rb += gridDim.x) {
@@ -731,7 +736,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   int64_t *ydst = y;
   auto flush = [&]() {
     const int64_t rbj = first_rb + (int64_t)(lane / R) * gridDim.x;
-    const int64_t row = rbj * (kWavesAl * R) + (int64_t)wave * R + lane % R;
+    const int64_t row = rbj * ((NT / 64) * R) + (int64_t)wave * R + lane % R;
     const bool ok = lane < nst && row < rows;
     ydst = y + (ok ? row : 0);
     if (ok) {
@@ -800,14 +805,14 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   if (nst > 0) flush();
 }
 
-template <int B, bool SGN>
+template <int B, bool SGN, int NT = AlCfg<B>::NT>
 int resident_blocks_al(size_t lds) {
   static int cached = 0;
   if (cached == 0) {
     int occ = 0, dev = 0, cus = 0;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_matvec_al<B, SGN>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_matvec_al<B, SGN, NT>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_matvec_al<B, SGN>, kThreadsAl,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_matvec_al<B, SGN, NT>, NT,
                                                      lds) != hipSuccess ||
         occ < 1)
       occ = 1;
@@ -820,12 +825,12 @@ int resident_blocks_al(size_t lds) {
   return cached;
 }
 
-template <int B, bool SGN>
+template <int B, bool SGN, int NT = AlCfg<B>::NT>
 hipError_t launch_aligned(const uint32_t *w, int64_t rows, int64_t cols, const int32_t *x,
                           int64_t *y, hipStream_t s) {
   constexpr int R = AlCfg<B>::R;
   const int64_t npanels = (cols + kPanelAl - 1) / kPanelAl;
-  const int64_t nrb = (rows + kWavesAl * R - 1) / (kWavesAl * R);
+  const int64_t nrb = (rows + (NT / 64) * R - 1) / ((NT / 64) * R);
   if (nrb > 0x7fffffffll || npanels > 65535) return hipErrorInvalidValue;
   if (npanels > 1) {
     hipError_t e = launch_fill_i64(y, (uint64_t)rows, 0, s);
@@ -833,34 +838,36 @@ hipError_t launch_aligned(const uint32_t *w, int64_t rows, int64_t cols, const i
   }
   const int64_t nqp = (cols < kPanelAl ? cols : kPanelAl) / (4 * kGroup);
   const size_t lds = (size_t)nqp * kQuadX * sizeof(int32_t);  // >= the digit words
-  int64_t gx = resident_blocks_al<B, SGN>((size_t)(kPanelAl / (4 * kGroup)) * kQuadX * 4) / npanels;
+  int64_t gx =
+      resident_blocks_al<B, SGN, NT>((size_t)(kPanelAl / (4 * kGroup)) * kQuadX * 4) / npanels;
   gx = gx < 1 ? 1 : (gx > nrb ? nrb : gx);  // every block owns at least one row block
-  k_matvec_al<B, SGN><<<dim3((unsigned)gx, (unsigned)npanels), kThreadsAl, lds, s>>>(
+  k_matvec_al<B, SGN, NT><<<dim3((unsigned)gx, (unsigned)npanels), NT, lds, s>>>(
       w, rows, cols, x, y, npanels > 1 ? 1 : 0);
   return hipGetLastError();
 }
 
 // Wide-field variant for b >= 16 and int32 x, any row alignment.  Same
-// pipeline as the aligned kernel: 512-lane blocks over 16384-column panels
-// (a 73.7 KB x panel, two blocks per CU), one row per wave, lane l owns
+// pipeline as the aligned kernel: 1024-lane blocks over 16384-column panels
+// (a 73.7 KB x panel, one block per CU), one row per wave, lane l owns
 // groups l, l+64, ... of the panel; a unit is (row, group slot), b+1 words per
 // lane (the extra word feeds the funnel shift of rows that start inside a
 // word).  With PF the next unit's words are in flight while the current one
 // is decoded; loads are issued in fixed count (clamped addresses) so the
 // compiler waits only for the older unit.  Products are 64-bit (int16-range
 // runs would be one element long at these widths).
-constexpr int kThreadsW = 512;
-constexpr int kWavesW = kThreadsW / 64;
 constexpr int kPanelW = 16384;
 constexpr int kPitchW = kGroup + 4;  // int32 per staged group
 
 template <int B>
 struct WCfg {
   static constexpr bool PF = B <= 24;  // measured: larger widths run faster without
+  // one 1024-lane block per CU (x staged once per CU): 1-2.5 us faster than two
+  // 512-lane blocks at b = 17 and 31 on the sweep
+  static constexpr int NT = 1024;
 };
 
-template <int B, bool SGN>
-__global__ __launch_bounds__(kThreadsW) __attribute__((amdgpu_waves_per_eu(4))) void
+template <int B, bool SGN, int NT = WCfg<B>::NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void
 k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
            const int32_t *__restrict__ x, int64_t *__restrict__ y, int atomic_out,
            int x_aligned16) {
@@ -874,12 +881,12 @@ k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   const int ng = (pc + kGroup - 1) / kGroup;
   const int nslot = (ng + 63) / 64;  // wave-uniform
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t nrb = (rows + kWavesW - 1) / kWavesW;  // > blockIdx.x
+  const int64_t nrb = (rows + (NT / 64) - 1) / (NT / 64);  // > blockIdx.x
 
   // the unit's words and the row's funnel shift (the same for every group of
   // a row); rows past the end and groups past the last are clamped
   auto load_unit = [&](uint32_t (&w)[NWG], int64_t rb, int h, int &shift) {
-    const int64_t r0 = rb * kWavesW + wave;
+    const int64_t r0 = rb * (NT / 64) + wave;
     const int64_t r = r0 < rows ? r0 : rows - 1;
     const int jj = lane + 64 * h;
     const int j = jj < ng ? jj : ng - 1;
@@ -900,22 +907,22 @@ k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
     // whole groups, aligned x: every chunk requested at once (a fixed count,
     // clamped), then the first unit, then the chunks stored -- the wait for
     // the chunks leaves the unit's loads in flight (the counter is in order)
-    constexpr int kXPer = kPanelW / 4 / kThreadsW;
+    constexpr int kXPer = kPanelW / 4 / NT;
     const int4 *x4 = reinterpret_cast<const int4 *>(x + c0);
     int4 xv[kXPer];
 #pragma unroll
     for (int u = 0; u < kXPer; ++u) {
-      const int q = (int)threadIdx.x + kThreadsW * u;
+      const int q = (int)threadIdx.x + NT * u;
       xv[u] = x4[q < nchunk ? q : nchunk - 1];
     }
     if constexpr (PF) load_unit(w0, rb, 0, s0);  // in flight across the barrier
 #pragma unroll
     for (int u = 0; u < kXPer; ++u) {
-      const int e = 4 * ((int)threadIdx.x + kThreadsW * u);
+      const int e = 4 * ((int)threadIdx.x + NT * u);
       if (e < 4 * nchunk) *reinterpret_cast<int4 *>(xs + (e >> 5) * kPitchW + (e & 31)) = xv[u];
     }
   } else {
-    for (int q = threadIdx.x; q < nchunk; q += kThreadsW) {
+    for (int q = threadIdx.x; q < nchunk; q += NT) {
       const int e = 4 * q;
       int4 v;
       if (x_aligned16 && e + 4 <= pc)
@@ -955,7 +962,7 @@ k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
     int64_t first_rb = rb;
     int64_t *ydst = y;
     auto flush = [&]() {
-      const int64_t row = (first_rb + (int64_t)lane * gridDim.x) * kWavesW + wave;
+      const int64_t row = (first_rb + (int64_t)lane * gridDim.x) * (NT / 64) + wave;
       const bool ok = lane < nst && row < rows;
       ydst = y + (ok ? row : 0);
       if (ok) {
@@ -1001,7 +1008,7 @@ k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
       }
       const int64_t sum = wave_sum((int64_t)acc);
       acc = 0;
-      const int64_t r = rb * kWavesW + wave;
+      const int64_t r = rb * (NT / 64) + wave;
       if (lane == 0 && r < rows) {
         if (atomic_out)
           atomicAdd((unsigned long long *)&y[r], (unsigned long long)sum);
@@ -1012,14 +1019,14 @@ k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   }
 }
 
-template <int B, bool SGN>
+template <int B, bool SGN, int NT = WCfg<B>::NT>
 int resident_blocks_w(size_t lds) {
   static int cached = 0;
   if (cached == 0) {
     int occ = 0, dev = 0, cus = 0;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_matvec_w<B, SGN>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_matvec_w<B, SGN, NT>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_matvec_w<B, SGN>, kThreadsW, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_matvec_w<B, SGN, NT>, NT, lds) !=
             hipSuccess ||
         occ < 1)
       occ = 1;
@@ -1032,11 +1039,11 @@ int resident_blocks_w(size_t lds) {
   return cached;
 }
 
-template <int B, bool SGN>
+template <int B, bool SGN, int NT = WCfg<B>::NT>
 hipError_t launch_wide(const uint32_t *w, int64_t rows, int64_t cols, const int32_t *x,
                        int64_t *y, hipStream_t s) {
   const int64_t npanels = (cols + kPanelW - 1) / kPanelW;
-  const int64_t nrb = (rows + kWavesW - 1) / kWavesW;
+  const int64_t nrb = (rows + (NT / 64) - 1) / (NT / 64);
   if (nrb > 0x7fffffffll || npanels > 65535) return hipErrorInvalidValue;
   if (npanels > 1) {
     hipError_t e = launch_fill_i64(y, (uint64_t)rows, 0, s);
@@ -1044,10 +1051,10 @@ hipError_t launch_wide(const uint32_t *w, int64_t rows, int64_t cols, const int3
   }
   const int64_t ngp = ((cols < kPanelW ? cols : kPanelW) + kGroup - 1) / kGroup;
   const size_t lds = (size_t)ngp * kPitchW * sizeof(int32_t);
-  int64_t gx = resident_blocks_w<B, SGN>((size_t)(kPanelW / kGroup) * kPitchW * 4) / npanels;
+  int64_t gx = resident_blocks_w<B, SGN, NT>((size_t)(kPanelW / kGroup) * kPitchW * 4) / npanels;
   gx = gx < 1 ? 1 : (gx > nrb ? nrb : gx);  // every block owns at least one row
   const int al = ((uintptr_t)x % 16) == 0;
-  k_matvec_w<B, SGN><<<dim3((unsigned)gx, (unsigned)npanels), kThreadsW, lds, s>>>(
+  k_matvec_w<B, SGN, NT><<<dim3((unsigned)gx, (unsigned)npanels), NT, lds, s>>>(
       w, rows, cols, x, y, npanels > 1 ? 1 : 0, al);
   return hipGetLastError();
 }
