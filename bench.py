@@ -70,6 +70,15 @@ def parse():
     ap.add_argument("--trace-out", default=os.path.join("profiles", "sweep_step_kernels.md"))
     ap.add_argument("--trace-title", default="", help="summary title (default: the step's)")
     ap.add_argument("--trace-note", default="", help="summary description (default: the step's)")
+    ap.add_argument("--summarize-traffic", metavar="DIR",
+                    help="write the HBM traffic per kernel of two rocprofv3 --pmc runs (DIR/fetch "
+                         "FETCH_SIZE, DIR/write WRITE_SIZE) of any command that ends with a "
+                         "1 GiB device copy, for kernels matching --traffic-kernels; no GPU use")
+    ap.add_argument("--traffic-kernels", default=".", help="regex of kernel names to list")
+    ap.add_argument("--traffic-out", default=os.path.join("profiles", "traffic.md"))
+    ap.add_argument("--traffic-title", default="HBM traffic per kernel")
+    ap.add_argument("--traffic-cmd", default="", help="the profiled command, recorded")
+    ap.add_argument("--traffic-note", default="")
     ap.add_argument("--extras-only", metavar="NAMES",
                     help="run only these measurements of bench_extras (comma list of "
                          "transposed, vlb, gemm, batched, serving) and print their JSON; for "
@@ -173,6 +182,55 @@ def summarize_counters(src_dir, out_path):
     lines += ["", f"HBM bytes per launch (mean over the sweep): {mean:.0f}", ""]
     with open(out_path, "w") as f:
         f.write("\n".join(lines))
+    print(out_path)
+
+
+def summarize_traffic(src_dir, out_path, pattern, title, cmd, note):
+    """HBM bytes per dispatch of the kernels matching `pattern`, from
+    rocprofv3 --pmc FETCH_SIZE (src_dir/fetch) and WRITE_SIZE (src_dir/write)
+    runs of one command, calibrated by that run's plain 1 GiB device copy."""
+    import csv
+    import glob
+    import re
+
+    def per_kernel(sub, counter):
+        vals = {}
+        for f in glob.glob(os.path.join(src_dir, sub, "**", "*counter_collection.csv"),
+                           recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter:
+                    vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    def short(name):
+        return name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+
+    fetch = per_kernel("fetch", "FETCH_SIZE")
+    write = per_kernel("write", "WRITE_SIZE")
+    copy_f = [v for k, vs in fetch.items() if "copyBuffer" in k for v in vs]
+    copy_w = [v for k, vs in write.items() if "copyBuffer" in k for v in vs]
+    gib_kib = float(1 << 20)
+    ff, fw = gib_kib / max(copy_f), gib_kib / max(copy_w)
+    rx = re.compile(pattern)
+    lines = ["# " + title, "",
+             "Commands (repo root on the MI355X box; rocprofv3 run from /tmp with TMPDIR=/tmp):",
+             "", "    " + cmd.replace("\n", "\n    "), "", note, "",
+             f"Calibration: the run's 1 GiB device copy reads FETCH_SIZE {max(copy_f):.0f} KiB and "
+             f"writes WRITE_SIZE {max(copy_w):.0f} KiB; bytes = KiB x 1024 x {ff:.3f} (fetch) and "
+             f"x {fw:.3f} (write).", "",
+             "| kernel | dispatches | mean FETCH_SIZE KiB | mean WRITE_SIZE KiB | mean HBM bytes "
+             "per dispatch (calibrated) | total HBM bytes |", "|---|---|---|---|---|---|"]
+    for name in sorted(set(fetch) | set(write)):
+        if not rx.search(name) or "copyBuffer" in name:
+            continue
+        fv, wv = fetch.get(name, [0.0]), write.get(name, [0.0])
+        f_kib, w_kib = sum(fv) / len(fv), sum(wv) / len(wv)
+        per = 1024 * (f_kib * ff + w_kib * fw)
+        tot = 1024 * (sum(fv) * ff + sum(wv) * fw)
+        lines.append(f"| `{short(name)}` | {max(len(fv), len(wv))} | {f_kib:.0f} | {w_kib:.0f} | "
+                     f"{per:.0f} | {tot:.0f} |")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
     print(out_path)
 
 
@@ -286,6 +344,10 @@ def main():
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, args.counters_out)
         return
+    if args.summarize_traffic:
+        summarize_traffic(args.summarize_traffic, args.traffic_out, args.traffic_kernels,
+                          args.traffic_title, args.traffic_cmd, args.traffic_note)
+        return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.trace_out, args.trace_json, args.trace_cmd,
                         args.trace_title, args.trace_note)
@@ -314,6 +376,10 @@ def main():
             res[name] = fns[name](torch, ccm)
             torch.cuda.empty_cache()
             log(f"{name} done")
+        # a plain 1 GiB device copy: calibrates FETCH_SIZE / WRITE_SIZE counter runs
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
         print(json.dumps({"extras_only": res}), flush=True)
         return
     bench_lib = ctypes.CDLL(os.path.join(ROOT, "paper_1303_0270_amd", "libccm_bench.so"))
