@@ -179,14 +179,18 @@ int ccm_scale(const ccm_desc *a, int64_t s, const ccm_desc *out, void *stream);
 
 /* ---- matvec and matmul --------------------------------------------------- */
 
-/* y = A x (y[i] = sum_j a_ij x_j modulo 2^64).  x: device, cols values of
- * xdtype (CCM_I32 or CCM_I64); y: device, rows int64.  Async; no error for
- * wrap-around. */
+/* y = A x (y[i] = sum_j a_ij x_j modulo 2^64), read straight from the
+ * packed fields (Introduction: compressed matrices take the same arithmetic
+ * as uncompressed ones; the fields are laid out as in Method 1, Eq. 3).
+ * x: device, cols values of xdtype (CCM_I32 or CCM_I64); y: device, rows
+ * int64.  Async; no error for wrap-around. */
 int ccm_matvec(const ccm_desc *a, const void *x, int32_t xdtype, int64_t *y, void *stream);
 
-/* C = A B.  CCM_E_OVERFLOW iff K * max|A| * max|B| >= 2^63 (max|M| =
- * max(|min|, |max|) from the headers; an O(1) conservative bound), so every
- * entry fits in int64.  Fields of at most 8 bits whose values fit int8 go
+/* C = A B on packed operands (Introduction: the product of the uncompressed
+ * matrices), re-encoded at the width of its exact range (Eq. 1, or two's
+ * complement for a negative minimum).  CCM_E_OVERFLOW iff
+ * K * max|A| * max|B| >= 2^63 (max|M| = max(|min|, |max|) from the headers;
+ * an O(1) conservative bound), so every entry fits in int64.  Fields of at most 8 bits whose values fit int8 go
  * through int8 MFMA tiles with exact integer accumulation; others through an
  * exact int64 path.
  *   scratch_bytes: device scratch the two calls need (dense C at 4 or 8 bytes

@@ -204,8 +204,9 @@ __device__ __forceinline__ int64_t wave_max(int64_t v) {
   return v;
 }
 
-// Reduction target of the range passes: exact min, max and an error flag.
-struct RangeSlot {
+// Reduction target of the range passes: exact min, max and an error flag
+// (32 bytes, so kRangeStride of them make one 128-byte line).
+struct alignas(32) RangeSlot {
   int64_t vmin;
   int64_t vmax;
   int32_t flag;
@@ -219,6 +220,7 @@ struct RangeSlot {
 constexpr int kRangeSpread = 64;
 constexpr int kRangeStride = 4;  // RangeSlot units per slot (128 bytes)
 constexpr size_t kRangeBytes = sizeof(RangeSlot) * kRangeStride * kRangeSpread;
+static_assert(sizeof(RangeSlot) * kRangeStride == 128, "one range slot per 128-byte line");
 
 // Spread 64-bit sums (pairs), laid out like the range slots: pair i at
 // uint64 offset 2 * kSumStride * i (128 bytes apart).

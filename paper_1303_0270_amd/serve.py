@@ -20,11 +20,16 @@ over time.  The loop runs continuous batching on a few HIP streams:
   launch;
 * completion is read from a GPU event per launch; latency is completion time
   minus arrival time, both on the run's clock (the GPU timestamps are taken
-  relative to an event recorded when the run starts).
+  relative to an event recorded when the run starts);
+* Python's cyclic garbage collector is paused for the run (a full collection
+  over a process that has imported torch can hold the loop for tens of
+  milliseconds); `max_loop_gap_ms` reports the longest time between two
+  passes of the loop, so a host-side stall shows in the statistics.
 """
 from __future__ import annotations
 
 import collections
+import gc
 import math
 import time
 from dataclasses import dataclass, field
@@ -101,6 +106,17 @@ class Server:
             r.footprint = request_footprint(r, self.pool)
             if r.footprint > self.arena:
                 raise ValueError(f"request {r.rid} needs {r.footprint} bytes, arena {self.arena}")
+        torch.cuda.synchronize()
+        gc_was_enabled = gc.isenabled()
+        gc.collect()
+        gc.disable()
+        try:
+            return self._loop(reqs, poll_sleep)
+        finally:
+            if gc_was_enabled:
+                gc.enable()
+
+    def _loop(self, reqs, poll_sleep):
         waiting = collections.deque()
         pending_mv, pending_mm = [], []
         inflight: list[_Launch] = []
@@ -114,12 +130,15 @@ class Server:
         launches = []
         done_launches = []
         max_inflight_seen = 0
-        torch.cuda.synchronize()
+        max_gap = 0.0
         start_evt = torch.cuda.Event(enable_timing=True)
         start_evt.record()
         t0 = time.perf_counter()
+        last = 0.0
         while finished < n:
             now = time.perf_counter() - t0
+            max_gap = max(max_gap, now - last)
+            last = now
             while nxt < n and reqs[nxt].arrival <= now:
                 waiting.append(reqs[nxt])
                 nxt += 1
@@ -215,6 +234,7 @@ class Server:
                 "max_launches_in_flight": max_inflight_seen,
                 "overlapped_launches": int(overlapped),
                 "mm_overlapping_mv": int(mm_with_mv),
+                "max_loop_gap_ms": round(max_gap * 1e3, 3),
                 "wall_s": round(wall, 4)}
 
 
