@@ -54,7 +54,37 @@ def gemm(torch, ccm, n=8192, reps=3, i8_peak_measured=None):
            "frac_i8_mfma": round(ops / tp / 1e12 / I8_PEAK_TOPS, 4)}
     if i8_peak_measured:
         out["frac_i8_mfma_measured_peak"] = round(ops / tp / 1e12 / i8_peak_measured, 4)
+    out["library_int8_gemm"] = library_int8_gemm(torch, ccm, A, B, C, reps)
     return out
+
+
+def library_int8_gemm(torch, ccm, A, B, C, reps):
+    """Reference point: the vendor int8 GEMM (torch._int_mm, hipBLASLt) on the
+    same operands already decoded to dense int8 (no decoding, no range, no
+    packing), B stored K-contiguous like the B^T the MFMA path decodes.
+    Checked against the packed result on the first 64 rows."""
+    if not hasattr(torch, "_int_mm"):
+        return None
+    a8 = ccm.decompress(A).to(torch.int8)
+    bt8 = ccm.decompress(B).to(torch.int8).t().contiguous()
+    b8 = bt8.t()  # K x N view of N x K storage
+    r = torch._int_mm(a8, b8)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(r[:64].to(torch.int64), ccm.decompress(C)[:64]))
+    ts = []
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        r = torch._int_mm(a8, b8)
+        e[1].record()
+        torch.cuda.synchronize()
+        ts.append(e[0].elapsed_time(e[1]) * 1e-3)
+    t = min(ts)
+    n = a8.shape[0]
+    del a8, bt8, b8, r
+    torch.cuda.empty_cache()
+    return {"kernel": "torch._int_mm (hipBLASLt), dense int8 operands", "ms": round(t * 1e3, 3),
+            "tops": round(2.0 * n * n * n / t / 1e12, 2), "first_64_rows_equal": same}
 
 
 def batched(torch, ccm, reps=30):

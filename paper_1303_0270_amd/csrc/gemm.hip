@@ -91,21 +91,18 @@ hipError_t launch_generic(const uint32_t *aw, int abits, int asgn, const uint32_
 // ---- int8 MFMA path --------------------------------------------------------
 //
 // Both operands are first decoded once into int8 scratch with K contiguous
-// and zero-padded to a multiple of the K chunk: A as M rows, B transposed as N rows
-// (B^T, the paper's other unravel order).  Decoding inside the GEMM's K loop
-// would redo it for every output tile (N/256 times per A element) and read
-// the packed rows one lane per row, which the memory pipeline serves one
+// and zero-padded to a multiple of the K step: A as M rows, B transposed as N
+// rows (B^T, the paper's other unravel order).  Decoding inside the GEMM's K
+// loop would redo it for every output tile (N/256 times per A element) and
+// read the packed rows one lane per row, which the memory pipeline serves one
 // cache line per lane; decoded once, the tiles stream with coalesced 16-byte
-// loads.  The GEMM then multiplies 256x256 output tiles per 1024-lane block
-// (sixteen waves, each a 64x64 block of 2x2 32x32 accumulators) with
-// v_mfma_i32_32x32x32_i8 over double-buffered LDS tiles, K in chunks of 128:
-// the next chunk is loaded into registers before the current chunk's MFMAs
-// and stored to the other buffer after them (tile shape, wave shape and chunk
-// length measured against 128x64 waves and 64-byte chunks on the 8192^3
-// product).  A and B operand lanes use the same assignment of
-// the 32 K values of a step to (lane half, byte), so the products summed per
-// output are exactly those of the dot product.  int32 accumulation is exact
-// because the host only takes this path when K * max|A| * max|B| < 2^31.
+// copies.  The GEMM (k_gemm_i8 below) multiplies 256x256 output tiles per
+// 512-lane block, eight waves of 128x64 outputs, with v_mfma_i32_32x32x32_i8
+// over two LDS buffers filled by memory-to-LDS copies, K in steps of 128.  A
+// and B operand lanes use the same assignment of the 32 K values of a slice
+// to (lane half, byte), so the products summed per output are exactly those
+// of the dot product.  int32 accumulation is exact because the host only
+// takes this path when K * max|A| * max|B| < 2^31.
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
@@ -234,7 +231,8 @@ __global__ __launch_bounds__(256) void k_decode_cols_i8(const uint32_t *__restri
 __device__ __forceinline__ int swz(int r) { return (r ^ (r >> 3)) & 7; }
 
 // C = A B^T-layout int8 GEMM with exact int32 accumulation (MFMA
-// v_mfma_i32_32x32x32_i8), C stored as OT, and C's exact range.
+// v_mfma_i32_32x32x32_i8), C stored as int32 (the host takes this path only
+// when every entry fits int32), and C's exact range.
 //   * Block = 8 waves, 256 x 256 outputs; each wave owns 128 x 64 (4 x 2
 //     MFMA blocks, 128 accumulator registers): 6 LDS reads of 16 bytes feed 8
 //     MFMAs.
@@ -242,14 +240,25 @@ __device__ __forceinline__ int swz(int r) { return (r ^ (r >> 3)) & 7; }
 //     into LDS with memory-to-LDS loads (global_load_lds_dwordx4: each wave
 //     instruction fills 8 rows, a lane's source chunk chosen so the row lands
 //     swizzled), into the other of two buffers while the MFMAs consume this
-//     one.  (Steps of 64 with a ring of four buffers, three in flight,
-//     measured slower: twice the barriers.)  Rows past M or N copy the last
-//     row (their outputs are not stored).
-template <typename OT>
+//     one.  Rows past M or N copy the last row (their outputs are not stored).
+//   * One barrier per step, a bare s_barrier after the lane's own copies have
+//     landed (vmcnt(0)); __syncthreads would add a workgroup fence, which
+//     waits for every outstanding memory operation again.
+//   * The operands of each 32-deep slice of K are read from LDS one slice
+//     ahead, into a second register set, one read issued after each MFMA.
+__device__ __forceinline__ void mfma_slice(const v4i (&a)[kFM], const v4i (&b)[kFN],
+                                           v16i (&acc)[kFM][kFN]) {
+#pragma unroll
+  for (int ta = 0; ta < kFM; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < kFN; ++tb)
+      acc[ta][tb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
+}
+
 __global__ __launch_bounds__(kGemmThreads) void k_gemm_i8(const int8_t *__restrict__ A,
                                                           const int8_t *__restrict__ Bt, int64_t M,
                                                           int64_t N, int64_t ldk,
-                                                          OT *__restrict__ C, RangeSlot *slot) {
+                                                          int32_t *__restrict__ C, RangeSlot *slot) {
   extern __shared__ __align__(16) int8_t gemm_lds[];
   // Tile of this block.  Tiles are taken in groups of kGroupM tile rows
   // (consecutive tiles walk down the group, then across), and when the tile
@@ -292,6 +301,32 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_i8(const int8_t *__restri
                                        (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
     }
   };
+  // LDS offsets of this lane's operand rows and their swizzle
+  int aoff[kFM], boff[kFN], asw[kFM], bsw[kFN];
+#pragma unroll
+  for (int t = 0; t < kFM; ++t) {
+    const int r = wm * kWM + t * 32 + (lane & 31);
+    aoff[t] = r * kBK;
+    asw[t] = swz(r);
+  }
+#pragma unroll
+  for (int t = 0; t < kFN; ++t) {
+    const int r = wn * kWN + t * 32 + (lane & 31);
+    boff[t] = kBM * kBK + r * kBK;
+    bsw[t] = swz(r);
+  }
+  // lanes 0-31 take bytes 0-15 of the slice's 32 K values, lanes 32-63 bytes
+  // 16-31, for both operands
+  auto fetch = [&](int buf, int kk, v4i(&a)[kFM], v4i(&b)[kFN]) {
+    const int8_t *base = gemm_lds + (size_t)buf * kTileBytes;
+    const int c = kk / 16 + (lane >> 5);
+#pragma unroll
+    for (int t = 0; t < kFM; ++t)
+      a[t] = *reinterpret_cast<const v4i *>(base + aoff[t] + 16 * (c ^ asw[t]));
+#pragma unroll
+    for (int t = 0; t < kFN; ++t)
+      b[t] = *reinterpret_cast<const v4i *>(base + boff[t] + 16 * (c ^ bsw[t]));
+  };
 
   v16i acc[kFM][kFN];
 #pragma unroll
@@ -303,55 +338,60 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_i8(const int8_t *__restri
 
   const int64_t nk = ldk / kBK;
   stage(0, 0);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
+  v4i a0[kFM], b0[kFN], a1[kFM], b1[kFN];
   for (int64_t kc = 0; kc < nk; ++kc) {
     const int cur = (int)(kc & 1);
+    // this lane's copies of step kc have landed; after the barrier everyone's
+    // have, and everyone has finished reading the other buffer (step kc - 1)
+    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
     if (kc + 1 < nk) stage((kc + 1) * kBK, cur ^ 1);  // in flight during the MFMAs
-    const int8_t *as = gemm_lds + (size_t)cur * kTileBytes;
-    const int8_t *bs = as + (size_t)kBM * kBK;
+    fetch(cur, 0, a0, b0);
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 32) {
-      const int c = kk / 16 + (lane >> 5);
-      v4i a[kFM], b[kFN];
-#pragma unroll
-      for (int t = 0; t < kFM; ++t) {
-        const int r = wm * kWM + t * 32 + (lane & 31);
-        a[t] = *reinterpret_cast<const v4i *>(as + r * kBK + 16 * (c ^ swz(r)));
+    for (int s = 0; s < kBK / 32; ++s) {
+      if (s % 2 == 0) {
+        if (s + 1 < kBK / 32) fetch(cur, 32 * (s + 1), a1, b1);
+        mfma_slice(a0, b0, acc);
+      } else {
+        if (s + 1 < kBK / 32) fetch(cur, 32 * (s + 1), a0, b0);
+        mfma_slice(a1, b1, acc);
       }
+      if (s + 1 < kBK / 32) {
+        // one LDS read after each of the first six MFMAs, then the last two
 #pragma unroll
-      for (int t = 0; t < kFN; ++t) {
-        const int r = wn * kWN + t * 32 + (lane & 31);
-        b[t] = *reinterpret_cast<const v4i *>(bs + r * kBK + 16 * (c ^ swz(r)));
+        for (int q = 0; q < kFM + kFN; ++q) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // an MFMA
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // an LDS read
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, kFM * kFN - (kFM + kFN), 0);
       }
-#pragma unroll
-      for (int ta = 0; ta < kFM; ++ta)
-#pragma unroll
-        for (int tb = 0; tb < kFN; ++tb)
-          acc[ta][tb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
     }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this lane's copies of the next step
-    __syncthreads();  // everyone's copies have landed and this buffer is read
   }
 
   // 32x32 accumulator layout: lane l, register r -> column l%32,
-  // row 8*(r/4) + 4*(l/32) + r%4
-  int64_t lo = INT64_MAX, hi = INT64_MIN;
+  // row 8*(r/4) + 4*(l/32) + r%4.  Row offsets are uniform multiples of N.
+  int lo = 0x7fffffff, hi = -0x7fffffff - 1;
+  const int64_t rbase = m0 + wm * kWM + 4 * (lane >> 5);
+  const int64_t cbase = n0 + wn * kWN + (lane & 31);
+  int32_t *cp = C + rbase * N + cbase;
 #pragma unroll
   for (int ta = 0; ta < kFM; ++ta)
 #pragma unroll
-    for (int tb = 0; tb < kFN; ++tb)
+    for (int r = 0; r < 16; ++r) {
+      const int ro = ta * 32 + 8 * (r / 4) + (r % 4);
+      int32_t *rowp = cp + (int64_t)ro * N;
+      const bool rok = rbase + ro < M;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t i = m0 + wm * kWM + ta * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-        const int64_t j = n0 + wn * kWN + tb * 32 + (lane & 31);
-        if (i < M && j < N) {
-          const int64_t v = acc[ta][tb][r];
-          C[i * N + j] = (OT)v;
+      for (int tb = 0; tb < kFN; ++tb) {
+        const int v = acc[ta][tb][r];
+        if (rok && cbase + tb * 32 < N) {
+          rowp[tb * 32] = v;
           lo = v < lo ? v : lo;
           hi = v > hi ? v : hi;
         }
       }
+      __builtin_amdgcn_sched_barrier(0);  // one row at a time: no copies of all 128 accumulators
+    }
   block_range_commit(lo, hi, 0, slot);
 }
 
@@ -365,6 +405,7 @@ hipError_t launch_matmul_i8(const uint32_t *aw, int abits, int asgn, const uint3
                             int bbits, int bsgn, int64_t M, int64_t K, int64_t N, int out32,
                             void *scratch_c, int8_t *scratch_i8, RangeSlot *slot, hipStream_t s) {
   const int64_t ldk = padded_k(K);
+  if (!out32) return hipErrorInvalidValue;  // every entry fits int32 on this path
   if (M > 0x7fffffffll || (N + 63) / 64 > 0x7fffffffll || ldk / 128 + 1 > 65535 ||
       (N + kBN - 1) / kBN > 0x7fffffffll || (M + kBM - 1) / kBM > 65535)
     return hipErrorInvalidValue;
@@ -399,18 +440,12 @@ hipError_t launch_matmul_i8(const uint32_t *aw, int abits, int asgn, const uint3
   const dim3 grid((unsigned)ntile);
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_gemm_i8<int32_t>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_gemm_i8<int64_t>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_gemm_i8),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds);
     attr = true;
   }
-  if (out32)
-    k_gemm_i8<int32_t><<<grid, kGemmThreads, kGemmLds, s>>>(ai8, bti8, M, N, ldk,
-                                                             (int32_t *)scratch_c, slot);
-  else
-    k_gemm_i8<int64_t><<<grid, kGemmThreads, kGemmLds, s>>>(ai8, bti8, M, N, ldk,
-                                                             (int64_t *)scratch_c, slot);
+  k_gemm_i8<<<grid, kGemmThreads, kGemmLds, s>>>(ai8, bti8, M, N, ldk, (int32_t *)scratch_c,
+                                                 slot);
   return hipGetLastError();
 }
 
