@@ -24,8 +24,8 @@
  *   The GPU reads the same bytes as 32-bit words: word q holds stream bits
  *   [32q, 32q+32).
  *
- * Operations (the paper asks that compressed matrices undergo the same
- * mathematical operations as the uncompressed ones, Introduction; it gives no
+ * Operations (the Introduction wants arithmetic on the compressed form to
+ * agree with arithmetic on the uncompressed matrix; the paper gives no
  * algorithm): exact integer arithmetic on the decoded values.  Every
  * matrix-valued result is re-encoded at the minimal width of its own values
  * (its signedness too), found by a max/min-reduction pass ("plan") before the
