@@ -297,3 +297,78 @@ def test_new_entry_points_reject_bad_arguments_before_gpu_work(L):
     assert L.lib.ccm_method_plan(0x1000, L.I64, 0, 2, ctypes.byref(info), None) == L.E_INVAL
     assert L.lib.ccm_method_plan(0x1000, 9, 2, 2, ctypes.byref(info), None) == L.E_INVAL
     assert L.lib.ccm_method_plan(0x1000, L.I64, 2, 2, None, None) == L.E_INVAL
+
+
+def test_async_entry_points_host_logic(L):
+    """Workspace size, result capacity and argument checks of the results
+    whose width stays on the device, all decided before any GPU work."""
+    assert L.lib.ccm_async_ws_bytes() == 256 + 64 * 128
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        m, k, n = (int(v) for v in rng.integers(1, 40, size=3))
+        a = rng.integers(-2**int(rng.integers(1, 8)), 2**int(rng.integers(1, 8)), size=(m, k))
+        b = rng.integers(-2**int(rng.integers(1, 8)), 2**int(rng.integers(1, 8)), size=(k, n))
+        pa, pb = oracle.compress(a), oracle.compress(b)
+        da, db = _desc_from(pa), _desc_from(pb)
+        bound = k * max(abs(pa.vmin), abs(pa.vmax)) * max(abs(pb.vmin), abs(pb.vmax))
+        bits, _ = oracle.width(-bound, bound)
+        want = L.lib.ccm_payload_capacity(m, n, bits)
+        assert L.lib.ccm_matmul_capacity(ctypes.byref(da), ctypes.byref(db)) == want
+        # the exact result's payload always fits the capacity
+        c = oracle.matmul(pa, pb)
+        assert L.lib.ccm_payload_capacity(m, n, c.bits) <= want
+    # shape mismatch and overflow: no capacity
+    pa = oracle.compress(np.array([[1, 2, 3]]))
+    pb = oracle.compress(np.array([[1], [2]]))
+    assert L.lib.ccm_matmul_capacity(ctypes.byref(_desc_from(pa)), ctypes.byref(_desc_from(pb))) == 0
+    big = oracle.compress(np.array([[2**62]]))
+    two = oracle.compress(np.array([[2]]))
+    assert L.lib.ccm_matmul_capacity(ctypes.byref(_desc_from(big)), ctypes.byref(_desc_from(two))) == 0
+
+    # ccm_add_async: every refusal comes before any device work (stand-in pointers)
+    p = oracle.compress(np.array([[1, 2], [3, 4]]))
+    q = oracle.compress(np.array([[5, 6, 7]]))
+    da, dq = _desc_from(p), _desc_from(q)
+    da.payload, dq.payload = 0x1000, 0x2000
+    cap = L.lib.ccm_add_capacity(ctypes.byref(da), ctypes.byref(da))
+    ws = 0x10000
+    assert L.lib.ccm_add_async(ctypes.byref(da), ctypes.byref(dq), 0x3000, cap, ws, None) == L.E_SHAPE
+    assert L.lib.ccm_add_async(ctypes.byref(da), ctypes.byref(da), None, cap, ws, None) == L.E_INVAL
+    assert L.lib.ccm_add_async(ctypes.byref(da), ctypes.byref(da), 0x3000, cap, None, None) == L.E_INVAL
+    assert L.lib.ccm_add_async(ctypes.byref(da), ctypes.byref(da), 0x3000, cap, ws + 16, None) == L.E_INVAL
+    assert L.lib.ccm_add_async(ctypes.byref(da), ctypes.byref(da), 0x3000, cap - 1, ws, None) == L.E_NOMEM
+    # ccm_matmul_async: the same, plus the scratch size and the overflow rule
+    sb = L.lib.ccm_matmul_scratch_bytes(ctypes.byref(da), ctypes.byref(da))
+    mc = L.lib.ccm_matmul_capacity(ctypes.byref(da), ctypes.byref(da))
+    assert sb > 0 and mc > 0
+    args = lambda pay, pb_, scr, sbytes, w: L.lib.ccm_matmul_async(
+        ctypes.byref(da), ctypes.byref(da), pay, pb_, scr, sbytes, w, None)
+    assert args(0x3000, mc, 0x4000, sb - 1, ws) == L.E_NOMEM
+    assert args(None, mc, 0x4000, sb, ws) == L.E_INVAL
+    assert args(0x3000, mc, 0x4000, sb, ws + 8) == L.E_INVAL
+    assert args(0x3000, mc - 1, 0x4000, sb, ws) == L.E_NOMEM
+    db, dt = _desc_from(big), _desc_from(two)
+    db.payload, dt.payload = 0x1000, 0x2000
+    assert L.lib.ccm_matmul_async(ctypes.byref(db), ctypes.byref(dt), 0x3000, 1 << 20, 0x4000,
+                                  1 << 20, ws, None) == L.E_OVERFLOW
+
+
+def test_result_desc_checks_the_device_written_fields(L):
+    """ccm_result_desc turns the 64 bytes the device wrote into a descriptor
+    only when they are consistent (width rule, word count), and passes a
+    device-found error through."""
+    p = oracle.compress(np.array([[-3, 5, 0], [2, -1, 4]]))
+    r = L.Result(p.rows, p.cols, p.vmin, p.vmax, p.bits, int(p.is_signed), p.words, L.OK, 0, 0)
+    out = L.Desc()
+    assert L.lib.ccm_result_desc(ctypes.byref(r), 0x5000, ctypes.byref(out)) == L.OK
+    assert (out.rows, out.cols, out.vmin, out.vmax, out.bits, out.is_signed, out.words) == \
+        (p.rows, p.cols, p.vmin, p.vmax, p.bits, int(p.is_signed), p.words)
+    assert out.payload == 0x5000
+    for field, bad in (("bits", p.bits + 1), ("is_signed", 0), ("words", p.words + 1),
+                       ("rows", 0)):
+        rb = L.Result.from_buffer_copy(r)
+        setattr(rb, field, bad)
+        assert L.lib.ccm_result_desc(ctypes.byref(rb), 0x5000, ctypes.byref(out)) == L.E_INVAL
+    rb = L.Result.from_buffer_copy(r)
+    rb.status = L.E_OVERFLOW
+    assert L.lib.ccm_result_desc(ctypes.byref(rb), 0x5000, ctypes.byref(out)) == L.E_OVERFLOW
