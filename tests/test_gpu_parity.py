@@ -380,6 +380,18 @@ def test_matmul_i8_every_width(b, signed):
                                oracle.matmul(pa, pb))
 
 
+@pytest.mark.parametrize("ba,sa,bb,sb", [(6, False, 4, True), (1, True, 8, True), (7, False, 2, False)])
+def test_matmul_i8_many_tiles(ba, sa, bb, sb):
+    """4 x 2 output tiles (a count the XCD-grouped tile order remaps), every
+    dimension ragged, three K steps, against the oracle byte for byte."""
+    c = ccm()
+    rng = np.random.default_rng(900 + ba + 10 * bb)
+    A = rand_matrix(rng, 1000, 300, ba, sa)
+    B = rand_matrix(rng, 300, 500, bb, sb)
+    assert_same_packed(c.matmul(c.compress(dev(A)), c.compress(dev(B))),
+                       oracle.matmul(oracle.compress(A), oracle.compress(B)))
+
+
 def test_matmul_overflow_rule():
     c = ccm()
     a = c.compress(dev(np.array([[2**31, 2**31]])))
