@@ -186,6 +186,17 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v) {
   return (int64_t)t;
 }
 
+// int32 sum over the 64 lanes of a wave (same steps as wave_sum); the caller
+// guarantees the total fits int32.
+__device__ __forceinline__ int32_t wave_sum32(int32_t v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+         __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
+}
+
 __device__ __forceinline__ int64_t wave_min(int64_t v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
