@@ -241,11 +241,13 @@ __device__ __forceinline__ int swz(int r) { return (r ^ (r >> 3)) & 7; }
 //     instruction fills 8 rows, a lane's source chunk chosen so the row lands
 //     swizzled), into the other of two buffers while the MFMAs consume this
 //     one.  Rows past M or N copy the last row (their outputs are not stored).
-//   * One barrier per step, a bare s_barrier after the lane's own copies have
-//     landed (vmcnt(0)); __syncthreads would add a workgroup fence, which
-//     waits for every outstanding memory operation again.
-//   * The operands of each 32-deep slice of K are read from LDS one slice
-//     ahead, into a second register set, one read issued after each MFMA.
+//   * One barrier per step, at its end, once the lane's copies of the next
+//     step have landed (its LDS reads of this step have returned by then:
+//     the barrier also waits for them).  Moving it to the start of the step
+//     with the operands read one 32-deep slice ahead (one LDS read issued
+//     after each MFMA) measured 3-5% slower once that barrier also waited
+//     for the LDS reads, which it must: the other buffer is refilled right
+//     after it.
 __device__ __forceinline__ void mfma_slice(const v4i (&a)[kFM], const v4i (&b)[kFN],
                                            v16i (&acc)[kFM][kFN]) {
 #pragma unroll
@@ -338,34 +340,19 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_i8(const int8_t *__restri
 
   const int64_t nk = ldk / kBK;
   stage(0, 0);
-  v4i a0[kFM], b0[kFN], a1[kFM], b1[kFN];
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
   for (int64_t kc = 0; kc < nk; ++kc) {
     const int cur = (int)(kc & 1);
-    // this lane's copies of step kc have landed; after the barrier everyone's
-    // have, and everyone has finished reading the other buffer (step kc - 1)
-    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
     if (kc + 1 < nk) stage((kc + 1) * kBK, cur ^ 1);  // in flight during the MFMAs
-    fetch(cur, 0, a0, b0);
 #pragma unroll
-    for (int s = 0; s < kBK / 32; ++s) {
-      if (s % 2 == 0) {
-        if (s + 1 < kBK / 32) fetch(cur, 32 * (s + 1), a1, b1);
-        mfma_slice(a0, b0, acc);
-      } else {
-        if (s + 1 < kBK / 32) fetch(cur, 32 * (s + 1), a0, b0);
-        mfma_slice(a1, b1, acc);
-      }
-      if (s + 1 < kBK / 32) {
-        // one LDS read after each of the first six MFMAs, then the last two
-#pragma unroll
-        for (int q = 0; q < kFM + kFN; ++q) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // an MFMA
-          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // an LDS read
-        }
-        __builtin_amdgcn_sched_group_barrier(0x008, kFM * kFN - (kFM + kFN), 0);
-      }
+    for (int kk = 0; kk < kBK; kk += 32) {
+      v4i a[kFM], b[kFN];
+      fetch(cur, kk, a, b);
+      mfma_slice(a, b, acc);
     }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this lane's copies of the next step
+    __syncthreads();  // everyone's copies have landed and this buffer is read
   }
 
   // 32x32 accumulator layout: lane l, register r -> column l%32,
