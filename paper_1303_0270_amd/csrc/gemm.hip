@@ -243,11 +243,11 @@ __device__ __forceinline__ int swz(int r) { return (r ^ (r >> 3)) & 7; }
 //     one.  Rows past M or N copy the last row (their outputs are not stored).
 //   * One barrier per step, at its end, once the lane's copies of the next
 //     step have landed (its LDS reads of this step have returned by then:
-//     the barrier also waits for them).  Moving it to the start of the step
-//     with the operands read one 32-deep slice ahead (one LDS read issued
-//     after each MFMA) measured 3-5% slower once that barrier also waited
-//     for the LDS reads, which it must: the other buffer is refilled right
-//     after it.
+//     the barrier also waits for them, as it must: the buffer just read is
+//     refilled right after it).
+//   * The operands of each 32-deep slice of K are read one slice ahead into
+//     a second register set, one LDS read issued after each MFMA; slice 0 of
+//     a step is read after the barrier that completes its buffer.
 __device__ __forceinline__ void mfma_slice(const v4i (&a)[kFM], const v4i (&b)[kFN],
                                            v16i (&acc)[kFM][kFN]) {
 #pragma unroll
@@ -342,17 +342,36 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_i8(const int8_t *__restri
   stage(0, 0);
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
+  // two operand sets: the reads of slice s + 1 are in flight during the
+  // MFMAs of slice s (within a step; slice 0 of the next step is read after
+  // the barrier, once its buffer is complete)
+  v4i a0[kFM], b0[kFN], a1[kFM], b1[kFN];
+  fetch(0, 0, a0, b0);
   for (int64_t kc = 0; kc < nk; ++kc) {
     const int cur = (int)(kc & 1);
     if (kc + 1 < nk) stage((kc + 1) * kBK, cur ^ 1);  // in flight during the MFMAs
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 32) {
-      v4i a[kFM], b[kFN];
-      fetch(cur, kk, a, b);
-      mfma_slice(a, b, acc);
+    for (int s = 0; s < kBK / 32; ++s) {
+      if (s % 2 == 0) {
+        if (s + 1 < kBK / 32) fetch(cur, 32 * (s + 1), a1, b1);
+        mfma_slice(a0, b0, acc);
+      } else {
+        if (s + 1 < kBK / 32) fetch(cur, 32 * (s + 1), a0, b0);
+        mfma_slice(a1, b1, acc);
+      }
+      if (s + 1 < kBK / 32) {
+        // one LDS read after each of the first six MFMAs, then the last two
+#pragma unroll
+        for (int q = 0; q < kFM + kFN; ++q) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // an MFMA
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // an LDS read
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, kFM * kFN - (kFM + kFN), 0);
+      }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this lane's copies of the next step
     __syncthreads();  // everyone's copies have landed and this buffer is read
+    if (kc + 1 < nk) fetch(cur ^ 1, 0, a0, b0);
   }
 
   // 32x32 accumulator layout: lane l, register r -> column l%32,
