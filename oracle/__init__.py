@@ -91,6 +91,17 @@ _SIGNATURES = {
     "ccmref_vlb_get": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _I64P]),
     "ccmref_vlb_matvec": (ctypes.c_int, [_VP, _I64P, _I64P]),
     "ccmref_vlb_offsets": (ctypes.c_int, [_VP, ctypes.c_int64, _U64P]),
+    "ccmref_frac_bits": (ctypes.c_int, [ctypes.c_double, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "ccmref_quantize_f64": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_int64,
+                                           ctypes.c_int32, _I64P]),
+    "ccmref_quantize_f32": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), ctypes.c_int64,
+                                           ctypes.c_int32, _I64P]),
+    "ccmref_dequantize_f64": (None, [_I64P, ctypes.c_int64, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_double)]),
+    "ccmref_dequantize_f32": (None, [_I64P, ctypes.c_int64, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_float)]),
+    "ccmref_header_fx": (None, [_MP, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8)]),
 }
 
 
@@ -363,6 +374,48 @@ class Oracle:
         self._lib.ccmref_header_cm(ctypes.byref(m), buf)
         return bytes(buf)
 
+    # -- floats in fixed point (Conclusion) ---------------------------------------
+    def frac_bits(self, absmax: float, sig_bits: int) -> int:
+        """Fraction bits f that keep sig_bits significant bits of the largest
+        magnitude: f = sig_bits - 1 - floor(log2 absmax) (0 for absmax 0)."""
+        f = ctypes.c_int32()
+        _check(self._lib.ccmref_frac_bits(float(absmax), sig_bits, ctypes.byref(f)))
+        return int(f.value)
+
+    def quantize(self, v, frac_bits: int) -> np.ndarray:
+        """q = round-half-to-even(v * 2^f) as int64 (v float32 or float64)."""
+        a = np.asarray(v)
+        q = np.empty(a.shape, dtype=np.int64)
+        if a.dtype == np.float32:
+            a = np.ascontiguousarray(a)
+            _check(self._lib.ccmref_quantize_f32(a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                 a.size, frac_bits, _i64(q)))
+        else:
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            _check(self._lib.ccmref_quantize_f64(a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 a.size, frac_bits, _i64(q)))
+        return q
+
+    def dequantize(self, q, frac_bits: int, dtype=np.float64) -> np.ndarray:
+        """v = q * 2^-f: q to double (round half to even), scaled, and for
+        float32 rounded once more."""
+        qa = np.ascontiguousarray(np.asarray(q, dtype=np.int64))
+        if np.dtype(dtype) == np.float32:
+            v = np.empty(qa.shape, dtype=np.float32)
+            self._lib.ccmref_dequantize_f32(_i64(qa), qa.size, frac_bits,
+                                            v.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        else:
+            v = np.empty(qa.shape, dtype=np.float64)
+            self._lib.ccmref_dequantize_f64(_i64(qa), qa.size, frac_bits,
+                                            v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return v
+
+    def header_fx(self, p: Packed, frac_bits: int) -> bytes:
+        buf = (ctypes.c_uint8 * 64)()
+        m = p._struct()
+        self._lib.ccmref_header_fx(ctypes.byref(m), frac_bits, buf)
+        return bytes(buf)
+
     # -- choosing the method -----------------------------------------------------
     def method_info(self, dense) -> dict:
         """Both methods' bit counts and efficiencies (Eq. 15, 17) and the one
@@ -476,6 +529,10 @@ vlb_decompress = _ORACLE.vlb_decompress
 vlb_get = _ORACLE.vlb_get
 vlb_matvec = _ORACLE.vlb_matvec
 vlb_offsets = _ORACLE.vlb_offsets
+frac_bits = _ORACLE.frac_bits
+quantize = _ORACLE.quantize
+dequantize = _ORACLE.dequantize
+header_fx = _ORACLE.header_fx
 
 
 def threads() -> int:

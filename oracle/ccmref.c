@@ -8,6 +8,7 @@
  */
 #include "ccmref.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -475,4 +476,69 @@ double ccmref_eta2_model(const double *p, int32_t k) {
   double mean = 0.0;
   for (int b = 1; b <= 64; b++) mean += (double)b * p[b - 1];
   return 1.0 - mean / 64.0 - (double)k / 64.0;
+}
+
+/* ---- floats in fixed point ------------------------------------------------ */
+
+int ccmref_frac_bits(double absmax, int32_t sig_bits, int32_t *frac_bits) {
+  if (!frac_bits || sig_bits < 1 || sig_bits > 62 || !(absmax >= 0.0) || isinf(absmax))
+    return CCMREF_E_INVAL;
+  if (absmax == 0.0) {
+    *frac_bits = 0;
+    return CCMREF_OK;
+  }
+  int ex = 0;
+  (void)frexp(absmax, &ex); /* absmax = m 2^ex, 1/2 <= m < 1: e = ex - 1 */
+  *frac_bits = sig_bits - 1 - (ex - 1);
+  return CCMREF_OK;
+}
+
+/* round half to even of a finite double, written out: the floor, the
+ * fraction above it (exact), then the nearer neighbour or the even one */
+static double round_half_even(double t) {
+  const double fl = floor(t);
+  const double d = t - fl;
+  if (d > 0.5) return fl + 1.0;
+  if (d < 0.5) return fl;
+  return fmod(fl, 2.0) == 0.0 ? fl : fl + 1.0;
+}
+
+static int quantize_one(double v, int32_t f, int64_t *q) {
+  if (isnan(v) || isinf(v)) return CCMREF_E_RANGE;
+  const double t = ldexp(v, f); /* exact unless it leaves the double range */
+  if (!(fabs(t) < 0x1p62)) return CCMREF_E_OVERFLOW;
+  *q = (int64_t)round_half_even(t);
+  return CCMREF_OK;
+}
+
+int ccmref_quantize_f64(const double *v, int64_t n, int32_t frac_bits, int64_t *q) {
+  if (!v || !q || n < 0) return CCMREF_E_INVAL;
+  for (int64_t i = 0; i < n; i++) {
+    const int rc = quantize_one(v[i], frac_bits, &q[i]);
+    if (rc != CCMREF_OK) return rc;
+  }
+  return CCMREF_OK;
+}
+
+int ccmref_quantize_f32(const float *v, int64_t n, int32_t frac_bits, int64_t *q) {
+  if (!v || !q || n < 0) return CCMREF_E_INVAL;
+  for (int64_t i = 0; i < n; i++) {
+    const int rc = quantize_one((double)v[i], frac_bits, &q[i]);
+    if (rc != CCMREF_OK) return rc;
+  }
+  return CCMREF_OK;
+}
+
+void ccmref_dequantize_f64(const int64_t *q, int64_t n, int32_t frac_bits, double *v) {
+  for (int64_t i = 0; i < n; i++) v[i] = ldexp((double)q[i], -frac_bits);
+}
+
+void ccmref_dequantize_f32(const int64_t *q, int64_t n, int32_t frac_bits, float *v) {
+  for (int64_t i = 0; i < n; i++) v[i] = (float)ldexp((double)q[i], -frac_bits);
+}
+
+void ccmref_header_fx(const ccmref_matrix *m, int32_t frac_bits, uint8_t out[64]) {
+  ccmref_header(m, out);
+  out[7] = (uint8_t)(out[7] | 4u);
+  put_le(out + 48, (uint64_t)(uint16_t)(int16_t)frac_bits, 2);
 }

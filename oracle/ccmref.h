@@ -223,6 +223,41 @@ typedef struct {
 int ccmref_method_info_of(const int64_t *dense, int64_t rows, int64_t cols,
                           ccmref_method_info *out);
 
+/* ---- Floats in fixed point (Conclusion) --------------------------------
+ *
+ * The Conclusion says floats fit the framework at the expense of precision
+ * and gives no encoding.  Reading: a float matrix is stored as the integer
+ * matrix q = round-half-to-even(v * 2^f) (f "fraction bits", one per
+ * matrix), which Method 1 then packs like any integer matrix; the only
+ * loss is that rounding, |v - q 2^-f| <= 2^-(f+1).  Everything after it is
+ * exact integer arithmetic on q, and a float result is the exact integer
+ * result converted back: to double with round-half-to-even, scaled by 2^-f
+ * (exact unless the result is subnormal, then rounded once), and for float32
+ * rounded once more to float.  The user picks f directly or as the number of
+ * significant bits p the largest magnitude keeps: with 2^e <= max|v| <
+ * 2^(e+1), f = p - 1 - e.
+ * Pins: exact rational arithmetic (Python Fractions) on every rounding and
+ * conversion, ties, subnormals, the error bound, a hand-computed header.
+ */
+
+/* f = sig_bits - 1 - e, 2^e <= absmax < 2^(e+1); f = 0 for absmax 0.
+ * CCMREF_E_INVAL unless 1 <= sig_bits <= 62 and absmax is finite, >= 0. */
+int ccmref_frac_bits(double absmax, int32_t sig_bits, int32_t *frac_bits);
+
+/* q[i] = round-half-to-even(v[i] * 2^frac_bits).  CCMREF_E_RANGE for NaN or
+ * infinity, CCMREF_E_OVERFLOW when |v * 2^f| >= 2^62. */
+int ccmref_quantize_f64(const double *v, int64_t n, int32_t frac_bits, int64_t *q);
+int ccmref_quantize_f32(const float *v, int64_t n, int32_t frac_bits, int64_t *q);
+
+/* v[i] = q[i] * 2^-frac_bits as above (double, or rounded on to float). */
+void ccmref_dequantize_f64(const int64_t *q, int64_t n, int32_t frac_bits, double *v);
+void ccmref_dequantize_f32(const int64_t *q, int64_t n, int32_t frac_bits, float *v);
+
+/* Header of a fixed-point matrix (this library's format): the integer
+ * matrix's header with flags bit 2 set and f as a little-endian int16 at
+ * bytes 48..49. */
+void ccmref_header_fx(const ccmref_matrix *m, int32_t frac_bits, uint8_t out[64]);
+
 /* Eq. 29: expected eta_2 for a bit-length distribution, p[b-1] = P(bit-length
  * = b) for b = 1..64, with a fixed k: 1 - sum_b b p_b / 64 - k / 64.  The
  * paper's analytic tables fix k = 7. */

@@ -745,10 +745,144 @@ def pin_method_bruteforce(o):
     assert tie["sm_nbits"] == tie["vlb_nbits"] == 32 and tie["method"] == 1
 
 
+# ---- floats in fixed point (Conclusion) ------------------------------------
+
+def _rne_fraction(x: Fraction) -> int:
+    """Round half to even of an exact rational (Python's round on Fraction)."""
+    return round(x)
+
+
+def _fx_cases(rng):
+    """(values as float64, f) cases: random magnitudes over the exponent
+    range, exact ties, subnormals, zeros of both signs."""
+    cases = []
+    for f in (0, 1, 7, 20, 52, -3, -40, 300, 1074):
+        # |v * 2^f| < 2^61: v = m * 2^(k - f) with |m| < 2^53, k <= 8
+        m = rng.integers(-(1 << 53) + 1, 1 << 53, size=40)
+        k = rng.integers(-60, 9, size=40)
+        v = np.array([math.ldexp(float(mi), int(ki) - f) for mi, ki in zip(m, k)])
+        t = rng.integers(-(1 << 40), 1 << 40, size=10)
+        ties = np.array([math.ldexp(float(ti) + 0.5, -f) for ti in t])
+        cases.append((np.concatenate([v, ties, [0.0, -0.0, math.ldexp(1.0, -f - 2),
+                                                 -math.ldexp(3.0, -f - 1)]]), f))
+    sub = np.array([5e-324, -5e-324, 2.5e-320, math.ldexp(1.0, -1074) * 7])
+    cases.append((sub, 1074))
+    cases.append((sub, 1076))
+    return cases
+
+
+def pin_fixed_point_quantize(o):
+    """q = round-half-to-even(v * 2^f) against exact rational arithmetic, for
+    float64 and float32 inputs, including ties (to even), subnormals and
+    signed zeros; the rounding error is at most 2^-(f+1)."""
+    rng = np.random.default_rng(53)
+    for v, f in _fx_cases(rng):
+        want = [_rne_fraction(Fraction(float(x)) * Fraction(2) ** f) for x in v]
+        assert o.quantize(v, f).tolist() == want, f
+        for x, q in zip(v, want):
+            assert abs(Fraction(float(x)) - Fraction(q) / Fraction(2) ** f) <= \
+                Fraction(1, 2) / Fraction(2) ** f
+        v32 = v.astype(np.float32)
+        want32 = [_rne_fraction(Fraction(float(x)) * Fraction(2) ** f) for x in v32]
+        assert o.quantize(v32, f).tolist() == want32, f
+    # every half-integer multiple of 2^-f goes to the even neighbour
+    halves = np.array([k + 0.5 for k in range(-6, 6)])
+    assert o.quantize(halves, 0).tolist() == [-6, -4, -4, -2, -2, 0, 0, 2, 2, 4, 4, 6]
+
+
+def pin_fixed_point_errors(o):
+    """NaN and infinities are out of range; |v * 2^f| >= 2^62 overflows, the
+    largest double below it does not."""
+    import oracle
+    for bad in (math.nan, math.inf, -math.inf):
+        try:
+            o.quantize(np.array([1.0, bad]), 3)
+            raise AssertionError("NaN / infinity accepted")
+        except oracle.OracleError as e:
+            assert e.code == oracle.E_RANGE
+    for f in (0, 10, -10):
+        edge = math.ldexp(1.0, 62 - f)
+        for v in (edge, -edge, math.ldexp(1.0, 1023)):
+            try:
+                o.quantize(np.array([v]), f)
+                raise AssertionError("overflow accepted")
+            except oracle.OracleError as e:
+                assert e.code == oracle.E_OVERFLOW
+        below = math.nextafter(edge, 0.0)
+        assert o.quantize(np.array([below, -below]), f).tolist() == [(1 << 62) - 512,
+                                                                      -(1 << 62) + 512]
+
+
+def pin_fixed_point_dequantize(o):
+    """v = q 2^-f: q rounded to double (half to even), then scaled (rounded
+    once if subnormal), against exact rationals; float32 rounds that double
+    once more."""
+    rng = np.random.default_rng(59)
+    q = np.concatenate([rng.integers(-(1 << 62), 1 << 62, size=40),
+                        rng.integers(-(1 << 20), 1 << 20, size=40),
+                        [0, 1, -1, (1 << 53) + 1, (1 << 62) - 1, -(1 << 62)]]).astype(np.int64)
+    for f in (0, 3, 40, -5, 1074, 1100, 1200):
+        got = o.dequantize(q, f)
+        want = [float(Fraction(float(int(x))) / Fraction(2) ** f) for x in q]
+        assert got.view(np.uint64).tolist() == np.array(want).view(np.uint64).tolist(), f
+        got32 = o.dequantize(q, f, np.float32)
+        assert got32.view(np.uint32).tolist() == \
+            np.array(want).astype(np.float32).view(np.uint32).tolist(), f
+
+
+def pin_fixed_point_frac_bits(o):
+    """f = p - 1 - floor(log2 max|v|), so that 2^(p-1) <= max|v| 2^f < 2^p;
+    the width of the quantized matrix is then p to p + 2 bits."""
+    import oracle
+    table = [(1.0, 10, 9), (0.75, 10, 10), (1000.0, 10, 0), (1023.999, 10, 0),
+             (1024.0, 10, -1), (0.0, 7, 0), (5e-324, 1, 1074), (5e-324, 62, 1135),
+             (1.7976931348623157e308, 62, -962), (0.5, 1, 1)]
+    for a, p, f in table:
+        assert o.frac_bits(a, p) == f, (a, p)
+    for a, p in ((1.0, 0), (1.0, 63), (-1.0, 5), (math.nan, 5), (math.inf, 5)):
+        try:
+            o.frac_bits(a, p)
+            raise AssertionError("invalid frac_bits arguments accepted")
+        except oracle.OracleError as e:
+            assert e.code == oracle.E_INVAL
+    rng = np.random.default_rng(61)
+    for _ in range(60):
+        p = int(rng.integers(1, 40))
+        v = rng.standard_normal(size=(3, 5)) * 10.0 ** rng.integers(-30, 30)
+        a = float(np.abs(v).max())
+        f = o.frac_bits(a, p)
+        s = Fraction(a) * Fraction(2) ** f
+        assert Fraction(2) ** (p - 1) <= s < Fraction(2) ** p
+        qm = o.quantize(v, f)
+        b = o.compress(qm).bits
+        assert p <= b <= p + 2, (p, b)
+
+
+def pin_fixed_point_headers(o):
+    """Fixed-point matrices against headers and bitstrings derived by hand:
+    the quantized values, flags bit 2, f at bytes 48..49 (positive and
+    negative f), and a tie rounded to even."""
+    g = _golden_kv("fixed_point_headers.txt")
+    hx = lambda key: bytes(int(t, 16) for t in g[key].split())
+    mat = lambda key, ty: np.array([[ty(v) for v in r.split()] for r in g[key].split(";")])
+    for c in ("a", "b"):
+        f = int(g[c + "_frac_bits"])
+        q = o.quantize(mat(c + "_values", float), f)
+        assert q.tolist() == mat(c + "_q", int).tolist()
+        p = o.compress(q)
+        assert p.bits == int(g[c + "_bits"])
+        assert o.header_fx(p, f) == hx(c + "_header")
+        assert [int(w) for w in p.payload] == [int(g[c + "_payload"], 16)]
+        assert o.dequantize(o.decompress(p), f).tolist() == mat(c + "_values", float).tolist() \
+            or c == "b"
+
+
 ALL_PINS = [pin_table1, pin_eq1_special_case, pin_bitlen_bruteforce, pin_width_bruteforce,
             pin_worked_example, pin_signed_headers, pin_word_count, pin_round_trip, pin_signed_small_bruteforce,
             pin_locality, pin_get, pin_ops_bruteforce, pin_ops_exhaustive_2x2, pin_identities,
             pin_overflow_rules, pin_vlb_worked_example, pin_vlb_layout, pin_vlb_extremes,
             pin_vlb_ops_bruteforce, pin_vlb_exhaustive_small, pin_cm_worked_example,
             pin_cm_layout, pin_transposed_products_bruteforce, pin_method_worked_example,
-            pin_method_paper_values, pin_eta2_model_tables, pin_method_bruteforce]
+            pin_method_paper_values, pin_eta2_model_tables, pin_method_bruteforce,
+            pin_fixed_point_quantize, pin_fixed_point_errors, pin_fixed_point_dequantize,
+            pin_fixed_point_frac_bits, pin_fixed_point_headers]

@@ -88,6 +88,19 @@ MUTANTS = {
     "vlb_matvec_last": [("for (int64_t j = 0; j < m->cols; j++) {\n      int64_t a = vlb_next(m, &p);",
                          "for (int64_t j = 0; j < m->cols; j++) {\n      int64_t a = vlb_next(m, &p);\n"
                          "      if (j == m->cols - 1) a = 0;")],
+    # fixed point: halves rounded up instead of to even
+    "fx_round_half_up": [("return fmod(fl, 2.0) == 0.0 ? fl : fl + 1.0;", "return fl + 1.0;")],
+    # fixed point: one fraction bit too many
+    "fx_frac_bits_off_by_one": [("*frac_bits = sig_bits - 1 - (ex - 1);",
+                                 "*frac_bits = sig_bits - (ex - 1);")],
+    # fixed point: dequantization scales the wrong way
+    "fx_dequantize_scale_sign": [("v[i] = ldexp((double)q[i], -frac_bits);",
+                                  "v[i] = ldexp((double)q[i], frac_bits);")],
+    # fixed point: the overflow bound admits exactly 2^62
+    "fx_overflow_bound": [("if (!(fabs(t) < 0x1p62))", "if (!(fabs(t) <= 0x1p62))")],
+    # fixed point: f written at the wrong header offset
+    "fx_header_offset": [("put_le(out + 48, (uint64_t)(uint16_t)(int16_t)frac_bits, 2);",
+                          "put_le(out + 56, (uint64_t)(uint16_t)(int16_t)frac_bits, 2);")],
 }
 
 
