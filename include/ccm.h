@@ -70,7 +70,7 @@ typedef enum {
   CCM_E_UNSUPPORTED = -7  /* valid request the library does not implement */
 } ccm_status;
 
-typedef enum { CCM_I32 = 0, CCM_I64 = 1 } ccm_dtype;
+typedef enum { CCM_I32 = 0, CCM_I64 = 1, CCM_F32 = 2, CCM_F64 = 3 } ccm_dtype;
 
 /* Descriptor of a compressed matrix "m" (the paper's lower-case name for the
  * compressed form of M).  Host struct; `payload` is a device pointer. */
@@ -460,6 +460,55 @@ int ccm_vlb_get(const ccm_vlb_desc *a, int64_t i, int64_t j, int64_t *value, voi
  * y: device, rows int64.  Async. */
 int ccm_vlb_matvec(const ccm_vlb_desc *a, const void *x, int32_t xdtype, int64_t *y,
                    void *stream);
+
+/* ---- floats in fixed point (Conclusion) ---------------------------------
+ *
+ * The Conclusion says floats fit the framework at the expense of precision;
+ * it gives no encoding.  This library's reading: a float matrix V is stored
+ * as the integer matrix q = round-half-to-even(v * 2^f), one f ("fraction
+ * bits", possibly negative) per matrix, which Method 1 packs like any
+ * integer matrix (ccm_compress on q).  The rounding is the only loss,
+ * |v - q 2^-f| <= 2^-(f+1); every operation after it is the exact integer
+ * operation on q.  An integer result r with scale 2^-g converts back as
+ * ccm_dequantize(r, g): r to double (round half to even), times 2^-g (exact
+ * unless subnormal, then rounded once), and for float32 rounded once more.
+ * So y = V x takes q (scale 2^-f) and a quantized x (scale 2^-g) through
+ * ccm_matvec and dequantizes y at f + g; y is exact modulo 2^64, so the
+ * caller keeps cols * max|q| * max|x_q| below 2^63.
+ * The fraction bits usually come from the significant bits p the largest
+ * magnitude should keep (the Conclusion's point: data with fewer
+ * significant digits compress better): f = p - 1 - e with
+ * 2^e <= max|v| < 2^(e+1), so the width of q is p to p + 2 bits.
+ * Float dtypes: CCM_F32 (float) and CCM_F64 (double). */
+
+/* Largest |v| of n device floats (dtype CCM_F32 or CCM_F64), exact.
+ * CCM_E_RANGE if any value is NaN or infinite.  Blocking. */
+int ccm_float_absmax(const void *v, int32_t dtype, int64_t n, double *absmax, void *stream);
+
+/* Host only: f = sig_bits - 1 - e with 2^e <= absmax < 2^(e+1); 0 for
+ * absmax 0.  CCM_E_INVAL unless 1 <= sig_bits <= 62 and absmax is finite
+ * and >= 0. */
+int ccm_float_frac_bits(double absmax, int32_t sig_bits, int32_t *frac_bits);
+
+/* q[i] = round-half-to-even(v[i] * 2^frac_bits) for n device floats into
+ * device int64 q, and the exact (min, max) of q, which is all a compression
+ * plan needs (ccm_width, ccm_words; then ccm_compress on q).  CCM_E_RANGE if
+ * any value is NaN or infinite, else CCM_E_OVERFLOW if some |v 2^f| >= 2^62;
+ * q is then unspecified.  |frac_bits| <= 1200.  Blocking. */
+int ccm_quantize(const void *v, int32_t dtype, int64_t n, int32_t frac_bits, int64_t *q,
+                 int64_t *qmin, int64_t *qmax, void *stream);
+
+/* out[i] = q[i] * 2^-frac_bits converted as described above, into device
+ * floats of dtype CCM_F32 or CCM_F64.  |frac_bits| <= 2400.  Async. */
+int ccm_dequantize(const int64_t *q, int64_t n, int32_t frac_bits, int32_t dtype, void *out,
+                   void *stream);
+
+/* Header of a fixed-point matrix (row-major): the integer header of q with
+ * flags bit 2 set and frac_bits as a little-endian int16 at bytes 48..49.
+ * decode_fx reads such a header (CCM_E_INVAL if flags bit 2 is clear or the
+ * other reserved bytes are not zero) into the descriptor of q and f. */
+int ccm_header_encode_fx(const ccm_desc *d, int32_t frac_bits, uint8_t out[64]);
+int ccm_header_decode_fx(const uint8_t in[64], ccm_desc *d, int32_t *frac_bits);
 
 #ifdef __cplusplus
 }

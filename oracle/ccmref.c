@@ -504,7 +504,6 @@ static double round_half_even(double t) {
 }
 
 static int quantize_one(double v, int32_t f, int64_t *q) {
-  if (isnan(v) || isinf(v)) return CCMREF_E_RANGE;
   const double t = ldexp(v, f); /* exact unless it leaves the double range */
   if (!(fabs(t) < 0x1p62)) return CCMREF_E_OVERFLOW;
   *q = (int64_t)round_half_even(t);
@@ -513,6 +512,8 @@ static int quantize_one(double v, int32_t f, int64_t *q) {
 
 int ccmref_quantize_f64(const double *v, int64_t n, int32_t frac_bits, int64_t *q) {
   if (!v || !q || n < 0) return CCMREF_E_INVAL;
+  for (int64_t i = 0; i < n; i++)
+    if (isnan(v[i]) || isinf(v[i])) return CCMREF_E_RANGE;
   for (int64_t i = 0; i < n; i++) {
     const int rc = quantize_one(v[i], frac_bits, &q[i]);
     if (rc != CCMREF_OK) return rc;
@@ -522,6 +523,8 @@ int ccmref_quantize_f64(const double *v, int64_t n, int32_t frac_bits, int64_t *
 
 int ccmref_quantize_f32(const float *v, int64_t n, int32_t frac_bits, int64_t *q) {
   if (!v || !q || n < 0) return CCMREF_E_INVAL;
+  for (int64_t i = 0; i < n; i++)
+    if (isnan(v[i]) || isinf(v[i])) return CCMREF_E_RANGE;
   for (int64_t i = 0; i < n; i++) {
     const int rc = quantize_one((double)v[i], frac_bits, &q[i]);
     if (rc != CCMREF_OK) return rc;

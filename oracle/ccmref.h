@@ -244,8 +244,9 @@ int ccmref_method_info_of(const int64_t *dense, int64_t rows, int64_t cols,
  * CCMREF_E_INVAL unless 1 <= sig_bits <= 62 and absmax is finite, >= 0. */
 int ccmref_frac_bits(double absmax, int32_t sig_bits, int32_t *frac_bits);
 
-/* q[i] = round-half-to-even(v[i] * 2^frac_bits).  CCMREF_E_RANGE for NaN or
- * infinity, CCMREF_E_OVERFLOW when |v * 2^f| >= 2^62. */
+/* q[i] = round-half-to-even(v[i] * 2^frac_bits).  CCMREF_E_RANGE when any
+ * value is NaN or infinite, else CCMREF_E_OVERFLOW when some
+ * |v * 2^f| >= 2^62. */
 int ccmref_quantize_f64(const double *v, int64_t n, int32_t frac_bits, int64_t *q);
 int ccmref_quantize_f32(const float *v, int64_t n, int32_t frac_bits, int64_t *q);
 

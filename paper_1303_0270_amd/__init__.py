@@ -21,7 +21,8 @@ __all__ = ["CMatrix", "CcmError", "compress", "decompress", "get", "gather", "ad
            "packed_bytes", "payload_capacity", "width", "Batch", "DynBatch",
            "method_info", "compress_auto",
            "VlbMatrix", "vlb_compress", "vlb_decompress", "vlb_get", "vlb_matvec",
-           "vlb_matvec_launcher"]
+           "vlb_matvec_launcher", "float_absmax", "float_frac_bits", "quantize", "dequantize",
+           "compress_float", "decompress_float", "matvec_float"]
 
 
 def _stream(stream=None) -> ctypes.c_void_p:
@@ -39,6 +40,17 @@ def _dtype_code(t: torch.Tensor) -> int:
     if t.dtype == torch.int64:
         return I64
     raise TypeError(f"int32 or int64 tensor expected, got {t.dtype}")
+
+
+F32, F64 = 2, 3  # float dtype codes of the C ABI
+
+
+def _float_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"float32 or float64 tensor expected, got {t.dtype}")
 
 
 def _device_tensor(t: torch.Tensor, what: str) -> torch.Tensor:
@@ -84,6 +96,8 @@ class CMatrix:
             payload = torch.empty(cap, dtype=torch.uint8, device=device or "cuda")
         self.payload = payload
         self.desc.payload = payload.data_ptr()
+        # fixed-point matrices (floats, Conclusion): the values are q 2^-frac_bits
+        self.frac_bits = None
 
     rows = property(lambda self: int(self.desc.rows if self.order == "C" else self.desc.cols))
     cols = property(lambda self: int(self.desc.cols if self.order == "C" else self.desc.rows))
@@ -107,11 +121,17 @@ class CMatrix:
         """The transpose: the same payload read in the other order."""
         d = Desc()
         ctypes.pointer(d)[0] = self.desc
-        return CMatrix(d, self.payload, order="F" if self.order == "C" else "C")
+        t = CMatrix(d, self.payload, order="F" if self.order == "C" else "C")
+        t.frac_bits = self.frac_bits
+        return t
 
     def header(self) -> bytes:
         buf = (ctypes.c_uint8 * 64)()
-        if self.order == "C":
+        if self.frac_bits is not None:
+            _row_major(self, "header of a fixed-point matrix")
+            check(lib.ccm_header_encode_fx(ctypes.byref(self.desc), self.frac_bits, buf),
+                  "ccm_header_encode_fx")
+        elif self.order == "C":
             check(lib.ccm_header_encode(ctypes.byref(self.desc), buf), "ccm_header_encode")
         else:
             check(lib.ccm_header_encode_cm(ctypes.byref(self.desc), buf), "ccm_header_encode_cm")
@@ -126,8 +146,9 @@ class CMatrix:
         return self.header() + self.payload_bytes()
 
     def __repr__(self):
+        fx = "" if self.frac_bits is None else f", frac_bits={self.frac_bits}"
         return (f"CMatrix({self.rows}x{self.cols}, order={self.order}, bits={self.bits}, "
-                f"signed={self.is_signed}, range=[{self.vmin}, {self.vmax}])")
+                f"signed={self.is_signed}, range=[{self.vmin}, {self.vmax}]{fx})")
 
 
 def _row_major(m: CMatrix, what: str) -> None:
@@ -142,7 +163,13 @@ def from_serialized(blob: bytes, device="cuda") -> CMatrix:
     d = Desc()
     hdr = (ctypes.c_uint8 * 64).from_buffer_copy(blob[:64])
     order = "F" if blob[7] & 2 else "C"
-    if order == "C":
+    fx = None
+    if blob[7] & 4:
+        f = ctypes.c_int32()
+        check(lib.ccm_header_decode_fx(hdr, ctypes.byref(d), ctypes.byref(f)),
+              "ccm_header_decode_fx")
+        fx = int(f.value)
+    elif order == "C":
         check(lib.ccm_header_decode(hdr, ctypes.byref(d)), "ccm_header_decode")
     else:
         check(lib.ccm_header_decode_cm(hdr, ctypes.byref(d)), "ccm_header_decode_cm")
@@ -150,6 +177,7 @@ def from_serialized(blob: bytes, device="cuda") -> CMatrix:
     if len(blob) != 64 + nbytes:
         raise CcmError(E_INVAL, "from_serialized: payload length")
     m = CMatrix(d, device=device, order=order)
+    m.frac_bits = fx
     m.payload.zero_()
     host = torch.frombuffer(bytearray(blob[64:]), dtype=torch.uint8)
     m.payload[:nbytes].copy_(host)
@@ -217,6 +245,14 @@ def add(a: CMatrix, b: CMatrix, stream=None, onepass: bool = True) -> CMatrix:
     exact range is reduced); otherwise ccm_add_plan then ccm_add."""
     if a.order != b.order:
         raise CcmError(E_UNSUPPORTED, "add: operands unravelled in different orders")
+    if a.frac_bits != b.frac_bits:
+        raise CcmError(E_UNSUPPORTED, "add: operands in different fixed-point scales")
+    c = _add(a, b, stream, onepass)
+    c.frac_bits = a.frac_bits
+    return c
+
+
+def _add(a: CMatrix, b: CMatrix, stream, onepass: bool) -> CMatrix:
     s = _stream(stream)
     d = Desc()
     if onepass:
@@ -246,6 +282,7 @@ def scale(a: CMatrix, s_: int, stream=None) -> CMatrix:
     c = CMatrix(d, device=a.payload.device, order=a.order)
     check(lib.ccm_scale(ctypes.byref(a.desc), s_, ctypes.byref(c.desc), _stream(stream)),
           "ccm_scale")
+    c.frac_bits = a.frac_bits
     return c
 
 
@@ -362,7 +399,10 @@ def matmul_pack(a: CMatrix, b: CMatrix, c: CMatrix, scratch: torch.Tensor, strea
 
 def matmul(a: CMatrix, b: CMatrix, scratch: torch.Tensor | None = None, stream=None) -> CMatrix:
     c, scratch = matmul_plan(a, b, scratch, stream)
-    return matmul_pack(a, b, c, scratch, stream)
+    c = matmul_pack(a, b, c, scratch, stream)
+    if a.frac_bits is not None or b.frac_bits is not None:
+        c.frac_bits = (a.frac_bits or 0) + (b.frac_bits or 0)
+    return c
 
 
 # ---- results whose width stays on the device ------------------------------
@@ -471,6 +511,8 @@ class VlbMatrix:
             payload = torch.empty(cap, dtype=torch.uint8, device=index.device)
         self.payload = payload
         self.desc.payload = payload.data_ptr()
+        # fixed-point matrices (floats, Conclusion): the values are q 2^-frac_bits
+        self.frac_bits = None
         self.desc.index = index.data_ptr()
 
     rows = property(lambda self: int(self.desc.rows))
@@ -622,3 +664,115 @@ def generate(rows: int, cols: int, lo: int, hi: int, seed: int, stream_id: int =
 
 
 from .batch import Batch, DynBatch  # noqa: E402
+
+
+# ---- floats in fixed point (Conclusion) -----------------------------------
+#
+# A float matrix is stored as q = round-half-to-even(v 2^f) (one f per matrix)
+# packed by Method 1; every operation is then the exact integer one on q, and
+# float results are the exact integer results converted back (include/ccm.h).
+
+def float_absmax(v: torch.Tensor, stream=None) -> float:
+    """Largest |v| of a float32/float64 device tensor (exact); CcmError
+    E_RANGE for NaN or infinity."""
+    t = _device_tensor(v, "v")
+    a = ctypes.c_double()
+    check(lib.ccm_float_absmax(_ptr(t), _float_code(t), t.numel(), ctypes.byref(a),
+                               _stream(stream)), "ccm_float_absmax")
+    return float(a.value)
+
+
+def float_frac_bits(absmax: float, sig_bits: int) -> int:
+    """Fraction bits keeping sig_bits significant bits of the largest
+    magnitude: sig_bits - 1 - floor(log2 absmax)."""
+    f = ctypes.c_int32()
+    check(lib.ccm_float_frac_bits(float(absmax), sig_bits, ctypes.byref(f)),
+          "ccm_float_frac_bits")
+    return int(f.value)
+
+
+def quantize(v: torch.Tensor, frac_bits: int, out: torch.Tensor | None = None, stream=None):
+    """(q, qmin, qmax): q = round-half-to-even(v 2^frac_bits) as int64, same
+    shape, and its exact extremes."""
+    t = _device_tensor(v, "v")
+    if out is None:
+        out = torch.empty(t.shape, dtype=torch.int64, device=t.device)
+    elif out.dtype != torch.int64 or out.numel() != t.numel() or not out.is_contiguous():
+        raise CcmError(E_INVAL, "quantize: out")
+    lo, hi = ctypes.c_int64(), ctypes.c_int64()
+    check(lib.ccm_quantize(_ptr(t), _float_code(t), t.numel(), frac_bits, _ptr(out),
+                           ctypes.byref(lo), ctypes.byref(hi), _stream(stream)), "ccm_quantize")
+    return out, int(lo.value), int(hi.value)
+
+
+def dequantize(q: torch.Tensor, frac_bits: int, dtype=torch.float64,
+               out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """q 2^-frac_bits as float64 or float32 (one rounding to double, the exact
+    scaling, and for float32 one more rounding)."""
+    t = _device_tensor(q, "q")
+    if t.dtype != torch.int64:
+        raise TypeError("int64 tensor expected")
+    if out is None:
+        out = torch.empty(t.shape, dtype=dtype, device=t.device)
+    elif out.numel() != t.numel() or not out.is_contiguous():
+        raise CcmError(E_INVAL, "dequantize: out")
+    check(lib.ccm_dequantize(_ptr(t), t.numel(), frac_bits, _float_code(out), _ptr(out),
+                             _stream(stream)), "ccm_dequantize")
+    return out
+
+
+def _frac_bits_of(v: torch.Tensor, sig_bits, frac_bits, stream) -> int:
+    if (sig_bits is None) == (frac_bits is None):
+        raise ValueError("give exactly one of sig_bits and frac_bits")
+    if frac_bits is not None:
+        return int(frac_bits)
+    return float_frac_bits(float_absmax(v, stream), sig_bits)
+
+
+def compress_float(dense: torch.Tensor, sig_bits: int | None = None,
+                   frac_bits: int | None = None, stream=None) -> CMatrix:
+    """A 2-D float32/float64 device tensor in fixed point: quantized at
+    frac_bits (or at the fraction bits that keep sig_bits significant bits of
+    its largest magnitude), then SM-packed like an integer matrix; the
+    quantization pass also yields the exact range, so no other pass runs."""
+    t = _device_tensor(dense, "dense")
+    if t.dim() != 2:
+        raise ValueError("2-D tensor expected")
+    f = _frac_bits_of(t, sig_bits, frac_bits, stream)
+    q, lo, hi = quantize(t, f, stream=stream)
+    b, sgn = width(lo, hi)
+    d = Desc()
+    d.rows, d.cols, d.vmin, d.vmax = t.shape[0], t.shape[1], lo, hi
+    d.bits, d.is_signed, d.words = b, 1 if sgn else 0, words(t.shape[0], t.shape[1], b)
+    m = CMatrix(d, device=t.device)
+    check(lib.ccm_compress(_ptr(q), I64, ctypes.byref(m.desc), _stream(stream)), "ccm_compress")
+    m.frac_bits = f
+    return m
+
+
+def decompress_float(m: CMatrix, dtype=torch.float64, stream=None) -> torch.Tensor:
+    """The fixed-point matrix as floats: q decoded, then q 2^-frac_bits."""
+    if m.frac_bits is None:
+        raise CcmError(E_INVAL, "decompress_float: not a fixed-point matrix")
+    q = decompress(m, stream=stream)
+    out = torch.empty(q.shape, dtype=dtype, device=q.device)
+    dequantize(q.contiguous(), m.frac_bits, dtype, out=out, stream=stream)
+    return out
+
+
+def matvec_float(m: CMatrix, x: torch.Tensor, x_sig_bits: int | None = None,
+                 x_frac_bits: int | None = None, stream=None) -> torch.Tensor:
+    """y = V x for a fixed-point V: x quantized at x_frac_bits (or keeping
+    x_sig_bits significant bits), the exact integer matvec, and y converted
+    back at frac_bits + x_frac_bits, as float64.  CcmError E_OVERFLOW when
+    cols * max|q| * max|x_q| >= 2^63 (the integer sums could wrap)."""
+    if m.frac_bits is None:
+        raise CcmError(E_INVAL, "matvec_float: not a fixed-point matrix")
+    t = _device_tensor(x, "x")
+    g = _frac_bits_of(t, x_sig_bits, x_frac_bits, stream)
+    xq, xlo, xhi = quantize(t, g, stream=stream)
+    amax = max(abs(m.vmin), abs(m.vmax))
+    if m.cols * amax * max(abs(xlo), abs(xhi)) >= (1 << 63):
+        raise CcmError(E_OVERFLOW, "matvec_float: the integer sums could leave int64")
+    y = matvec(m, xq, stream=stream)
+    return dequantize(y, m.frac_bits + g, torch.float64, stream=stream)

@@ -2,6 +2,7 @@
 // blocking range ("plan") passes and kernel dispatch.  See include/ccm.h.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -840,6 +841,99 @@ int ccm_header_decode_cm(const uint8_t in[64], ccm_desc *at) {
   t.rows = a.cols;
   t.cols = a.rows;
   *at = t;
+  return CCM_OK;
+}
+
+// ---- floats in fixed point (Conclusion) ----------------------------------
+
+int ccm_float_absmax(const void *v, int32_t dtype, int64_t n, double *absmax, void *stream) {
+  if (!v || !absmax || n < 1 || (dtype != CCM_F32 && dtype != CCM_F64)) return CCM_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx *c = nullptr;
+  int rc = device_ctx(&c);
+  if (rc != CCM_OK) return rc;
+  CCM_HIP(ccm::launch_range_init(c->slot, s));
+  CCM_HIP(ccm::launch_float_absmax(v, dtype, (uint64_t)n, c->slot, s));
+  ccm::RangeSlot r;
+  rc = read_slot(c, s, &r);
+  if (rc != CCM_OK) return rc;
+  if (r.vmax >= 0x7FF0000000000000ll) return CCM_E_RANGE;  // NaN or infinity
+  double a;
+  std::memcpy(&a, &r.vmax, sizeof a);
+  *absmax = a;
+  return CCM_OK;
+}
+
+int ccm_float_frac_bits(double absmax, int32_t sig_bits, int32_t *frac_bits) {
+  if (!frac_bits || sig_bits < 1 || sig_bits > 62 || !(absmax >= 0.0) || std::isinf(absmax))
+    return CCM_E_INVAL;
+  if (absmax == 0.0) {
+    *frac_bits = 0;
+    return CCM_OK;
+  }
+  int ex = 0;
+  (void)std::frexp(absmax, &ex);  // absmax = m 2^ex, 1/2 <= m < 1
+  *frac_bits = sig_bits - ex;     // sig_bits - 1 - floor(log2 absmax)
+  return CCM_OK;
+}
+
+int ccm_quantize(const void *v, int32_t dtype, int64_t n, int32_t frac_bits, int64_t *q,
+                 int64_t *qmin, int64_t *qmax, void *stream) {
+  if (!v || !q || !qmin || !qmax || n < 1 || (dtype != CCM_F32 && dtype != CCM_F64) ||
+      frac_bits < -1200 || frac_bits > 1200)
+    return CCM_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx *c = nullptr;
+  int rc = device_ctx(&c);
+  if (rc != CCM_OK) return rc;
+  CCM_HIP(ccm::launch_range_init(c->slot, s));
+  CCM_HIP(ccm::launch_quantize(v, dtype, (uint64_t)n, frac_bits, q, c->slot, s));
+  ccm::RangeSlot r;
+  rc = read_slot(c, s, &r);
+  if (rc != CCM_OK) return rc;
+  if (r.flag) return CCM_E_RANGE;
+  if (r.vmax == INT64_MAX) return CCM_E_OVERFLOW;
+  *qmin = r.vmin;
+  *qmax = r.vmax;
+  return CCM_OK;
+}
+
+int ccm_dequantize(const int64_t *q, int64_t n, int32_t frac_bits, int32_t dtype, void *out,
+                   void *stream) {
+  if (!q || !out || n < 1 || (dtype != CCM_F32 && dtype != CCM_F64) || frac_bits < -2400 ||
+      frac_bits > 2400)
+    return CCM_E_INVAL;
+  CCM_HIP(ccm::launch_dequantize(q, (uint64_t)n, frac_bits, dtype, out, (hipStream_t)stream));
+  return CCM_OK;
+}
+
+int ccm_header_encode_fx(const ccm_desc *d, int32_t frac_bits, uint8_t out[64]) {
+  if (frac_bits < -1200 || frac_bits > 1200) return CCM_E_INVAL;
+  int rc = ccm_header_encode(d, out);
+  if (rc != CCM_OK) return rc;
+  out[7] = (uint8_t)(out[7] | 4u);
+  const uint16_t f = (uint16_t)(int16_t)frac_bits;
+  out[48] = (uint8_t)(f & 0xFFu);
+  out[49] = (uint8_t)(f >> 8);
+  return CCM_OK;
+}
+
+int ccm_header_decode_fx(const uint8_t in[64], ccm_desc *d, int32_t *frac_bits) {
+  if (!in || !d || !frac_bits) return CCM_E_INVAL;
+  if (!(in[7] & 4u)) return CCM_E_INVAL;
+  uint8_t h[64];
+  std::memcpy(h, in, 64);
+  h[7] = (uint8_t)(h[7] & ~4u);
+  const int32_t f = (int16_t)(uint16_t)(in[48] | ((uint16_t)in[49] << 8));
+  h[48] = h[49] = 0;
+  if (f < -1200 || f > 1200) return CCM_E_INVAL;
+  ccm_desc t;
+  int rc = ccm_header_decode(h, &t);  // also rejects any other reserved byte or flag
+  if (rc != CCM_OK) return rc;
+  *d = t;
+  *frac_bits = f;
   return CCM_OK;
 }
 

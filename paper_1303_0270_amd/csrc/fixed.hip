@@ -1,0 +1,140 @@
+// Floats in fixed point (the Conclusion's floats "at the expense of
+// precision"): the quantization that turns a float matrix into the integer
+// matrix Method 1 packs, the exact largest magnitude that picks its scale,
+// and the conversion of integer results back to floats (gfx950).
+//
+//   q = round-half-to-even(v * 2^f): v_ldexp_f64 scales exactly (or leaves
+//   the double range: then |v 2^f| is far beyond 2^62, or below 2^-1022,
+//   where the rounding gives 0 either way), v_rndne_f64 rounds half to even.
+//   Back: int64 -> double rounds half to even (one rounding: the high half
+//   scaled by 2^32 plus the exact low half), ldexp by -f, and for float32 one
+//   more rounding (v_cvt_f32_f64, round to nearest even).
+#include "ccm_internal.hpp"
+
+#include <cmath>
+
+namespace ccm {
+namespace {
+
+constexpr int kFxThreads = 256;
+
+// |v| as the bit pattern of a non-negative double: these order like the
+// values, and NaN and the infinities have the largest ones (>= 0x7FF0...).
+__device__ __forceinline__ int64_t abs_bits(double v) {
+  return __double_as_longlong(fabs(v));
+}
+
+template <typename F>
+__global__ __launch_bounds__(kFxThreads) void k_float_absmax(const F *__restrict__ v, uint64_t n,
+                                                             RangeSlot *slot) {
+  int64_t hi = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // four loads in flight per lane, then the tail
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    F t[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t[u] = v[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t b = abs_bits((double)t[u]);
+      hi = b > hi ? b : hi;
+    }
+  }
+  for (; i < n; i += stride) {
+    const int64_t b = abs_bits((double)v[i]);
+    hi = b > hi ? b : hi;
+  }
+  block_range_commit(INT64_MAX, hi, 0, slot);
+}
+
+// q = RNE(v 2^f) with the range of q folded into slot.  A NaN or infinity
+// sets the slot's flag; a |v 2^f| >= 2^62 folds INT64_MAX into the maximum
+// (every valid q is below 2^62 in magnitude).
+template <typename F>
+__global__ __launch_bounds__(kFxThreads) void k_quantize(const F *__restrict__ v, uint64_t n,
+                                                         int f, int64_t *__restrict__ q,
+                                                         RangeSlot *slot) {
+  int64_t lo = INT64_MAX, hi = INT64_MIN;
+  int bad = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  auto one = [&](F x, uint64_t e) {
+    const double d = (double)x;
+    const double t = ldexp(d, f);
+    int64_t r = 0;
+    if (!isfinite(d)) {
+      bad = 1;
+    } else if (!(fabs(t) < 0x1p62)) {
+      hi = INT64_MAX;
+    } else {
+      r = (int64_t)rint(t);
+      lo = r < lo ? r : lo;
+      hi = r > hi ? r : hi;
+    }
+    q[e] = r;
+  };
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    F t[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t[u] = v[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) one(t[u], i + u * stride);
+  }
+  for (; i < n; i += stride) one(v[i], i);
+  block_range_commit(lo, hi, bad, slot);
+}
+
+template <typename F>
+__global__ __launch_bounds__(kFxThreads) void k_dequantize(const int64_t *__restrict__ q,
+                                                           uint64_t n, int f,
+                                                           F *__restrict__ out) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    int64_t t[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t[u] = q[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) out[i + u * stride] = (F)ldexp((double)t[u], -f);
+  }
+  for (; i < n; i += stride) out[i] = (F)ldexp((double)q[i], -f);
+}
+
+unsigned fx_grid(uint64_t n) {
+  const uint64_t g = (n + 4ull * kFxThreads - 1) / (4ull * kFxThreads);
+  return (unsigned)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+}  // namespace
+
+hipError_t launch_float_absmax(const void *v, int dtype, uint64_t n, RangeSlot *slot,
+                               hipStream_t s) {
+  if (dtype == CCM_F64)
+    k_float_absmax<double><<<fx_grid(n), kFxThreads, 0, s>>>((const double *)v, n, slot);
+  else
+    k_float_absmax<float><<<fx_grid(n), kFxThreads, 0, s>>>((const float *)v, n, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize(const void *v, int dtype, uint64_t n, int frac_bits, int64_t *q,
+                           RangeSlot *slot, hipStream_t s) {
+  if (dtype == CCM_F64)
+    k_quantize<double><<<fx_grid(n), kFxThreads, 0, s>>>((const double *)v, n, frac_bits, q,
+                                                         slot);
+  else
+    k_quantize<float><<<fx_grid(n), kFxThreads, 0, s>>>((const float *)v, n, frac_bits, q,
+                                                        slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_dequantize(const int64_t *q, uint64_t n, int frac_bits, int dtype, void *out,
+                             hipStream_t s) {
+  if (dtype == CCM_F64)
+    k_dequantize<double><<<fx_grid(n), kFxThreads, 0, s>>>(q, n, frac_bits, (double *)out);
+  else
+    k_dequantize<float><<<fx_grid(n), kFxThreads, 0, s>>>(q, n, frac_bits, (float *)out);
+  return hipGetLastError();
+}
+
+}  // namespace ccm

@@ -791,12 +791,13 @@ def pin_fixed_point_quantize(o):
 
 
 def pin_fixed_point_errors(o):
-    """NaN and infinities are out of range; |v * 2^f| >= 2^62 overflows, the
-    largest double below it does not."""
+    """NaN and infinities are out of range (wherever they are, before any
+    overflow); |v * 2^f| >= 2^62 overflows, the largest double below it does
+    not."""
     import oracle
     for bad in (math.nan, math.inf, -math.inf):
         try:
-            o.quantize(np.array([1.0, bad]), 3)
+            o.quantize(np.array([1.0, math.ldexp(1.0, 70), bad]), 3)
             raise AssertionError("NaN / infinity accepted")
         except oracle.OracleError as e:
             assert e.code == oracle.E_RANGE

@@ -372,3 +372,50 @@ def test_result_desc_checks_the_device_written_fields(L):
     rb = L.Result.from_buffer_copy(r)
     rb.status = L.E_OVERFLOW
     assert L.lib.ccm_result_desc(ctypes.byref(rb), 0x5000, ctypes.byref(out)) == L.E_OVERFLOW
+
+
+def test_fixed_point_host_logic_matches_oracle(L):
+    """Floats in fixed point, host side: the fraction bits for a number of
+    significant bits, and the fixed-point header (flags bit 2, f at bytes
+    48..49) encoded and decoded against the oracle; invalid arguments are
+    rejected before any GPU work."""
+    import math
+    f = ctypes.c_int32()
+    for a, p in ((1.0, 10), (0.75, 10), (1000.0, 10), (1024.0, 10), (0.0, 7), (5e-324, 1),
+                 (5e-324, 62), (1.7976931348623157e308, 62), (3.3e-5, 24), (12345.678, 53)):
+        assert L.lib.ccm_float_frac_bits(a, p, ctypes.byref(f)) == L.OK
+        assert f.value == oracle.frac_bits(a, p), (a, p)
+    for a, p in ((1.0, 0), (1.0, 63), (-1.0, 5), (math.nan, 5), (math.inf, 5)):
+        assert L.lib.ccm_float_frac_bits(a, p, ctypes.byref(f)) == L.E_INVAL
+    rng = np.random.default_rng(71)
+    for fb in (0, 2, -3, 40, -700, 1000, 1200, -1000):
+        v = np.ldexp(rng.standard_normal(size=(3, 5)), int(rng.integers(0, 20)) - fb)
+        p = oracle.compress(oracle.quantize(v, fb))
+        d = _desc_from(p)
+        buf = (ctypes.c_uint8 * 64)()
+        assert L.lib.ccm_header_encode_fx(ctypes.byref(d), fb, buf) == L.OK
+        assert bytes(buf) == oracle.header_fx(p, fb)
+        back, fo = L.Desc(), ctypes.c_int32()
+        assert L.lib.ccm_header_decode_fx(buf, ctypes.byref(back), ctypes.byref(fo)) == L.OK
+        assert fo.value == fb and (back.vmin, back.vmax, back.bits) == (d.vmin, d.vmax, d.bits)
+        # the plain decoder refuses it; decode_fx refuses a plain header
+        assert L.lib.ccm_header_decode(buf, ctypes.byref(back)) == L.E_INVAL
+        plain = (ctypes.c_uint8 * 64).from_buffer_copy(oracle.header(p))
+        assert L.lib.ccm_header_decode_fx(plain, ctypes.byref(back), ctypes.byref(fo)) == L.E_INVAL
+    bad = (ctypes.c_uint8 * 64).from_buffer_copy(oracle.header_fx(p, 5)[:50] + b"\x01" +
+                                                 bytes(13))
+    assert L.lib.ccm_header_decode_fx(bad, ctypes.byref(back), ctypes.byref(fo)) == L.E_INVAL
+    assert L.lib.ccm_header_encode_fx(ctypes.byref(d), 1201, buf) == L.E_INVAL
+    q, lo, hi = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    a = ctypes.c_double()
+    stand = ctypes.c_void_p(16)  # never dereferenced: every call below fails its checks
+    assert L.lib.ccm_quantize(stand, 2, 10, 1201, stand, ctypes.byref(lo), ctypes.byref(hi),
+                              None) == L.E_INVAL
+    assert L.lib.ccm_quantize(stand, 1, 10, 3, stand, ctypes.byref(lo), ctypes.byref(hi),
+                              None) == L.E_INVAL
+    assert L.lib.ccm_quantize(stand, 3, 0, 3, stand, ctypes.byref(lo), ctypes.byref(hi),
+                              None) == L.E_INVAL
+    assert L.lib.ccm_dequantize(stand, 10, 2401, 3, stand, None) == L.E_INVAL
+    assert L.lib.ccm_dequantize(stand, 10, 0, 0, stand, None) == L.E_INVAL
+    assert L.lib.ccm_float_absmax(stand, 0, 10, ctypes.byref(a), None) == L.E_INVAL
+    del q
