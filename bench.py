@@ -393,7 +393,7 @@ def main():
     if args.extras_only:
         import bench_extras as X
         fns = {"transposed": X.transposed, "vlb": X.vlb, "gemm": X.gemm, "batched": X.batched,
-               "serving": X.serving}
+               "serving": X.serving, "floats": X.floats}
         res = {}
         for name in args.extras_only.split(","):
             res[name] = fns[name](torch, ccm)

@@ -1,7 +1,8 @@
 """Measurements beside the main benchmark line: Method 2 (variable length
 blocks) matvec on the paper's Beta bit-length distributions, the dense
-compressed GEMM (8192^3, A in [0, 2^6), B in [-2^3, 2^3)), the batched matvec
-and the serving loop.  Called by bench.py after its timed steps."""
+compressed GEMM (8192^3, A in [0, 2^6), B in [-2^3, 2^3)), the batched matvec,
+the serving loop and float matrices in fixed point.  Called by bench.py after
+its timed steps."""
 from __future__ import annotations
 
 import time
@@ -313,6 +314,71 @@ def transposed(torch, ccm, reps=10):
     return out
 
 
+def floats(torch, ccm, n=16384, reps=10):
+    """Floats in fixed point (Conclusion): a 16384 x 16384 float32 matrix
+    (v = m 2^e, m in [-2^23, 2^23), e in [-20, 0]) kept to p = 8, 12 and 16
+    significant bits of its largest magnitude: compression (largest
+    magnitude, quantization with the exact range, packing), size against
+    float32, the largest rounding error, y = V x with x kept to 14
+    significant bits (the int32 fast matvec path) per call and the packed
+    matvec kernels alone, beside a dense float32 matvec (torch.mv)."""
+    import numpy as np
+    ms, es, xs = W.float_matrix(n)
+    mt = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    et = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    ccm.fill_uniform(mt, ms.lo, ms.hi, ms.seed, ms.stream)
+    ccm.fill_uniform(et, es.lo, es.hi, es.seed, es.stream)
+    V = torch.ldexp(mt.to(torch.float32), et.to(torch.float32))
+    del mt, et
+    xm = torch.empty(n, dtype=torch.int32, device="cuda")
+    ccm.fill_uniform(xm, xs.lo, xs.hi, xs.seed, xs.stream)
+    x = torch.ldexp(xm.to(torch.float32), torch.full_like(xm, -23, dtype=torch.float32))
+    torch.cuda.synchronize()
+    out = {"workload": f"{n}x{n} float32, v = m 2^e, m uniform in [-2^23, 2^23), e in [-20, 0];"
+                       " x in [-1, 1)", "float32_bytes": 4 * n * n}
+
+    def timed(fn, k=reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(k):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    for p in (8, 12, 16):
+        t_c = timed(lambda: ccm.compress_float(V, sig_bits=p), 3)
+        m = ccm.compress_float(V, sig_bits=p)
+        back = ccm.decompress_float(m, torch.float32)
+        err = float((back.double() - V.double()).abs().max())
+        del back
+        t_mv = timed(lambda: ccm.matvec_float(m, x, x_sig_bits=14))
+        # the packed matvec alone: the quantized x, launches back to back
+        xq, _, _ = ccm.quantize(x, ccm.float_frac_bits(ccm.float_absmax(x), 14),
+                                dtype=torch.int32)
+        y = torch.empty(n, dtype=torch.int64, device="cuda")
+        go = ccm.matvec_launcher(m, xq, y)
+        t_k = timed(lambda: [go() for _ in range(10)]) / 10
+        pb = 8 * m.words
+        out[f"p{p}"] = {"frac_bits": m.frac_bits, "bits": m.bits, "packed_bytes": pb,
+                        "vs_float32": round(pb / (4 * n * n), 4),
+                        "max_abs_error": err, "error_bound": 2.0 ** (-m.frac_bits - 1),
+                        "compress_ms": round(t_c * 1e3, 3),
+                        "compress_gb_s_float32_in": round(4 * n * n / t_c / 1e9, 1),
+                        "matvec_float_call_us": round(t_mv * 1e6, 1),
+                        "matvec_kernels_us": round(t_k * 1e6, 1),
+                        "matvec_gb_s_packed": round(pb / t_k / 1e9, 1)}
+        del m
+        torch.cuda.empty_cache()
+    yd = torch.empty(n, dtype=torch.float32, device="cuda")
+    t_d = timed(lambda: [torch.mv(V, x, out=yd) for _ in range(10)]) / 10
+    out["dense_float32_mv"] = {"us": round(t_d * 1e6, 1), "gb_s": round(4 * n * n / t_d / 1e9, 1),
+                               "kernel": "torch.mv (rocBLAS gemv), float32"}
+    return out
+
+
 def run_extras(torch, ccm, log=None, i8_peak_measured=None):
     out = {}
     t0 = time.perf_counter()
@@ -338,6 +404,12 @@ def run_extras(torch, ccm, log=None, i8_peak_measured=None):
     torch.cuda.empty_cache()
     if log:
         log("batched done")
+    t0 = time.perf_counter()
+    out["floats"] = floats(torch, ccm)
+    out["floats"]["wall_s"] = round(time.perf_counter() - t0, 2)
+    torch.cuda.empty_cache()
+    if log:
+        log("floats done")
     t0 = time.perf_counter()
     out["serving"] = serving(torch, ccm, log=log)
     out["serving"]["wall_s"] = round(time.perf_counter() - t0, 2)

@@ -155,6 +155,18 @@ def dense_gemm(n: int = 8192, k: int | None = None, m: int | None = None):
     return a, b
 
 
+# Floats in fixed point: an n x n float32 matrix v = m 2^e with m uniform in
+# [-2^23, 2^23) and e uniform in [-20, 0] (exact float32 values spread over
+# six decimal orders of magnitude), and x = m' 2^-23 with m' uniform in
+# [-2^23, 2^23).  Returns (mantissas, exponents, x mantissas); the floats are
+# formed from them exactly (ldexp) wherever they are needed.
+def float_matrix(n: int = 16384):
+    m = MatrixSpec(n, n, -(1 << 23), 1 << 23, seed_for(7, 0), 0)
+    e = MatrixSpec(n, n, -20, 1, seed_for(7, 0), 1)
+    x = VectorSpec(n, -(1 << 23), 1 << 23, seed_for(7, 2))
+    return m, e, x
+
+
 @dataclass(frozen=True)
 class BatchItem:
     a: MatrixSpec

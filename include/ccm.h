@@ -463,8 +463,8 @@ int ccm_vlb_matvec(const ccm_vlb_desc *a, const void *x, int32_t xdtype, int64_t
 
 /* ---- floats in fixed point (Conclusion) ---------------------------------
  *
- * The Conclusion says floats fit the framework at the expense of precision;
- * it gives no encoding.  This library's reading: a float matrix V is stored
+ * The Conclusion says floats fit the framework if some precision is given
+ * up; it gives no encoding.  This library's reading: a float matrix V is stored
  * as the integer matrix q = round-half-to-even(v * 2^f), one f ("fraction
  * bits", possibly negative) per matrix, which Method 1 packs like any
  * integer matrix (ccm_compress on q).  The rounding is the only loss,
@@ -491,12 +491,14 @@ int ccm_float_absmax(const void *v, int32_t dtype, int64_t n, double *absmax, vo
 int ccm_float_frac_bits(double absmax, int32_t sig_bits, int32_t *frac_bits);
 
 /* q[i] = round-half-to-even(v[i] * 2^frac_bits) for n device floats into
- * device int64 q, and the exact (min, max) of q, which is all a compression
+ * device q of qdtype (CCM_I64, or CCM_I32 for a vector the int32 matvec
+ * path takes), and the exact (min, max) of q, which is all a compression
  * plan needs (ccm_width, ccm_words; then ccm_compress on q).  CCM_E_RANGE if
- * any value is NaN or infinite, else CCM_E_OVERFLOW if some |v 2^f| >= 2^62;
- * q is then unspecified.  |frac_bits| <= 1200.  Blocking. */
-int ccm_quantize(const void *v, int32_t dtype, int64_t n, int32_t frac_bits, int64_t *q,
-                 int64_t *qmin, int64_t *qmax, void *stream);
+ * any value is NaN or infinite, else CCM_E_OVERFLOW if some |v 2^f| >= 2^62
+ * or, for CCM_I32, some q leaves int32; q is then unspecified.
+ * |frac_bits| <= 1200.  Blocking. */
+int ccm_quantize(const void *v, int32_t dtype, int64_t n, int32_t frac_bits, void *q,
+                 int32_t qdtype, int64_t *qmin, int64_t *qmax, void *stream);
 
 /* out[i] = q[i] * 2^-frac_bits converted as described above, into device
  * floats of dtype CCM_F32 or CCM_F64.  |frac_bits| <= 2400.  Async. */

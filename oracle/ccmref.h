@@ -225,8 +225,8 @@ int ccmref_method_info_of(const int64_t *dense, int64_t rows, int64_t cols,
 
 /* ---- Floats in fixed point (Conclusion) --------------------------------
  *
- * The Conclusion says floats fit the framework at the expense of precision
- * and gives no encoding.  Reading: a float matrix is stored as the integer
+ * The Conclusion says floats fit the framework if some precision is given
+ * up, and gives no encoding.  Reading: a float matrix is stored as the integer
  * matrix q = round-half-to-even(v * 2^f) (f "fraction bits", one per
  * matrix), which Method 1 then packs like any integer matrix; the only
  * loss is that rounding, |v - q 2^-f| <= 2^-(f+1).  Everything after it is

@@ -691,17 +691,19 @@ def float_frac_bits(absmax: float, sig_bits: int) -> int:
     return int(f.value)
 
 
-def quantize(v: torch.Tensor, frac_bits: int, out: torch.Tensor | None = None, stream=None):
-    """(q, qmin, qmax): q = round-half-to-even(v 2^frac_bits) as int64, same
-    shape, and its exact extremes."""
+def quantize(v: torch.Tensor, frac_bits: int, out: torch.Tensor | None = None, stream=None,
+             dtype=torch.int64):
+    """(q, qmin, qmax): q = round-half-to-even(v 2^frac_bits) as int64 (or
+    int32), same shape, and its exact extremes."""
     t = _device_tensor(v, "v")
     if out is None:
-        out = torch.empty(t.shape, dtype=torch.int64, device=t.device)
-    elif out.dtype != torch.int64 or out.numel() != t.numel() or not out.is_contiguous():
+        out = torch.empty(t.shape, dtype=dtype, device=t.device)
+    elif out.numel() != t.numel() or not out.is_contiguous():
         raise CcmError(E_INVAL, "quantize: out")
     lo, hi = ctypes.c_int64(), ctypes.c_int64()
     check(lib.ccm_quantize(_ptr(t), _float_code(t), t.numel(), frac_bits, _ptr(out),
-                           ctypes.byref(lo), ctypes.byref(hi), _stream(stream)), "ccm_quantize")
+                           _dtype_code(out), ctypes.byref(lo), ctypes.byref(hi),
+                           _stream(stream)), "ccm_quantize")
     return out, int(lo.value), int(hi.value)
 
 
@@ -770,7 +772,10 @@ def matvec_float(m: CMatrix, x: torch.Tensor, x_sig_bits: int | None = None,
         raise CcmError(E_INVAL, "matvec_float: not a fixed-point matrix")
     t = _device_tensor(x, "x")
     g = _frac_bits_of(t, x_sig_bits, x_frac_bits, stream)
-    xq, xlo, xhi = quantize(t, g, stream=stream)
+    # with at most 31 significant bits kept, |x_q| <= 2^31 - 1 after rounding
+    # is not guaranteed (2^31 itself can appear), so int32 only up to 30
+    narrow = x_sig_bits is not None and x_sig_bits <= 30
+    xq, xlo, xhi = quantize(t, g, stream=stream, dtype=torch.int32 if narrow else torch.int64)
     amax = max(abs(m.vmin), abs(m.vmax))
     if m.cols * amax * max(abs(xlo), abs(xhi)) >= (1 << 63):
         raise CcmError(E_OVERFLOW, "matvec_float: the integer sums could leave int64")

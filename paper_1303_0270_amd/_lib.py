@@ -129,7 +129,7 @@ SIGNATURES = {
     "ccm_vlb_matvec": (ctypes.c_int, [_vdp, _vp, _i32, _vp, _vp]),
     "ccm_float_absmax": (ctypes.c_int, [_vp, _i32, _i64, ctypes.POINTER(ctypes.c_double), _vp]),
     "ccm_float_frac_bits": (ctypes.c_int, [ctypes.c_double, _i32, ctypes.POINTER(_i32)]),
-    "ccm_quantize": (ctypes.c_int, [_vp, _i32, _i64, _i32, _vp, ctypes.POINTER(_i64),
+    "ccm_quantize": (ctypes.c_int, [_vp, _i32, _i64, _i32, _vp, _i32, ctypes.POINTER(_i64),
                                     ctypes.POINTER(_i64), _vp]),
     "ccm_dequantize": (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp]),
     "ccm_header_encode_fx": (ctypes.c_int, [_dp, _i32, ctypes.POINTER(ctypes.c_uint8)]),

@@ -878,10 +878,10 @@ int ccm_float_frac_bits(double absmax, int32_t sig_bits, int32_t *frac_bits) {
   return CCM_OK;
 }
 
-int ccm_quantize(const void *v, int32_t dtype, int64_t n, int32_t frac_bits, int64_t *q,
-                 int64_t *qmin, int64_t *qmax, void *stream) {
+int ccm_quantize(const void *v, int32_t dtype, int64_t n, int32_t frac_bits, void *q,
+                 int32_t qdtype, int64_t *qmin, int64_t *qmax, void *stream) {
   if (!v || !q || !qmin || !qmax || n < 1 || (dtype != CCM_F32 && dtype != CCM_F64) ||
-      frac_bits < -1200 || frac_bits > 1200)
+      (qdtype != CCM_I32 && qdtype != CCM_I64) || frac_bits < -1200 || frac_bits > 1200)
     return CCM_E_INVAL;
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -889,7 +889,7 @@ int ccm_quantize(const void *v, int32_t dtype, int64_t n, int32_t frac_bits, int
   int rc = device_ctx(&c);
   if (rc != CCM_OK) return rc;
   CCM_HIP(ccm::launch_range_init(c->slot, s));
-  CCM_HIP(ccm::launch_quantize(v, dtype, (uint64_t)n, frac_bits, q, c->slot, s));
+  CCM_HIP(ccm::launch_quantize(v, dtype, (uint64_t)n, frac_bits, q, qdtype, c->slot, s));
   ccm::RangeSlot r;
   rc = read_slot(c, s, &r);
   if (rc != CCM_OK) return rc;

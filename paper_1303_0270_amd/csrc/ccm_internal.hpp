@@ -311,13 +311,13 @@ hipError_t launch_add_pack_range(PackedOperand a, PackedOperand b, uint64_t n, i
 
 hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t s);
 // floats in fixed point: largest |v| (as the bit pattern of a double) into
-// slot's vmax; q = RNE(v 2^f) with q's range in slot (flag: NaN or infinity;
-// vmax INT64_MAX: some |v 2^f| >= 2^62); out = q 2^-f (slots initialised by
-// launch_range_init)
+// slot's vmax; q = RNE(v 2^f) as int64 or int32 with q's range in slot (flag:
+// NaN or infinity; vmax INT64_MAX: some |v 2^f| >= 2^62 or q outside the
+// output type); out = q 2^-f (slots initialised by launch_range_init)
 hipError_t launch_float_absmax(const void *v, int dtype, uint64_t n, RangeSlot *slot,
                                hipStream_t s);
-hipError_t launch_quantize(const void *v, int dtype, uint64_t n, int frac_bits, int64_t *q,
-                           RangeSlot *slot, hipStream_t s);
+hipError_t launch_quantize(const void *v, int dtype, uint64_t n, int frac_bits, void *q,
+                           int qdtype, RangeSlot *slot, hipStream_t s);
 hipError_t launch_dequantize(const int64_t *q, uint64_t n, int frac_bits, int dtype, void *out,
                              hipStream_t s);
 

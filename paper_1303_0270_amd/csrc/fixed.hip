@@ -1,5 +1,5 @@
-// Floats in fixed point (the Conclusion's floats "at the expense of
-// precision"): the quantization that turns a float matrix into the integer
+// Floats in fixed point (the Conclusion allows floats if some precision is
+// given up): the quantization that turns a float matrix into the integer
 // matrix Method 1 packs, the exact largest magnitude that picks its scale,
 // and the conversion of integer results back to floats (gfx950).
 //
@@ -49,11 +49,12 @@ __global__ __launch_bounds__(kFxThreads) void k_float_absmax(const F *__restrict
 }
 
 // q = RNE(v 2^f) with the range of q folded into slot.  A NaN or infinity
-// sets the slot's flag; a |v 2^f| >= 2^62 folds INT64_MAX into the maximum
-// (every valid q is below 2^62 in magnitude).
-template <typename F>
+// sets the slot's flag; a |v 2^f| >= 2^62, or for int32 output a q outside
+// int32, folds INT64_MAX into the maximum (every valid q is below 2^62 in
+// magnitude).
+template <typename F, typename Q>
 __global__ __launch_bounds__(kFxThreads) void k_quantize(const F *__restrict__ v, uint64_t n,
-                                                         int f, int64_t *__restrict__ q,
+                                                         int f, Q *__restrict__ q,
                                                          RangeSlot *slot) {
   int64_t lo = INT64_MAX, hi = INT64_MIN;
   int bad = 0;
@@ -68,10 +69,15 @@ __global__ __launch_bounds__(kFxThreads) void k_quantize(const F *__restrict__ v
       hi = INT64_MAX;
     } else {
       r = (int64_t)rint(t);
-      lo = r < lo ? r : lo;
-      hi = r > hi ? r : hi;
+      if (sizeof(Q) == 4 && (r < INT32_MIN || r > INT32_MAX)) {
+        hi = INT64_MAX;
+        r = 0;
+      } else {
+        lo = r < lo ? r : lo;
+        hi = r > hi ? r : hi;
+      }
     }
-    q[e] = r;
+    q[e] = (Q)r;
   };
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i + 3 * stride < n; i += 4 * stride) {
@@ -117,14 +123,21 @@ hipError_t launch_float_absmax(const void *v, int dtype, uint64_t n, RangeSlot *
   return hipGetLastError();
 }
 
-hipError_t launch_quantize(const void *v, int dtype, uint64_t n, int frac_bits, int64_t *q,
-                           RangeSlot *slot, hipStream_t s) {
-  if (dtype == CCM_F64)
-    k_quantize<double><<<fx_grid(n), kFxThreads, 0, s>>>((const double *)v, n, frac_bits, q,
-                                                         slot);
+hipError_t launch_quantize(const void *v, int dtype, uint64_t n, int frac_bits, void *q,
+                           int qdtype, RangeSlot *slot, hipStream_t s) {
+  const unsigned g = fx_grid(n);
+  if (dtype == CCM_F64 && qdtype == CCM_I64)
+    k_quantize<double, int64_t><<<g, kFxThreads, 0, s>>>((const double *)v, n, frac_bits,
+                                                         (int64_t *)q, slot);
+  else if (dtype == CCM_F64)
+    k_quantize<double, int32_t><<<g, kFxThreads, 0, s>>>((const double *)v, n, frac_bits,
+                                                         (int32_t *)q, slot);
+  else if (qdtype == CCM_I64)
+    k_quantize<float, int64_t><<<g, kFxThreads, 0, s>>>((const float *)v, n, frac_bits,
+                                                        (int64_t *)q, slot);
   else
-    k_quantize<float><<<fx_grid(n), kFxThreads, 0, s>>>((const float *)v, n, frac_bits, q,
-                                                        slot);
+    k_quantize<float, int32_t><<<g, kFxThreads, 0, s>>>((const float *)v, n, frac_bits,
+                                                        (int32_t *)q, slot);
   return hipGetLastError();
 }
 

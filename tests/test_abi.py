@@ -409,11 +409,13 @@ def test_fixed_point_host_logic_matches_oracle(L):
     q, lo, hi = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     a = ctypes.c_double()
     stand = ctypes.c_void_p(16)  # never dereferenced: every call below fails its checks
-    assert L.lib.ccm_quantize(stand, 2, 10, 1201, stand, ctypes.byref(lo), ctypes.byref(hi),
+    assert L.lib.ccm_quantize(stand, 2, 10, 1201, stand, 1, ctypes.byref(lo), ctypes.byref(hi),
                               None) == L.E_INVAL
-    assert L.lib.ccm_quantize(stand, 1, 10, 3, stand, ctypes.byref(lo), ctypes.byref(hi),
+    assert L.lib.ccm_quantize(stand, 1, 10, 3, stand, 1, ctypes.byref(lo), ctypes.byref(hi),
                               None) == L.E_INVAL
-    assert L.lib.ccm_quantize(stand, 3, 0, 3, stand, ctypes.byref(lo), ctypes.byref(hi),
+    assert L.lib.ccm_quantize(stand, 3, 0, 3, stand, 1, ctypes.byref(lo), ctypes.byref(hi),
+                              None) == L.E_INVAL
+    assert L.lib.ccm_quantize(stand, 3, 10, 3, stand, 2, ctypes.byref(lo), ctypes.byref(hi),
                               None) == L.E_INVAL
     assert L.lib.ccm_dequantize(stand, 10, 2401, 3, stand, None) == L.E_INVAL
     assert L.lib.ccm_dequantize(stand, 10, 0, 0, stand, None) == L.E_INVAL

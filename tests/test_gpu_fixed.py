@@ -1,7 +1,7 @@
 """Floats in fixed point on the GPU against the CPU oracle.
 
-The Conclusion's floats "at the expense of precision", in this library's
-reading: q = round-half-to-even(v 2^f), SM-packed like any integer matrix,
+Floats, which the Conclusion allows if some precision is given up, in this
+library's reading: q = round-half-to-even(v 2^f), SM-packed like any integer matrix,
 every operation exact on q, results converted back.  Quantization (float32
 and float64, ties, subnormals, signed zeros, values next to the 2^62 bound),
 the error codes, the exact largest magnitude, dequantization (bit patterns of
@@ -97,6 +97,24 @@ def test_quantize_errors_and_bounds():
         q, lo, hi = c.quantize(dev(w), f)
         assert (lo, hi) == (-(1 << 62) + 512, (1 << 62) - 512)
         assert np.array_equal(q.cpu().numpy(), oracle.quantize(w, f))
+    # int32 output: the same q while it fits int32 (both ends exactly), an
+    # overflow as soon as one q leaves it (2^31 - 1/2 rounds to the even 2^31)
+    for f in (0, 5, -3):
+        w = v.copy() * 1000.0
+        w[10], w[11] = math.ldexp((1 << 31) - 1, -f), math.ldexp(-(1 << 31), -f)
+        q, lo, hi = c.quantize(dev(w), f, dtype=torch.int32)
+        assert q.dtype == torch.int32 and (lo, hi) == (-(1 << 31), (1 << 31) - 1)
+        assert np.array_equal(q.cpu().numpy().astype(np.int64), oracle.quantize(w, f))
+        for x in (math.ldexp((1 << 31) - 0.5, -f), math.ldexp(-(1 << 31) - 1.0, -f)):
+            w2 = w.copy()
+            w2[12] = x
+            with pytest.raises(c.CcmError) as e:
+                c.quantize(dev(w2), f, dtype=torch.int32)
+            assert e.value.status == c.E_OVERFLOW
+        w2 = w.copy()
+        w2[12] = math.ldexp(-(1 << 31) - 0.5, -f)  # the tie rounds to the even -2^31
+        q, lo, _ = c.quantize(dev(w2), f, dtype=torch.int32)
+        assert lo == -(1 << 31)
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
@@ -186,6 +204,11 @@ def test_matvec_float_matches_oracle(shape):
     assert np.array_equal(y.view(np.uint64), want.view(np.uint64))
     y2 = c.matvec_float(m, dev(x), x_sig_bits=16).cpu().numpy()
     assert np.array_equal(y2.view(np.uint64), want.view(np.uint64))
+    # x kept to 14 significant bits: the int32 vector the fast matvec path takes
+    g14 = oracle.frac_bits(float(np.abs(x.astype(np.float64)).max()), 14)
+    y3 = c.matvec_float(m, dev(x), x_sig_bits=14).cpu().numpy()
+    want3 = oracle.dequantize(oracle.matvec(p, oracle.quantize(x, g14)), f + g14)
+    assert np.array_equal(y3.view(np.uint64), want3.view(np.uint64))
 
 
 def test_matvec_float_overflow_rule():
