@@ -723,6 +723,13 @@ def dequantize(q: torch.Tensor, frac_bits: int, dtype=torch.float64,
     return out
 
 
+def _keep(t: torch.Tensor, stream) -> None:
+    """A temporary read by work enqueued on `stream`: tell the caching
+    allocator, so its memory is not handed out again before that work ran."""
+    if stream is not None:
+        t.record_stream(stream)
+
+
 def _frac_bits_of(v: torch.Tensor, sig_bits, frac_bits, stream) -> int:
     if (sig_bits is None) == (frac_bits is None):
         raise ValueError("give exactly one of sig_bits and frac_bits")
@@ -748,6 +755,7 @@ def compress_float(dense: torch.Tensor, sig_bits: int | None = None,
     d.bits, d.is_signed, d.words = b, 1 if sgn else 0, words(t.shape[0], t.shape[1], b)
     m = CMatrix(d, device=t.device)
     check(lib.ccm_compress(_ptr(q), I64, ctypes.byref(m.desc), _stream(stream)), "ccm_compress")
+    _keep(q, stream)
     m.frac_bits = f
     return m
 
@@ -758,7 +766,9 @@ def decompress_float(m: CMatrix, dtype=torch.float64, stream=None) -> torch.Tens
         raise CcmError(E_INVAL, "decompress_float: not a fixed-point matrix")
     q = decompress(m, stream=stream)
     out = torch.empty(q.shape, dtype=dtype, device=q.device)
-    dequantize(q.contiguous(), m.frac_bits, dtype, out=out, stream=stream)
+    q = q.contiguous()
+    dequantize(q, m.frac_bits, dtype, out=out, stream=stream)
+    _keep(q, stream)
     return out
 
 
@@ -780,4 +790,7 @@ def matvec_float(m: CMatrix, x: torch.Tensor, x_sig_bits: int | None = None,
     if m.cols * amax * max(abs(xlo), abs(xhi)) >= (1 << 63):
         raise CcmError(E_OVERFLOW, "matvec_float: the integer sums could leave int64")
     y = matvec(m, xq, stream=stream)
-    return dequantize(y, m.frac_bits + g, torch.float64, stream=stream)
+    out = dequantize(y, m.frac_bits + g, torch.float64, stream=stream)
+    _keep(xq, stream)
+    _keep(y, stream)
+    return out
