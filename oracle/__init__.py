@@ -416,6 +416,16 @@ class Oracle:
         self._lib.ccmref_header_fx(ctypes.byref(m), frac_bits, buf)
         return bytes(buf)
 
+    def header_fx_of(self, rows: int, cols: int, vmin: int, vmax: int, frac_bits: int) -> bytes:
+        """Fixed-point header of the rows x cols matrix of quantized values
+        with exact extremes vmin and vmax (no payload needed)."""
+        bits, signed = self.width(vmin, vmax)
+        m = _Matrix(rows, cols, vmin, vmax, bits, 1 if signed else 0,
+                    self.words(rows, cols, bits), None)
+        buf = (ctypes.c_uint8 * 64)()
+        self._lib.ccmref_header_fx(ctypes.byref(m), frac_bits, buf)
+        return bytes(buf)
+
     # -- choosing the method -----------------------------------------------------
     def method_info(self, dense) -> dict:
         """Both methods' bit counts and efficiencies (Eq. 15, 17) and the one
@@ -533,6 +543,7 @@ frac_bits = _ORACLE.frac_bits
 quantize = _ORACLE.quantize
 dequantize = _ORACLE.dequantize
 header_fx = _ORACLE.header_fx
+header_fx_of = _ORACLE.header_fx_of
 
 
 def threads() -> int:

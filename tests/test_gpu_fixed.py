@@ -10,10 +10,12 @@ header and payload, decompress, y = V x, serialization and the scale carried
 through add, scale and matmul are compared bit for bit with the oracle.
 """
 import math
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
 
+import ccm_workloads as W
 import oracle
 
 pytestmark = pytest.mark.gpu
@@ -251,3 +253,62 @@ def test_scale_carried_through_operations():
                                                              oracle.compress(qs))), 8)
     assert np.array_equal(c.decompress_float(mm).cpu().numpy(), want)
     assert ma.T.frac_bits == 6
+
+
+def test_float_workload_full_size_sampled():
+    """The benchmark's 16384^2 float32 matrix at 12 significant bits, built
+    on the device as the benchmark builds it: the fraction bits from the
+    exact largest magnitude and the header from the exact range of q, both
+    computed on the host over all 2^28 elements; sampled rows of the payload,
+    of decompress_float and of matvec_float equal the oracle's."""
+    c = ccm()
+    n = 16384
+    ms, es, xs = W.float_matrix(n)
+    mt = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    et = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    c.fill_uniform(mt, ms.lo, ms.hi, ms.seed, ms.stream)
+    c.fill_uniform(et, es.lo, es.hi, es.seed, es.stream)
+    V = torch.ldexp(mt.to(torch.float32), et.to(torch.float32))
+    del mt, et
+    xm = torch.empty(n, dtype=torch.int32, device="cuda")
+    c.fill_uniform(xm, xs.lo, xs.hi, xs.seed, xs.stream)
+    x = torch.ldexp(xm.to(torch.float32), torch.full((n,), -23.0, device="cuda"))
+    m = c.compress_float(V, sig_bits=12)
+    y = c.matvec_float(m, x, x_sig_bits=14).cpu().numpy()
+    back = c.decompress_float(m, torch.float32)
+    torch.cuda.synchronize()
+
+    def rows_of(r0, r1):
+        return np.ldexp(ms.rows_slice(r0, r1).astype(np.float64),
+                        es.rows_slice(r0, r1)).astype(np.float32)
+
+    def amax(r0):
+        return float(np.abs(rows_of(r0, min(n, r0 + 1024)).astype(np.float64)).max())
+    with ThreadPoolExecutor(8) as ex:
+        a = max(ex.map(amax, range(0, n, 1024)))
+    f = oracle.frac_bits(a, 12)
+    assert m.frac_bits == f
+
+    def qrange(r0):
+        q = oracle.quantize(rows_of(r0, min(n, r0 + 1024)), f)
+        return int(q.min()), int(q.max())
+    with ThreadPoolExecutor(8) as ex:
+        parts = list(ex.map(qrange, range(0, n, 1024)))
+    lo, hi = min(p[0] for p in parts), max(p[1] for p in parts)
+    assert m.header() == oracle.header_fx_of(n, n, lo, hi, f)
+    bits, sgn = oracle.width(lo, hi)
+    xv = np.ldexp(xs.dense().astype(np.float64), -23).astype(np.float32)
+    g = oracle.frac_bits(float(np.abs(xv.astype(np.float64)).max()), 14)
+    xq = oracle.quantize(xv, g)
+    per_row = n * bits // 64
+    for r in (0, 1, 4095, 8192, 12345, n - 1):
+        q = oracle.quantize(rows_of(r, r + 1), f)
+        words = oracle.encode_run(q, bits)
+        got = np.frombuffer(m.payload[8 * r * per_row: 8 * (r + 1) * per_row].cpu().numpy()
+                            .tobytes(), dtype="<u8")
+        assert np.array_equal(got, words[: per_row])
+        assert np.array_equal(back[r].cpu().numpy().view(np.uint32),
+                              oracle.dequantize(q[0], f, np.float32).view(np.uint32))
+        p = oracle.Packed(1, n, int(q.min()), int(q.max()), bits, sgn, words)
+        want = oracle.dequantize(oracle.matvec(p, xq), f + g)
+        assert y[r:r + 1].view(np.uint64).tolist() == want.view(np.uint64).tolist()
