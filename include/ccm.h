@@ -493,12 +493,21 @@ int ccm_float_frac_bits(double absmax, int32_t sig_bits, int32_t *frac_bits);
 /* q[i] = round-half-to-even(v[i] * 2^frac_bits) for n device floats into
  * device q of qdtype (CCM_I64, or CCM_I32 for a vector the int32 matvec
  * path takes), and the exact (min, max) of q, which is all a compression
- * plan needs (ccm_width, ccm_words; then ccm_compress on q).  CCM_E_RANGE if
- * any value is NaN or infinite, else CCM_E_OVERFLOW if some |v 2^f| >= 2^62
- * or, for CCM_I32, some q leaves int32; q is then unspecified.
- * |frac_bits| <= 1200.  Blocking. */
+ * plan needs (ccm_width, ccm_words; then ccm_compress_fx on v, or
+ * ccm_compress on q).  q may be NULL (qdtype ignored): the range and the
+ * checks only.  CCM_E_RANGE if any value is NaN or infinite, else
+ * CCM_E_OVERFLOW if some |v 2^f| >= 2^62 or, for CCM_I32, some q leaves
+ * int32; q is then unspecified.  |frac_bits| <= 1200.  Blocking. */
 int ccm_quantize(const void *v, int32_t dtype, int64_t n, int32_t frac_bits, void *q,
                  int32_t qdtype, int64_t *qmin, int64_t *qmax, void *stream);
+
+/* Pack q = round-half-to-even(v * 2^frac_bits) of rows*cols device floats
+ * straight into out->payload at out->bits (Method 1's packing, no int64
+ * copy of q).  `out` must describe exactly these quantized values: its
+ * range from ccm_quantize with the same frac_bits (which also rejected
+ * NaN, infinities and overflow).  Async. */
+int ccm_compress_fx(const void *v, int32_t dtype, int32_t frac_bits, const ccm_desc *out,
+                    void *stream);
 
 /* out[i] = q[i] * 2^-frac_bits converted as described above, into device
  * floats of dtype CCM_F32 or CCM_F64.  |frac_bits| <= 2400.  Async. */

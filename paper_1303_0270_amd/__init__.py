@@ -742,20 +742,24 @@ def compress_float(dense: torch.Tensor, sig_bits: int | None = None,
                    frac_bits: int | None = None, stream=None) -> CMatrix:
     """A 2-D float32/float64 device tensor in fixed point: quantized at
     frac_bits (or at the fraction bits that keep sig_bits significant bits of
-    its largest magnitude), then SM-packed like an integer matrix; the
-    quantization pass also yields the exact range, so no other pass runs."""
+    its largest magnitude) and SM-packed like an integer matrix: one pass
+    yields the quantized values' exact range, a second packs them straight
+    from the floats."""
     t = _device_tensor(dense, "dense")
     if t.dim() != 2:
         raise ValueError("2-D tensor expected")
     f = _frac_bits_of(t, sig_bits, frac_bits, stream)
-    q, lo, hi = quantize(t, f, stream=stream)
-    b, sgn = width(lo, hi)
+    lo, hi = ctypes.c_int64(), ctypes.c_int64()
+    check(lib.ccm_quantize(_ptr(t), _float_code(t), t.numel(), f, None, I64, ctypes.byref(lo),
+                           ctypes.byref(hi), _stream(stream)), "ccm_quantize")
+    b, sgn = width(lo.value, hi.value)
     d = Desc()
-    d.rows, d.cols, d.vmin, d.vmax = t.shape[0], t.shape[1], lo, hi
+    d.rows, d.cols, d.vmin, d.vmax = t.shape[0], t.shape[1], lo.value, hi.value
     d.bits, d.is_signed, d.words = b, 1 if sgn else 0, words(t.shape[0], t.shape[1], b)
     m = CMatrix(d, device=t.device)
-    check(lib.ccm_compress(_ptr(q), I64, ctypes.byref(m.desc), _stream(stream)), "ccm_compress")
-    _keep(q, stream)
+    check(lib.ccm_compress_fx(_ptr(t), _float_code(t), f, ctypes.byref(m.desc),
+                              _stream(stream)), "ccm_compress_fx")
+    _keep(t, stream)
     m.frac_bits = f
     return m
 

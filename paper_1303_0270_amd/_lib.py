@@ -131,6 +131,7 @@ SIGNATURES = {
     "ccm_float_frac_bits": (ctypes.c_int, [ctypes.c_double, _i32, ctypes.POINTER(_i32)]),
     "ccm_quantize": (ctypes.c_int, [_vp, _i32, _i64, _i32, _vp, _i32, ctypes.POINTER(_i64),
                                     ctypes.POINTER(_i64), _vp]),
+    "ccm_compress_fx": (ctypes.c_int, [_vp, _i32, _i32, _dp, _vp]),
     "ccm_dequantize": (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp]),
     "ccm_header_encode_fx": (ctypes.c_int, [_dp, _i32, ctypes.POINTER(ctypes.c_uint8)]),
     "ccm_header_decode_fx": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint8), _dp,

@@ -880,8 +880,8 @@ int ccm_float_frac_bits(double absmax, int32_t sig_bits, int32_t *frac_bits) {
 
 int ccm_quantize(const void *v, int32_t dtype, int64_t n, int32_t frac_bits, void *q,
                  int32_t qdtype, int64_t *qmin, int64_t *qmax, void *stream) {
-  if (!v || !q || !qmin || !qmax || n < 1 || (dtype != CCM_F32 && dtype != CCM_F64) ||
-      (qdtype != CCM_I32 && qdtype != CCM_I64) || frac_bits < -1200 || frac_bits > 1200)
+  if (!v || !qmin || !qmax || n < 1 || (dtype != CCM_F32 && dtype != CCM_F64) ||
+      (q && qdtype != CCM_I32 && qdtype != CCM_I64) || frac_bits < -1200 || frac_bits > 1200)
     return CCM_E_INVAL;
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -897,6 +897,18 @@ int ccm_quantize(const void *v, int32_t dtype, int64_t n, int32_t frac_bits, voi
   if (r.vmax == INT64_MAX) return CCM_E_OVERFLOW;
   *qmin = r.vmin;
   *qmax = r.vmax;
+  return CCM_OK;
+}
+
+int ccm_compress_fx(const void *v, int32_t dtype, int32_t frac_bits, const ccm_desc *out,
+                    void *stream) {
+  if (!v || (dtype != CCM_F32 && dtype != CCM_F64) || frac_bits < -1200 || frac_bits > 1200)
+    return CCM_E_INVAL;
+  int rc = check_desc(out, true);
+  if (rc != CCM_OK) return rc;
+  const uint64_t n = nelem(out);
+  CCM_HIP(ccm::launch_compress_fx(v, dtype, n, frac_bits, out->bits, (uint32_t *)out->payload,
+                                  ccm::cap_words32(n, out->bits), (hipStream_t)stream));
   return CCM_OK;
 }
 

@@ -311,7 +311,8 @@ hipError_t launch_add_pack_range(PackedOperand a, PackedOperand b, uint64_t n, i
 
 hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t s);
 // floats in fixed point: largest |v| (as the bit pattern of a double) into
-// slot's vmax; q = RNE(v 2^f) as int64 or int32 with q's range in slot (flag:
+// slot's vmax; q = RNE(v 2^f) as int64 or int32 (q null: not written) with
+// q's range in slot (flag:
 // NaN or infinity; vmax INT64_MAX: some |v 2^f| >= 2^62 or q outside the
 // output type); out = q 2^-f (slots initialised by launch_range_init)
 hipError_t launch_float_absmax(const void *v, int dtype, uint64_t n, RangeSlot *slot,
@@ -320,6 +321,9 @@ hipError_t launch_quantize(const void *v, int dtype, uint64_t n, int frac_bits, 
                            int qdtype, RangeSlot *slot, hipStream_t s);
 hipError_t launch_dequantize(const int64_t *q, uint64_t n, int frac_bits, int dtype, void *out,
                              hipStream_t s);
+// packs RNE(v 2^f) at `bits` straight from n floats (values checked before)
+hipError_t launch_compress_fx(const void *v, int dtype, uint64_t n, int frac_bits, int bits,
+                              uint32_t *out, uint64_t cap32, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Results whose width stays on the device.  A reduced range (the spread

@@ -10,6 +10,7 @@
 //   scaled by 2^32 plus the exact low half), ldexp by -f, and for float32 one
 //   more rounding (v_cvt_f32_f64, round to nearest even).
 #include "ccm_internal.hpp"
+#include "group_codec.hpp"
 
 #include <cmath>
 
@@ -52,6 +53,8 @@ __global__ __launch_bounds__(kFxThreads) void k_float_absmax(const F *__restrict
 // sets the slot's flag; a |v 2^f| >= 2^62, or for int32 output a q outside
 // int32, folds INT64_MAX into the maximum (every valid q is below 2^62 in
 // magnitude).
+// q may be null: the range and the checks only (the pass before packing
+// straight from the floats)
 template <typename F, typename Q>
 __global__ __launch_bounds__(kFxThreads) void k_quantize(const F *__restrict__ v, uint64_t n,
                                                          int f, Q *__restrict__ q,
@@ -77,7 +80,7 @@ __global__ __launch_bounds__(kFxThreads) void k_quantize(const F *__restrict__ v
         hi = r > hi ? r : hi;
       }
     }
-    q[e] = (Q)r;
+    if (q) q[e] = (Q)r;
   };
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i + 3 * stride < n; i += 4 * stride) {
@@ -105,6 +108,54 @@ __global__ __launch_bounds__(kFxThreads) void k_dequantize(const int64_t *__rest
     for (int u = 0; u < 4; ++u) out[i + u * stride] = (F)ldexp((double)t[u], -f);
   }
   for (; i < n; i += stride) out[i] = (F)ldexp((double)q[i], -f);
+}
+
+// Packs RNE(v 2^f) at `bits` straight from the floats: a block stages its
+// 32 x 128 floats through LDS with 16-byte loads, then lane g quantizes group
+// g's 32 values and writes its b words (as the integer packing kernel does).
+// The values were checked by the range pass before (finite, inside the
+// width), so no test is repeated here.
+constexpr int kFxTile = 128;
+constexpr int kFxPad = kGroup + 1;
+
+template <typename F>
+__global__ __launch_bounds__(kFxTile) void k_compress_fx(const F *__restrict__ d, uint64_t n,
+                                                         int f, int bits,
+                                                         uint32_t *__restrict__ out,
+                                                         uint64_t cap32, uint64_t ngroups,
+                                                         int aligned16) {
+  constexpr int PER = 16 / sizeof(F);
+  constexpr int NLOAD = kFxTile * kGroup / (kFxTile * PER);
+  __shared__ F tile[kFxTile * kFxPad];
+  const uint64_t g0 = (uint64_t)blockIdx.x * kFxTile;
+  const uint64_t e0 = g0 * kGroup;
+  if (aligned16 && e0 + (uint64_t)kFxTile * kGroup <= n) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(d + e0);
+    uint4 r[NLOAD];
+#pragma unroll
+    for (int j = 0; j < NLOAD; ++j) r[j] = src[threadIdx.x + j * kFxTile];
+#pragma unroll
+    for (int j = 0; j < NLOAD; ++j) {
+      const int q = (threadIdx.x + j * kFxTile) * PER;
+      const F *t = reinterpret_cast<const F *>(&r[j]);
+#pragma unroll
+      for (int u = 0; u < PER; ++u) tile[q + u + (q >> 5)] = t[u];
+    }
+  } else {
+    for (int q = threadIdx.x; q < kFxTile * kGroup; q += kFxTile) {
+      const uint64_t e = e0 + q;
+      tile[q + (q >> 5)] = e < n ? d[e] : F(0);
+    }
+  }
+  __syncthreads();
+  const uint64_t g = g0 + threadIdx.x;
+  if (g >= ngroups) return;
+  int64_t v[kGroup];
+  const F *row = tile + threadIdx.x * kFxPad;
+#pragma unroll
+  for (int i = 0; i < kGroup; ++i) v[i] = (int64_t)rint(ldexp((double)row[i], f));
+  const uint64_t w0 = g * (uint64_t)bits;
+  codec::encode_rt(v, bits, out + w0, cap32 - w0);
 }
 
 unsigned fx_grid(uint64_t n) {
@@ -138,6 +189,21 @@ hipError_t launch_quantize(const void *v, int dtype, uint64_t n, int frac_bits, 
   else
     k_quantize<float, int32_t><<<g, kFxThreads, 0, s>>>((const float *)v, n, frac_bits,
                                                         (int32_t *)q, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_compress_fx(const void *v, int dtype, uint64_t n, int frac_bits, int bits,
+                              uint32_t *out, uint64_t cap32, hipStream_t s) {
+  const uint64_t ngroups = (cap32 + bits - 1) / bits;
+  const uint64_t grid = (ngroups + kFxTile - 1) / kFxTile;
+  if (grid > 0x7fffffffull) return hipErrorInvalidValue;
+  const int al = ((uintptr_t)v % 16) == 0;
+  if (dtype == CCM_F64)
+    k_compress_fx<double><<<(unsigned)grid, kFxTile, 0, s>>>((const double *)v, n, frac_bits,
+                                                             bits, out, cap32, ngroups, al);
+  else
+    k_compress_fx<float><<<(unsigned)grid, kFxTile, 0, s>>>((const float *)v, n, frac_bits,
+                                                            bits, out, cap32, ngroups, al);
   return hipGetLastError();
 }
 

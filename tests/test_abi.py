@@ -418,6 +418,12 @@ def test_fixed_point_host_logic_matches_oracle(L):
     assert L.lib.ccm_quantize(stand, 3, 10, 3, stand, 2, ctypes.byref(lo), ctypes.byref(hi),
                               None) == L.E_INVAL
     assert L.lib.ccm_dequantize(stand, 10, 2401, 3, stand, None) == L.E_INVAL
+    for dt, fb in ((1, 0), (3, 1201), (2, -1201)):
+        assert L.lib.ccm_compress_fx(stand, dt, fb, ctypes.byref(d), None) == L.E_INVAL
+    bad_d = L.Desc()
+    ctypes.pointer(bad_d)[0] = d
+    bad_d.bits = d.bits + 1  # not the width of its range
+    assert L.lib.ccm_compress_fx(stand, 3, 0, ctypes.byref(bad_d), None) == L.E_INVAL
     assert L.lib.ccm_dequantize(stand, 10, 0, 0, stand, None) == L.E_INVAL
     assert L.lib.ccm_float_absmax(stand, 0, 10, ctypes.byref(a), None) == L.E_INVAL
     del q
