@@ -261,46 +261,23 @@ def summarize_trace(stats_csv, out_path, bench_json=None, cmd="", title="", note
         lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['Percentage']):.2f} |")
-    # per-dispatch durations (the kernel trace next to the stats): each step
-    # launches every matvec kernel twice, the sweep after the compress calls
-    # first and the timed sweep second
-    trace_csv = stats_csv.replace("kernel_stats", "kernel_trace")
-    split = {}
-    if trace_csv != stats_csv and os.path.exists(trace_csv):
-        for r in csv.DictReader(open(trace_csv)):
-            if "k_matvec" in r["Kernel_Name"]:
-                split.setdefault(r["Kernel_Name"], []).append(
-                    (int(r["Start_Timestamp"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
-    for k in split:
-        ds = [t for _, t in sorted(split[k])]
-        split[k] = (sum(ds[0::2]) / len(ds[0::2]), sum(ds[1::2]) / max(1, len(ds[1::2])))
     if bench_json:
         d = json.loads(open(bench_json).read().strip().splitlines()[-1])
-        lines += ["", "Matvec kernels: rocprofv3 averages (the timed sweep, and the same sweep "
-                  "run first, right after the compress calls) against the HIP-event time "
-                  "bench.py took for the timed sweep in the same run (`per_width[].matvec_us`).",
-                  "", "| width | signed | trace avg us, timed sweep | trace avg us, sweep after "
-                  "compress | bench event us |", "|---|---|---|---|---|"]
-        sums = [0.0, 0.0]
+        lines += ["", "Matvec kernels: rocprofv3 average against the HIP-event time bench.py took "
+                  "in the same run (`per_width[].matvec_us`).", "",
+                  "| width | signed | trace avg us | bench event us |", "|---|---|---|---|"]
         for pw in d["per_width"]:
             sg = "true" if pw["signed"] else "false"
             pat = re.compile(r"k_matvec\w*<%d, %s" % (pw["bits"], sg))
-            tr = [v for k, v in split.items() if pat.search(k)]
-            if tr:
-                sums[0] += tr[0][1]
-                sums[1] += tr[0][0]
-                lines.append(f"| {pw['bits']} | {sg} | {tr[0][1]:.1f} | {tr[0][0]:.1f} | "
-                             f"{pw['matvec_us']:.1f} |")
-            else:
-                lines.append(f"| {pw['bits']} | {sg} | - | - | {pw['matvec_us']:.1f} |")
-        first = d["ops"].get("matvec_after_compress", {})
+            tr = [float(r["AverageNs"]) / 1e3 for r in rows if pat.search(r["Name"])]
+            lines.append(f"| {pw['bits']} | {sg} | {tr[0]:.1f} | {pw['matvec_us']:.1f} |" if tr
+                         else f"| {pw['bits']} | {sg} | - | {pw['matvec_us']:.1f} |")
+        mv = [float(r["AverageNs"]) / 1e3 for r in rows if "k_matvec" in r["Name"]]
         lines += ["", "Per-width event intervals each include one event marker; the value "
                   "uses the even steps' pair of events around all twelve launches instead:", "",
-                  f"* sum of the matvec kernels' trace averages: {sums[0]:.1f} us per timed sweep, "
-                  f"{sums[1]:.1f} us per sweep after compress",
+                  f"* sum of the matvec kernels' trace averages: {sum(mv):.1f} us per sweep",
                   f"* bench matvec phase (event pair): {d['ops']['matvec']['ms_per_sweep'] * 1e3:.1f}"
-                  f" us per timed sweep"
-                  + (f", {first['ms_per_sweep'] * 1e3:.1f} us after compress" if first else ""),
+                  f" us per sweep",
                   f"* bench value: {d['value']} GB/s (roofline frac {d['roofline']['frac']})"]
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -452,20 +429,11 @@ def main():
             with timer.span(f"compress:{c['k']}:{int(c['signed'])}"):
                 a = ccm.compress(c["dense"])
             packed.append(a)
-        # The sweep runs twice.  The first one directly follows the compress
-        # calls, whose 4.7 GB of packed output the caches still partly hold
-        # dirty: its reads evict those lines, so it also pays their write-back
-        # to HBM (a 1 GiB write just before them makes a k = 3 matvec take
-        # 50 us instead of 28.5).  It is timed and reported on its own
-        # ("matvec_after_compress"); the second sweep, which reads the same
-        # 4.7 GB (far beyond the 256 MB cache, so nothing is served from it),
-        # is the value.  Even steps time the twelve back-to-back launches as
-        # one phase; odd steps put one event between neighbouring launches
-        # for the per-width breakdown -- each marker adds a few us to its
-        # interval.
+        # Even steps time the twelve back-to-back launches as one phase (the
+        # value); odd steps put one event between neighbouring launches for the
+        # per-width breakdown -- each marker adds a few us to its interval.
         launches = [(f"matvec:{c['k']}:{int(c['signed'])}", ccm.matvec_launcher(a, x, y, stream))
                     for c, a in zip(cases, packed)]
-        timer.phase("matvec_after_compress", [go for _, go in launches])
         if nstep[0] % 2 == 0:
             timer.phase("matvec_phase", [go for _, go in launches])
         else:
@@ -535,14 +503,6 @@ def main():
 
     ops = {"matvec": {"ms_per_sweep": round(tot_t / len(phases) * 1e3, 3),
                       "alg_gbs": round(value, 1)}}
-    first = times.get("matvec_after_compress")
-    if first:
-        ft = float(np.sum(first))
-        ops["matvec_after_compress"] = {
-            "ms_per_sweep": round(ft / len(first) * 1e3, 3),
-            "alg_gbs": round(sweep_bytes * len(first) / ft / 1e9, 1),
-            "note": "the same sweep run first, right after the compress calls: it also pays "
-                    "the write-back of their outputs still held dirty in the caches"}
     ops["compress"] = op_stats("compress", lambda c, a: 16 * n * n + 8 * a.words)
     if not args.profile:
         ops["add"] = op_stats("add", lambda c, a: 8 * (a.words + c["B"].words + c["sum"].words))

@@ -171,6 +171,50 @@ __device__ __forceinline__ uint64_t dpp_add64(uint64_t v) {
 // Sum over the 64 lanes of a wave, mod 2^64; every lane must be active.  Four
 // DPP steps leave each 16-lane row's sum in all of its lanes (quad swaps, then
 // the half-row and row mirrors); the four row sums are read out as scalars.
+// Stores of large outputs that no kernel reads again soon (packed payloads,
+// decompressed matrices): marked nontemporal, so the caches do not keep them
+// dirty.  Dirty lines left by one kernel are written back while the next one
+// reads, at its expense (measured: a k = 3 matvec right after a plain 1 GiB
+// write takes 50 us, after the same write made nontemporal 28 us, as after a
+// read).
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_nt(uint32_t *p, uint32_t v) {
+  __builtin_nontemporal_store(v, p);
+}
+__device__ __forceinline__ void st_nt(int64_t *p, int64_t v) {
+  __builtin_nontemporal_store(v, p);
+}
+__device__ __forceinline__ void st_nt4(uint32_t *p, uint32_t a, uint32_t b, uint32_t c,
+                                       uint32_t d) {
+  const u32x4_t t = {a, b, c, d};
+  __builtin_nontemporal_store(t, reinterpret_cast<u32x4_t *>(p));
+}
+
+// Writes a block's output run: thread t of block x encoded group
+// blockDim.x x + t into s_out[t out_bits ..), and the block's groups are
+// consecutive, so its words are out[blockDim.x x out_bits ..) contiguous:
+// 16-byte nontemporal stores, words at or past cap32 dropped.  (A thread
+// storing its own group directly issues out_bits stores of 64 lanes each at
+// a stride of out_bits words, which nontemporal stores turn into partial-line
+// writes: compress took 1.48 ms per 16384^2 matrix that way against 0.87 ms
+// with plain stores.)
+__device__ __forceinline__ void store_block_run(const uint32_t *s_out, int out_bits,
+                                                uint32_t *__restrict__ out, uint64_t cap32) {
+  const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * (uint64_t)out_bits;  // a word index
+  if (base >= cap32) return;
+  const uint64_t left = cap32 - base;
+  const uint64_t run = (uint64_t)blockDim.x * (uint64_t)out_bits;
+  const uint32_t nw = (uint32_t)(left < run ? left : run);
+  uint4 *o4 = reinterpret_cast<uint4 *>(out + base);  // 1024 out_bits bytes per block: aligned
+  const uint4 *l4 = reinterpret_cast<const uint4 *>(s_out);
+  for (uint32_t q = threadIdx.x; q < nw / 4; q += blockDim.x) {
+    const uint4 t = l4[q];
+    st_nt4(reinterpret_cast<uint32_t *>(o4 + q), t.x, t.y, t.z, t.w);
+  }
+  for (uint32_t q = (nw & ~3u) + threadIdx.x; q < nw; q += blockDim.x)
+    st_nt(out + base + q, s_out[q]);
+}
+
 __device__ __forceinline__ int64_t wave_sum(int64_t v) {
   uint64_t u = (uint64_t)v;
   u = dpp_add64<0xB1>(u);   // quad_perm [1,0,3,2]

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kFxThreads) void k_dequantize(const int64_t *__rest
 
 // Packs RNE(v 2^f) at `bits` straight from the floats: a block stages its
 // 32 x 128 floats through LDS with 16-byte loads, then lane g quantizes group
-// g's 32 values and writes its b words (as the integer packing kernel does).
+// g's 32 values and encodes its b words (as the integer packing kernel does).
 // The values were checked by the range pass before (finite, inside the
 // width), so no test is repeated here.
 constexpr int kFxTile = 128;
@@ -126,7 +126,12 @@ __global__ __launch_bounds__(kFxTile) void k_compress_fx(const F *__restrict__ d
                                                          int aligned16) {
   constexpr int PER = 16 / sizeof(F);
   constexpr int NLOAD = kFxTile * kGroup / (kFxTile * PER);
-  __shared__ F tile[kFxTile * kFxPad];
+  // the input tile, reused for the block's packed words (up to 64 a group)
+  constexpr size_t kBytes = sizeof(F) * kFxTile * kFxPad > 4 * (size_t)kFxTile * 64
+                                ? sizeof(F) * kFxTile * kFxPad
+                                : 4 * (size_t)kFxTile * 64;
+  __shared__ __align__(16) unsigned char lds[kBytes];
+  F *tile = reinterpret_cast<F *>(lds);
   const uint64_t g0 = (uint64_t)blockIdx.x * kFxTile;
   const uint64_t e0 = g0 * kGroup;
   if (aligned16 && e0 + (uint64_t)kFxTile * kGroup <= n) {
@@ -148,14 +153,18 @@ __global__ __launch_bounds__(kFxTile) void k_compress_fx(const F *__restrict__ d
     }
   }
   __syncthreads();
-  const uint64_t g = g0 + threadIdx.x;
-  if (g >= ngroups) return;
   int64_t v[kGroup];
   const F *row = tile + threadIdx.x * kFxPad;
 #pragma unroll
   for (int i = 0; i < kGroup; ++i) v[i] = (int64_t)rint(ldexp((double)row[i], f));
-  const uint64_t w0 = g * (uint64_t)bits;
-  codec::encode_rt(v, bits, out + w0, cap32 - w0);
+  // group g into LDS, then the block's contiguous run of words (as the
+  // integer packing kernel)
+  __syncthreads();
+  uint32_t *s_out = reinterpret_cast<uint32_t *>(lds);
+  codec::encode_rt(v, bits, s_out + threadIdx.x * bits, (uint64_t)bits);
+  __syncthreads();
+  store_block_run(s_out, bits, out, cap32);
+  (void)ngroups;
 }
 
 unsigned fx_grid(uint64_t n) {

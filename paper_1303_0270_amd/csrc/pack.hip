@@ -99,7 +99,14 @@ __global__ __launch_bounds__(kTileThreads) void k_compress(const T *__restrict__
   }
   constexpr int PER = 16 / sizeof(T);
   constexpr int NLOAD = kTileElems / (kTileThreads * PER);
-  __shared__ T tile[kTileThreads * kPad];
+  // the input tile, reused for the block's packed words (at most 32 words a
+  // group for int32 input, 64 for int64)
+  constexpr int kOutWords = kTileThreads * (sizeof(T) == 4 ? 32 : 64);
+  constexpr size_t kBytes = sizeof(T) * kTileThreads * kPad > 4 * (size_t)kOutWords
+                                ? sizeof(T) * kTileThreads * kPad
+                                : 4 * (size_t)kOutWords;
+  __shared__ __align__(16) unsigned char lds[kBytes];
+  T *tile = reinterpret_cast<T *>(lds);
   const uint64_t g0 = (uint64_t)blockIdx.x * kTileThreads;
   const uint64_t e0 = g0 * kGroup;
   if (aligned16 && e0 + kTileElems <= n) {
@@ -121,14 +128,18 @@ __global__ __launch_bounds__(kTileThreads) void k_compress(const T *__restrict__
     }
   }
   __syncthreads();
-  const uint64_t g = g0 + threadIdx.x;
-  if (g >= ngroups) return;
   int64_t v[kGroup];
   const T *row = tile + threadIdx.x * kPad;
 #pragma unroll
   for (int i = 0; i < kGroup; ++i) v[i] = (int64_t)row[i];
-  const uint64_t w0 = g * (uint64_t)bits;
-  codec::encode_rt(v, bits, out + w0, cap32 - w0);
+  // lane g encodes group g into LDS; the block's contiguous run of words then
+  // leaves with 16-byte stores (past the last group: zeros, never stored)
+  __syncthreads();
+  uint32_t *s_out = reinterpret_cast<uint32_t *>(lds);
+  codec::encode_rt(v, bits, s_out + threadIdx.x * bits, (uint64_t)bits);
+  __syncthreads();
+  store_block_run(s_out, bits, out, cap32);
+  (void)ngroups;
 }
 
 // packed -> dense int64 (n values)
@@ -150,7 +161,7 @@ __global__ __launch_bounds__(kTileThreads) void k_decompress(const uint32_t *__r
   const uint64_t e0 = g0 * kGroup;
   for (int q = threadIdx.x; q < kTileElems; q += kTileThreads) {
     const uint64_t e = e0 + q;
-    if (e < n) out[e] = tile[q + (q >> 5)];
+    if (e < n) st_nt(out + e, tile[q + (q >> 5)]);
   }
 }
 
@@ -244,23 +255,6 @@ __device__ inline void block_range_fold(int64_t lo, int64_t hi, RangeSlot *slot)
   }
 }
 
-// Writes a block's output run: thread t of block x encoded group 256 x + t
-// into s_out[t out_bits ..), and the block's groups are consecutive, so its
-// words are out[256 x out_bits ..) contiguous: 16-byte stores, words at or
-// past cap32 dropped.  (A thread storing its own group directly issues
-// out_bits stores of 64 lanes each at a stride of out_bits words.)
-__device__ __forceinline__ void store_block_run(const uint32_t *s_out, int out_bits,
-                                                uint32_t *__restrict__ out, uint64_t cap32) {
-  const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * (uint64_t)out_bits;  // a word index
-  if (base >= cap32) return;
-  const uint64_t left = cap32 - base;
-  const uint64_t run = (uint64_t)blockDim.x * (uint64_t)out_bits;
-  const uint32_t nw = (uint32_t)(left < run ? left : run);
-  uint4 *o4 = reinterpret_cast<uint4 *>(out + base);  // 1024 out_bits bytes per block: aligned
-  const uint4 *l4 = reinterpret_cast<const uint4 *>(s_out);
-  for (uint32_t q = threadIdx.x; q < nw / 4; q += blockDim.x) o4[q] = l4[q];
-  for (uint32_t q = (nw & ~3u) + threadIdx.x; q < nw; q += blockDim.x) out[base + q] = s_out[q];
-}
 
 // Packing pass of an elementwise result: thread t of block x packs the 32
 // results of group 256 x + t (zeros past n) at out_bits, through LDS.  With
