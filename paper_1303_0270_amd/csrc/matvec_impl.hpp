@@ -448,11 +448,17 @@ hipError_t launch_one(const uint32_t *w, int64_t rows, int64_t cols, const XT *x
 //     (the load counter is in order) instead of draining the queue.  The x
 //     panel is requested first, then the first unit, so the unit's latency
 //     overlaps the LDS staging.
-//   * LDS keeps each quad's x values (128 int32) or b = 1 digit words (64)
+//   * LDS keeps each quad's x values (128 int32) or digit words (64)
 //     contiguous plus a 4-dword skew, so the 16-byte LDS reads of neighbouring
 //     lanes fall in distinct banks.
 //   * b = 1: lane g builds the digit words of group g straight from its 32 x
 //     values (byte permutes and nibble masks), with no int32 copy of x.
+//   * b = 2..4 with int16-range x: nibble dot products as well.  The fields
+//     of eight consecutive columns are moved to the eight nibbles of a word
+//     (nib_spread: two bit-selects and a masked shift for b = 2 and 3,
+//     nothing for b = 4) and v_dot8 multiplies them by the matching base-16
+//     digits of x + 2^15, one product per digit, so a field costs about 1.4
+//     instructions instead of an extract and a 24-bit multiply-add.
 constexpr int kPanelAl = 16384;
 constexpr int kQuadX = 4 * kGroup + 4;  // int32 per quad of groups
 constexpr int kQuadD = 4 * 16 + 4;      // digit words per quad of groups
@@ -464,9 +470,12 @@ constexpr int kQuadD = 4 * 16 + 4;      // digit words per quad of groups
 // NT: lanes per block.  1024 (one block per CU) stages x once per CU instead of
 // twice; measured on the sweep it pays for b <= 4 (about 0.5 us of 15-28 us)
 // and loses 1-2 us at b = 7 and 12.
+// R: rows per wave and unit.  b = 2..4 (nibble products) take one row per
+// unit: measured at b = 3 on the sweep, 22.8 us against 23.9 us with two rows
+// (the smaller last unit leaves less decode after the last load lands).
 template <int B>
 struct AlCfg {
-  static constexpr int R = B == 1 ? 4 : B <= 4 ? 2 : 1;  // rows per wave and unit
+  static constexpr int R = B == 1 ? 4 : 1;
   static constexpr bool PF = B <= 4;
   static constexpr int NT = B <= 4 ? 1024 : 512;
 };
@@ -520,6 +529,96 @@ __device__ __forceinline__ void store_digits_al(const uint32_t *v, int g, uint32
     *reinterpret_cast<uint4 *>(dst + 4 * d) = make_uint4(D[d][0], D[d][1], D[d][2], D[d][3]);
 }
 
+
+// ---- b = 2..4: nibble dot products -------------------------------------
+// Digit words of one group: chunk c (columns 32g + 8c .. 32g + 8c + 7) at
+// words 4c .. 4c + 3 of the group's 16; word 4c + d holds in nibble i digit d
+// of u = x_{32g+8c+i} + 2^15.  For b <= 3 the top digit is stored as d - 8 (a
+// signed nibble): x = d0 + 16 d1 + 256 d2 + 4096 (d3 - 8), so the products
+// with non-negative fields need no offset term.  Fields of b = 4 reach 15,
+// which is no signed nibble, so there the top digit stays unsigned and the
+// offset 2^15 * sum(fields) is taken off.  Word 64 of each quad (in the skew)
+// holds the quad's sum of x, for signed fields (below).
+// Two threads per group: thread half h builds chunks 2h and 2h + 1 from its
+// 16 values v[] (already offset by 2^15); st: whether group g exists.
+template <int B>
+__device__ __forceinline__ void nib_store_digits(const uint32_t *v, int g, int h, bool st,
+                                                 uint32_t *xd) {
+  uint32_t *dst = xd + (g >> 2) * kQuadD + (g & 3) * 16 + 8 * h;
+  int32_t gs = 0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    uint32_t D[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t u = v[8 * c + i];
+      gs += (int32_t)u - 32768;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) D[d] |= ((u >> (4 * d)) & 15u) << (4 * i);
+    }
+    if constexpr (B < 4) D[3] ^= 0x88888888u;
+    if (st) *reinterpret_cast<uint4 *>(dst + 4 * c) = make_uint4(D[0], D[1], D[2], D[3]);
+  }
+  // the quad's four groups are the eight lanes 8k .. 8k + 7
+  gs += __shfl_xor(gs, 1);
+  gs += __shfl_xor(gs, 2);
+  gs += __shfl_xor(gs, 4);
+  if (st && (g & 3) == 0 && h == 0) xd[(g >> 2) * kQuadD + 64] = (uint32_t)gs;
+}
+
+// Signed fields: flipping a field's top bit turns its two's complement value a
+// into p = a + 2^(b-1) in [0, 2^b), so sum a x = sum p x - 2^(b-1) sum x.
+// The bits to flip in word k of a group (top bit of field i at 32-bit stream
+// position b i + b - 1).
+template <int B>
+__device__ __forceinline__ constexpr uint32_t nib_top_bits(int k) {
+  if constexpr (B == 2) return 0xAAAAAAAAu;
+  else if constexpr (B == 4) return 0x88888888u;
+  else return k == 0 ? 0x24924924u : (k == 1 ? 0x49249249u : 0x92492492u);
+}
+
+// The four chunks of eight fields of one group's b words, each in the low 8b
+// bits (higher bits are ignored by nib_spread).
+template <int B>
+__device__ __forceinline__ void nib_chunks(const uint32_t *w, uint32_t (&ch)[4]) {
+  if constexpr (B == 2) {
+    ch[0] = w[0];
+    ch[1] = w[0] >> 16;
+    ch[2] = w[1];
+    ch[3] = w[1] >> 16;
+  } else if constexpr (B == 3) {
+    ch[0] = w[0];
+    ch[1] = __builtin_amdgcn_alignbit(w[1], w[0], 24);
+    ch[2] = __builtin_amdgcn_alignbit(w[2], w[1], 16);
+    ch[3] = w[2] >> 8;
+  } else {
+    ch[0] = w[0];
+    ch[1] = w[1];
+    ch[2] = w[2];
+    ch[3] = w[3];
+  }
+}
+
+// Field i (bits i b .. i b + b - 1 of c) to nibble i, zero-extended.  Three
+// halving steps move the upper half of every block by the block's slack;
+// v_bitop3_b32 with table 0xE4 selects bit by bit (third operand ? first :
+// second), written as the builtin so the compiler does not re-associate the
+// masks of consecutive steps.
+template <int B>
+__device__ __forceinline__ uint32_t nib_spread(uint32_t c) {
+  if constexpr (B == 2) {
+    const uint32_t t1 = __builtin_amdgcn_bitop3_b32(c, c << 8, 0x000000FFu, 0xE4);
+    const uint32_t t2 = __builtin_amdgcn_bitop3_b32(t1, t1 << 4, 0x000F000Fu, 0xE4);
+    return ((t2 << 2) & 0x30303030u) | (t2 & 0x03030303u);
+  } else if constexpr (B == 3) {
+    const uint32_t t1 = __builtin_amdgcn_bitop3_b32(c, c << 4, 0x00000FFFu, 0xE4);
+    const uint32_t t2 = __builtin_amdgcn_bitop3_b32(t1, t1 << 2, 0x003F003Fu, 0xE4);
+    return ((t2 << 1) & 0x70707070u) | (t2 & 0x07070707u);
+  } else {
+    return c;
+  }
+}
+
 template <int B, bool SGN, int NT = AlCfg<B>::NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void
 k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
@@ -528,9 +627,10 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   constexpr int R = AlCfg<B>::R;
   constexpr bool PF = AlCfg<B>::PF;
   constexpr int NWD = 4 * B;  // words per (row, quad)
+  constexpr bool kNib = B >= 2 && B <= 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int32_t *xs = reinterpret_cast<int32_t *>(smem_raw);
-  uint32_t *xd = reinterpret_cast<uint32_t *>(smem_raw);  // b = 1 fast path only
+  uint32_t *xd = reinterpret_cast<uint32_t *>(smem_raw);  // b <= 4 fast path only
 
   const int64_t c0 = (int64_t)blockIdx.y * kPanelAl;
   const int pc = (int)(cols - c0 < kPanelAl ? cols - c0 : kPanelAl);  // a multiple of 128
@@ -571,7 +671,14 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   // request x (clamped, fixed count), then the first unit, then consume x
   const int4 *x4 = reinterpret_cast<const int4 *>(x + c0);
   int4 xv[8];
-  if constexpr (B == 1) {
+  if constexpr (kNib) {
+    // lane t: half t % 2 of group t / 2 (16 values)
+    const int ng = pc / kGroup;
+    const int g0 = (int)threadIdx.x >> 1;
+    const int g = g0 < ng ? g0 : ng - 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) xv[i] = x4[8 * g + 4 * ((int)threadIdx.x & 1) + i];
+  } else if constexpr (B == 1) {
     // lane g: the 32 values of group g (pc <= 16384: one group per lane)
     const int ng = pc / kGroup;
     const int g = (int)threadIdx.x < ng ? (int)threadIdx.x : ng - 1;
@@ -606,6 +713,19 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
 #pragma unroll
     for (int i = 0; i < kGroup; i += 2) m |= v[i] | v[i + 1];
     if ((int)threadIdx.x < pc / kGroup) store_digits_al(v, threadIdx.x, xd);
+  } else if constexpr (kNib) {
+    uint32_t v[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[4 * i] = (uint32_t)xv[i].x + 32768u;
+      v[4 * i + 1] = (uint32_t)xv[i].y + 32768u;
+      v[4 * i + 2] = (uint32_t)xv[i].z + 32768u;
+      v[4 * i + 3] = (uint32_t)xv[i].w + 32768u;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i += 2) m |= v[i] | v[i + 1];
+    const int g = (int)threadIdx.x >> 1;
+    nib_store_digits<B>(v, g, (int)threadIdx.x & 1, g < pc / kGroup, xd);
   } else {
     const int nchunk = pc / 4;
 #pragma unroll
@@ -624,7 +744,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
 
   if (!fast) {
     // general x: 64-bit products, one row and one group at a time
-    if constexpr (B == 1) {
+    if constexpr (B == 1 || kNib) {
       (void)stage_x_al<NT>(x, c0, pc, xs);
       __syncthreads();
     }
@@ -708,6 +828,52 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
         const int32_t tt = (int32_t)(dacc[rr][0] + (dacc[rr][1] << 4) + (dacc[rr][2] << 8) +
                                      (dacc[rr][3] << 12) - (dacc[rr][4] << 15));
         acc32[rr] += live ? (SGN ? -tt : tt) : 0;
+      }
+    } else if constexpr (kNib) {
+      // per row: a[0..3] digit sums (a[3] signed for b <= 3), a[4] the sum
+      // of the fields (b = 4)
+      uint32_t a[R][5];
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int d = 0; d < 5; ++d) a[rr][d] = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint4 *dg = reinterpret_cast<const uint4 *>(xd + q * kQuadD + t * 16);
+        uint4 D[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) D[c] = dg[c];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+          uint32_t wv[B];
+#pragma unroll
+          for (int k = 0; k < B; ++k) wv[k] = w[rr][t * B + k] ^ (SGN ? nib_top_bits<B>(k) : 0u);
+          uint32_t ch[4];
+          nib_chunks<B>(wv, ch);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const uint32_t n = nib_spread<B>(ch[c]);
+            a[rr][0] = __builtin_amdgcn_udot8(n, D[c].x, a[rr][0], false);
+            a[rr][1] = __builtin_amdgcn_udot8(n, D[c].y, a[rr][1], false);
+            a[rr][2] = __builtin_amdgcn_udot8(n, D[c].z, a[rr][2], false);
+            if constexpr (B < 4) {
+              a[rr][3] = (uint32_t)__builtin_amdgcn_sdot8((int)n, (int)D[c].w, (int)a[rr][3], false);
+            } else {
+              a[rr][3] = __builtin_amdgcn_udot8(n, D[c].w, a[rr][3], false);
+              a[rr][4] = __builtin_amdgcn_udot8(n, 0x11111111u, a[rr][4], false);
+            }
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // a unit's share of a row (128 fields) fits int32: |sum| <= 128 * 15 *
+      // 2^16; the quad's sum of x times 2^(b-1) for signed fields
+      const uint32_t corr = SGN ? xd[q * kQuadD + 64] << (B - 1) : 0u;
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const int32_t tt = (int32_t)(a[rr][0] + (a[rr][1] << 4) + (a[rr][2] << 8) +
+                                     (a[rr][3] << 12) - (a[rr][4] << 15) - corr);
+        acc[rr] += live ? (uint64_t)(int64_t)tt : 0u;
       }
     } else {
       uint64_t part[R];
