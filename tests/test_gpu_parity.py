@@ -343,6 +343,36 @@ def test_matvec_all_widths(b):
                 assert np.array_equal(y, oracle.matvec(pa, x)), (b, signed, rows, cols, dt)
 
 
+# Fields at their largest magnitudes against x at the ends of the int16 range,
+# on the aligned kernel's shapes: the exact 32-bit sums of the int16-x paths
+# (digit products at b <= 4, 24-bit multiply-add runs above) at their bounds.
+@pytest.mark.parametrize("b", list(range(1, 16)))
+def test_matvec_int16_x_extremes(b):
+    c = ccm()
+    shapes = [(37, 16512)] + ([(9, 8320), (130, 1024)] if b <= 4 else [])
+    for signed in (False, True):
+        lo, hi = ((-(1 << (b - 1)), (1 << (b - 1)) - 1) if signed else (0, (1 << b) - 1))
+        if b == 1 and signed:
+            lo, hi = -1, 0
+        for rows, cols in shapes:
+            j = np.arange(cols)
+            fields = {"max": np.full((rows, cols), hi), "min": np.full((rows, cols), lo),
+                      "alternate": np.broadcast_to(np.where(j % 2 == 0, hi, lo), (rows, cols))}
+            xs = {"-2^15": np.full(cols, -(1 << 15)), "2^15-1": np.full(cols, (1 << 15) - 1),
+                  "alternate": np.where(j % 2 == 0, (1 << 15) - 1, -(1 << 15))}
+            for fname, A in fields.items():
+                if not signed and fname == "min":
+                    continue
+                A = np.ascontiguousarray(A, dtype=np.int64)
+                pa = oracle.compress(A)
+                g = c.compress(dev(A))
+                assert g.header() == oracle.header(pa), (b, signed, fname)
+                for xname, x in xs.items():
+                    y = c.matvec(g, dev(x, torch.int32)).cpu().numpy()
+                    assert np.array_equal(y, oracle.matvec(pa, x)), (b, signed, rows, cols,
+                                                                     fname, xname)
+
+
 # operands whose values fit int8 take the MFMA path (unsigned b <= 7, signed b <= 8)
 @pytest.mark.parametrize("ba,sa,bb,sb", [(10, False, 10, False), (6, False, 4, True),
                                          (1, False, 1, True), (20, True, 17, False),
