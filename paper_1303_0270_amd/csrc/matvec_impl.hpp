@@ -619,7 +619,15 @@ __device__ __forceinline__ uint32_t nib_spread(uint32_t c) {
   }
 }
 
-template <int B, bool SGN, int NT = AlCfg<B>::NT>
+// RG (ragged): any number of columns.  Rows then start at any bit, so a unit
+// fetches the 16-byte-aligned superset of each quad (b + 1 vectors, clamped to
+// the payload capacity) and shifts it into place when it is decoded: the
+// offset o = (r cols + c0) b mod 128 is the same for every quad of a row and
+// uniform across the wave, so the word part of the shift is a uniform branch
+// and the bit part one funnel shift per word.  x is staged zero-padded to
+// whole quads (the fields past the row's end, which belong to the next row,
+// meet x = 0).
+template <int B, bool SGN, int NT = AlCfg<B>::NT, bool RG = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void
 k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
             const int32_t *__restrict__ x, int64_t *__restrict__ y, int atomic_out) {
@@ -627,14 +635,17 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   constexpr int R = AlCfg<B>::R;
   constexpr bool PF = AlCfg<B>::PF;
   constexpr int NWD = 4 * B;  // words per (row, quad)
+  constexpr int NWR = RG ? NWD + 4 : NWD;  // words a unit holds per row
   constexpr bool kNib = B >= 2 && B <= 4;
+  static_assert(!kNib || NT == 1024, "two lanes per group of a 16384-column panel");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int32_t *xs = reinterpret_cast<int32_t *>(smem_raw);
   uint32_t *xd = reinterpret_cast<uint32_t *>(smem_raw);  // b <= 4 fast path only
 
   const int64_t c0 = (int64_t)blockIdx.y * kPanelAl;
-  const int pc = (int)(cols - c0 < kPanelAl ? cols - c0 : kPanelAl);  // a multiple of 128
-  const int nq = pc / (4 * kGroup);
+  // a multiple of 128 unless RG
+  const int pc = (int)(cols - c0 < kPanelAl ? cols - c0 : kPanelAl);
+  const int nq = (pc + 4 * kGroup - 1) / (4 * kGroup);
   const int nslot = (nq + 63) / 64;  // quad slots per lane: 1 or 2 (wave-uniform)
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -648,14 +659,30 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
     const int64_t left = rows - r0;
     return left >= R ? R : (left > 0 ? (int)left : 0);
   };
+  // RG: last 16-byte vector inside the payload capacity
+  const uint64_t vmax = RG ? cap_words32((uint64_t)rows * (uint64_t)cols, B) / 4 - 1 : 0;
   // the unit's words; rows and quads past the end are clamped to the last one
-  auto load_unit = [&](uint32_t (&w)[R][NWD], int64_t rb, int h) {
+  auto load_unit = [&](uint32_t (&w)[R][NWR], int64_t rb, int h) {
     const int64_t r0 = rb * ((NT / 64) * R) + (int64_t)wave * R;
     const int qq = lane + 64 * h;
     const int q = qq < nq ? qq : nq - 1;
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
       const int64_t r = r0 + rr < rows ? r0 + rr : rows - 1;
+      if constexpr (RG) {
+        const uint64_t v0 = (((uint64_t)r * (uint64_t)cols + (uint64_t)c0) * B >> 7) +
+                            (uint64_t)q * B;
+        const uint4 *src = reinterpret_cast<const uint4 *>(A);
+#pragma unroll
+        for (int u = 0; u <= B; ++u) {
+          const uint4 t = src[v0 + u < vmax ? v0 + u : vmax];
+          w[rr][4 * u] = t.x;
+          w[rr][4 * u + 1] = t.y;
+          w[rr][4 * u + 2] = t.z;
+          w[rr][4 * u + 3] = t.w;
+        }
+        continue;
+      }
       const uint4 *src = reinterpret_cast<const uint4 *>(A + (uint64_t)r * row_words + panel_word +
                                                          (uint64_t)q * NWD);
 #pragma unroll
@@ -671,7 +698,26 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   // request x (clamped, fixed count), then the first unit, then consume x
   const int4 *x4 = reinterpret_cast<const int4 *>(x + c0);
   int4 xv[8];
-  if constexpr (kNib) {
+  // RG: the 16-byte chunk of x at panel offset e (4 | e), zero past the end
+  auto x_chunk = [&](int e) -> int4 {
+    if (e + 4 <= pc) return x4[e >> 2];
+    int4 v = {0, 0, 0, 0};
+    if (e < pc) v.x = x[c0 + e];
+    if (e + 1 < pc) v.y = x[c0 + e + 1];
+    if (e + 2 < pc) v.z = x[c0 + e + 2];
+    return v;
+  };
+  if constexpr (RG && (kNib || B == 1)) {
+    // as below, groups past the end of x read as zeros
+    constexpr int NV = kNib ? 4 : 8;
+    const int e0 = kNib ? 32 * ((int)threadIdx.x >> 1) + 16 * ((int)threadIdx.x & 1)
+                        : 32 * (int)threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) xv[i] = x_chunk(e0 + 4 * i);
+  } else if constexpr (RG) {
+#pragma unroll
+    for (int u = 0; u < kPanelAl / 4 / NT; ++u) xv[u] = x_chunk(4 * ((int)threadIdx.x + NT * u));
+  } else if constexpr (kNib) {
     // lane t: half t % 2 of group t / 2 (16 values)
     const int ng = pc / kGroup;
     const int g0 = (int)threadIdx.x >> 1;
@@ -693,7 +739,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
       xv[u] = x4[q < nchunk ? q : nchunk - 1];
     }
   }
-  uint32_t w0[R][NWD], w1[R][NWD];
+  uint32_t w0[R][NWR], w1[R][NWR];
   int64_t rb = blockIdx.x;
   __builtin_amdgcn_sched_barrier(0);  // x requests first
   // the first unit overlaps the staging (measured: a loss for b > 8)
@@ -712,7 +758,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
     }
 #pragma unroll
     for (int i = 0; i < kGroup; i += 2) m |= v[i] | v[i + 1];
-    if ((int)threadIdx.x < pc / kGroup) store_digits_al(v, threadIdx.x, xd);
+    if ((int)threadIdx.x < (RG ? 4 * nq : pc / kGroup)) store_digits_al(v, threadIdx.x, xd);
   } else if constexpr (kNib) {
     uint32_t v[16];
 #pragma unroll
@@ -725,9 +771,9 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
 #pragma unroll
     for (int i = 0; i < 16; i += 2) m |= v[i] | v[i + 1];
     const int g = (int)threadIdx.x >> 1;
-    nib_store_digits<B>(v, g, (int)threadIdx.x & 1, g < pc / kGroup, xd);
+    nib_store_digits<B>(v, g, (int)threadIdx.x & 1, g < (RG ? 4 * nq : pc / kGroup), xd);
   } else {
-    const int nchunk = pc / 4;
+    const int nchunk = RG ? 32 * nq : pc / 4;  // RG: the zero padding too
 #pragma unroll
     for (int u = 0; u < kPanelAl / 4 / NT; ++u) {
       const int q = (int)threadIdx.x + NT * u;
@@ -744,6 +790,46 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
 
   if (!fast) {
     // general x: 64-bit products, one row and one group at a time
+    if constexpr (RG) {
+      if constexpr (B == 1 || kNib) {
+        for (int q = threadIdx.x; q < 32 * nq; q += NT) {
+          const int e = 4 * q;
+          *reinterpret_cast<int4 *>(xs + e + 4 * (e >> 7)) = x_chunk(e);
+        }
+        __syncthreads();
+      }
+      for (; rb < nrb; rb += gridDim.x) {
+        int64_t r0;
+        const int nv = rows_of(rb, r0);
+#pragma unroll 1
+        for (int rr = 0; rr < nv; ++rr) {
+          uint64_t a = 0;
+#pragma unroll 1
+          for (int gi = lane; 32 * gi < pc; gi += 64) {
+            // b + 1 words from the group's first (inside the capacity's
+            // guard words), shifted into place
+            const uint64_t pb = ((uint64_t)(r0 + rr) * (uint64_t)cols + (uint64_t)c0 +
+                                 32u * (uint64_t)gi) * B;
+            const uint32_t *src = A + (pb >> 5);
+            const int sh = (int)(pb & 31u);
+            uint32_t w[B + 1];
+#pragma unroll
+            for (int k = 0; k <= B; ++k) w[k] = src[k];
+#pragma unroll
+            for (int k = 0; k < B; ++k) w[k] = __builtin_amdgcn_alignbit(w[k + 1], w[k], sh);
+            a += group_dot_wide<B, SGN, int32_t>(w, xs + (gi >> 2) * kQuadX + (gi & 3) * kGroup);
+          }
+          const int64_t sum = wave_sum((int64_t)a);
+          if (lane == 0) {
+            if (atomic_out)
+              atomicAdd((unsigned long long *)&y[r0 + rr], (unsigned long long)sum);
+            else
+              y[r0 + rr] = sum;
+          }
+        }
+      }
+      return;
+    }
     if constexpr (B == 1 || kNib) {
       (void)stage_x_al<NT>(x, c0, pc, xs);
       __syncthreads();
@@ -793,7 +879,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   // Branch-free: lanes past the last quad decode the clamped copy and add
   // nothing, rows past the end are decoded and never stored -- so every path
   // waits for the unit's loads at the same point.
-  auto compute_unit = [&](const uint32_t (&w)[R][NWD], int h) {
+  auto decode_unit = [&](const uint32_t (&w)[R][NWD], int h) {
     const int qq = lane + 64 * h;
     const bool live = qq < nq;
     const int q = live ? qq : nq - 1;
@@ -895,6 +981,35 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
     }
   };
 
+  // RG: each row's words shifted into place first (see the kernel's header)
+  auto compute_unit = [&](const uint32_t (&w)[R][NWR], int h) {
+    if constexpr (RG) {
+      const int64_t r0 = rb * ((NT / 64) * R) + (int64_t)wave * R;
+      uint32_t wa[R][NWD];
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const int64_t r = r0 + rr < rows ? r0 + rr : rows - 1;
+        const uint32_t o = (uint32_t)((((uint64_t)r * (uint64_t)cols + (uint64_t)c0) * B) & 127u);
+        const int sh = (int)(o & 31u);
+        switch (o >> 5) {
+#define CCM_REALIGN(hw)                                                                     \
+  case hw:                                                                                  \
+    _Pragma("unroll") for (int k = 0; k < NWD; ++k) wa[rr][k] =                              \
+        __builtin_amdgcn_alignbit(w[rr][k + hw + 1], w[rr][k + hw], sh);                     \
+    break;
+          CCM_REALIGN(0)
+          CCM_REALIGN(1)
+          CCM_REALIGN(2)
+          CCM_REALIGN(3)
+#undef CCM_REALIGN
+        }
+      }
+      decode_unit(wa, h);
+    } else {
+      decode_unit(w, h);
+    }
+  };
+
   // Row sums of the fast path wait in a register: lane j holds entry j of the
   // wave's current batch (row j % R of the wave's rows in row block first_rb +
   // (j / R) * gridDim.x), written with one store per 64 entries.  A store's
@@ -940,7 +1055,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   // units in order (rb, 0), (rb, 1), ..., (rb + gridDim.x, 0), ...
   int h = 0;
   if constexpr (PF) {
-    auto step = [&](uint32_t (&cur)[R][NWD], uint32_t (&nxt)[R][NWD]) -> bool {
+    auto step = [&](uint32_t (&cur)[R][NWR], uint32_t (&nxt)[R][NWR]) -> bool {
       if (nst == 64) flush();
       int64_t rb2 = rb;
       int h2 = h + 1;
@@ -984,14 +1099,14 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   if (nst > 0) flush();
 }
 
-template <int B, bool SGN, int NT = AlCfg<B>::NT>
+template <int B, bool SGN, int NT = AlCfg<B>::NT, bool RG = false>
 int resident_blocks_al(size_t lds) {
   static int cached = 0;
   if (cached == 0) {
     int occ = 0, dev = 0, cus = 0;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_matvec_al<B, SGN, NT>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_matvec_al<B, SGN, NT, RG>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_matvec_al<B, SGN, NT>, NT,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_matvec_al<B, SGN, NT, RG>, NT,
                                                      lds) != hipSuccess ||
         occ < 1)
       occ = 1;
@@ -1004,7 +1119,7 @@ int resident_blocks_al(size_t lds) {
   return cached;
 }
 
-template <int B, bool SGN, int NT = AlCfg<B>::NT>
+template <int B, bool SGN, bool RG = false, int NT = AlCfg<B>::NT>
 hipError_t launch_aligned(const uint32_t *w, int64_t rows, int64_t cols, const int32_t *x,
                           int64_t *y, hipStream_t s) {
   constexpr int R = AlCfg<B>::R;
@@ -1015,12 +1130,12 @@ hipError_t launch_aligned(const uint32_t *w, int64_t rows, int64_t cols, const i
     hipError_t e = launch_fill_i64(y, (uint64_t)rows, 0, s);
     if (e != hipSuccess) return e;
   }
-  const int64_t nqp = (cols < kPanelAl ? cols : kPanelAl) / (4 * kGroup);
+  const int64_t nqp = ((cols < kPanelAl ? cols : kPanelAl) + 4 * kGroup - 1) / (4 * kGroup);
   const size_t lds = (size_t)nqp * kQuadX * sizeof(int32_t);  // >= the digit words
-  int64_t gx =
-      resident_blocks_al<B, SGN, NT>((size_t)(kPanelAl / (4 * kGroup)) * kQuadX * 4) / npanels;
+  int64_t gx = resident_blocks_al<B, SGN, NT, RG>((size_t)(kPanelAl / (4 * kGroup)) * kQuadX * 4) /
+               npanels;
   gx = gx < 1 ? 1 : (gx > nrb ? nrb : gx);  // every block owns at least one row block
-  k_matvec_al<B, SGN, NT><<<dim3((unsigned)gx, (unsigned)npanels), NT, lds, s>>>(
+  k_matvec_al<B, SGN, NT, RG><<<dim3((unsigned)gx, (unsigned)npanels), NT, lds, s>>>(
       w, rows, cols, x, y, npanels > 1 ? 1 : 0);
   return hipGetLastError();
 }
@@ -1248,6 +1363,15 @@ hipError_t launch_width(const uint32_t *w, int64_t rows, int64_t cols, int sgn, 
         ((uintptr_t)x % 16) == 0)
       return sgn ? launch_aligned<B, true>(w, rows, cols, (const int32_t *)x, y, s)
                  : launch_aligned<B, false>(w, rows, cols, (const int32_t *)x, y, s);
+  }
+  // any other column count at b <= 4: measured on 16384 x 16383 and
+  // 16384 x 12345 against the general kernel, b = 1 19.1 / 18.1 us against
+  // 24.1 / 21.9, b = 3 28.1 / 26.2 against 37.0 / 31.8; at b = 7 it lost
+  // (58.7 / 49.1 against 51.9 / 44.1), so wider fields keep the general kernel
+  if constexpr (B <= 4) {
+    if (xdtype == CCM_I32 && ((uintptr_t)w % 16) == 0 && ((uintptr_t)x % 16) == 0)
+      return sgn ? launch_aligned<B, true, true>(w, rows, cols, (const int32_t *)x, y, s)
+                 : launch_aligned<B, false, true>(w, rows, cols, (const int32_t *)x, y, s);
   }
   if constexpr (B >= 16) {
     if (xdtype == CCM_I32)

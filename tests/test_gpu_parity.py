@@ -373,6 +373,50 @@ def test_matvec_int16_x_extremes(b):
                                                                      fname, xname)
 
 
+# Column counts that are not a multiple of 128 (rows start at any bit): the
+# aligned kernel's ragged form at b <= 7, whose units fetch 16-byte-aligned
+# supersets of each quad and shift them into place.  One, two and three column
+# panels, panels that end inside a group, x zero-padded to whole quads.
+MV_RAGGED = [(1, 1), (3, 127), (37, 129), (5, 16383), (9, 16385), (4, 32845), (130, 1000),
+             (1000, 130), (2, 77)]
+
+
+@pytest.mark.parametrize("b", list(range(1, 9)))
+def test_matvec_ragged_columns(b):
+    c = ccm()
+    rng = np.random.default_rng(3000 + b)
+    for signed in (False, True):
+        for rows, cols in MV_RAGGED:
+            if signed and b == 1 and rows * cols < 2:
+                continue
+            A = rand_matrix(rng, rows, cols, b, signed)
+            pa = oracle.compress(A)
+            g = c.compress(dev(A))
+            x16 = rng.integers(-(1 << 15), (1 << 15) - 1, size=cols, endpoint=True)
+            x16[int(rng.integers(0, cols))] = -(1 << 15)
+            x16[int(rng.integers(0, cols))] = (1 << 15) - 1
+            x17 = x16.copy()
+            x17[int(rng.integers(0, cols))] = 1 << 15  # one value outside int16
+            x32 = rng.integers(-(1 << 31), 1 << 31, size=cols)
+            for x in (x16, x17, x32):
+                y = c.matvec(g, dev(x, torch.int32)).cpu().numpy()
+                assert np.array_equal(y, oracle.matvec(pa, x)), (b, signed, rows, cols)
+        # fields at their largest magnitudes against x at both ends of int16
+        lo, hi = ((-(1 << (b - 1)), (1 << (b - 1)) - 1) if signed else (0, (1 << b) - 1))
+        if b == 1 and signed:
+            lo, hi = -1, 0
+        for rows, cols in ((7, 16385), (3, 32845)):
+            j = np.arange(cols)
+            A = np.ascontiguousarray(np.broadcast_to(np.where(j % 3 == 0, lo, hi), (rows, cols)),
+                                     dtype=np.int64)
+            pa = oracle.compress(A)
+            g = c.compress(dev(A))
+            for x in (np.full(cols, -(1 << 15)), np.full(cols, (1 << 15) - 1),
+                      np.where(j % 2 == 0, (1 << 15) - 1, -(1 << 15))):
+                y = c.matvec(g, dev(x, torch.int32)).cpu().numpy()
+                assert np.array_equal(y, oracle.matvec(pa, x)), (b, signed, rows, cols, "extremes")
+
+
 # operands whose values fit int8 take the MFMA path (unsigned b <= 7, signed b <= 8)
 @pytest.mark.parametrize("ba,sa,bb,sb", [(10, False, 10, False), (6, False, 4, True),
                                          (1, False, 1, True), (20, True, 17, False),
