@@ -24,7 +24,13 @@ over time.  The loop runs continuous batching on a few HIP streams:
 * Python's cyclic garbage collector is paused for the run (a full collection
   over a process that has imported torch can hold the loop for tens of
   milliseconds); `max_loop_gap_ms` reports the longest time between two
-  passes of the loop, so a host-side stall shows in the statistics.
+  passes of the loop, so a host-side stall shows in the statistics;
+* the loop allocates no device memory: every result buffer (y of each
+  matvec, the payload and workspace of each matmul) and one matmul scratch
+  per stream are carved out of a few tensors before the first request, so
+  that no block the caching allocator does not hold yet can mean a hipMalloc
+  inside the loop (a run that still allocated there once showed a 6 ms
+  stall of the loop at 95 % load; its cause was not isolated).
 """
 from __future__ import annotations
 
@@ -54,6 +60,8 @@ class Request:
     y: torch.Tensor | None = None  # matvec result
     c: CMatrix | None = None  # matmul result
     pending: Pending | None = None  # matmul result while in flight
+    buf: torch.Tensor | None = None  # y (matvec) or the result payload (matmul), preassigned
+    ws: torch.Tensor | None = None  # matmul result workspace, preassigned
     done: float = math.nan  # completion, seconds after the start of the run
     launch: int = -1  # id of the launch that served it
 
@@ -106,17 +114,49 @@ class Server:
             r.footprint = request_footprint(r, self.pool)
             if r.footprint > self.arena:
                 raise ValueError(f"request {r.rid} needs {r.footprint} bytes, arena {self.arena}")
+        scratch = self._prepare(reqs)
         torch.cuda.synchronize()
         gc_was_enabled = gc.isenabled()
         gc.collect()
         gc.disable()
         try:
-            return self._loop(reqs, poll_sleep)
+            return self._loop(reqs, poll_sleep, scratch)
         finally:
             if gc_was_enabled:
                 gc.enable()
 
-    def _loop(self, reqs, poll_sleep):
+    def _prepare(self, reqs):
+        """Device buffers of the whole run, assigned before the loop starts:
+        views of one int64 tensor for the matvec results, of one byte tensor
+        (256-byte aligned slices) for the matmul payloads and workspaces, and
+        one scratch per stream (a stream runs its matmuls in order, so each
+        reuses it).  Returns the per-stream scratch list."""
+        dev = torch.device("cuda")
+        mv = [r for r in reqs if r.kind == "mv"]
+        mm = [r for r in reqs if r.kind != "mv"]
+        rows = [self.pool[r.mat].rows for r in mv]
+        ys = torch.empty(max(1, sum(rows)), dtype=torch.int64, device=dev)
+        off = 0
+        for r, n in zip(mv, rows):
+            r.buf = ys[off:off + n]
+            off += n
+        def up(n):
+            return (n + 255) // 256 * 256
+        wsb = int(lib.ccm_async_ws_bytes())
+        caps = [matmul_capacity(self.pool[r.mat], r.b) for r in mm]
+        need = max([matmul_scratch_bytes(self.pool[r.mat], r.b) for r in mm], default=0)
+        blob = torch.empty(max(1, sum(up(c) + up(wsb) for c in caps)), dtype=torch.uint8,
+                           device=dev)
+        off = 0
+        for r, c in zip(mm, caps):
+            r.buf = blob[off:off + c]
+            off += up(c)
+            r.ws = blob[off:off + wsb]
+            off += up(wsb)
+        return [torch.empty(max(1, need), dtype=torch.uint8, device=dev)
+                for _ in self.streams]
+
+    def _loop(self, reqs, poll_sleep, scratch):
         waiting = collections.deque()
         pending_mv, pending_mm = [], []
         inflight: list[_Launch] = []
@@ -180,7 +220,9 @@ class Server:
                     if pending_mm and (not pending_mv or len(pending_mm) * 8 >= len(pending_mv)):
                         r = pending_mm.pop(0)
                         host = self._hosts.pop()
-                        r.pending = matmul_async(self.pool[r.mat], r.b, host=host, stream=stream)
+                        r.pending = matmul_async(self.pool[r.mat], r.b, scratch=scratch[si],
+                                                 ws=r.ws, payload=r.buf, host=host,
+                                                 stream=stream)
                         L.requests.append(r)
                         L.hosts.append(host)
                     else:
@@ -189,7 +231,7 @@ class Server:
                         narrow = []
                         for r in group:
                             a = self.pool[r.mat]
-                            r.y = torch.empty(a.rows, dtype=torch.int64, device="cuda")
+                            r.y = r.buf
                             if a.cols <= BATCH_MAX_COLS:
                                 narrow.append(r)
                             else:
