@@ -630,7 +630,7 @@ __device__ __forceinline__ uint32_t nib_spread(uint32_t c) {
 template <int B, bool SGN, int NT = AlCfg<B>::NT, bool RG = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void
 k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
-            const int32_t *__restrict__ x, int64_t *__restrict__ y, int atomic_out) {
+            const int32_t *__restrict__ x, int64_t *__restrict__ y, int atomic_out, int g_full) {
   static_assert(NT >= 512 && NT % 64 == 0, "a lane per b = 1 group of a 16384-column panel");
   constexpr int R = AlCfg<B>::R;
   constexpr bool PF = AlCfg<B>::PF;
@@ -642,14 +642,23 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   int32_t *xs = reinterpret_cast<int32_t *>(smem_raw);
   uint32_t *xd = reinterpret_cast<uint32_t *>(smem_raw);  // b <= 4 fast path only
 
-  const int64_t c0 = (int64_t)blockIdx.y * kPanelAl;
+  // A 1-D grid over the column panels: g_full blocks for each full panel,
+  // the rest for the last one (the host sizes the shares by the panels'
+  // quads), each share striding over the row blocks.
+  const int npan = (int)((cols + kPanelAl - 1) / kPanelAl);
+  const int nfb = (npan - 1) * g_full;
+  const bool in_full = (int)blockIdx.x < nfb;
+  const int pan = in_full ? (int)blockIdx.x / g_full : npan - 1;
+  const int bj = in_full ? (int)blockIdx.x % g_full : (int)blockIdx.x - nfb;
+  const int gstr = in_full ? g_full : (int)gridDim.x - nfb;
+  const int64_t c0 = (int64_t)pan * kPanelAl;
   // a multiple of 128 unless RG
   const int pc = (int)(cols - c0 < kPanelAl ? cols - c0 : kPanelAl);
   const int nq = (pc + 4 * kGroup - 1) / (4 * kGroup);
   const int nslot = (nq + 63) / 64;  // quad slots per lane: 1 or 2 (wave-uniform)
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t nrb = (rows + (NT / 64) * R - 1) / ((NT / 64) * R);  // > blockIdx.x
+  const int64_t nrb = (rows + (NT / 64) * R - 1) / ((NT / 64) * R);  // > bj
   const uint64_t row_words = (uint64_t)cols * B / 32;  // a multiple of 4
   const uint64_t panel_word = (uint64_t)c0 * B / 32;
 
@@ -740,7 +749,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
     }
   }
   uint32_t w0[R][NWR], w1[R][NWR];
-  int64_t rb = blockIdx.x;
+  int64_t rb = bj;
   __builtin_amdgcn_sched_barrier(0);  // x requests first
   // the first unit overlaps the staging (measured: a loss for b > 8)
   constexpr bool kEarly = PF || B <= 8;
@@ -798,7 +807,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
         }
         __syncthreads();
       }
-      for (; rb < nrb; rb += gridDim.x) {
+      for (; rb < nrb; rb += gstr) {
         int64_t r0;
         const int nv = rows_of(rb, r0);
 #pragma unroll 1
@@ -834,7 +843,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
       (void)stage_x_al<NT>(x, c0, pc, xs);
       __syncthreads();
     }
-    for (; rb < nrb; rb += gridDim.x) {
+    for (; rb < nrb; rb += gstr) {
       int64_t r0;
       const int nv = rows_of(rb, r0);
 #pragma unroll 1
@@ -1012,7 +1021,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
 
   // Row sums of the fast path wait in a register: lane j holds entry j of the
   // wave's current batch (row j % R of the wave's rows in row block first_rb +
-  // (j / R) * gridDim.x), written with one store per 64 entries.  A store's
+  // (j / R) * gstr), written with one store per 64 entries.  A store's
   // address and data registers may only be reused once it has completed, and
   // the load counter is in order, so a store issued after a unit's loads
   // would make the next reuse wait for those loads as well: the batch store is
@@ -1023,7 +1032,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
   int64_t first_rb = rb;
   int64_t *ydst = y;
   auto flush = [&]() {
-    const int64_t rbj = first_rb + (int64_t)(lane / R) * gridDim.x;
+    const int64_t rbj = first_rb + (int64_t)(lane / R) * gstr;
     const int64_t row = rbj * ((NT / 64) * R) + (int64_t)wave * R + lane % R;
     const bool ok = lane < nst && row < rows;
     ydst = y + (ok ? row : 0);
@@ -1052,7 +1061,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
     nst += R;
   };
 
-  // units in order (rb, 0), (rb, 1), ..., (rb + gridDim.x, 0), ...
+  // units in order (rb, 0), (rb, 1), ..., (rb + gstr, 0), ...
   int h = 0;
   if constexpr (PF) {
     auto step = [&](uint32_t (&cur)[R][NWR], uint32_t (&nxt)[R][NWR]) -> bool {
@@ -1061,7 +1070,7 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
       int h2 = h + 1;
       if (h2 == nslot) {
         h2 = 0;
-        rb2 += gridDim.x;
+        rb2 += gstr;
       }
       const bool more = rb2 < nrb;
       load_unit(nxt, more ? rb2 : rb, more ? h2 : h);
@@ -1076,9 +1085,9 @@ k_matvec_al(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
     }
   } else {
     // one unit at a time: row sums are stored as they complete
-    for (; rb < nrb; rb += gridDim.x) {
+    for (; rb < nrb; rb += gstr) {
       for (h = 0; h < nslot; ++h) {
-        if (!kEarly || h > 0 || rb != (int64_t)blockIdx.x) load_unit(w0, rb, h);
+        if (!kEarly || h > 0 || rb != (int64_t)bj) load_unit(w0, rb, h);
         compute_unit(w0, h);
       }
       int64_t r0;
@@ -1132,11 +1141,23 @@ hipError_t launch_aligned(const uint32_t *w, int64_t rows, int64_t cols, const i
   }
   const int64_t nqp = ((cols < kPanelAl ? cols : kPanelAl) + 4 * kGroup - 1) / (4 * kGroup);
   const size_t lds = (size_t)nqp * kQuadX * sizeof(int32_t);  // >= the digit words
-  int64_t gx = resident_blocks_al<B, SGN, NT, RG>((size_t)(kPanelAl / (4 * kGroup)) * kQuadX * 4) /
-               npanels;
-  gx = gx < 1 ? 1 : (gx > nrb ? nrb : gx);  // every block owns at least one row block
-  k_matvec_al<B, SGN, NT, RG><<<dim3((unsigned)gx, (unsigned)npanels), NT, lds, s>>>(
-      w, rows, cols, x, y, npanels > 1 ? 1 : 0);
+  const int64_t res =
+      resident_blocks_al<B, SGN, NT, RG>((size_t)(kPanelAl / (4 * kGroup)) * kQuadX * 4);
+  auto clampg = [&](int64_t g) { return g < 1 ? 1 : (g > nrb ? nrb : g); };
+  // resident blocks shared by the panels in proportion to their units per
+  // row block (quad slots: 2 for a full panel, 1 for a last panel of at most
+  // 64 quads, whose units cost as much however few of their lanes are live),
+  // so that a narrow last panel does not hold blocks the full panels need;
+  // every block owns at least one row block
+  const int64_t nq_last = (cols - (npanels - 1) * kPanelAl + 4 * kGroup - 1) / (4 * kGroup);
+  const int64_t ns_last = (nq_last + 63) / 64;
+  const int64_t g_full =
+      npanels == 1 ? clampg(res) : clampg(res * 2 / ((npanels - 1) * 2 + ns_last));
+  const int64_t g_last = npanels == 1 ? g_full : clampg(g_full * ns_last / 2);
+  const int64_t grid = (npanels - 1) * g_full + g_last;
+  if (grid > 0x7fffffffll) return hipErrorInvalidValue;
+  k_matvec_al<B, SGN, NT, RG><<<dim3((unsigned)grid), NT, lds, s>>>(
+      w, rows, cols, x, y, npanels > 1 ? 1 : 0, (int)g_full);
   return hipGetLastError();
 }
 
