@@ -1185,18 +1185,25 @@ template <int B, bool SGN, int NT = WCfg<B>::NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void
 k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
            const int32_t *__restrict__ x, int64_t *__restrict__ y, int atomic_out,
-           int x_aligned16) {
+           int x_aligned16, int g_full) {
   constexpr bool PF = WCfg<B>::PF;
   constexpr int NWG = B + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int32_t *xs = reinterpret_cast<int32_t *>(smem_raw);
 
-  const int64_t c0 = (int64_t)blockIdx.y * kPanelW;
+  // a 1-D grid over the column panels, as in the aligned kernel
+  const int npan = (int)((cols + kPanelW - 1) / kPanelW);
+  const int nfb = (npan - 1) * g_full;
+  const bool in_full = (int)blockIdx.x < nfb;
+  const int pan = in_full ? (int)blockIdx.x / g_full : npan - 1;
+  const int bj = in_full ? (int)blockIdx.x % g_full : (int)blockIdx.x - nfb;
+  const int gstr = in_full ? g_full : (int)gridDim.x - nfb;
+  const int64_t c0 = (int64_t)pan * kPanelW;
   const int pc = (int)(cols - c0 < kPanelW ? cols - c0 : kPanelW);
   const int ng = (pc + kGroup - 1) / kGroup;
   const int nslot = (ng + 63) / 64;  // wave-uniform
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t nrb = (rows + (NT / 64) - 1) / (NT / 64);  // > blockIdx.x
+  const int64_t nrb = (rows + (NT / 64) - 1) / (NT / 64);  // > bj
 
   // the unit's words and the row's funnel shift (the same for every group of
   // a row); rows past the end and groups past the last are clamped
@@ -1214,7 +1221,7 @@ k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
 
   uint32_t w0[NWG], w1[NWG];
   int s0 = 0, s1 = 0;
-  int64_t rb = blockIdx.x;
+  int64_t rb = bj;
 
   // stage the x panel, zero-padded to whole groups
   const int nchunk = ng * kGroup / 4;
@@ -1270,14 +1277,14 @@ k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
 
   if constexpr (PF) {
     // row sums wait in a register (lane j: entry j of the batch, row
-    // first_rb + j * gridDim.x of this wave) and are stored once per 64 rows,
+    // first_rb + j * gstr of this wave) and are stored once per 64 rows,
     // before a step's loads (see the aligned kernel)
     uint64_t ybuf = 0;
     int nst = 0;
     int64_t first_rb = rb;
     int64_t *ydst = y;
     auto flush = [&]() {
-      const int64_t row = (first_rb + (int64_t)lane * gridDim.x) * (NT / 64) + wave;
+      const int64_t row = (first_rb + (int64_t)lane * gstr) * (NT / 64) + wave;
       const bool ok = lane < nst && row < rows;
       ydst = y + (ok ? row : 0);
       if (ok) {
@@ -1295,7 +1302,7 @@ k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
       int h2 = h + 1;
       if (h2 == nslot) {
         h2 = 0;
-        rb2 += gridDim.x;
+        rb2 += gstr;
       }
       const bool more = rb2 < nrb;
       load_unit(nxt, more ? rb2 : rb, more ? h2 : h, snxt);
@@ -1316,7 +1323,7 @@ k_matvec_w(const uint32_t *__restrict__ A, int64_t rows, int64_t cols,
     }
     if (nst > 0) flush();
   } else {
-    for (; rb < nrb; rb += gridDim.x) {
+    for (; rb < nrb; rb += gstr) {
       for (int h = 0; h < nslot; ++h) {
         load_unit(w0, rb, h, s0);
         compute_unit(w0, s0, h);
@@ -1366,11 +1373,22 @@ hipError_t launch_wide(const uint32_t *w, int64_t rows, int64_t cols, const int3
   }
   const int64_t ngp = ((cols < kPanelW ? cols : kPanelW) + kGroup - 1) / kGroup;
   const size_t lds = (size_t)ngp * kPitchW * sizeof(int32_t);
-  int64_t gx = resident_blocks_w<B, SGN, NT>((size_t)(kPanelW / kGroup) * kPitchW * 4) / npanels;
-  gx = gx < 1 ? 1 : (gx > nrb ? nrb : gx);  // every block owns at least one row
+  const int64_t res = resident_blocks_w<B, SGN, NT>((size_t)(kPanelW / kGroup) * kPitchW * 4);
+  auto clampg = [&](int64_t g) { return g < 1 ? 1 : (g > nrb ? nrb : g); };
+  // blocks shared by the panels in proportion to their group slots per row
+  // (8 for a full panel), as in the aligned kernel; every block owns at least
+  // one row
+  const int64_t ng_last = (cols - (npanels - 1) * kPanelW + kGroup - 1) / kGroup;
+  const int64_t ns_last = (ng_last + 63) / 64;
+  const int64_t ns_full = kPanelW / kGroup / 64;
+  const int64_t g_full = npanels == 1 ? clampg(res)
+                                      : clampg(res * ns_full / ((npanels - 1) * ns_full + ns_last));
+  const int64_t g_last = npanels == 1 ? g_full : clampg(g_full * ns_last / ns_full);
+  const int64_t grid = (npanels - 1) * g_full + g_last;
+  if (grid > 0x7fffffffll) return hipErrorInvalidValue;
   const int al = ((uintptr_t)x % 16) == 0;
-  k_matvec_w<B, SGN, NT><<<dim3((unsigned)gx, (unsigned)npanels), NT, lds, s>>>(
-      w, rows, cols, x, y, npanels > 1 ? 1 : 0, al);
+  k_matvec_w<B, SGN, NT><<<dim3((unsigned)grid), NT, lds, s>>>(
+      w, rows, cols, x, y, npanels > 1 ? 1 : 0, al, (int)g_full);
   return hipGetLastError();
 }
 
