@@ -377,10 +377,11 @@ def test_matvec_int16_x_extremes(b):
 # aligned kernel's ragged form at b <= 4, whose units fetch 16-byte-aligned
 # supersets of each quad and shift them into place, the general kernel at
 # 5..8 and the wide kernel at 16 and up.  One, two and three column panels
-# (the grid shared by panels of unequal width), panels that end inside a
-# group, x zero-padded to whole quads.
+# (the grid shared by panels of unequal width) up to seven (100001 columns;
+# 98304 = six whole panels), panels that end inside a group, x zero-padded to
+# whole quads.
 MV_RAGGED = [(1, 1), (3, 127), (37, 129), (5, 16383), (9, 16385), (4, 32845), (130, 1000),
-             (1000, 130), (2, 77)]
+             (1000, 130), (2, 77), (3, 100001), (2, 98304)]
 
 
 @pytest.mark.parametrize("b", list(range(1, 9)) + [16, 17, 24, 31])
