@@ -87,17 +87,47 @@ __device__ __forceinline__ void encode(const int64_t *v, uint32_t *__restrict__ 
   }
 }
 
-// 32-bit values (b <= 32): fields zero-extended, or sign-extended when sgn.
+// Field i of a group as a 32-bit value: one bit-field extract (v_bfe_i32
+// sign-extending when S, v_bfe_u32 otherwise), after a funnel shift when the
+// field straddles two words.
+template <int B, bool S>
+__device__ __forceinline__ uint32_t field32(const uint32_t *w, int i) {
+  const int p = i * B;
+  const int k = p >> 5;
+  const int off = p & 31;
+  if constexpr (B == 32) {
+    return w[k];
+  } else {
+    uint32_t src;
+    int o;
+    if (off + B <= 32) {
+      src = w[k];
+      o = off;
+    } else {
+      src = __builtin_amdgcn_alignbit(w[k + 1], w[k], off);
+      o = 0;
+    }
+    if constexpr (S)
+      return (uint32_t)__builtin_amdgcn_sbfe((int32_t)src, o, B);
+    else
+      return __builtin_amdgcn_ubfe(src, o, B);
+  }
+}
+
+// 32-bit values (b <= 32): fields zero-extended, or sign-extended when sgn
+// (tested once per group, not per field).
 template <int B>
 __device__ __forceinline__ void decode32(const uint32_t *__restrict__ p, int sgn, uint32_t *v) {
   static_assert(B <= 32, "32-bit decode");
   uint32_t w[B];
 #pragma unroll
   for (int k = 0; k < B; ++k) w[k] = p[k];
+  if (sgn) {
 #pragma unroll
-  for (int i = 0; i < kGroup; ++i) {
-    const uint32_t u = (uint32_t)field<B>(w, i);
-    v[i] = (sgn && B < 32) ? (uint32_t)(((int32_t)(u << (32 - B))) >> (32 - B)) : u;
+    for (int i = 0; i < kGroup; ++i) v[i] = field32<B, true>(w, i);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) v[i] = field32<B, false>(w, i);
   }
 }
 

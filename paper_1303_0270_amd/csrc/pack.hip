@@ -383,31 +383,41 @@ __global__ __launch_bounds__(256) void k_ewise_pack32(PackedOperand a, PackedOpe
     cap32 = cap_words32(n, out_bits);
   }
   extern __shared__ __align__(16) uint32_t s_out[];  // 256 out_bits words
-  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t nfull = n / kGroup;
-  uint32_t vc[kGroup];
-  if (g < nfull) {
-    ewise_group32<OP, VT, false>(a, b, (VT)scalar, g, n, vc);
-  } else if (g * kGroup < n) {
-    ewise_group32<OP, VT, true>(a, b, (VT)scalar, g, n, vc);
-  } else {
+  VT lo = std::numeric_limits<VT>::max(), hi = std::numeric_limits<VT>::min();
+  {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t vc[kGroup];
+    if (g < nfull) {
+      ewise_group32<OP, VT, false>(a, b, (VT)scalar, g, n, vc);
+      if constexpr (RANGE) {
+        // a whole group: every result counts (no per-element test)
 #pragma unroll
-    for (int i = 0; i < kGroup; ++i) vc[i] = 0;
-  }
-  if constexpr (RANGE) {
-    // every thread of the block reaches the commit's barriers (no early exit)
-    const uint64_t left = g < nfull ? (uint64_t)kGroup : g * kGroup < n ? n - g * kGroup : 0;
-    VT lo = std::numeric_limits<VT>::max(), hi = std::numeric_limits<VT>::min();
-#pragma unroll
-    for (int i = 0; i < kGroup; ++i) {
-      if ((uint64_t)i < left) {
-        lo = (VT)vc[i] < lo ? (VT)vc[i] : lo;
-        hi = (VT)vc[i] > hi ? (VT)vc[i] : hi;
+        for (int i = 0; i < kGroup; ++i) {
+          lo = (VT)vc[i] < lo ? (VT)vc[i] : lo;
+          hi = (VT)vc[i] > hi ? (VT)vc[i] : hi;
+        }
       }
+    } else if (g * kGroup < n) {
+      ewise_group32<OP, VT, true>(a, b, (VT)scalar, g, n, vc);
+      if constexpr (RANGE) {
+        const int left = (int)(n - g * kGroup);
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+          if (i < left) {
+            lo = (VT)vc[i] < lo ? (VT)vc[i] : lo;
+            hi = (VT)vc[i] > hi ? (VT)vc[i] : hi;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kGroup; ++i) vc[i] = 0;
     }
-    block_range_fold((int64_t)lo, (int64_t)hi, slot);
+    codec::encode32_rt(vc, out_bits, s_out + threadIdx.x * out_bits, (uint64_t)out_bits);
   }
-  codec::encode32_rt(vc, out_bits, s_out + threadIdx.x * out_bits, (uint64_t)out_bits);
+  // every thread of the block reaches the commit's barriers (no early exit)
+  if constexpr (RANGE) block_range_fold((int64_t)lo, (int64_t)hi, slot);
   __syncthreads();
   store_block_run(s_out, out_bits, out, cap32);
 }
