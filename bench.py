@@ -8,8 +8,10 @@ a second matrix of each kind for add, and an int32 x uniform in
 
 One step runs every operation of the path over the twelve matrices, in
 phases: width + compress (from the dense int64 input), matvec, add (one
-pass: pack at the headers' bound width with the exact range folded in),
-scale by 7, decompress and 1000 element gets.  The reported
+pass: pack at the headers' bound width with the exact range folded in; the
+asynchronous form, its width decided on the device and the twelve headers
+read back once all adds are enqueued), scale by 7, decompress and 1000
+element gets.  The reported
 value is the packed-matvec bandwidth: the packed bytes of A (8*W per matrix)
 over the time of the matvec phase, taken with a pair of HIP events on the
 launch stream around the twelve back-to-back launches (even steps); odd steps
@@ -248,7 +250,7 @@ def summarize_trace(stats_csv, out_path, bench_json=None, cmd="", title="", note
 
     rows = list(csv.DictReader(open(stats_csv)))
     title = title or "Kernel times: one benchmark step over the 16384 x 16384 bandwidth sweep"
-    note = note or ("A step runs width + compress, matvec, add (one pass, the exact range "
+    note = note or ("A step runs width + compress, matvec, add (asynchronous, one pass, the exact range "
                     "folded into the pack), scale by 7, "
                     "decompress and 1000 gets over the twelve sweep matrices (k in "
                     "{1,3,7,12,17,31}, unsigned and signed); the dense int32 comparison, the read "
