@@ -422,6 +422,60 @@ __global__ __launch_bounds__(256) void k_ewise_pack32(PackedOperand a, PackedOpe
   store_block_run(s_out, out_bits, out, cap32);
 }
 
+// One-pass add of two operands of one width b and one signedness into a
+// result of b + 1 bits, the usual case (random operands of one width): the
+// same work as k_ewise_pack32<add, int32_t, RANGE> with every width known at
+// compile time, so no per-group dispatch on the widths (b <= 15: the sums
+// fit int32).
+template <int B, bool SGN>
+__global__ __launch_bounds__(256) void k_add_same(const uint32_t *__restrict__ aw,
+                                                  const uint32_t *__restrict__ bw, uint64_t n,
+                                                  uint32_t *__restrict__ out, uint64_t cap32,
+                                                  RangeSlot *slot) {
+  constexpr int OB = B + 1;
+  __shared__ __align__(16) uint32_t s_out[256 * OB];
+  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t nfull = n / kGroup;
+  int32_t lo = INT32_MAX, hi = INT32_MIN;
+  uint32_t vc[kGroup];
+  if (g * kGroup < n) {
+    uint32_t wa[B], wb[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      wa[q] = aw[g * B + q];
+      wb[q] = bw[g * B + q];
+    }
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i)
+      vc[i] = codec::field32<B, SGN>(wa, i) + codec::field32<B, SGN>(wb, i);
+    if (g < nfull) {
+#pragma unroll
+      for (int i = 0; i < kGroup; ++i) {
+        lo = (int32_t)vc[i] < lo ? (int32_t)vc[i] : lo;
+        hi = (int32_t)vc[i] > hi ? (int32_t)vc[i] : hi;
+      }
+    } else {
+      const int left = (int)(n - g * kGroup);
+#pragma unroll
+      for (int i = 0; i < kGroup; ++i) {
+        vc[i] = i < left ? vc[i] : 0u;
+        if (i < left) {
+          lo = (int32_t)vc[i] < lo ? (int32_t)vc[i] : lo;
+          hi = (int32_t)vc[i] > hi ? (int32_t)vc[i] : hi;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) vc[i] = 0;
+  }
+  // every thread of the block reaches the commit's barriers (no early exit)
+  block_range_fold((int64_t)lo, (int64_t)hi, slot);
+  codec::encode32<OB>(vc, s_out + threadIdx.x * OB, (uint64_t)OB);
+  __syncthreads();
+  store_block_run(s_out, OB, out, cap32);
+}
+
 // One wave folds the spread range slots into a ccm_result.
 __global__ __launch_bounds__(64) void k_result_finalize(const RangeSlot *slot, int64_t rows,
                                                         int64_t cols, int check_flag,
@@ -606,6 +660,24 @@ hipError_t launch_add_pack_range(PackedOperand a, PackedOperand b, uint64_t n, i
   const uint64_t ngroups_out = (cap32 + out_bits - 1) / out_bits;
   const unsigned grid = grid_for(ngroups_out, 256, 0x7fffffffu);
   const size_t lds = (size_t)256 * (size_t)out_bits * 4u;
+  if (a.bits == b.bits && a.sgn == b.sgn && out_bits == a.bits + 1 && a.bits <= 15) {
+    switch (a.bits * 2 + (a.sgn ? 1 : 0)) {
+#define CCM_ADD_SAME(bb)                                                                       \
+  case 2 * bb:                                                                                 \
+    k_add_same<bb, false><<<grid, 256, 0, s>>>(a.w, b.w, n, out, cap32, slot);                 \
+    break;                                                                                     \
+  case 2 * bb + 1:                                                                             \
+    k_add_same<bb, true><<<grid, 256, 0, s>>>(a.w, b.w, n, out, cap32, slot);                  \
+    break;
+      CCM_ADD_SAME(1) CCM_ADD_SAME(2) CCM_ADD_SAME(3) CCM_ADD_SAME(4) CCM_ADD_SAME(5)
+      CCM_ADD_SAME(6) CCM_ADD_SAME(7) CCM_ADD_SAME(8) CCM_ADD_SAME(9) CCM_ADD_SAME(10)
+      CCM_ADD_SAME(11) CCM_ADD_SAME(12) CCM_ADD_SAME(13) CCM_ADD_SAME(14) CCM_ADD_SAME(15)
+#undef CCM_ADD_SAME
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   if (vclass == EW_I32)
     k_ewise_pack32<EW_ADD, int32_t, true>
         <<<grid, 256, lds, s>>>(a, b, 0, n, out_bits, out, cap32, slot);
