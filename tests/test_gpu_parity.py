@@ -127,6 +127,30 @@ def test_add_matches_oracle(ba, sa, bb, sb, onepass):
         assert_same_packed(c.add(c.compress(dev(A)), c.compress(dev(B)), onepass=onepass), ref)
 
 
+# Operands of one width and signedness whose sums need one more bit: the
+# one-pass add's compile-time kernel, at every width it covers (b <= 15),
+# over many packing blocks and a ragged last group, with each operand's
+# extremes present (so the sums reach both ends of their bound).
+@pytest.mark.parametrize("b", list(range(1, 16)))
+def test_add_same_width_every_b(b):
+    c = ccm()
+    rng = np.random.default_rng(4000 + b)
+    for signed in (False, True):
+        for rows, cols in ((300, 1001), (3, 37)):
+            A = rand_matrix(rng, rows, cols, b, signed)
+            B = rand_matrix(rng, rows, cols, b, signed)
+            lo, hi = ((-(1 << (b - 1)), (1 << (b - 1)) - 1) if signed else (0, (1 << b) - 1))
+            A.reshape(-1)[-1], B.reshape(-1)[-1] = hi, hi
+            A.reshape(-1)[0], B.reshape(-1)[0] = lo, lo
+            ref = oracle.add(oracle.compress(A), oracle.compress(B))
+            for onepass in (True, False):
+                g = c.add(c.compress(dev(A)), c.compress(dev(B)), onepass=onepass)
+                assert g.bits == b + 1, (b, signed, rows, cols)
+                assert_same_packed(g, ref)
+            pend = c.add_async(c.compress(dev(A)), c.compress(dev(B)))
+            assert_same_packed(pend.get(), ref)
+
+
 # Operand ranges at the edges of the 32-bit elementwise classes (every operand
 # and result in int32, or all non-negative with results below 2^32) and just
 # past them, so each class and the int64 path meet their boundary values.
